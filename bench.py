@@ -1,0 +1,175 @@
+"""Benchmark of the short-range P3M pair force on one MI355X.
+
+Workload (default): N = 128^3 clustered particles (Zel'dovich lattice plus
+200 NFW-like halos holding 30 % of the particles), PM grid 256^3,
+x_s = 1.25 cells, r_cut = 4.5 x_s, unit box, G*m = 1, all particles active.
+Inputs are synthetic and seeded (see workloads/).
+
+One step = one full short-range force evaluation through the C ABI: tile
+keys, counting sort, receiver compaction, cluster/work-item planning and the
+persistent pair kernel, with inputs already resident in HBM.  The headline
+value is accepted ordered pair interactions per second of the FP32 path
+(FP32 kernel shape, FP64 separations and accumulation); the FP64 path is
+timed beside it.  Prints ONE JSON line.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--workload clustered128]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_PER_INTERACTION = 40          # forward pair, algorithmic convention
+PEAK_FP32_TFLOPS = 157.3            # MI355X FP32 vector (packed) peak
+PEAK_FP64_TFLOPS = 78.6             # MI355X FP64 vector peak
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="clustered128")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_steps(torch, ctx, pos, mass, wl, prec, steps, warmup):
+    kw = dict(box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut, precision=prec)
+    out = torch.empty((wl.n, 3), dtype=torch.float64, device=pos.device)
+    ctx.set_timing(False)
+    for _ in range(warmup):
+        ctx.force(pos, mass, None, out=out, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.force(pos, mass, None, out=out, **kw)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    # per-kernel durations from HIP events on the launch stream, same calls
+    ctx.set_timing(True)
+    pairs_ms, build_ms = [], []
+    for _ in range(steps):
+        ctx.force(pos, mass, None, out=out, **kw)
+        st = ctx.stats()
+        pairs_ms.append(st["ms_pairs"])
+        build_ms.append(st["ms_build"])
+    ctx.set_timing(False)
+    st = ctx.stats()
+    return out, wall, st, sum(pairs_ms) / len(pairs_ms), sum(build_ms) / len(build_ms)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2112_01508_amd as p3
+    from workloads import make_workload, sample_indices
+
+    log("generating workload", args.workload)
+    wl = make_workload(args.workload, with_rungs=False)
+    dev = torch.device("cuda", 0)
+    pos = torch.from_numpy(wl.pos).to(dev)
+    mass = torch.from_numpy(wl.mass).to(dev)
+    ctx = p3.Context(0)
+
+    results = {}
+    for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
+        if not args.no_autotune:
+            log("autotuning", prec)
+            ctx.autotune(pos, mass, None, box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut,
+                         precision=prec, level=2)
+        log("timing", prec)
+        out, wall, st, pairs_ms, build_ms = time_steps(torch, ctx, pos, mass, wl, prec,
+                                                       args.steps, args.warmup)
+        results[prec] = dict(out=out.cpu().numpy(), wall=wall, stats=st, pairs_ms=pairs_ms,
+                             build_ms=build_ms)
+        log(prec, "ms/step %.3f  pairs %.3f ms  build %.3f ms  interactions %d  ns %d target %d"
+            % (wall * 1e3, pairs_ms, build_ms, st["interactions"], st["subtiles_per_dim"],
+               st["item_target"]))
+
+    r32 = results["fp32"]
+    inter = r32["stats"]["interactions"]
+    value = inter / r32["wall"]
+    achieved = FLOPS_PER_INTERACTION * inter / (r32["pairs_ms"] * 1e-3) / 1e12
+
+    line = {
+        "metric": "short-range pair interactions/s (FP32 vs FP64) at stated force error, "
+                  "% VALU peak",
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["wall"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: N=%d clustered (200 NFW halos hold 30%%), PM grid %d^3, "
+                               "x_s=1.25 cells, r_cut=4.5 x_s, all active, G*m=1"
+                               % (args.workload, wl.n, wl.n_pm),
+                   "n": wl.n, "interactions_per_step": inter,
+                   "tiles_per_dim": r32["stats"]["tiles_per_dim"],
+                   "subtiles_per_dim": r32["stats"]["subtiles_per_dim"],
+                   "item_target": r32["stats"]["item_target"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
+        "pair_kernel_ms": r32["pairs_ms"],
+        "build_ms": r32["build_ms"],
+    }
+    if "fp64" in results:
+        r64 = results["fp64"]
+        a64 = FLOPS_PER_INTERACTION * r64["stats"]["interactions"] / (r64["pairs_ms"] * 1e-3) / 1e12
+        line["fp64"] = {"value": r64["stats"]["interactions"] / r64["wall"],
+                        "ms_per_step": r64["wall"] * 1e3, "pair_kernel_ms": r64["pairs_ms"],
+                        "achieved_tflops": a64, "frac_fp64_peak": a64 / PEAK_FP64_TFLOPS}
+
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        # size the receiver sample for about args.cpu_seconds of oracle work
+        probe = sample_indices(wl.n, 64, wl.config_id, salt=1)
+        t0 = time.perf_counter()
+        oracle.force(wl.pos, wl.mass, wl.box, wl.x_s, wl.r_cut, recv=probe)
+        per = (time.perf_counter() - t0) / probe.size
+        m = int(max(256, min(wl.n, args.cpu_seconds / max(per, 1e-9))))
+        idx = sample_indices(wl.n, m, wl.config_id)
+        log("cpu oracle on %d receivers" % idx.size)
+        t0 = time.perf_counter()
+        ref, cnt, absum, _ = oracle.force(wl.pos, wl.mass, wl.box, wl.x_s, wl.r_cut, recv=idx)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {
+            "value": float(cnt.sum()) / dt, "unit": "interactions/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": "FP64 brute force over all N suppliers for %d seeded receivers "
+                      "(%d interactions, %.1f s)" % (idx.size, int(cnt.sum()), dt)}
+        errs = {}
+        for prec, r in results.items():
+            errs[prec] = oracle.errors(r["out"][idx], ref, absum)
+        line["force_error"] = {p: {"e_l2": e["e_l2"], "e_max_cond": e["e_max_cond"],
+                                   "p999": e["p999"]} for p, e in errs.items()}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * p3msr.h - C ABI of the MI355X short-range P3M pair-force library.
+ *
+ * The library computes the short-range ("particle-particle") half of the
+ * P3M gravity of the CONCEPT 1.0 paper (arXiv:2112.01508), section 2.1.3,
+ * lower half of eq. p3m_gravity with point-particle shape (no softening):
+ *
+ *   a_i = - sum_{j != i, |r_ij| < r_cut} mu_j g(|r_ij| / (2 x_s)) r_ij / |r_ij|^3,
+ *   g(u) = erfc(u) + (2 / sqrt(pi)) u exp(-u^2),
+ *
+ * with mu_j = G m_j and r_ij the separation to the nearest periodic image of
+ * j (the single image n' of eq. p3m_gravity).  The sum is strict
+ * (|r| < r_cut); a pair at zero separation contributes nothing.  Receivers
+ * are the active particles only; every particle is a supplier (section
+ * 2.2.2, individual time steps: particles receive kicks only on their own
+ * rung but supply force on every rung).
+ *
+ * Conventions shared by every entry point:
+ *   - All array pointers are DEVICE pointers owned by the caller.  The
+ *     library never frees them and only reads inputs / writes outputs.
+ *   - pos is n x 3 row-major FP64 (x0 y0 z0 x1 ...); positions outside
+ *     [0, box) are wrapped into the box.  Positions must be finite.
+ *   - mass is n FP64 values holding G*m_j; NULL means all ones.
+ *   - Every call is asynchronous on `stream` (a hipStream_t passed as
+ *     void*, NULL = the null stream) apart from one small device-to-host
+ *     read of work counts inside each force call; pointers must stay valid
+ *     until the stream's work has completed.
+ *   - Outputs are fully overwritten (rows of non-receivers become 0).
+ *   - Errors return a negative code, leave outputs untouched when detected
+ *     before any launch, and set a per-thread message (p3m_sr_last_error).
+ *   - A handle is not thread-safe: use one handle per host thread.
+ *
+ * Geometry requirements (EINVAL otherwise): box > 0, x_s > 0, r_cut > 0,
+ * r_cut < box / 2 (a single nearest image, as eq. p3m_gravity assumes), and
+ * floor(box / r_cut) >= 3 tiles per dimension (section 2.1.3: at least three
+ * tiles across the box so that no tile pair is visited twice).
+ */
+#ifndef P3MSR_H
+#define P3MSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct p3m_sr_context *p3m_sr_handle;
+
+typedef enum {
+    P3M_FP64 = 0, /* all pair arithmetic in FP64 */
+    P3M_FP32 = 1  /* FP64 separation, cut-off test and accumulation; FP32 kernel shape */
+} p3m_precision;
+
+enum {
+    P3M_OK = 0,
+    P3M_EINVAL = -1,      /* invalid argument (no work launched) */
+    P3M_ENOMEM = -2,      /* device workspace could not be grown */
+    P3M_EHIP = -3,        /* a HIP runtime call failed */
+    P3M_EUNSUPPORTED = -4 /* valid request outside what this build supports */
+};
+
+/* Per-call counters of the most recent force / backward / batched call. */
+typedef struct {
+    int64_t n;               /* particles */
+    int64_t receivers;       /* receiver rows summed over subsets */
+    int64_t interactions;    /* accepted ordered pairs (i receiver, j != i, r < r_cut) */
+    int64_t candidates;      /* (receiver lane, supplier) pairs tested after culling */
+    int64_t clusters;        /* receiver groups of <= 64 */
+    int64_t items;           /* work items of the persistent launch */
+    int32_t tiles_per_dim;   /* tiles per dimension (>= 3) */
+    int32_t subtiles_per_dim;/* subtiles per tile per dimension */
+    int32_t item_target;     /* work-item size target (supplier candidates) */
+    int32_t precision;       /* p3m_precision of the call */
+    float ms_build;          /* sort + compaction + planning, when timing is on, else -1 */
+    float ms_pairs;          /* the persistent pair-kernel launch, when timing is on, else -1 */
+    float ms_total;          /* whole call, when timing is on, else -1 */
+    int32_t pad;
+} p3m_sr_stats;
+
+/* Create a context on HIP device `device`.  *h receives the handle. */
+int p3m_sr_create(p3m_sr_handle *h, int device);
+
+/* Destroy a context and free its workspace (synchronises the device). */
+int p3m_sr_destroy(p3m_sr_handle h);
+
+/* Message of the last error on this host thread; never NULL. */
+const char *p3m_sr_last_error(void);
+
+/* Library version string; never NULL. */
+const char *p3m_sr_version(void);
+
+/*
+ * Short-range acceleration (section 2.1.3, lower half of eq. p3m_gravity).
+ *   active  n uint8 (nonzero = receiver) or NULL (all receive).
+ *   acc_out n x 3 FP64; rows of non-receivers are set to 0.
+ * Ownership: caller owns every array.  Errors: EINVAL for bad geometry,
+ * n < 0, NULL pos/acc_out or pointers not 8-byte aligned; ENOMEM when the
+ * workspace cannot grow; EHIP on runtime failure.
+ */
+int p3m_sr_force(p3m_sr_handle h, const double *pos, const double *mass,
+                 const uint8_t *active, int64_t n, double box, double x_s, double r_cut,
+                 int precision, double *acc_out, void *stream);
+
+/*
+ * Vector-Jacobian product of p3m_sr_force with respect to positions, for a
+ * fixed pair set (the pairs with |r| < r_cut at these positions):
+ *   grad_pos_k = sum_i (d acc_i / d x_k)^T grad_acc_i
+ *             = - sum_{j: |r_kj| < r_cut} J(r_kj) (mu_j w_k [k act] - mu_k w_j [j act]),
+ *   J(r) = (g/r^3) I - (3 g / r^5 + exp(-u^2) / (2 sqrt(pi) x_s^3 r^2)) r r^T,
+ * with w = grad_acc.  Rows of grad_acc for non-receivers are ignored.
+ * grad_pos is n x 3 FP64, fully overwritten.  Same errors as p3m_sr_force
+ * plus EINVAL for NULL grad_acc / grad_pos.
+ */
+int p3m_sr_force_backward(p3m_sr_handle h, const double *pos, const double *mass,
+                          const uint8_t *active, int64_t n, double box, double x_s,
+                          double r_cut, int precision, const double *grad_acc,
+                          double *grad_pos, void *stream);
+
+/*
+ * Rung-batched short-range acceleration: n_sub receiver subsets evaluated at
+ * the same positions in ONE persistent launch.  Subset k holds the particles
+ * with rung[i] >= min_rung[k] (the kick at hierarchy depth k of the
+ * rung-based leapfrog of section 2.2.2 touches every rung >= k); every
+ * particle supplies.  Each subset's pairs are evaluated in full.
+ *   rung      n uint8 on the device.
+ *   min_rung  n_sub uint8 thresholds in HOST memory, 1 <= n_sub <= 64.
+ *   acc_out   n_sub x n x 3 FP64 on the device, subset-major.
+ */
+int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
+                         const uint8_t *rung, int64_t n, int n_sub, const uint8_t *min_rung,
+                         double box, double x_s, double r_cut, int precision,
+                         double *acc_out, void *stream);
+
+/*
+ * Measure-and-keep autotuning (the paper's automatic subtile refinement,
+ * section 2.1.3 "Subtiles": try a finer subdivision, time it, keep it if
+ * faster).  Times p3m_sr_force on these inputs for candidate subtile counts
+ * per dimension (and, at level >= 2, work-item sizes) and stores the fastest
+ * in the handle; later calls on the same particle count and geometry use it.
+ * acc_scratch is an n x 3 FP64 device buffer the trials write into.
+ * level: 1 = subtiles only, 2 = subtiles and item size.  Synchronises.
+ */
+int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass,
+                    const uint8_t *active, int64_t n, double box, double x_s, double r_cut,
+                    int precision, int level, double *acc_scratch, void *stream);
+
+/*
+ * Fix the decomposition instead of autotuning: subtiles per tile per
+ * dimension (1..16, 0 = automatic) and work-item target size in supplier
+ * candidates (64..1<<20, 0 = automatic).  EINVAL outside those ranges.
+ */
+int p3m_sr_set_config(p3m_sr_handle h, int subtiles_per_dim, int item_target);
+
+/*
+ * Record HIP events on the call's stream around the build phase and the
+ * pair-kernel launch of every following call (enable != 0), reported in
+ * p3m_sr_stats.  Off by default.
+ */
+int p3m_sr_set_timing(p3m_sr_handle h, int enable);
+
+/* Counters of the most recent call on this handle (synchronises its stream). */
+int p3m_sr_get_stats(p3m_sr_handle h, p3m_sr_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* P3MSR_H */

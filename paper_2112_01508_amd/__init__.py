@@ -1,0 +1,278 @@
+"""MI355X (gfx950) short-range P3M pair force: Python binding of libp3msr.
+
+Thin ctypes layer over the C ABI declared in include/p3msr.h.  PyTorch only
+supplies device memory and the current HIP stream; every step of the force
+path runs in the library's HIP kernels.  There is no CPU fallback: if the
+library is not built, or no GPU is present, calls raise.
+
+    import paper_2112_01508_amd as p3
+    acc = p3.sr_force(pos, mass, active, box=1.0, x_s=x_s, r_cut=r_cut, precision="fp32")
+
+`sr_force` is differentiable with respect to `pos` (torch.autograd): its
+backward calls the library's hand-written adjoint kernel.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libp3msr.so")
+
+P3M_FP64 = 0
+P3M_FP32 = 1
+P3M_OK = 0
+P3M_EINVAL = -1
+P3M_ENOMEM = -2
+P3M_EHIP = -3
+P3M_EUNSUPPORTED = -4
+_CODES = {P3M_EINVAL: "EINVAL", P3M_ENOMEM: "ENOMEM", P3M_EHIP: "EHIP",
+          P3M_EUNSUPPORTED: "EUNSUPPORTED"}
+
+
+class P3MError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("p3msr %s (%d): %s" % (_CODES.get(code, "?"), code, message))
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("receivers", ctypes.c_int64),
+                ("interactions", ctypes.c_int64), ("candidates", ctypes.c_int64),
+                ("clusters", ctypes.c_int64), ("items", ctypes.c_int64),
+                ("tiles_per_dim", ctypes.c_int32), ("subtiles_per_dim", ctypes.c_int32),
+                ("item_target", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("ms_build", ctypes.c_float), ("ms_pairs", ctypes.c_float),
+                ("ms_total", ctypes.c_float), ("pad", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_lib_lock = threading.Lock()
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+
+EXPORTS = {
+    "p3m_sr_create": ([ctypes.POINTER(_P), _I], _I),
+    "p3m_sr_destroy": ([_P], _I),
+    "p3m_sr_last_error": ([], ctypes.c_char_p),
+    "p3m_sr_version": ([], ctypes.c_char_p),
+    "p3m_sr_force": ([_P, _P, _P, _P, _I64, _D, _D, _D, _I, _P, _P], _I),
+    "p3m_sr_force_backward": ([_P, _P, _P, _P, _I64, _D, _D, _D, _I, _P, _P, _P], _I),
+    "p3m_sr_force_batched": ([_P, _P, _P, _P, _I64, _I, _P, _D, _D, _D, _I, _P, _P], _I),
+    "p3m_sr_autotune": ([_P, _P, _P, _P, _I64, _D, _D, _D, _I, _I, _P, _P], _I),
+    "p3m_sr_set_config": ([_P, _I, _I], _I),
+    "p3m_sr_set_timing": ([_P, _I], _I),
+    "p3m_sr_get_stats": ([_P, ctypes.POINTER(Stats)], _I),
+}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libp3msr.so (raises if it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise ImportError("libp3msr.so is not built (%s); run __graft_entry__.build() or "
+                              "python paper_2112_01508_amd/build.py" % path)
+        lib = ctypes.CDLL(path)
+        for name, (args, res) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+        return lib
+
+
+def _check(rc: int):
+    if rc != P3M_OK:
+        raise P3MError(rc, load_library().p3m_sr_last_error().decode())
+
+
+def _prec(precision) -> int:
+    if precision in ("fp32", "float32", P3M_FP32):
+        return P3M_FP32
+    if precision in ("fp64", "float64", P3M_FP64):
+        return P3M_FP64
+    raise ValueError("precision must be 'fp32' or 'fp64'")
+
+
+def _dev_ptr(t, dtype, shape_tail, name, device):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device != device:
+        raise ValueError("%s must be a tensor on %s" % (name, device))
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s (got %s)" % (name, dtype, t.dtype))
+    if tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError("%s has shape %s" % (name, tuple(t.shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def _stream_ptr(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """One library handle bound to a GPU (not thread-safe)."""
+
+    def __init__(self, device=None):
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available: the p3msr path has no CPU fallback")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        h = _P()
+        _check(lib.p3m_sr_create(ctypes.byref(h), self.device.index))
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.p3m_sr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- marshalling helpers -------------------------------------------------
+    def _inputs(self, pos, mass, sel, sel_name):
+        pos = _dev_ptr(pos, torch.float64, (3,), "pos", self.device)
+        if pos.dim() != 2:
+            raise ValueError("pos must be (n, 3)")
+        n = pos.shape[0]
+        mass = _dev_ptr(mass, torch.float64, (), "mass", self.device)
+        if mass is not None and mass.shape[0] != n:
+            raise ValueError("mass must have n entries")
+        sel = _dev_ptr(sel, torch.uint8, (), sel_name, self.device)
+        if sel is not None and sel.shape[0] != n:
+            raise ValueError("%s must have n entries" % sel_name)
+        return pos, mass, sel, n
+
+    @staticmethod
+    def _p(t):
+        return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+    # -- entry points ------------------------------------------------------------
+    def force(self, pos, mass=None, active=None, *, box, x_s, r_cut, precision="fp32", out=None):
+        pos, mass, active, n = self._inputs(pos, mass, active, "active")
+        if out is None:
+            out = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        else:
+            _dev_ptr(out, torch.float64, (3,), "out", self.device)
+        _check(self._lib.p3m_sr_force(self._h, self._p(pos), self._p(mass), self._p(active), n,
+                                      float(box), float(x_s), float(r_cut), _prec(precision),
+                                      self._p(out), _stream_ptr(self.device)))
+        return out
+
+    def force_backward(self, pos, mass, active, grad_acc, *, box, x_s, r_cut, precision="fp32"):
+        pos, mass, active, n = self._inputs(pos, mass, active, "active")
+        grad_acc = _dev_ptr(grad_acc.contiguous(), torch.float64, (3,), "grad_acc", self.device)
+        out = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        _check(self._lib.p3m_sr_force_backward(self._h, self._p(pos), self._p(mass),
+                                               self._p(active), n, float(box), float(x_s),
+                                               float(r_cut), _prec(precision), self._p(grad_acc),
+                                               self._p(out), _stream_ptr(self.device)))
+        return out
+
+    def force_batched(self, pos, mass, rung, min_rung, *, box, x_s, r_cut, precision="fp32",
+                      out=None):
+        pos, mass, rung, n = self._inputs(pos, mass, rung, "rung")
+        thr = bytes(int(v) for v in min_rung)
+        n_sub = len(thr)
+        if out is None:
+            out = torch.empty((n_sub, n, 3), dtype=torch.float64, device=self.device)
+        buf = ctypes.create_string_buffer(thr, max(n_sub, 1))
+        _check(self._lib.p3m_sr_force_batched(self._h, self._p(pos), self._p(mass),
+                                              self._p(rung), n, n_sub,
+                                              ctypes.cast(buf, ctypes.c_void_p), float(box),
+                                              float(x_s), float(r_cut), _prec(precision),
+                                              self._p(out), _stream_ptr(self.device)))
+        return out
+
+    def autotune(self, pos, mass=None, active=None, *, box, x_s, r_cut, precision="fp32",
+                 level=1):
+        pos, mass, active, n = self._inputs(pos, mass, active, "active")
+        scratch = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        _check(self._lib.p3m_sr_autotune(self._h, self._p(pos), self._p(mass), self._p(active),
+                                         n, float(box), float(x_s), float(r_cut),
+                                         _prec(precision), int(level), self._p(scratch),
+                                         _stream_ptr(self.device)))
+
+    def set_config(self, subtiles_per_dim=0, item_target=0):
+        _check(self._lib.p3m_sr_set_config(self._h, int(subtiles_per_dim), int(item_target)))
+
+    def set_timing(self, enable=True):
+        _check(self._lib.p3m_sr_set_timing(self._h, 1 if enable else 0))
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(self._lib.p3m_sr_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+
+_contexts: dict = {}
+
+
+def default_context(device=None) -> Context:
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+    ctx = _contexts.get(dev)
+    if ctx is None:
+        ctx = Context(dev)
+        _contexts[dev] = ctx
+    return ctx
+
+
+class _SRForce(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, pos, mass, active, box, x_s, r_cut, precision, ctx):
+        acc = ctx.force(pos.detach(), mass, active, box=box, x_s=x_s, r_cut=r_cut,
+                        precision=precision)
+        fctx.save_for_backward(pos.detach())
+        fctx.extra = (mass, active, box, x_s, r_cut, precision, ctx)
+        return acc
+
+    @staticmethod
+    def backward(fctx, grad_acc):
+        (pos,) = fctx.saved_tensors
+        mass, active, box, x_s, r_cut, precision, ctx = fctx.extra
+        grad_pos = ctx.force_backward(pos, mass, active, grad_acc, box=box, x_s=x_s, r_cut=r_cut,
+                                      precision=precision)
+        return grad_pos, None, None, None, None, None, None, None
+
+
+def sr_force(pos, mass=None, active=None, *, box=1.0, x_s, r_cut, precision="fp32",
+             context: Context | None = None):
+    """Short-range P3M acceleration (n, 3) FP64 of the active particles.
+
+    Differentiable with respect to `pos` for a fixed pair set; `mass` and
+    `active` are not differentiated."""
+    ctx = context or default_context(pos.device)
+    if pos.requires_grad and torch.is_grad_enabled():
+        return _SRForce.apply(pos, mass, active, box, x_s, r_cut, precision, ctx)
+    return ctx.force(pos, mass, active, box=box, x_s=x_s, r_cut=r_cut, precision=precision)
+
+
+def sr_force_batched(pos, mass, rung, min_rung, *, box=1.0, x_s, r_cut, precision="fp32",
+                     context: Context | None = None):
+    """Accelerations (n_sub, n, 3) of the nested rung subsets rung >= min_rung[k]."""
+    ctx = context or default_context(pos.device)
+    return ctx.force_batched(pos, mass, rung, min_rung, box=box, x_s=x_s, r_cut=r_cut,
+                             precision=precision)
+
+
+__all__ = ["Context", "P3MError", "Stats", "default_context", "load_library", "sr_force",
+           "sr_force_batched", "LIB_PATH", "P3M_FP32", "P3M_FP64", "EXPORTS"]

@@ -1,0 +1,604 @@
+// C ABI of libp3msr: argument checks, workspace, the launch pipeline, the
+// measure-and-keep autotuner and per-call counters.
+//
+// Pipeline of one force call (all on the caller's stream):
+//   keys      tile/subtile key per particle + rank inside its cell (atomics)
+//   scan      exclusive scan of the cell histogram -> cell_start
+//   scatter   particles into tile -> subtile order (section 2.1.3, memory
+//             reorder of "Other optimisations")
+//   flags     receiver flags per subset, scan, compaction
+//   clusters  <= 64 receivers of one tile per cluster
+//   items     clusters split over their 27 neighbour tiles (work estimate)
+//   [read back the cluster and item totals: the only host synchronisation]
+//   pairs     one persistent launch over all items, atomic FP64 accumulation
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/p3msr.h"
+#include "p3msr_internal.hpp"
+
+using namespace p3m;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int set_error(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define P3M_HIP(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return set_error(P3M_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct TuneKey {
+    int64_t n;
+    int nt;
+    int precision;
+    int mode;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(n, nt, precision, mode) < std::tie(o.n, o.nt, o.precision, o.mode);
+    }
+};
+struct TuneVal {
+    int ns;
+    int target;
+};
+
+}  // namespace
+
+struct p3m_sr_context {
+    int device = 0;
+    int n_cu = 0;
+    int blocks_per_cu[4] = {0, 0, 0, 0};
+    DevBuf key, rank, cells, sp, perm, sel, flags, actpos, ncl, clusters, itemcnt, items, bsum,
+        counters, wa, scal;
+    int cfg_ns = 0, cfg_target = 0;
+    std::map<TuneKey, TuneVal> tuned;
+    p3m_sr_stats stats{};
+    hipStream_t last_stream = nullptr;
+    bool timing = false;
+    bool timed_last = false;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // call start, pairs start, pairs end
+};
+
+namespace {
+
+int ensure(p3m_sr_context *h, DevBuf &b, size_t bytes, hipStream_t s) {
+    if (bytes == 0) bytes = 16;
+    if (b.cap >= bytes) return P3M_OK;
+    // work queued on the caller's stream may still use the old buffer
+    P3M_HIP(hipStreamSynchronize(s));
+    if (h->last_stream && h->last_stream != s) P3M_HIP(hipStreamSynchronize(h->last_stream));
+    if (b.p) {
+        P3M_HIP(hipFree(b.p));
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        if (hipMalloc(&b.p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            b.p = nullptr;
+            return set_error(P3M_ENOMEM, "device workspace of %zu bytes could not be allocated",
+                             bytes);
+        }
+        want = bytes;
+    }
+    b.cap = want;
+    return P3M_OK;
+}
+
+bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+int check_geometry(int64_t n, double box, double x_s, double r_cut) {
+    if (n < 0) return set_error(P3M_EINVAL, "n must be >= 0 (got %lld)", (long long)n);
+    if (n > (int64_t)0x7fffffff - 64)
+        return set_error(P3M_EUNSUPPORTED, "n = %lld exceeds the 2^31 particle limit",
+                         (long long)n);
+    if (!(box > 0) || !std::isfinite(box)) return set_error(P3M_EINVAL, "box must be > 0");
+    if (!(x_s > 0) || !std::isfinite(x_s)) return set_error(P3M_EINVAL, "x_s must be > 0");
+    if (!(r_cut > 0) || !std::isfinite(r_cut))
+        return set_error(P3M_EINVAL, "r_cut must be > 0");
+    if (!(r_cut < 0.5 * box))
+        return set_error(P3M_EINVAL, "r_cut must be < box/2 for a single nearest image");
+    if (std::floor(box / r_cut) < 3.0)
+        return set_error(P3M_EINVAL, "need at least 3 tiles of side >= r_cut per dimension");
+    return P3M_OK;
+}
+
+// Tiles per dimension: as many as possible with side >= r_cut (kept a hair
+// above r_cut so that rounding in the cell assignment cannot put a partner
+// two tiles away), capped so that the cell index fits in 32 bits.
+int tiles_per_dim(double box, double r_cut) {
+    double q = std::floor(box / (r_cut * (1.0 + 1e-12)));
+    int nt = (int)std::min(q, 1024.0);
+    while (nt > 3 && box / nt < r_cut * (1.0 + 1e-12)) --nt;
+    return nt < 3 ? 3 : nt;
+}
+
+int pick_subtiles(int nt, int64_t n, int requested) {
+    int ns = requested;
+    if (ns <= 0) {
+        // default before tuning: finer subtiles when tiles hold more particles
+        double per_tile = (double)n / ((double)nt * nt * nt);
+        ns = per_tile > 64 ? 4 : (per_tile > 8 ? 3 : 2);
+    }
+    while (ns > 1 && (double)nt * ns * nt * ns * nt * ns > 2.0e9) --ns;
+    return ns;
+}
+
+Geom make_geom(double box, double x_s, double r_cut, int nt, int ns) {
+    Geom g{};
+    g.box = box;
+    g.inv_box = 1.0 / box;
+    g.rc2 = r_cut * r_cut;
+    g.nt = nt;
+    g.ns = ns;
+    g.nc = nt * ns;
+    g.ns3 = ns * ns * ns;
+    g.nt3 = nt * nt * nt;
+    g.tile = box / nt;
+    g.sub = g.tile / ns;
+    g.inv_cell = (double)g.nc / box;
+    double margin = r_cut * 1e-9 + box * 1e-12;
+    g.cull2 = (r_cut + margin) * (r_cut + margin);
+    g.x_s = x_s;
+    g.k1 = 1.0 / (2.0 * x_s);
+    g.k2 = -1.4426950408889634074 / (4.0 * x_s * x_s);
+    g.kb = 1.0 / (2.0 * 1.77245385090551602730 * x_s * x_s * x_s);
+    g.k1f = (float)g.k1;
+    g.kbf = (float)g.kb;
+    return g;
+}
+
+struct Request {
+    const double *pos;
+    const double *mass;
+    const uint8_t *sel;      // active mask or rung
+    int sel_kind;            // SelKind for receivers
+    int n_sub;
+    const uint8_t *thr;      // host thresholds (rung mode)
+    int64_t n;
+    double box, x_s, r_cut;
+    int precision;
+    bool backward;
+    const double *grad_acc;
+    double *out;
+    hipStream_t stream;
+    int force_ns;            // >0: override subtiles (autotune trials)
+    int force_target;
+};
+
+int run(p3m_sr_context *h, const Request &r) {
+    hipStream_t s = r.stream;
+    const int n = (int)r.n;
+    const bool fp32 = r.precision == P3M_FP32;
+    const int n_sub = r.n_sub;
+    const int nt = tiles_per_dim(r.box, r.r_cut);
+
+    // decomposition: explicit override > user config > autotuned > default
+    int ns = 0, target = 0;
+    const int mode = (r.backward ? 2 : 0) + (fp32 ? 0 : 1);
+    auto it = h->tuned.find(TuneKey{r.n, nt, r.precision, r.backward ? 1 : 0});
+    if (it != h->tuned.end()) {
+        ns = it->second.ns;
+        target = it->second.target;
+    }
+    if (h->cfg_ns > 0) ns = h->cfg_ns;
+    if (h->cfg_target > 0) target = h->cfg_target;
+    if (r.force_ns > 0) ns = r.force_ns;
+    if (r.force_target > 0) target = r.force_target;
+    ns = pick_subtiles(nt, r.n, ns);
+    if (target <= 0) target = 1024;
+    const Geom g = make_geom(r.box, r.x_s, r.r_cut, nt, ns);
+    const size_t ncells = (size_t)g.nt3 * g.ns3;
+
+    p3m_sr_stats st{};
+    st.n = r.n;
+    st.tiles_per_dim = nt;
+    st.subtiles_per_dim = ns;
+    st.item_target = target;
+    st.precision = r.precision;
+    st.ms_build = st.ms_pairs = st.ms_total = -1.0f;
+    h->last_stream = s;
+    h->timed_last = false;
+    if (h->timing) {
+        for (int k = 0; k < 3; ++k)
+            if (!h->ev[k]) P3M_HIP(hipEventCreate(&h->ev[k]));
+        P3M_HIP(hipEventRecord(h->ev[0], s));
+    }
+
+    const size_t out_elems = (size_t)n_sub * (size_t)n * 3;
+    if (n == 0) {
+        h->stats = st;
+        return P3M_OK;
+    }
+
+    // ---- workspace ----
+    const size_t nflags = (size_t)n * n_sub;
+    const size_t ncl_len = (size_t)n_sub * g.nt3;
+    const size_t cl_bound = ncl_len + (nflags + kWave - 1) / kWave;
+    const size_t scan_max = std::max(std::max(ncells, nflags), std::max(ncl_len, cl_bound));
+    int rc;
+    if ((rc = ensure(h, h->key, sizeof(int) * n, s))) return rc;
+    if ((rc = ensure(h, h->rank, sizeof(int) * n, s))) return rc;
+    if ((rc = ensure(h, h->cells, sizeof(int) * (ncells + 1), s))) return rc;
+    if ((rc = ensure(h, h->sp, sizeof(double4) * ((size_t)n + 8), s))) return rc;
+    if ((rc = ensure(h, h->perm, sizeof(int) * n, s))) return rc;
+    if ((rc = ensure(h, h->sel, (size_t)n, s))) return rc;
+    if ((rc = ensure(h, h->flags, sizeof(int) * (nflags + 1), s))) return rc;
+    if ((rc = ensure(h, h->actpos, sizeof(int) * (nflags + 1), s))) return rc;
+    if ((rc = ensure(h, h->ncl, sizeof(int) * (ncl_len + 1), s))) return rc;
+    if ((rc = ensure(h, h->clusters, sizeof(Cluster) * cl_bound, s))) return rc;
+    if ((rc = ensure(h, h->itemcnt, sizeof(int) * (cl_bound + 1), s))) return rc;
+    if ((rc = ensure(h, h->bsum, sizeof(int) * scan_block_sums_needed(scan_max), s))) return rc;
+    if ((rc = ensure(h, h->counters, sizeof(Counters), s))) return rc;
+    if ((rc = ensure(h, h->scal, sizeof(int) * 16, s))) return rc;
+    if (r.backward && (rc = ensure(h, h->wa, sizeof(double4) * ((size_t)n + 8), s))) return rc;
+
+    int *key = (int *)h->key.p, *rank = (int *)h->rank.p, *cells = (int *)h->cells.p;
+    double4 *sp = (double4 *)h->sp.p;
+    int *perm = (int *)h->perm.p;
+    uint8_t *sel_s = (uint8_t *)h->sel.p;
+    int *flags = (int *)h->flags.p, *actpos = (int *)h->actpos.p, *ncl = (int *)h->ncl.p;
+    Cluster *clusters = (Cluster *)h->clusters.p;
+    int *itemcnt = (int *)h->itemcnt.p, *bsum = (int *)h->bsum.p;
+    Counters *counters = (Counters *)h->counters.p;
+    int *scal = (int *)h->scal.p;   // [0] cells total, [1] flags total, [2] clusters, [3] items
+
+    // ---- sort ----
+    P3M_HIP(launch_fill_i32(cells, 0, ncells + 1, s));
+    P3M_HIP(launch_fill_i32((int *)counters, 0, sizeof(Counters) / sizeof(int), s));
+    P3M_HIP(launch_keys(r.pos, n, g, key, rank, cells, s));
+    P3M_HIP(launch_scan(cells, cells, ncells, bsum, s));
+    const uint8_t *sel_src = (r.sel_kind == SEL_ALL && !r.backward) ? nullptr : r.sel;
+    P3M_HIP(launch_scatter(r.pos, r.mass, sel_src, n, g, key, rank, cells, fp32 ? 1 : 0, sp, perm,
+                           sel_s, s));
+    P3M_HIP(launch_fill_i32((int *)(sp + n), 0, 8 * sizeof(double4) / sizeof(int), s));
+
+    // ---- receivers -> clusters -> items ----
+    // the adjoint needs every particle as a receiver (its output rows are
+    // the particles near any active one); activity enters through wa
+    const int kind = r.backward ? SEL_ALL : r.sel_kind;
+    P3M_HIP(launch_flags(sel_s, n, n_sub, kind, r.thr, flags, s));
+    P3M_HIP(launch_scan(flags, flags, nflags, bsum, s));
+    P3M_HIP(launch_compact(flags, n, n_sub, actpos, s));
+    P3M_HIP(launch_cluster_count(cells, flags, n, n_sub, g, ncl, s));
+    P3M_HIP(launch_scan(ncl, ncl, ncl_len, bsum, s));
+    P3M_HIP(launch_cluster_write(cells, flags, ncl, n, n_sub, g, clusters, s));
+    P3M_HIP(launch_item_count(clusters, ncl + ncl_len, (int)cl_bound, cells, g, target, itemcnt,
+                              s));
+    P3M_HIP(launch_scan(itemcnt, itemcnt, cl_bound, bsum, s));
+    P3M_HIP(hipMemcpyAsync(scal + 0, flags + nflags, sizeof(int), hipMemcpyDeviceToDevice, s));
+    P3M_HIP(hipMemcpyAsync(scal + 1, ncl + ncl_len, sizeof(int), hipMemcpyDeviceToDevice, s));
+    P3M_HIP(hipMemcpyAsync(scal + 2, itemcnt + cl_bound, sizeof(int), hipMemcpyDeviceToDevice, s));
+    int host_scal[3] = {0, 0, 0};
+    P3M_HIP(hipMemcpyAsync(host_scal, scal, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    P3M_HIP(hipStreamSynchronize(s));
+    const int n_recv = host_scal[0], n_clusters = host_scal[1], n_items = host_scal[2];
+    st.receivers = n_recv;
+    st.clusters = n_clusters;
+    st.items = n_items;
+
+    if ((rc = ensure(h, h->items, sizeof(Item) * (size_t)(n_items > 0 ? n_items : 1), s)))
+        return rc;
+    Item *items = (Item *)h->items.p;
+    P3M_HIP(launch_item_write(clusters, n_clusters, cells, g, target, itemcnt, items, s));
+
+    // ---- pairs ----
+    if (r.backward) P3M_HIP(launch_gather_weights(r.grad_acc, sel_s, perm, n, fp32, (double4 *)h->wa.p, s));
+    P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, s));
+    PairArgs a{};
+    a.sp = sp;
+    a.perm = perm;
+    a.act_pos = actpos;
+    a.cell_start = cells;
+    a.clusters = clusters;
+    a.items = items;
+    a.wa = (const double4 *)h->wa.p;
+    a.out = r.out;
+    a.counters = counters;
+    a.out_stride = 3ll * n;
+    a.n_items = n_items;
+    a.g = g;
+    if (h->blocks_per_cu[mode] == 0) h->blocks_per_cu[mode] = pairs_blocks_per_cu(mode);
+    long long waves_wanted = (n_items + 0ll);
+    long long grid = std::min<long long>((waves_wanted + 3) / 4,
+                                         (long long)h->n_cu * h->blocks_per_cu[mode]);
+    if (grid < 1) grid = 1;
+    if (h->timing) P3M_HIP(hipEventRecord(h->ev[1], s));
+    P3M_HIP(launch_pairs(mode, a, (int)grid, s));
+    if (h->timing) {
+        P3M_HIP(hipEventRecord(h->ev[2], s));
+        h->timed_last = true;
+    }
+    h->stats = st;
+    return P3M_OK;
+}
+
+int check_handle(p3m_sr_handle h) {
+    if (!h) return set_error(P3M_EINVAL, "NULL handle");
+    return P3M_OK;
+}
+
+int set_device(p3m_sr_handle h) {
+    int cur = -1;
+    P3M_HIP(hipGetDevice(&cur));
+    if (cur != h->device) P3M_HIP(hipSetDevice(h->device));
+    return P3M_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *p3m_sr_last_error(void) { return g_last_error.c_str(); }
+
+const char *p3m_sr_version(void) { return "p3msr 0.1 (gfx950)"; }
+
+int p3m_sr_create(p3m_sr_handle *out, int device) {
+    if (!out) return set_error(P3M_EINVAL, "NULL output pointer");
+    *out = nullptr;
+    int ndev = 0;
+    P3M_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev)
+        return set_error(P3M_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    P3M_HIP(hipSetDevice(device));
+    p3m_sr_context *h = new p3m_sr_context();
+    h->device = device;
+    if (hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, device) !=
+            hipSuccess ||
+        h->n_cu <= 0)
+        h->n_cu = 256;
+    *out = h;
+    return P3M_OK;
+}
+
+int p3m_sr_destroy(p3m_sr_handle h) {
+    if (!h) return P3M_OK;
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    DevBuf *bufs[] = {&h->key,      &h->rank,    &h->cells,   &h->sp,    &h->perm,
+                      &h->sel,      &h->flags,   &h->actpos,  &h->ncl,   &h->clusters,
+                      &h->itemcnt,  &h->items,   &h->bsum,    &h->counters, &h->wa,
+                      &h->scal};
+    for (DevBuf *b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    for (hipEvent_t e : h->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete h;
+    return P3M_OK;
+}
+
+int p3m_sr_force(p3m_sr_handle h, const double *pos, const double *mass, const uint8_t *active,
+                 int64_t n, double box, double x_s, double r_cut, int precision, double *acc_out,
+                 void *stream) {
+    int rc;
+    if ((rc = check_geometry(n, box, x_s, r_cut))) return rc;
+    if (precision != P3M_FP32 && precision != P3M_FP64)
+        return set_error(P3M_EINVAL, "precision must be P3M_FP64 or P3M_FP32");
+    if (n > 0 && (!pos || !acc_out)) return set_error(P3M_EINVAL, "pos and acc_out are required");
+    if (!aligned8(pos) || !aligned8(acc_out) || !aligned8(mass))
+        return set_error(P3M_EINVAL, "pos, mass and acc_out must be 8-byte aligned");
+    if ((rc = check_handle(h))) return rc;
+    if ((rc = set_device(h))) return rc;
+    Request r{};
+    r.pos = pos;
+    r.mass = mass;
+    r.sel = active;
+    r.sel_kind = active ? SEL_MASK : SEL_ALL;
+    r.n_sub = 1;
+    r.n = n;
+    r.box = box;
+    r.x_s = x_s;
+    r.r_cut = r_cut;
+    r.precision = precision;
+    r.out = acc_out;
+    r.stream = (hipStream_t)stream;
+    return run(h, r);
+}
+
+int p3m_sr_force_backward(p3m_sr_handle h, const double *pos, const double *mass,
+                          const uint8_t *active, int64_t n, double box, double x_s, double r_cut,
+                          int precision, const double *grad_acc, double *grad_pos,
+                          void *stream) {
+    int rc;
+    if ((rc = check_geometry(n, box, x_s, r_cut))) return rc;
+    if (precision != P3M_FP32 && precision != P3M_FP64)
+        return set_error(P3M_EINVAL, "precision must be P3M_FP64 or P3M_FP32");
+    if (n > 0 && (!pos || !grad_acc || !grad_pos))
+        return set_error(P3M_EINVAL, "pos, grad_acc and grad_pos are required");
+    if (!aligned8(pos) || !aligned8(mass) || !aligned8(grad_acc) || !aligned8(grad_pos))
+        return set_error(P3M_EINVAL, "pos, mass, grad_acc and grad_pos must be 8-byte aligned");
+    if ((rc = check_handle(h))) return rc;
+    if ((rc = set_device(h))) return rc;
+    Request r{};
+    r.pos = pos;
+    r.mass = mass;
+    r.sel = active;
+    r.sel_kind = active ? SEL_MASK : SEL_ALL;
+    r.n_sub = 1;
+    r.n = n;
+    r.box = box;
+    r.x_s = x_s;
+    r.r_cut = r_cut;
+    r.precision = precision;
+    r.backward = true;
+    r.grad_acc = grad_acc;
+    r.out = grad_pos;
+    r.stream = (hipStream_t)stream;
+    return run(h, r);
+}
+
+int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
+                         const uint8_t *rung, int64_t n, int n_sub, const uint8_t *min_rung,
+                         double box, double x_s, double r_cut, int precision, double *acc_out,
+                         void *stream) {
+    int rc;
+    if ((rc = check_geometry(n, box, x_s, r_cut))) return rc;
+    if (precision != P3M_FP32 && precision != P3M_FP64)
+        return set_error(P3M_EINVAL, "precision must be P3M_FP64 or P3M_FP32");
+    if (n_sub < 1 || n_sub > 64) return set_error(P3M_EINVAL, "n_sub must be in 1..64");
+    if (!min_rung) return set_error(P3M_EINVAL, "min_rung (host array) is required");
+    if (n > 0 && (!pos || !rung || !acc_out))
+        return set_error(P3M_EINVAL, "pos, rung and acc_out are required");
+    if ((double)n * n_sub > 2.0e9)
+        return set_error(P3M_EUNSUPPORTED, "n * n_sub exceeds the 2^31 receiver-row limit");
+    if (!aligned8(pos) || !aligned8(mass) || !aligned8(acc_out))
+        return set_error(P3M_EINVAL, "pos, mass and acc_out must be 8-byte aligned");
+    if ((rc = check_handle(h))) return rc;
+    if ((rc = set_device(h))) return rc;
+    Request r{};
+    r.pos = pos;
+    r.mass = mass;
+    r.sel = rung;
+    r.sel_kind = SEL_RUNG;
+    r.n_sub = n_sub;
+    r.thr = min_rung;
+    r.n = n;
+    r.box = box;
+    r.x_s = x_s;
+    r.r_cut = r_cut;
+    r.precision = precision;
+    r.out = acc_out;
+    r.stream = (hipStream_t)stream;
+    return run(h, r);
+}
+
+int p3m_sr_set_config(p3m_sr_handle h, int subtiles_per_dim, int item_target) {
+    int rc;
+    if ((rc = check_handle(h))) return rc;
+    if (subtiles_per_dim < 0 || subtiles_per_dim > 16)
+        return set_error(P3M_EINVAL, "subtiles_per_dim must be in 0..16");
+    if (item_target != 0 && (item_target < 64 || item_target > (1 << 20)))
+        return set_error(P3M_EINVAL, "item_target must be 0 or in 64..2^20");
+    h->cfg_ns = subtiles_per_dim;
+    h->cfg_target = item_target;
+    return P3M_OK;
+}
+
+int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, const uint8_t *active,
+                    int64_t n, double box, double x_s, double r_cut, int precision, int level,
+                    double *acc_scratch, void *stream) {
+    int rc;
+    if ((rc = check_geometry(n, box, x_s, r_cut))) return rc;
+    if (precision != P3M_FP32 && precision != P3M_FP64)
+        return set_error(P3M_EINVAL, "precision must be P3M_FP64 or P3M_FP32");
+    if (level < 1 || level > 2) return set_error(P3M_EINVAL, "level must be 1 or 2");
+    if (n > 0 && (!pos || !acc_scratch))
+        return set_error(P3M_EINVAL, "pos and acc_scratch are required");
+    if ((rc = check_handle(h))) return rc;
+    if ((rc = set_device(h))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Request r{};
+    r.pos = pos;
+    r.mass = mass;
+    r.sel = active;
+    r.sel_kind = active ? SEL_MASK : SEL_ALL;
+    r.n_sub = 1;
+    r.n = n;
+    r.box = box;
+    r.x_s = x_s;
+    r.r_cut = r_cut;
+    r.precision = precision;
+    r.out = acc_scratch;
+    r.stream = s;
+    const int nt = tiles_per_dim(box, r_cut);
+    std::vector<int> ns_list = {1, 2, 3, 4, 5, 6};
+    std::vector<int> tg_list = {1024};
+    if (level >= 2) tg_list = {256, 512, 1024, 2048, 4096};
+    hipEvent_t e0, e1;
+    P3M_HIP(hipEventCreate(&e0));
+    P3M_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    TuneVal best_v{pick_subtiles(nt, n, 0), 1024};
+    for (int ns : ns_list) {
+        if (pick_subtiles(nt, n, ns) != ns) continue;
+        for (int tg : tg_list) {
+            r.force_ns = ns;
+            r.force_target = tg;
+            if ((rc = run(h, r))) return rc;   // warm-up (also grows the workspace)
+            float tot = 0;
+            const int reps = 3;
+            for (int k = 0; k < reps; ++k) {
+                P3M_HIP(hipEventRecord(e0, s));
+                if ((rc = run(h, r))) return rc;
+                P3M_HIP(hipEventRecord(e1, s));
+                P3M_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                P3M_HIP(hipEventElapsedTime(&ms, e0, e1));
+                tot += ms;
+            }
+            if (tot < best) {
+                best = tot;
+                best_v = TuneVal{ns, tg};
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->tuned[TuneKey{n, nt, precision, 0}] = best_v;
+    h->tuned[TuneKey{n, nt, precision, 1}] = best_v;
+    return P3M_OK;
+}
+
+int p3m_sr_set_timing(p3m_sr_handle h, int enable) {
+    int rc;
+    if ((rc = check_handle(h))) return rc;
+    h->timing = enable != 0;
+    return P3M_OK;
+}
+
+int p3m_sr_get_stats(p3m_sr_handle h, p3m_sr_stats *out) {
+    int rc;
+    if ((rc = check_handle(h))) return rc;
+    if (!out) return set_error(P3M_EINVAL, "NULL stats pointer");
+    if ((rc = set_device(h))) return rc;
+    p3m_sr_stats st = h->stats;
+    if (h->counters.p && st.n > 0) {
+        Counters c{};
+        P3M_HIP(hipStreamSynchronize(h->last_stream));
+        P3M_HIP(hipMemcpy(&c, h->counters.p, sizeof(c), hipMemcpyDeviceToHost));
+        st.interactions = (int64_t)c.interactions;
+        st.candidates = (int64_t)c.candidates;
+    }
+    if (h->timed_last) {
+        float a = 0, b = 0;
+        P3M_HIP(hipEventSynchronize(h->ev[2]));
+        P3M_HIP(hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
+        P3M_HIP(hipEventElapsedTime(&b, h->ev[1], h->ev[2]));
+        st.ms_build = a;
+        st.ms_pairs = b;
+        st.ms_total = a + b;
+    }
+    *out = st;
+    return P3M_OK;
+}
+
+}  // extern "C"

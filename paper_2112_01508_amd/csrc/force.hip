@@ -1,0 +1,338 @@
+// Short-range pair kernels: forward force and its adjoint, FP32 and FP64.
+//
+// Force (section 2.1.3, lower half of eq. p3m_gravity, no softening):
+//   a_i = - sum_{j != i, r < r_cut} mu_j g(u) r_ij / r^3,  u = r / (2 x_s),
+//   g(u) = erfc(u) + (2/sqrt(pi)) u exp(-u^2),
+// with r_ij taken to the nearest periodic image n'.  The image is fixed per
+// neighbour tile (section 2.1.3, "Other optimisations": n' follows from the
+// tile pair), and the zero-shift case runs in its own loop.
+//
+// Traversal (one wavefront per work item, persistent grid): the lanes hold
+// the <= 64 receivers of one cluster in registers; for each neighbour tile
+// of the item the lanes test one subtile each against the cluster's
+// bounding box (the subtile-pair culling of section 2.1.3, "Subtiles", done
+// against the receivers' actual extent), a ballot gives the surviving
+// subtiles, and consecutive survivors merge into supplier ranges.  Supplier
+// particles are read at wave-uniform addresses, i.e. through the scalar
+// unit into SGPRs, and every lane evaluates its receiver against them.
+//
+// Precision: the separation r_ij, the squared distance and the cut-off
+// test are FP64 and bitwise the same as a plain FP64 evaluation, so both
+// paths accept exactly the same pairs.  The FP32 path then evaluates the
+// kernel shape in FP32 (hardware rsqrt and exp2 plus a degree-9 polynomial
+// for erfcx(u) + 2u/sqrt(pi)) and accumulates in FP64.
+#include "p3msr_internal.hpp"
+#include "gpoly.inc"
+
+namespace p3m {
+
+namespace {
+
+constexpr double kTwoOverSqrtPi = 1.12837916709551257390;
+
+// Pointer into the constant address space: loads through it at uniform
+// addresses become scalar (s_load) loads.  The arrays read this way are not
+// written by the kernels that read them.
+template <class T>
+using ConstPtr = const __attribute__((address_space(4))) T *;
+
+__device__ inline double4 load_uniform(const double4 *base, int j) {
+    ConstPtr<double> q = (ConstPtr<double>)base + 4 * (long long)j;
+    return make_double4(q[0], q[1], q[2], q[3]);
+}
+__device__ inline float4 load_uniform(const float4 *base, int j) {
+    ConstPtr<float> q = (ConstPtr<float>)base + 4 * (long long)j;
+    return make_float4(q[0], q[1], q[2], q[3]);
+}
+
+__device__ inline unsigned long long ballot64(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ inline double wave_min(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+__device__ inline double wave_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ inline float q_poly(float v) {
+    float q = kGpoly[P3M_GPOLY_DEGREE];
+#pragma unroll
+    for (int k = P3M_GPOLY_DEGREE - 1; k >= 0; --k) q = fmaf(q, v, kGpoly[k]);
+    return q;
+}
+
+__device__ inline float mu_f32(double w) {
+    return __uint_as_float((unsigned int)(unsigned long long)__double_as_longlong(w));
+}
+
+// Squared distance in the order of a plain evaluation: ((dx*dx + dy*dy) + dz*dz),
+// every product and sum rounded (no fused multiply-add).
+__device__ inline double dist2(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+    double xx = dx * dx;
+    double yy = dy * dy;
+    double zz = dz * dz;
+    return (xx + yy) + zz;
+}
+
+// ---- per-pair bodies ---------------------------------------------------------
+
+struct FwdF32 {
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
+                                         const double4 &pj, int, const PairArgs &a) {
+        const Geom &g = a.g;
+        float r2f = (float)r2;
+        float ri = __builtin_amdgcn_rsqf(r2f);
+        float v = fmaf(r2f * ri, g.k1f, -P3M_GPOLY_C0);
+        float e = __builtin_amdgcn_exp2f((float)(r2 * g.k2));
+        float s = mu_f32(pj.w) * (e * q_poly(v)) * (ri * ri * ri);
+        double sd = (double)s;
+        ax = fma(-sd, dx, ax);
+        ay = fma(-sd, dy, ay);
+        az = fma(-sd, dz, az);
+    }
+};
+
+struct FwdF64 {
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
+                                         const double4 &pj, int, const PairArgs &a) {
+        double r = sqrt(r2);
+        double u = r * a.g.k1;
+        double gu = erfc(u) + kTwoOverSqrtPi * u * exp(-u * u);
+        double s = pj.w * gu / (r2 * r);
+        ax -= s * dx;
+        ay -= s * dy;
+        az -= s * dz;
+    }
+};
+
+// Adjoint: grad_k -= J(r_kj) (mu_j wa_k - mu_k wa_j), wa = w * [active],
+// J = phi I - c r r^T, phi = g / r^3, c = 3 g / r^5 + exp(-u^2) / (2 sqrt(pi) x_s^3 r^2).
+struct BwdF64 {
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    double wkx, wky, wkz, muk;
+    __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
+                                         const double4 &pj, int j, const PairArgs &a) {
+        const double4 wj = load_uniform(a.wa, j);
+        double vx = pj.w * wkx - muk * wj.x;
+        double vy = pj.w * wky - muk * wj.y;
+        double vz = pj.w * wkz - muk * wj.z;
+        double r = sqrt(r2);
+        double u = r * a.g.k1;
+        double e = exp(-u * u);
+        double gu = erfc(u) + kTwoOverSqrtPi * u * e;
+        double phi = gu / (r2 * r);
+        double c = 3.0 * gu / (r2 * r2 * r) + e * a.g.kb / r2;
+        double rv = dx * vx + dy * vy + dz * vz;
+        ax -= phi * vx - c * rv * dx;
+        ay -= phi * vy - c * rv * dy;
+        az -= phi * vz - c * rv * dz;
+    }
+};
+
+struct BwdF32 {
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    float wkx, wky, wkz, muk;
+    __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
+                                         const double4 &pj, int j, const PairArgs &a) {
+        const Geom &g = a.g;
+        const float4 wj = load_uniform(reinterpret_cast<const float4 *>(a.wa), j);
+        const float muj = mu_f32(pj.w);
+        float vx = muj * wkx - muk * wj.x;
+        float vy = muj * wky - muk * wj.y;
+        float vz = muj * wkz - muk * wj.z;
+        float r2f = (float)r2;
+        float ri = __builtin_amdgcn_rsqf(r2f);
+        float ri2 = ri * ri;
+        float v = fmaf(r2f * ri, g.k1f, -P3M_GPOLY_C0);
+        float e = __builtin_amdgcn_exp2f((float)(r2 * g.k2));
+        float gu = e * q_poly(v);
+        float phi = gu * ri2 * ri;
+        float c = ri2 * fmaf(3.0f, phi, g.kbf * e);
+        float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+        float rv = fx * vx + fy * vy + fz * vz;
+        float crv = c * rv;
+        ax -= (double)fmaf(phi, vx, -crv * fx);
+        ay -= (double)fmaf(phi, vy, -crv * fy);
+        az -= (double)fmaf(phi, vz, -crv * fz);
+    }
+};
+
+// ---- supplier range loop ------------------------------------------------------
+
+template <bool SHIFT, class Body>
+__device__ __forceinline__ void range_loop(Body &body, double xi, double yi, double zi, int j0,
+                                           int j1, double shx, double shy, double shz,
+                                           const PairArgs &a, int &n_acc) {
+    // Supplier records are read at wave-uniform addresses from the constant
+    // address space, so they arrive through scalar loads into SGPRs.
+    const double rc2 = a.g.rc2;
+    j0 = __builtin_amdgcn_readfirstlane(j0);
+    j1 = __builtin_amdgcn_readfirstlane(j1);
+    for (int j = j0; j < j1; ++j) {
+        const double4 pj = load_uniform(a.sp, j);
+        double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
+        if (SHIFT) {
+            dx -= shx;
+            dy -= shy;
+            dz -= shz;
+        }
+        const double r2 = dist2(dx, dy, dz);
+        if ((r2 < rc2) & (r2 > 0.0)) {
+            ++n_acc;   // per-lane count of accepted pairs
+            body.pair(dx, dy, dz, r2, pj, j, a);
+        }
+    }
+}
+
+// One work item: the cluster's receivers against the suppliers of its
+// neighbour-tile / subtile range, with subtile culling by bounding box.
+template <class Body>
+__device__ __forceinline__ void walk_item(Body &body, const Item &item, const Cluster &cl,
+                                          double xi, double yi, double zi, const double lo[3],
+                                          const double hi[3], const PairArgs &a, int lane,
+                                          int &n_acc, unsigned long long &n_cand) {
+    const Geom &g = a.g;
+    const int *__restrict__ cs = a.cell_start;
+    const int tx = cl.tile / (g.nt * g.nt), ty = (cl.tile / g.nt) % g.nt, tz = cl.tile % g.nt;
+    const int t0 = item.tiles & 0xff, t1 = (item.tiles >> 8) & 0xff;
+    const int s0 = item.subs & 0xffff, s1 = (item.subs >> 16) & 0xffff;
+    const int nss = g.ns * g.ns;
+    for (int t = t0; t < t1; ++t) {
+        int nx = tx + t / 9 - 1, ny = ty + (t / 3) % 3 - 1, nz = tz + t % 3 - 1;
+        int ix = 0, iy = 0, iz = 0;   // image of the supplier tile, in box lengths
+        if (nx < 0) { nx += g.nt; ix = -1; } else if (nx >= g.nt) { nx -= g.nt; ix = 1; }
+        if (ny < 0) { ny += g.nt; iy = -1; } else if (ny >= g.nt) { ny -= g.nt; iy = 1; }
+        if (nz < 0) { nz += g.nt; iz = -1; } else if (nz >= g.nt) { nz -= g.nt; iz = 1; }
+        const double shx = ix * g.box, shy = iy * g.box, shz = iz * g.box;
+        const bool shifted = (ix | iy | iz) != 0;
+        // origin of the supplier tile's image
+        const double ox = nx * g.tile + shx, oy = ny * g.tile + shy, oz = nz * g.tile + shz;
+        const int cbase = ((nx * g.nt + ny) * g.nt + nz) * g.ns3;
+        for (int base = s0; base < s1; base += kWave) {
+            const int s = base + lane;
+            const int nvalid = min(kWave, s1 - base);
+            bool keep = false;
+            int cstart = 0;
+            if (s < s1) {
+                const int sa = s / nss, sb = (s / g.ns) % g.ns, sc = s % g.ns;
+                const double bx0 = ox + sa * g.sub, by0 = oy + sb * g.sub, bz0 = oz + sc * g.sub;
+                const double gx = fmax(0.0, fmax(bx0 - hi[0], lo[0] - (bx0 + g.sub)));
+                const double gy = fmax(0.0, fmax(by0 - hi[1], lo[1] - (by0 + g.sub)));
+                const double gz = fmax(0.0, fmax(bz0 - hi[2], lo[2] - (bz0 + g.sub)));
+                keep = gx * gx + gy * gy + gz * gz < g.cull2;
+                cstart = cs[cbase + s];
+            }
+            unsigned long long m = ballot64(keep);
+            while (m) {
+                const int ra = __builtin_ctzll(m);
+                const unsigned long long rest = ~(m >> ra);
+                const int rb = rest ? ra + __builtin_ctzll(rest) : kWave;   // run [ra, rb)
+                const int j0 = __builtin_amdgcn_readlane(cstart, ra);
+                const int j1 = rb < nvalid ? __builtin_amdgcn_readlane(cstart, rb)
+                                           : cs[cbase + base + rb];
+                m = rb >= kWave ? 0ull : (m & (~0ull << rb));
+                if (j1 > j0) {
+                    n_cand += (unsigned long long)(j1 - j0) * (unsigned long long)cl.count;
+                    if (shifted)
+                        range_loop<true>(body, xi, yi, zi, j0, j1, shx, shy, shz, a, n_acc);
+                    else
+                        range_loop<false>(body, xi, yi, zi, j0, j1, 0.0, 0.0, 0.0, a, n_acc);
+                }
+            }
+        }
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = (int)((blockIdx.x * (unsigned)kForceBlock + threadIdx.x) / kWave);
+    const int nwaves = (int)(gridDim.x * (kForceBlock / kWave));
+    for (int it = wave; it < a.n_items; it += nwaves) {
+        const Item item = a.items[it];
+        const Cluster cl = a.clusters[item.cluster];
+        const bool live = lane < cl.count;
+        const int p = a.act_pos[cl.begin + (live ? lane : 0)];
+        const double4 xp = a.sp[p];
+        const double lo[3] = {wave_min(xp.x), wave_min(xp.y), wave_min(xp.z)};
+        const double hi[3] = {wave_max(xp.x), wave_max(xp.y), wave_max(xp.z)};
+        // lanes without a receiver sit far outside the box: no pair passes r < r_cut
+        const double far = live ? 0.0 : 1.0e300;
+        const double xi = xp.x + far, yi = xp.y + far, zi = xp.z + far;
+        int n_acc = 0;
+        unsigned long long n_cand = 0;
+        double ax, ay, az;
+        if constexpr (MODE == FWD_F32) {
+            FwdF32 b;
+            walk_item(b, item, cl, xi, yi, zi, lo, hi, a, lane, n_acc, n_cand);
+            ax = b.ax; ay = b.ay; az = b.az;
+        } else if constexpr (MODE == FWD_F64) {
+            FwdF64 b;
+            walk_item(b, item, cl, xi, yi, zi, lo, hi, a, lane, n_acc, n_cand);
+            ax = b.ax; ay = b.ay; az = b.az;
+        } else if constexpr (MODE == BWD_F64) {
+            BwdF64 b;
+            const double4 w = a.wa[p];
+            b.wkx = w.x; b.wky = w.y; b.wkz = w.z; b.muk = xp.w;
+            walk_item(b, item, cl, xi, yi, zi, lo, hi, a, lane, n_acc, n_cand);
+            ax = b.ax; ay = b.ay; az = b.az;
+        } else {
+            BwdF32 b;
+            const float4 w = reinterpret_cast<const float4 *>(a.wa)[p];
+            b.wkx = w.x; b.wky = w.y; b.wkz = w.z; b.muk = mu_f32(xp.w);
+            walk_item(b, item, cl, xi, yi, zi, lo, hi, a, lane, n_acc, n_cand);
+            ax = b.ax; ay = b.ay; az = b.az;
+        }
+        if (live) {
+            double *o = a.out + (long long)cl.subset * a.out_stride + 3ll * a.perm[p];
+            atomicAdd(o, ax);
+            atomicAdd(o + 1, ay);
+            atomicAdd(o + 2, az);
+        }
+        int tot = n_acc;
+        for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, kWave);
+        if (lane == 0 && a.counters) {
+            atomicAdd(&a.counters->interactions, (unsigned long long)tot);
+            atomicAdd(&a.counters->candidates, n_cand);
+        }
+    }
+}
+
+template <int MODE>
+int blocks_per_cu_of() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs<MODE>, kForceBlock, 0) !=
+        hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+}  // namespace
+
+hipError_t launch_pairs(int mode, const PairArgs &a, int grid, hipStream_t s) {
+    if (a.n_items <= 0) return hipSuccess;
+    dim3 gr((unsigned)grid), bl(kForceBlock);
+    switch (mode) {
+    case FWD_F32: hipLaunchKernelGGL(k_pairs<FWD_F32>, gr, bl, 0, s, a); break;
+    case FWD_F64: hipLaunchKernelGGL(k_pairs<FWD_F64>, gr, bl, 0, s, a); break;
+    case BWD_F32: hipLaunchKernelGGL(k_pairs<BWD_F32>, gr, bl, 0, s, a); break;
+    default: hipLaunchKernelGGL(k_pairs<BWD_F64>, gr, bl, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+int pairs_blocks_per_cu(int mode) {
+    switch (mode) {
+    case FWD_F32: return blocks_per_cu_of<FWD_F32>();
+    case FWD_F64: return blocks_per_cu_of<FWD_F64>();
+    case BWD_F32: return blocks_per_cu_of<BWD_F32>();
+    default: return blocks_per_cu_of<BWD_F64>();
+    }
+}
+
+}  // namespace p3m

@@ -1,0 +1,122 @@
+// Internal definitions shared by the HIP translation units of libp3msr.
+//
+// Data layout in HBM (all built per call from the caller's arrays):
+//   sp[p]        double4 (x, y, z, w) of the p-th particle in tile -> subtile
+//                order, positions wrapped into [0, box); w = mu (FP64 path) or
+//                the bits of float mu in the low word (FP32 path)
+//   perm[p]      original index of sorted particle p
+//   sel[p]       receiver selector of sorted particle p (active flag or rung)
+//   cell_start[c] first sorted index of fine cell c (c = tile*ns^3 + subtile),
+//                cell_start[ncells] = n
+//   act_pos[]    sorted indices of the receivers, subset-major, tile order
+//   clusters[]   receiver groups of <= 64 particles inside one tile
+//   items[]      (cluster, neighbour-tile range, subtile range) work units
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace p3m {
+
+constexpr int kWave = 64;
+constexpr int kScanBlock = 256;             // threads per scan block
+constexpr int kScanPerThread = 16;          // elements per scan thread
+constexpr int kScanTile = kScanBlock * kScanPerThread;
+constexpr int kForceBlock = 256;            // 4 waves, each with its own work item
+
+// Geometry of one call.  Tiles are cubes of side box/nt >= r_cut; each tile
+// holds ns^3 subtiles; fine cells are the subtiles, nc = nt*ns per dimension.
+struct Geom {
+    double box, inv_box;
+    double rc2;        // r_cut^2: the pair test is r^2 < rc2 (strict)
+    double tile;       // tile side
+    double sub;        // subtile side
+    double inv_cell;   // nc / box
+    double cull2;      // (r_cut + margin)^2 for conservative subtile culling
+    double k1;         // 1 / (2 x_s)
+    double k2;         // -log2(e) / (4 x_s^2): exp(-u^2) = 2^(r^2 k2)
+    double kb;         // 1 / (2 sqrt(pi) x_s^3), Gaussian term of the pair Jacobian
+    double x_s;
+    int nt, ns, nc, ns3, nt3;
+    float k1f, kbf;    // FP32 copies of k1 and kb
+};
+
+struct Cluster {
+    int tile;     // tile index (tx*nt + ty)*nt + tz
+    int subset;   // receiver subset (batched calls)
+    int begin;    // first entry in act_pos
+    int count;    // 1..64 receivers
+};
+
+// Work item: receivers of one cluster against suppliers in neighbour tiles
+// [t0, t1) of the 27-tile stencil (t = (ox+1)*9 + (oy+1)*3 + (oz+1)) and,
+// when t1 == t0 + 1, only subtiles [s0, s1) of that tile.
+struct Item {
+    int cluster;
+    int tiles;    // t0 | t1 << 8
+    int subs;     // s0 | s1 << 16
+    int pad;
+};
+
+struct Counters {
+    unsigned long long interactions;
+    unsigned long long candidates;
+    unsigned long long pad[6];
+};
+
+enum SelKind { SEL_ALL = 0, SEL_MASK = 1, SEL_RUNG = 2 };
+
+// ---- launchers (host functions defined in the .hip files) -----------------
+
+// sort.hip
+hipError_t launch_fill_i32(int *p, int v, size_t n, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
+hipError_t launch_keys(const double *pos, int n, const Geom &g, int *key, int *rank,
+                       int *cell_count, hipStream_t s);
+size_t scan_block_sums_needed(size_t n);
+// exclusive scan of n int32 values; out has n+1 entries (out[n] = total).
+// in may equal out.
+hipError_t launch_scan(const int *in, int *out, size_t n, int *block_sums, hipStream_t s);
+hipError_t launch_scatter(const double *pos, const double *mass, const uint8_t *sel, int n,
+                          const Geom &g, const int *key, const int *rank,
+                          const int *cell_start, int fp32, double4 *sp, int *perm,
+                          uint8_t *sel_s, hipStream_t s);
+hipError_t launch_flags(const uint8_t *sel_s, int n, int n_sub, int kind,
+                        const uint8_t *thr_host, int *flags, hipStream_t s);
+hipError_t launch_compact(const int *scan, int n, int n_sub, int *act_pos, hipStream_t s);
+hipError_t launch_cluster_count(const int *cell_start, const int *scan, int n, int n_sub,
+                                const Geom &g, int *ncl, hipStream_t s);
+hipError_t launch_cluster_write(const int *cell_start, const int *scan, const int *cl_off,
+                                int n, int n_sub, const Geom &g, Cluster *clusters,
+                                hipStream_t s);
+hipError_t launch_item_count(const Cluster *clusters, const int *n_clusters_dev,
+                             int cluster_bound, const int *cell_start, const Geom &g,
+                             int target, int *item_cnt, hipStream_t s);
+hipError_t launch_item_write(const Cluster *clusters, int n_clusters, const int *cell_start,
+                             const Geom &g, int target, const int *item_off, Item *items,
+                             hipStream_t s);
+hipError_t launch_gather_weights(const double *grad_acc, const uint8_t *sel_s, const int *perm,
+                                 int n, int fp32, double4 *wa, hipStream_t s);
+
+// force.hip
+enum PairMode { FWD_F32 = 0, FWD_F64 = 1, BWD_F32 = 2, BWD_F64 = 3 };
+struct PairArgs {
+    const double4 *sp;
+    const int *perm;
+    const int *act_pos;
+    const int *cell_start;
+    const Cluster *clusters;
+    const Item *items;
+    const double4 *wa;       // backward: w * [active], sorted (FP32 path: float4 bits)
+    double *out;             // acc_out / grad_pos, n x 3 per subset
+    Counters *counters;
+    long long out_stride;    // elements between subsets (3 n)
+    int n_items;
+    Geom g;
+};
+hipError_t launch_pairs(int mode, const PairArgs &a, int grid, hipStream_t s);
+int pairs_blocks_per_cu(int mode);
+
+}  // namespace p3m

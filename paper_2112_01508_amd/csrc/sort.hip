@@ -1,0 +1,434 @@
+// Tile/subtile counting sort, receiver compaction and work-item planning.
+//
+// Section 2.1.3 ("Tiles", "Subtiles", "Other optimisations"): particles are
+// sorted in O(N) into tiles of side >= r_cut, each split into ns^3
+// subtiles, and stored in tile -> subtile -> particle order.  On the GPU the
+// sort is a counting sort over the fine cells (histogram with atomics ->
+// exclusive scan -> scatter).  Receivers (the particles on active rungs,
+// section 2.2.2) are compacted per tile and grouped into clusters of at most
+// one wavefront; each cluster is then split into work items over its 27
+// neighbour tiles so that one persistent launch can balance the very uneven
+// work of clustered particle sets.
+#include "p3msr_internal.hpp"
+
+namespace p3m {
+
+namespace {
+
+__global__ void k_fill_i32(int *p, int v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_fill_f64(double *p, double v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+// Position wrapped into [0, box).
+__device__ inline double wrap_coord(double x, const Geom &g) {
+    double w = x - g.box * floor(x * g.inv_box);
+    if (!(w < g.box)) w = 0.0;   // rounding up to box, or NaN
+    if (w < 0.0) w = 0.0;
+    return w;
+}
+
+__device__ inline int cell_of(double w, const Geom &g) {
+    int c = (int)(w * g.inv_cell);
+    return c < 0 ? 0 : (c >= g.nc ? g.nc - 1 : c);
+}
+
+__device__ inline int key_of(int cx, int cy, int cz, const Geom &g) {
+    int tx = cx / g.ns, ty = cy / g.ns, tz = cz / g.ns;
+    int sx = cx - tx * g.ns, sy = cy - ty * g.ns, sz = cz - tz * g.ns;
+    int tile = (tx * g.nt + ty) * g.nt + tz;
+    return tile * g.ns3 + (sx * g.ns + sy) * g.ns + sz;
+}
+
+__global__ void k_keys(const double *__restrict__ pos, int n, Geom g, int *__restrict__ key,
+                       int *__restrict__ rank, int *__restrict__ cell_count) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double wx = wrap_coord(pos[3 * (size_t)i], g);
+    double wy = wrap_coord(pos[3 * (size_t)i + 1], g);
+    double wz = wrap_coord(pos[3 * (size_t)i + 2], g);
+    int k = key_of(cell_of(wx, g), cell_of(wy, g), cell_of(wz, g), g);
+    key[i] = k;
+    rank[i] = atomicAdd(&cell_count[k], 1);
+}
+
+// ---- exclusive scan (reduce / top / down-sweep) -----------------------------
+
+__device__ inline int block_exclusive_scan(int v, int *lds, int *total) {
+    // wave-level inclusive scan with shuffles, then across the block's waves
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    int x = v;
+    for (int off = 1; off < kWave; off <<= 1) {
+        int y = __shfl_up(x, off, kWave);
+        if (lane >= off) x += y;
+    }
+    if (lane == kWave - 1) lds[wave] = x;
+    __syncthreads();
+    const int nw = blockDim.x / kWave;
+    int base = 0, all = 0;
+    for (int w = 0; w < nw; ++w) {
+        int s = lds[w];
+        if (w < wave) base += s;
+        all += s;
+    }
+    __syncthreads();
+    *total = all;
+    return base + x - v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const int *__restrict__ in, size_t n,
+                                                            int *__restrict__ bsum) {
+    __shared__ int lds[kScanBlock / kWave];
+    size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanPerThread;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        size_t i = base + k;
+        if (i < n) s += in[i];
+    }
+    int total;
+    block_exclusive_scan(s, lds, &total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(int *__restrict__ bsum, int nb,
+                                                   int *__restrict__ out_total) {
+    __shared__ int lds[1024 / kWave];
+    int carry = 0;
+    for (int base = 0; base < nb; base += 1024) {
+        int i = base + threadIdx.x;
+        int v = i < nb ? bsum[i] : 0;
+        int total;
+        int ex = block_exclusive_scan(v, lds, &total);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        bsum[nb] = carry;
+        *out_total = carry;
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_down(const int *in, int *out, size_t n,
+                                                          const int *__restrict__ bsum) {
+    __shared__ int lds[kScanBlock / kWave];
+    size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanPerThread;
+    int v[kScanPerThread];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        size_t i = base + k;
+        v[k] = i < n ? in[i] : 0;
+        s += v[k];
+    }
+    int total;
+    int run = block_exclusive_scan(s, lds, &total) + bsum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        size_t i = base + k;
+        if (i < n) out[i] = run;
+        run += v[k];
+    }
+}
+
+// ---- scatter into tile -> subtile order --------------------------------------
+
+__global__ void k_scatter(const double *__restrict__ pos, const double *__restrict__ mass,
+                          const uint8_t *__restrict__ sel, int n, Geom g,
+                          const int *__restrict__ key, const int *__restrict__ rank,
+                          const int *__restrict__ cell_start, int fp32,
+                          double4 *__restrict__ sp, int *__restrict__ perm,
+                          uint8_t *__restrict__ sel_s) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int dst = cell_start[key[i]] + rank[i];
+    double4 v;
+    v.x = wrap_coord(pos[3 * (size_t)i], g);
+    v.y = wrap_coord(pos[3 * (size_t)i + 1], g);
+    v.z = wrap_coord(pos[3 * (size_t)i + 2], g);
+    double mu = mass ? mass[i] : 1.0;
+    if (fp32) {
+        float mf = (float)mu;
+        v.w = __longlong_as_double((long long)(unsigned int)__float_as_uint(mf));
+    } else {
+        v.w = mu;
+    }
+    sp[dst] = v;
+    perm[dst] = i;
+    sel_s[dst] = sel ? sel[i] : (uint8_t)1;
+}
+
+// ---- receiver selection and compaction ---------------------------------------
+
+struct Thresholds { uint8_t t[64]; };
+
+__global__ void k_flags(const uint8_t *__restrict__ sel_s, int n, int n_sub, int kind,
+                        Thresholds thr, int *__restrict__ flags) {
+    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t total = (size_t)n * n_sub;
+    if (idx >= total) return;
+    int k = (int)(idx / n);
+    int p = (int)(idx - (size_t)k * n);
+    int f;
+    if (kind == SEL_ALL) f = 1;
+    else if (kind == SEL_MASK) f = sel_s[p] != 0;
+    else f = sel_s[p] >= thr.t[k];
+    flags[idx] = f;
+}
+
+__global__ void k_compact(const int *__restrict__ scan, int n, int n_sub, int *__restrict__ act_pos) {
+    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t total = (size_t)n * n_sub;
+    if (idx >= total) return;
+    int a = scan[idx];
+    if (scan[idx + 1] > a) {
+        int k = (int)(idx / n);
+        act_pos[a] = (int)(idx - (size_t)k * n);
+    }
+}
+
+__global__ void k_cluster_count(const int *__restrict__ cs, const int *__restrict__ scan, int n,
+                                int n_sub, Geom g, int *__restrict__ ncl) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_sub * g.nt3) return;
+    int k = idx / g.nt3;
+    int t = idx - k * g.nt3;
+    size_t off = (size_t)k * n;
+    int a0 = scan[off + cs[(size_t)t * g.ns3]];
+    int a1 = scan[off + cs[(size_t)(t + 1) * g.ns3]];
+    ncl[idx] = (a1 - a0 + kWave - 1) / kWave;
+}
+
+__global__ void k_cluster_write(const int *__restrict__ cs, const int *__restrict__ scan, int n,
+                                int n_sub, Geom g, const int *__restrict__ cl_off,
+                                Cluster *__restrict__ clusters) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_sub * g.nt3) return;
+    int k = idx / g.nt3;
+    int t = idx - k * g.nt3;
+    size_t off = (size_t)k * n;
+    int a0 = scan[off + cs[(size_t)t * g.ns3]];
+    int a1 = scan[off + cs[(size_t)(t + 1) * g.ns3]];
+    int o = cl_off[idx];
+    for (int b = a0; b < a1; b += kWave) {
+        Cluster c;
+        c.tile = t;
+        c.subset = k;
+        c.begin = b;
+        c.count = min(kWave, a1 - b);
+        clusters[o++] = c;
+    }
+}
+
+// ---- work items ------------------------------------------------------------
+
+__device__ inline int neighbour_tile(int tile, int t, const Geom &g) {
+    int tx = tile / (g.nt * g.nt), ty = (tile / g.nt) % g.nt, tz = tile % g.nt;
+    int nx = tx + t / 9 - 1, ny = ty + (t / 3) % 3 - 1, nz = tz + t % 3 - 1;
+    nx += nx < 0 ? g.nt : (nx >= g.nt ? -g.nt : 0);
+    ny += ny < 0 ? g.nt : (ny >= g.nt ? -g.nt : 0);
+    nz += nz < 0 ? g.nt : (nz >= g.nt ? -g.nt : 0);
+    return (nx * g.nt + ny) * g.nt + nz;
+}
+
+// Greedy grouping of the 27 neighbour tiles into items of about `target`
+// supplier candidates (before subtile culling); a tile holding more than
+// `target` particles is split by subtile ranges.  Returns the item count and
+// writes the items when `out` is non-null.
+__device__ int plan_items(int cidx, const Cluster &cl, const int *__restrict__ cs, const Geom &g,
+                          int target, Item *out) {
+    int n = 0, acc = 0, t0 = 0;
+    auto emit = [&](int a, int b, int s0, int s1) {
+        if (out) {
+            Item it;
+            it.cluster = cidx;
+            it.tiles = a | (b << 8);
+            it.subs = s0 | (s1 << 16);
+            it.pad = 0;
+            out[n] = it;
+        }
+        ++n;
+    };
+    for (int t = 0; t < 27; ++t) {
+        int nb = neighbour_tile(cl.tile, t, g);
+        int w = cs[(size_t)(nb + 1) * g.ns3] - cs[(size_t)nb * g.ns3];
+        if (w > target) {
+            if (acc > 0) emit(t0, t, 0, g.ns3);
+            int parts = min((w + target - 1) / target, g.ns3);
+            for (int q = 0; q < parts; ++q)
+                emit(t, t + 1, q * g.ns3 / parts, (q + 1) * g.ns3 / parts);
+            t0 = t + 1;
+            acc = 0;
+        } else if (acc + w > target) {
+            emit(t0, t, 0, g.ns3);
+            t0 = t;
+            acc = w;
+        } else {
+            if (acc == 0 && w == 0) t0 = t + 1;   // skip leading empty tiles
+            acc += w;
+        }
+    }
+    if (acc > 0) emit(t0, 27, 0, g.ns3);
+    return n;
+}
+
+__global__ void k_item_count(const Cluster *__restrict__ clusters, const int *__restrict__ n_cl,
+                             int bound, const int *__restrict__ cs, Geom g, int target,
+                             int *__restrict__ item_cnt) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= bound) return;
+    item_cnt[c] = c < *n_cl ? plan_items(c, clusters[c], cs, g, target, nullptr) : 0;
+}
+
+__global__ void k_item_write(const Cluster *__restrict__ clusters, int n_clusters,
+                             const int *__restrict__ cs, Geom g, int target,
+                             const int *__restrict__ item_off, Item *__restrict__ items) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_clusters) return;
+    plan_items(c, clusters[c], cs, g, target, items + item_off[c]);
+}
+
+__global__ void k_gather_weights(const double *__restrict__ w, const uint8_t *__restrict__ sel_s,
+                                 const int *__restrict__ perm, int n, int fp32,
+                                 double4 *__restrict__ wa) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    size_t i = (size_t)perm[p];
+    double x = 0, y = 0, z = 0;
+    if (sel_s[p]) {
+        x = w[3 * i];
+        y = w[3 * i + 1];
+        z = w[3 * i + 2];
+    }
+    if (fp32) {
+        reinterpret_cast<float4 *>(wa)[p] = make_float4((float)x, (float)y, (float)z, 0.0f);
+    } else {
+        wa[p] = make_double4(x, y, z, 0.0);
+    }
+}
+
+inline unsigned grid_for(size_t n, int block) {
+    size_t g = (n + block - 1) / block;
+    return (unsigned)(g > 0 ? g : 1);
+}
+
+}  // namespace
+
+hipError_t launch_fill_i32(int *p, int v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)g), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)g), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_keys(const double *pos, int n, const Geom &g, int *key, int *rank,
+                       int *cell_count, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, pos, n, g, key, rank,
+                       cell_count);
+    return hipGetLastError();
+}
+
+size_t scan_block_sums_needed(size_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+hipError_t launch_scan(const int *in, int *out, size_t n, int *bsum, hipStream_t s) {
+    size_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, out, 0, (size_t)1);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, (int)nb, out + n);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out, n, bsum);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const double *pos, const double *mass, const uint8_t *sel, int n,
+                          const Geom &g, const int *key, const int *rank, const int *cell_start,
+                          int fp32, double4 *sp, int *perm, uint8_t *sel_s, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, pos, mass, sel, n, g,
+                       key, rank, cell_start, fp32, sp, perm, sel_s);
+    return hipGetLastError();
+}
+
+hipError_t launch_flags(const uint8_t *sel_s, int n, int n_sub, int kind, const uint8_t *thr_host,
+                        int *flags, hipStream_t s) {
+    size_t total = (size_t)n * n_sub;
+    if (total == 0) return hipSuccess;
+    Thresholds thr{};
+    if (thr_host)
+        for (int k = 0; k < n_sub && k < 64; ++k) thr.t[k] = thr_host[k];
+    hipLaunchKernelGGL(k_flags, dim3(grid_for(total, 256)), dim3(256), 0, s, sel_s, n, n_sub, kind,
+                       thr, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const int *scan, int n, int n_sub, int *act_pos, hipStream_t s) {
+    size_t total = (size_t)n * n_sub;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact, dim3(grid_for(total, 256)), dim3(256), 0, s, scan, n, n_sub,
+                       act_pos);
+    return hipGetLastError();
+}
+
+hipError_t launch_cluster_count(const int *cs, const int *scan, int n, int n_sub, const Geom &g,
+                                int *ncl, hipStream_t s) {
+    size_t total = (size_t)n_sub * g.nt3;
+    hipLaunchKernelGGL(k_cluster_count, dim3(grid_for(total, 256)), dim3(256), 0, s, cs, scan, n,
+                       n_sub, g, ncl);
+    return hipGetLastError();
+}
+
+hipError_t launch_cluster_write(const int *cs, const int *scan, const int *cl_off, int n,
+                                int n_sub, const Geom &g, Cluster *clusters, hipStream_t s) {
+    size_t total = (size_t)n_sub * g.nt3;
+    hipLaunchKernelGGL(k_cluster_write, dim3(grid_for(total, 256)), dim3(256), 0, s, cs, scan, n,
+                       n_sub, g, cl_off, clusters);
+    return hipGetLastError();
+}
+
+hipError_t launch_item_count(const Cluster *clusters, const int *n_clusters_dev, int bound,
+                             const int *cs, const Geom &g, int target, int *item_cnt,
+                             hipStream_t s) {
+    if (bound == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_item_count, dim3(grid_for(bound, 128)), dim3(128), 0, s, clusters,
+                       n_clusters_dev, bound, cs, g, target, item_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_item_write(const Cluster *clusters, int n_clusters, const int *cs,
+                             const Geom &g, int target, const int *item_off, Item *items,
+                             hipStream_t s) {
+    if (n_clusters == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_item_write, dim3(grid_for(n_clusters, 128)), dim3(128), 0, s, clusters,
+                       n_clusters, cs, g, target, item_off, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_weights(const double *grad_acc, const uint8_t *sel_s, const int *perm,
+                                 int n, int fp32, double4 *wa, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_weights, dim3(grid_for(n, 256)), dim3(256), 0, s, grad_acc, sel_s,
+                       perm, n, fp32, wa);
+    return hipGetLastError();
+}
+
+}  // namespace p3m

@@ -1,0 +1,80 @@
+"""GPU adjoint (vector-Jacobian product of the short-range force with
+respect to positions) vs the oracle's analytic VJP and central finite
+differences, through the C ABI and through torch.autograd."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import gpu_or_skip, to_dev
+from workloads import make_workload, random_particles, sample_indices
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch, p3 = gpu_or_skip()
+    return torch, p3, p3.Context(0)
+
+
+def gpu_vjp(env, pos, mass, active, w, box, x_s, r_cut, prec):
+    torch, p3, ctx = env
+    g = ctx.force_backward(to_dev(torch, pos), to_dev(torch, mass), to_dev(torch, active),
+                           to_dev(torch, w), box=box, x_s=x_s, r_cut=r_cut, precision=prec)
+    torch.cuda.synchronize()
+    return g.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec, tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("frac", [None, 0.3])
+def test_vjp_matches_oracle(env, prec, tol, frac):
+    print("vjp clustered n_side=32", prec, frac, flush=True)
+    wl = make_workload("diff64", n_side=32)
+    rng = np.random.default_rng(11)
+    mass = rng.uniform(0.5, 2.0, wl.n)
+    active = None if frac is None else (rng.random(wl.n) < frac).astype(np.uint8)
+    w = rng.standard_normal((wl.n, 3))
+    ref = oracle.vjp(wl.pos, mass, active, w, 1.0, wl.x_s, wl.r_cut, method="tiled")
+    g = gpu_vjp(env, wl.pos, mass, active, w, 1.0, wl.x_s, wl.r_cut, prec)
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    row = np.max(np.linalg.norm(g - ref, axis=1)) / np.max(np.linalg.norm(ref, axis=1))
+    print("rel L2 %.3e  max row %.3e" % (rel, row), flush=True)
+    assert rel <= tol and row <= tol
+    if active is not None:
+        # particles with no active particle within r_cut get exactly zero
+        zero = np.linalg.norm(ref, axis=1) == 0
+        assert np.all(g[zero] == 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_vjp_finite_differences_diff64(env, prec):
+    """Config with N = 64^3 clustered particles, Gaussian weights: adjoint vs
+    central differences (step 1e-6 L, pair set frozen) on 64 samples."""
+    print("diff64 FD", prec, flush=True)
+    wl = make_workload("diff64")
+    g = gpu_vjp(env, wl.pos, wl.mass, None, wl.weights, 1.0, wl.x_s, wl.r_cut, prec)
+    idx = sample_indices(wl.n, 64, wl.config_id)
+    fd, _ = oracle.fd_grad(wl.pos, wl.mass, None, wl.weights, 1.0, wl.x_s, wl.r_cut, idx,
+                           h=1e-6, mode="fixed")
+    rel = np.linalg.norm(g[idx] - fd, axis=1) / np.linalg.norm(fd, axis=1)
+    print("max rel %.3e median %.3e" % (rel.max(), np.median(rel)), flush=True)
+    assert rel.max() <= 1e-4
+    # translation invariance with every particle active: sum_k grad_k = 0
+    assert np.all(np.abs(g.sum(axis=0)) <= 1e-6 * np.abs(g).sum(axis=0))
+
+
+def test_autograd_function(env):
+    torch, p3, ctx = env
+    pos_np, mass_np, active_np = random_particles(3000, seed=21, active_frac=0.5)
+    x_s = 1.25 / 28
+    r_cut = 4.5 * x_s
+    pos = to_dev(torch, pos_np).requires_grad_(True)
+    mass = to_dev(torch, mass_np)
+    active = to_dev(torch, active_np)
+    w = torch.randn((3000, 3), dtype=torch.float64, device="cuda:0")
+    acc = p3.sr_force(pos, mass, active, box=1.0, x_s=x_s, r_cut=r_cut, precision="fp64",
+                      context=ctx)
+    (acc * w).sum().backward()
+    ref = oracle.vjp(pos_np, mass_np, active_np, w.cpu().numpy(), 1.0, x_s, r_cut)
+    got = pos.grad.cpu().numpy()
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
