@@ -67,13 +67,14 @@ typedef struct {
     int64_t candidates;      /* (receiver lane, supplier) pairs tested after culling */
     int64_t clusters;        /* receiver groups of <= 64 */
     int64_t items;           /* work items of the persistent launch */
+    int64_t steps;           /* wavefront steps over suppliers (64 lane-slots each) */
     int32_t tiles_per_dim;   /* tiles per dimension (>= 3) */
     int32_t subtiles_per_dim;/* subtiles per tile per dimension */
     int32_t item_target;     /* work-item size target (supplier candidates) */
     int32_t precision;       /* p3m_precision of the call */
     float ms_build;          /* sort + compaction + planning, when timing is on, else -1 */
     float ms_pairs;          /* the persistent pair-kernel launch, when timing is on, else -1 */
-    float ms_total;          /* whole call, when timing is on, else -1 */
+    float ms_total;          /* whole call (GPU side), when timing is on, else -1 */
     int32_t pad;
 } p3m_sr_stats;
 

@@ -43,6 +43,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("receivers", ctypes.c_int64),
                 ("interactions", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("clusters", ctypes.c_int64), ("items", ctypes.c_int64),
+                ("steps", ctypes.c_int64),
                 ("tiles_per_dim", ctypes.c_int32), ("subtiles_per_dim", ctypes.c_int32),
                 ("item_target", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("ms_build", ctypes.c_float), ("ms_pairs", ctypes.c_float),

@@ -10,7 +10,8 @@
 //   clusters  <= 64 receivers of one tile per cluster
 //   items     clusters split over their 27 neighbour tiles (work estimate)
 //   [read back the cluster and item totals: the only host synchronisation]
-//   pairs     one persistent launch over all items, atomic FP64 accumulation
+//   pairs     one persistent launch over all items, per-item partial sums
+//   reduce    partial sums of each cluster's items added in item order
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -75,14 +76,14 @@ struct p3m_sr_context {
     int n_cu = 0;
     int blocks_per_cu[4] = {0, 0, 0, 0};
     DevBuf key, rank, cells, sp, perm, sel, flags, actpos, ncl, clusters, itemcnt, items, bsum,
-        counters, wa, scal;
+        counters, wa, scal, part, rp, rperm, rwa;
     int cfg_ns = 0, cfg_target = 0;
     std::map<TuneKey, TuneVal> tuned;
     p3m_sr_stats stats{};
     hipStream_t last_stream = nullptr;
     bool timing = false;
     bool timed_last = false;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // call start, pairs start, pairs end
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // start, pairs start/end, end
 };
 
 namespace {
@@ -229,7 +230,7 @@ int run(p3m_sr_context *h, const Request &r) {
     h->last_stream = s;
     h->timed_last = false;
     if (h->timing) {
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 4; ++k)
             if (!h->ev[k]) P3M_HIP(hipEventCreate(&h->ev[k]));
         P3M_HIP(hipEventRecord(h->ev[0], s));
     }
@@ -249,7 +250,7 @@ int run(p3m_sr_context *h, const Request &r) {
     if ((rc = ensure(h, h->key, sizeof(int) * n, s))) return rc;
     if ((rc = ensure(h, h->rank, sizeof(int) * n, s))) return rc;
     if ((rc = ensure(h, h->cells, sizeof(int) * (ncells + 1), s))) return rc;
-    if ((rc = ensure(h, h->sp, sizeof(double4) * ((size_t)n + 8), s))) return rc;
+    if ((rc = ensure(h, h->sp, sizeof(double4) * ((size_t)n + kSupplierPad), s))) return rc;
     if ((rc = ensure(h, h->perm, sizeof(int) * n, s))) return rc;
     if ((rc = ensure(h, h->sel, (size_t)n, s))) return rc;
     if ((rc = ensure(h, h->flags, sizeof(int) * (nflags + 1), s))) return rc;
@@ -259,8 +260,11 @@ int run(p3m_sr_context *h, const Request &r) {
     if ((rc = ensure(h, h->itemcnt, sizeof(int) * (cl_bound + 1), s))) return rc;
     if ((rc = ensure(h, h->bsum, sizeof(int) * scan_block_sums_needed(scan_max), s))) return rc;
     if ((rc = ensure(h, h->counters, sizeof(Counters), s))) return rc;
-    if ((rc = ensure(h, h->scal, sizeof(int) * 16, s))) return rc;
-    if (r.backward && (rc = ensure(h, h->wa, sizeof(double4) * ((size_t)n + 8), s))) return rc;
+    if ((rc = ensure(h, h->scal, sizeof(int) * (16 + kXcds), s))) return rc;
+    if ((rc = ensure(h, h->rp, sizeof(double4) * (nflags + 1), s))) return rc;
+    if ((rc = ensure(h, h->rperm, sizeof(int) * (nflags + 1), s))) return rc;
+    if (r.backward && (rc = ensure(h, h->rwa, sizeof(double4) * (nflags + 1), s))) return rc;
+    if (r.backward && (rc = ensure(h, h->wa, sizeof(double4) * ((size_t)n + kSupplierPad), s))) return rc;
 
     int *key = (int *)h->key.p, *rank = (int *)h->rank.p, *cells = (int *)h->cells.p;
     double4 *sp = (double4 *)h->sp.p;
@@ -280,7 +284,7 @@ int run(p3m_sr_context *h, const Request &r) {
     const uint8_t *sel_src = (r.sel_kind == SEL_ALL && !r.backward) ? nullptr : r.sel;
     P3M_HIP(launch_scatter(r.pos, r.mass, sel_src, n, g, key, rank, cells, fp32 ? 1 : 0, sp, perm,
                            sel_s, s));
-    P3M_HIP(launch_fill_i32((int *)(sp + n), 0, 8 * sizeof(double4) / sizeof(int), s));
+    P3M_HIP(launch_fill_i32((int *)(sp + n), 0, kSupplierPad * sizeof(double4) / sizeof(int), s));
 
     // ---- receivers -> clusters -> items ----
     // the adjoint needs every particle as a receiver (its output rows are
@@ -308,23 +312,32 @@ int run(p3m_sr_context *h, const Request &r) {
 
     if ((rc = ensure(h, h->items, sizeof(Item) * (size_t)(n_items > 0 ? n_items : 1), s)))
         return rc;
+    if ((rc = ensure(h, h->part, sizeof(double) * 3 * kWave * (size_t)(n_items > 0 ? n_items : 1),
+                     s)))
+        return rc;
     Item *items = (Item *)h->items.p;
     P3M_HIP(launch_item_write(clusters, n_clusters, cells, g, target, itemcnt, items, s));
+    double4 *wa = r.backward ? (double4 *)h->wa.p : nullptr;
+    if (r.backward) P3M_HIP(launch_gather_weights(r.grad_acc, sel_s, perm, n, fp32, wa, s));
+    P3M_HIP(launch_cluster_finish(clusters, n_clusters, actpos, sp, perm, wa, (double4 *)h->rp.p,
+                                  (int *)h->rperm.p, r.backward ? (double4 *)h->rwa.p : nullptr,
+                                  s));
+    int *queue = scal + 16;
+    P3M_HIP(launch_fill_i32(queue, 0, kXcds, s));
 
     // ---- pairs ----
-    if (r.backward) P3M_HIP(launch_gather_weights(r.grad_acc, sel_s, perm, n, fp32, (double4 *)h->wa.p, s));
     P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, s));
     PairArgs a{};
     a.sp = sp;
-    a.perm = perm;
-    a.act_pos = actpos;
+    a.rp = (const double4 *)h->rp.p;
+    a.rwa = (const double4 *)h->rwa.p;
     a.cell_start = cells;
     a.clusters = clusters;
     a.items = items;
-    a.wa = (const double4 *)h->wa.p;
-    a.out = r.out;
+    a.wa = wa;
+    a.queue = queue;
+    a.part = (double *)h->part.p;
     a.counters = counters;
-    a.out_stride = 3ll * n;
     a.n_items = n_items;
     a.g = g;
     if (h->blocks_per_cu[mode] == 0) h->blocks_per_cu[mode] = pairs_blocks_per_cu(mode);
@@ -338,6 +351,9 @@ int run(p3m_sr_context *h, const Request &r) {
         P3M_HIP(hipEventRecord(h->ev[2], s));
         h->timed_last = true;
     }
+    P3M_HIP(launch_reduce_items(clusters, n_clusters, itemcnt, (const int *)h->rperm.p,
+                                (double *)h->part.p, r.out, 3ll * n, s));
+    if (h->timing) P3M_HIP(hipEventRecord(h->ev[3], s));
     h->stats = st;
     return P3M_OK;
 }
@@ -387,7 +403,7 @@ int p3m_sr_destroy(p3m_sr_handle h) {
     DevBuf *bufs[] = {&h->key,      &h->rank,    &h->cells,   &h->sp,    &h->perm,
                       &h->sel,      &h->flags,   &h->actpos,  &h->ncl,   &h->clusters,
                       &h->itemcnt,  &h->items,   &h->bsum,    &h->counters, &h->wa,
-                      &h->scal};
+                      &h->scal,     &h->part,    &h->rp,      &h->rperm, &h->rwa};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : h->ev)
@@ -587,15 +603,17 @@ int p3m_sr_get_stats(p3m_sr_handle h, p3m_sr_stats *out) {
         P3M_HIP(hipMemcpy(&c, h->counters.p, sizeof(c), hipMemcpyDeviceToHost));
         st.interactions = (int64_t)c.interactions;
         st.candidates = (int64_t)c.candidates;
+        st.steps = (int64_t)c.steps;
     }
     if (h->timed_last) {
-        float a = 0, b = 0;
-        P3M_HIP(hipEventSynchronize(h->ev[2]));
+        float a = 0, b = 0, t = 0;
+        P3M_HIP(hipEventSynchronize(h->ev[3]));
         P3M_HIP(hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
         P3M_HIP(hipEventElapsedTime(&b, h->ev[1], h->ev[2]));
+        P3M_HIP(hipEventElapsedTime(&t, h->ev[0], h->ev[3]));
         st.ms_build = a;
         st.ms_pairs = b;
-        st.ms_total = a + b;
+        st.ms_total = t;
     }
     *out = st;
     return P3M_OK;

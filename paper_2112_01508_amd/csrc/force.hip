@@ -13,8 +13,9 @@
 // bounding box (the subtile-pair culling of section 2.1.3, "Subtiles", done
 // against the receivers' actual extent), a ballot gives the surviving
 // subtiles, and consecutive survivors merge into supplier ranges.  Supplier
-// particles are read at wave-uniform addresses, i.e. through the scalar
-// unit into SGPRs, and every lane evaluates its receiver against them.
+// particles are streamed by every lane; when a cluster holds fewer than 64
+// receivers the wave carries G = 64 / count copies of it and each copy walks
+// a different stride of the supplier range, so lanes are not left idle.
 //
 // Precision: the separation r_ij, the squared distance and the cut-off
 // test are FP64 and bitwise the same as a plain FP64 evaluation, so both
@@ -30,31 +31,7 @@ namespace {
 
 constexpr double kTwoOverSqrtPi = 1.12837916709551257390;
 
-// Pointer into the constant address space: loads through it at uniform
-// addresses become scalar (s_load) loads.  The arrays read this way are not
-// written by the kernels that read them.
-template <class T>
-using ConstPtr = const __attribute__((address_space(4))) T *;
-
-__device__ inline double4 load_uniform(const double4 *base, int j) {
-    ConstPtr<double> q = (ConstPtr<double>)base + 4 * (long long)j;
-    return make_double4(q[0], q[1], q[2], q[3]);
-}
-__device__ inline float4 load_uniform(const float4 *base, int j) {
-    ConstPtr<float> q = (ConstPtr<float>)base + 4 * (long long)j;
-    return make_float4(q[0], q[1], q[2], q[3]);
-}
-
 __device__ inline unsigned long long ballot64(bool p) { return __builtin_amdgcn_ballot_w64(p); }
-
-__device__ inline double wave_min(double v) {
-    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));
-    return v;
-}
-__device__ inline double wave_max(double v) {
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
-    return v;
-}
 
 __device__ inline float q_poly(float v) {
     float q = kGpoly[P3M_GPOLY_DEGREE];
@@ -117,7 +94,7 @@ struct BwdF64 {
     double wkx, wky, wkz, muk;
     __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
                                          const double4 &pj, int j, const PairArgs &a) {
-        const double4 wj = load_uniform(a.wa, j);
+        const double4 wj = a.wa[j];
         double vx = pj.w * wkx - muk * wj.x;
         double vy = pj.w * wky - muk * wj.y;
         double vz = pj.w * wkz - muk * wj.z;
@@ -140,7 +117,7 @@ struct BwdF32 {
     __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
                                          const double4 &pj, int j, const PairArgs &a) {
         const Geom &g = a.g;
-        const float4 wj = load_uniform(reinterpret_cast<const float4 *>(a.wa), j);
+        const float4 wj = reinterpret_cast<const float4 *>(a.wa)[j];
         const float muj = mu_f32(pj.w);
         float vx = muj * wkx - muk * wj.x;
         float vy = muj * wky - muk * wj.y;
@@ -164,17 +141,25 @@ struct BwdF32 {
 
 // ---- supplier range loop ------------------------------------------------------
 
+// The wave holds G copies ("groups") of the cluster's receivers; group g
+// takes suppliers j0 + g, j0 + g + G, ...  Lanes past the last group, and
+// groups past the end of the range, test a supplier that cannot pass.
 template <bool SHIFT, class Body>
 __device__ __forceinline__ void range_loop(Body &body, double xi, double yi, double zi, int j0,
-                                           int j1, double shx, double shy, double shz,
-                                           const PairArgs &a, int &n_acc) {
-    // Supplier records are read at wave-uniform addresses from the constant
-    // address space, so they arrive through scalar loads into SGPRs.
+                                           int j1, int grp, int G, double shx, double shy,
+                                           double shz, const PairArgs &a, int &n_acc) {
     const double rc2 = a.g.rc2;
     j0 = __builtin_amdgcn_readfirstlane(j0);
-    j1 = __builtin_amdgcn_readfirstlane(j1);
-    for (int j = j0; j < j1; ++j) {
-        const double4 pj = load_uniform(a.sp, j);
+    const int len = __builtin_amdgcn_readfirstlane(j1) - j0;
+    // the sorted array is padded by kSupplierPad >= 2*64 records, so the
+    // strided reads of the last step and the prefetch after it stay inside
+    // the allocation
+    const double4 *__restrict__ base = a.sp + j0;
+    double4 nxt = base[grp];
+    for (int k = 0; k < len; k += G) {
+        const double4 pj = nxt;
+        nxt = base[k + G + grp];   // next step's supplier, loaded one step ahead
+        const bool ok = grp < len - k;
         double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
         if (SHIFT) {
             dx -= shx;
@@ -182,9 +167,9 @@ __device__ __forceinline__ void range_loop(Body &body, double xi, double yi, dou
             dz -= shz;
         }
         const double r2 = dist2(dx, dy, dz);
-        if ((r2 < rc2) & (r2 > 0.0)) {
+        if (ok & (r2 < rc2) & (r2 > 0.0)) {
             ++n_acc;   // per-lane count of accepted pairs
-            body.pair(dx, dy, dz, r2, pj, j, a);
+            body.pair(dx, dy, dz, r2, pj, j0 + k + grp, a);
         }
     }
 }
@@ -193,9 +178,11 @@ __device__ __forceinline__ void range_loop(Body &body, double xi, double yi, dou
 // neighbour-tile / subtile range, with subtile culling by bounding box.
 template <class Body>
 __device__ __forceinline__ void walk_item(Body &body, const Item &item, const Cluster &cl,
-                                          double xi, double yi, double zi, const double lo[3],
-                                          const double hi[3], const PairArgs &a, int lane,
-                                          int &n_acc, unsigned long long &n_cand) {
+                                          double xi, double yi, double zi, const double *lo,
+                                          const double *hi, const PairArgs &a, int lane,
+                                          int grp, int G, int &n_acc,
+                                          unsigned long long &n_cand,
+                                          unsigned long long &n_steps) {
     const Geom &g = a.g;
     const int *__restrict__ cs = a.cell_start;
     const int tx = cl.tile / (g.nt * g.nt), ty = (cl.tile / g.nt) % g.nt, tz = cl.tile % g.nt;
@@ -238,69 +225,146 @@ __device__ __forceinline__ void walk_item(Body &body, const Item &item, const Cl
                 m = rb >= kWave ? 0ull : (m & (~0ull << rb));
                 if (j1 > j0) {
                     n_cand += (unsigned long long)(j1 - j0) * (unsigned long long)cl.count;
+                    n_steps += (unsigned long long)((j1 - j0 + G - 1) / G);
                     if (shifted)
-                        range_loop<true>(body, xi, yi, zi, j0, j1, shx, shy, shz, a, n_acc);
+                        range_loop<true>(body, xi, yi, zi, j0, j1, grp, G, shx, shy, shz, a,
+                                         n_acc);
                     else
-                        range_loop<false>(body, xi, yi, zi, j0, j1, 0.0, 0.0, 0.0, a, n_acc);
+                        range_loop<false>(body, xi, yi, zi, j0, j1, grp, G, 0.0, 0.0, 0.0, a,
+                                          n_acc);
                 }
             }
         }
     }
 }
 
+// Sum a value over the G copies of each receiver: after the loop, lane
+// il (group 0) holds the total of lanes il, il + cnt, ..., il + (G-1) cnt.
+__device__ inline double group_sum(double v, int lane, int grp, int cnt, int G) {
+    for (int step = 1; step < G; step <<= 1) {
+        const double o = __shfl(v, (lane + step * cnt) & (kWave - 1), kWave);
+        if ((grp & (2 * step - 1)) == 0 && grp + step < G) v += o;
+    }
+    return v;
+}
+
+// Next work item for this wave.  Items are cut into kXcds contiguous chunks
+// (the item list follows the tile order, so a chunk is a compact region of
+// the box); the workgroups of XCD x (blockIdx % kXcds, the round-robin
+// dispatch order) draw from chunk x through its own counter, so that XCD's
+// L2 serves a compact set of suppliers, and steal from the other chunks once
+// theirs is empty.  Returns -1 when every chunk is exhausted.
+__device__ inline int next_item(const PairArgs &a, int lane, int &victim) {
+    const int home = (int)(blockIdx.x % kXcds);
+    while (victim < kXcds) {
+        const int x = (home + victim) % kXcds;
+        const int c0 = (int)((long long)a.n_items * x / kXcds);
+        const int c1 = (int)((long long)a.n_items * (x + 1) / kXcds);
+        int got = 0;
+        if (lane == 0) got = atomicAdd(&a.queue[x], 1);
+        got = __builtin_amdgcn_readfirstlane(got);
+        if (c0 + got < c1) return c0 + got;
+        ++victim;
+    }
+    return -1;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = (int)((blockIdx.x * (unsigned)kForceBlock + threadIdx.x) / kWave);
-    const int nwaves = (int)(gridDim.x * (kForceBlock / kWave));
-    for (int it = wave; it < a.n_items; it += nwaves) {
+    int victim = 0;
+    // statistics stay in registers until the wave has run out of work: a
+    // contended atomic per item would also delay the next item's loads
+    // (vector memory operations retire in order)
+    int n_acc = 0;
+    unsigned long long n_cand = 0, n_steps = 0;
+    for (int it = next_item(a, lane, victim); it >= 0; it = next_item(a, lane, victim)) {
         const Item item = a.items[it];
         const Cluster cl = a.clusters[item.cluster];
-        const bool live = lane < cl.count;
-        const int p = a.act_pos[cl.begin + (live ? lane : 0)];
-        const double4 xp = a.sp[p];
-        const double lo[3] = {wave_min(xp.x), wave_min(xp.y), wave_min(xp.z)};
-        const double hi[3] = {wave_max(xp.x), wave_max(xp.y), wave_max(xp.z)};
-        // lanes without a receiver sit far outside the box: no pair passes r < r_cut
+        // receivers replicated over G lane groups; lanes past G*cnt are idle
+        const int cnt = __builtin_amdgcn_readfirstlane(cl.count);
+        const int G = __builtin_amdgcn_readfirstlane(kWave / cnt);
+        const int grp = lane / cnt;
+        const int il = lane - grp * cnt;
+        const bool live = grp < G;
+        const double4 xp = a.rp[cl.begin + il];
+        // idle lanes sit far outside the box: no pair passes r < r_cut
         const double far = live ? 0.0 : 1.0e300;
         const double xi = xp.x + far, yi = xp.y + far, zi = xp.z + far;
-        int n_acc = 0;
-        unsigned long long n_cand = 0;
         double ax, ay, az;
         if constexpr (MODE == FWD_F32) {
             FwdF32 b;
-            walk_item(b, item, cl, xi, yi, zi, lo, hi, a, lane, n_acc, n_cand);
+            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_cand,
+                      n_steps);
             ax = b.ax; ay = b.ay; az = b.az;
         } else if constexpr (MODE == FWD_F64) {
             FwdF64 b;
-            walk_item(b, item, cl, xi, yi, zi, lo, hi, a, lane, n_acc, n_cand);
+            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_cand,
+                      n_steps);
             ax = b.ax; ay = b.ay; az = b.az;
         } else if constexpr (MODE == BWD_F64) {
             BwdF64 b;
-            const double4 w = a.wa[p];
+            const double4 w = a.rwa[cl.begin + il];
             b.wkx = w.x; b.wky = w.y; b.wkz = w.z; b.muk = xp.w;
-            walk_item(b, item, cl, xi, yi, zi, lo, hi, a, lane, n_acc, n_cand);
+            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_cand,
+                      n_steps);
             ax = b.ax; ay = b.ay; az = b.az;
         } else {
             BwdF32 b;
-            const float4 w = reinterpret_cast<const float4 *>(a.wa)[p];
+            const float4 w = reinterpret_cast<const float4 *>(a.rwa)[cl.begin + il];
             b.wkx = w.x; b.wky = w.y; b.wkz = w.z; b.muk = mu_f32(xp.w);
-            walk_item(b, item, cl, xi, yi, zi, lo, hi, a, lane, n_acc, n_cand);
+            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_cand,
+                      n_steps);
             ax = b.ax; ay = b.ay; az = b.az;
         }
-        if (live) {
-            double *o = a.out + (long long)cl.subset * a.out_stride + 3ll * a.perm[p];
-            atomicAdd(o, ax);
-            atomicAdd(o + 1, ay);
-            atomicAdd(o + 2, az);
+        if (G > 1) {
+            ax = group_sum(ax, lane, grp, cnt, G);
+            ay = group_sum(ay, lane, grp, cnt, G);
+            az = group_sum(az, lane, grp, cnt, G);
         }
-        int tot = n_acc;
-        for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, kWave);
-        if (lane == 0 && a.counters) {
-            atomicAdd(&a.counters->interactions, (unsigned long long)tot);
-            atomicAdd(&a.counters->candidates, n_cand);
+        // per-item partial sums (group 0 holds them); a separate pass adds
+        // the items of each cluster in a fixed order
+        if (grp == 0) {
+            double *o = a.part + (long long)it * (3 * kWave) + il;
+            o[0] = ax;
+            o[kWave] = ay;
+            o[2 * kWave] = az;
         }
     }
+    unsigned long long tot = (unsigned long long)n_acc;
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, kWave);
+    if (lane == 0 && a.counters) {
+        atomicAdd(&a.counters->interactions, tot);
+        atomicAdd(&a.counters->candidates, n_cand);
+        atomicAdd(&a.counters->steps, n_steps);
+    }
+}
+
+// acc_out[subset][original index] = sum over the cluster's items of their
+// partials, added in item order (deterministic).  One 64-thread block per
+// cluster.
+__global__ __launch_bounds__(kWave) void k_reduce_items(const Cluster *__restrict__ clusters,
+                                                        const int *__restrict__ item_off,
+                                                        const int *__restrict__ rperm,
+                                                        const double *__restrict__ part,
+                                                        double *__restrict__ out,
+                                                        long long out_stride) {
+    const int c = blockIdx.x;
+    const Cluster cl = clusters[c];
+    const int il = threadIdx.x;
+    if (il >= cl.count) return;
+    const int i0 = item_off[c], i1 = item_off[c + 1];
+    double x = 0.0, y = 0.0, z = 0.0;
+    for (int it = i0; it < i1; ++it) {
+        const double *q = part + (long long)it * (3 * kWave) + il;
+        x += q[0];
+        y += q[kWave];
+        z += q[2 * kWave];
+    }
+    double *o = out + (long long)cl.subset * out_stride + 3ll * rperm[cl.begin + il];
+    o[0] = x;
+    o[1] = y;
+    o[2] = z;
 }
 
 template <int MODE>
@@ -313,6 +377,15 @@ int blocks_per_cu_of() {
 }
 
 }  // namespace
+
+hipError_t launch_reduce_items(const Cluster *clusters, int n_clusters, const int *item_off,
+                               const int *rperm, const double *part, double *out,
+                               long long out_stride, hipStream_t s) {
+    if (n_clusters <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_items, dim3((unsigned)n_clusters), dim3(kWave), 0, s, clusters,
+                       item_off, rperm, part, out, out_stride);
+    return hipGetLastError();
+}
 
 hipError_t launch_pairs(int mode, const PairArgs &a, int grid, hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;

@@ -25,6 +25,7 @@ constexpr int kScanBlock = 256;             // threads per scan block
 constexpr int kScanPerThread = 16;          // elements per scan thread
 constexpr int kScanTile = kScanBlock * kScanPerThread;
 constexpr int kForceBlock = 256;            // 4 waves, each with its own work item
+constexpr int kSupplierPad = 128;           // zeroed records after the sorted particles
 
 // Geometry of one call.  Tiles are cubes of side box/nt >= r_cut; each tile
 // holds ns^3 subtiles; fine cells are the subtiles, nc = nt*ns per dimension.
@@ -46,8 +47,10 @@ struct Geom {
 struct Cluster {
     int tile;     // tile index (tx*nt + ty)*nt + tz
     int subset;   // receiver subset (batched calls)
-    int begin;    // first entry in act_pos
+    int begin;    // first entry in act_pos / rp / rperm
     int count;    // 1..64 receivers
+    double lo[3]; // bounding box of the receivers (wrapped positions)
+    double hi[3];
 };
 
 // Work item: receivers of one cluster against suppliers in neighbour tiles
@@ -63,7 +66,8 @@ struct Item {
 struct Counters {
     unsigned long long interactions;
     unsigned long long candidates;
-    unsigned long long pad[6];
+    unsigned long long steps;        // wave steps over suppliers
+    unsigned long long pad[5];
 };
 
 enum SelKind { SEL_ALL = 0, SEL_MASK = 1, SEL_RUNG = 2 };
@@ -99,24 +103,34 @@ hipError_t launch_item_write(const Cluster *clusters, int n_clusters, const int 
                              hipStream_t s);
 hipError_t launch_gather_weights(const double *grad_acc, const uint8_t *sel_s, const int *perm,
                                  int n, int fp32, double4 *wa, hipStream_t s);
+// per cluster: receivers copied to rp / rperm / rwa (indexed like act_pos) and
+// the bounding box filled in
+hipError_t launch_cluster_finish(Cluster *clusters, int n_clusters, const int *act_pos,
+                                 const double4 *sp, const int *perm, const double4 *wa,
+                                 double4 *rp, int *rperm, double4 *rwa, hipStream_t s);
 
 // force.hip
 enum PairMode { FWD_F32 = 0, FWD_F64 = 1, BWD_F32 = 2, BWD_F64 = 3 };
+constexpr int kXcds = 8;   // MI355X: workgroups are dealt round-robin to 8 XCDs
+
 struct PairArgs {
-    const double4 *sp;
-    const int *perm;
-    const int *act_pos;
+    const double4 *sp;       // suppliers in sorted order
+    const double4 *rp;       // receivers, indexed like act_pos
+    const double4 *rwa;      // backward: receivers' w * [active] (FP32 path: float4 bits)
     const int *cell_start;
     const Cluster *clusters;
     const Item *items;
-    const double4 *wa;       // backward: w * [active], sorted (FP32 path: float4 bits)
-    double *out;             // acc_out / grad_pos, n x 3 per subset
+    const double4 *wa;       // backward: suppliers' w * [active], sorted (FP32: float4 bits)
+    int *queue;              // kXcds work counters, zero at launch
+    double *part;            // per-item partial sums, n_items x 3 x 64
     Counters *counters;
-    long long out_stride;    // elements between subsets (3 n)
     int n_items;
     Geom g;
 };
 hipError_t launch_pairs(int mode, const PairArgs &a, int grid, hipStream_t s);
+hipError_t launch_reduce_items(const Cluster *clusters, int n_clusters, const int *item_off,
+                               const int *rperm, const double *part, double *out,
+                               long long out_stride, hipStream_t s);
 int pairs_blocks_per_cu(int mode);
 
 }  // namespace p3m

@@ -219,7 +219,7 @@ __global__ void k_cluster_write(const int *__restrict__ cs, const int *__restric
     int a1 = scan[off + cs[(size_t)(t + 1) * g.ns3]];
     int o = cl_off[idx];
     for (int b = a0; b < a1; b += kWave) {
-        Cluster c;
+        Cluster c{};
         c.tile = t;
         c.subset = k;
         c.begin = b;
@@ -315,12 +315,61 @@ __global__ void k_gather_weights(const double *__restrict__ w, const uint8_t *__
     }
 }
 
+__device__ inline double wave_min(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+__device__ inline double wave_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// One wave per cluster: gather the receivers into contiguous arrays and
+// compute their bounding box (lanes past count repeat receiver 0).
+__global__ __launch_bounds__(kWave) void k_cluster_finish(Cluster *__restrict__ clusters,
+                                                          const int *__restrict__ act_pos,
+                                                          const double4 *__restrict__ sp,
+                                                          const int *__restrict__ perm,
+                                                          const double4 *__restrict__ wa,
+                                                          double4 *__restrict__ rp,
+                                                          int *__restrict__ rperm,
+                                                          double4 *__restrict__ rwa) {
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x;
+    Cluster cl = clusters[c];
+    const bool live = lane < cl.count;
+    const int a = cl.begin + (live ? lane : 0);
+    const int p = act_pos[a];
+    const double4 x = sp[p];
+    if (live) {
+        rp[a] = x;
+        rperm[a] = perm[p];
+        if (rwa) rwa[a] = wa[p];
+    }
+    const double lx = wave_min(x.x), ly = wave_min(x.y), lz = wave_min(x.z);
+    const double hx = wave_max(x.x), hy = wave_max(x.y), hz = wave_max(x.z);
+    if (lane == 0) {
+        cl.lo[0] = lx; cl.lo[1] = ly; cl.lo[2] = lz;
+        cl.hi[0] = hx; cl.hi[1] = hy; cl.hi[2] = hz;
+        clusters[c] = cl;
+    }
+}
+
 inline unsigned grid_for(size_t n, int block) {
     size_t g = (n + block - 1) / block;
     return (unsigned)(g > 0 ? g : 1);
 }
 
 }  // namespace
+
+hipError_t launch_cluster_finish(Cluster *clusters, int n_clusters, const int *act_pos,
+                                 const double4 *sp, const int *perm, const double4 *wa,
+                                 double4 *rp, int *rperm, double4 *rwa, hipStream_t s) {
+    if (n_clusters <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cluster_finish, dim3((unsigned)n_clusters), dim3(kWave), 0, s, clusters,
+                       act_pos, sp, perm, wa, rp, rperm, rwa);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_i32(int *p, int v, size_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
