@@ -36,6 +36,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="clustered128")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--ns", type=int, default=0, help="fixed subtiles per tile (0 = autotune)")
+    ap.add_argument("--target", type=int, default=0, help="fixed work-item size (0 = autotune)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 512 MiB device copy (HBM counter calibration)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
@@ -72,8 +76,41 @@ def time_steps(torch, ctx, pos, mass, wl, prec, steps, warmup):
     return out, wall, st, sum(pairs_ms) / len(pairs_ms), sum(build_ms) / len(build_ms)
 
 
+def profiled_traffic(name, ns, target):
+    """HBM bytes per launch of the pair kernel from the committed rocprofv3
+    counter runs (profiles/traffic.json), or None when the kernel sources or
+    the decomposition differ from the ones the counters were taken with."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[name]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in ("force.hip", "p3msr_internal.hpp", "gpoly.inc"):
+        with open(os.path.join(ROOT, "paper_2112_01508_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if (h.hexdigest() != rec.get("kernel_sources_sha256") or rec.get("subtiles_per_dim") != ns
+            or rec.get("item_target") != target):
+        return None
+    return rec["traffic_bytes"]
+
+
+def copy_probe():
+    import torch
+    n = 64 * 1024 * 1024                      # 64 Mi doubles = 512 MiB
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8, "copies": 3}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -92,8 +129,10 @@ def main():
     ctx = p3.Context(0)
 
     results = {}
+    if args.ns or args.target:
+        ctx.set_config(args.ns, args.target)
     for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
-        if not args.no_autotune:
+        if not args.no_autotune and not (args.ns or args.target):
             log("autotuning", prec)
             ctx.autotune(pos, mass, None, box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut,
                          precision=prec, level=2)
@@ -133,7 +172,10 @@ def main():
                    "subtiles_per_dim": r32["stats"]["subtiles_per_dim"],
                    "item_target": r32["stats"]["item_target"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": profiled_traffic("k_pairs_fwd_fp32_%s" % args.workload,
+                                                 r32["stats"]["subtiles_per_dim"],
+                                                 r32["stats"]["item_target"])},
         "pair_kernel_ms": r32["pairs_ms"],
         "build_ms": r32["build_ms"],
     }
@@ -148,7 +190,7 @@ def main():
         import oracle
         oracle.build(force=False)
         # size the receiver sample for about args.cpu_seconds of oracle work
-        probe = sample_indices(wl.n, 64, wl.config_id, salt=1)
+        probe = sample_indices(wl.n, 2048, wl.config_id, salt=1)
         t0 = time.perf_counter()
         oracle.force(wl.pos, wl.mass, wl.box, wl.x_s, wl.r_cut, recv=probe)
         per = (time.perf_counter() - t0) / probe.size
