@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="adjoint,batched",
+                    help="extra measured legs beside the forward force: adjoint, batched")
+    ap.add_argument("--batched-workload", default="clustered256")
     return ap.parse_args()
 
 
@@ -74,6 +77,70 @@ def time_steps(torch, ctx, pos, mass, wl, prec, steps, warmup):
     ctx.set_timing(False)
     st = ctx.stats()
     return out, wall, st, sum(pairs_ms) / len(pairs_ms), sum(build_ms) / len(build_ms)
+
+
+def time_calls(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def adjoint_leg(torch, ctx, pos, mass, wl, steps, warmup):
+    """Vector-Jacobian product of the force (60 algorithmic flops per pair)."""
+    gen = torch.Generator(device=pos.device).manual_seed(4003)
+    w = torch.randn((wl.n, 3), dtype=torch.float64, device=pos.device, generator=gen)
+    out = {}
+    for prec in ("fp32", "fp64"):
+        kw = dict(box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut, precision=prec)
+        wall = time_calls(torch, lambda: ctx.force_backward(pos, mass, None, w, **kw),
+                          max(2, steps // 4), 1)
+        ctx.set_timing(True)
+        ctx.force_backward(pos, mass, None, w, **kw)
+        st = ctx.stats()
+        ctx.set_timing(False)
+        out[prec] = {"ms_per_call": wall * 1e3, "pair_kernel_ms": st["ms_pairs"],
+                     "interactions": st["interactions"],
+                     "value": st["interactions"] / wall,
+                     "achieved_tflops": 60 * st["interactions"] / (st["ms_pairs"] * 1e-3) / 1e12}
+        log("adjoint", prec, "%.3f ms" % (wall * 1e3))
+    return out
+
+
+def batched_leg(torch, p3, name, steps, warmup):
+    """All 8 nested rung subsets (rung >= k, k = 0..7) in one persistent launch."""
+    from workloads import make_workload
+    log("generating", name, "with rungs")
+    wl = make_workload(name)
+    dev = torch.device("cuda", 0)
+    pos = torch.from_numpy(wl.pos).to(dev)
+    mass = torch.from_numpy(wl.mass).to(dev)
+    rung = torch.from_numpy(wl.rung).to(dev)
+    ctx = p3.Context(0)
+    thr = list(range(8))
+    out = torch.empty((8, wl.n, 3), dtype=torch.float64, device=dev)
+    res = {"workload": "%s: N=%d clustered, PM grid %d^3, k-NN density rungs 0-7, 8 nested "
+                       "subsets rung>=k in one launch" % (name, wl.n, wl.n_pm),
+           "subset_sizes": [int((wl.rung >= k).sum()) for k in thr]}
+    for prec in ("fp32", "fp64"):
+        kw = dict(box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut, precision=prec)
+        wall = time_calls(torch, lambda: ctx.force_batched(pos, mass, rung, thr, out=out, **kw),
+                          max(2, steps // 5), 1)
+        ctx.set_timing(True)
+        ctx.force_batched(pos, mass, rung, thr, out=out, **kw)
+        st = ctx.stats()
+        ctx.set_timing(False)
+        res[prec] = {"ms_per_call": wall * 1e3, "pair_kernel_ms": st["ms_pairs"],
+                     "interactions": st["interactions"], "value": st["interactions"] / wall,
+                     "achieved_tflops": 40 * st["interactions"] / (st["ms_pairs"] * 1e-3) / 1e12,
+                     "subtiles_per_dim": st["subtiles_per_dim"], "items": st["items"]}
+        log("batched", prec, "%.3f ms  interactions %d" % (wall * 1e3, st["interactions"]))
+    ctx.close()
+    return res
 
 
 def profiled_traffic(name, ns, target):
@@ -185,6 +252,12 @@ def main():
         line["fp64"] = {"value": r64["stats"]["interactions"] / r64["wall"],
                         "ms_per_step": r64["wall"] * 1e3, "pair_kernel_ms": r64["pairs_ms"],
                         "achieved_tflops": a64, "frac_fp64_peak": a64 / PEAK_FP64_TFLOPS}
+
+    legs = [l for l in args.legs.split(",") if l]
+    if "adjoint" in legs:
+        line["adjoint"] = adjoint_leg(torch, ctx, pos, mass, wl, args.steps, args.warmup)
+    if "batched" in legs:
+        line["batched"] = batched_leg(torch, p3, args.batched_workload, args.steps, args.warmup)
 
     if not args.no_cpu_baseline:
         import oracle

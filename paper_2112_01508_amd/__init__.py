@@ -196,6 +196,10 @@ class Context:
         n_sub = len(thr)
         if out is None:
             out = torch.empty((n_sub, n, 3), dtype=torch.float64, device=self.device)
+        elif (out.device != self.device or out.dtype != torch.float64
+              or tuple(out.shape) != (n_sub, n, 3) or not out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 (%d, %d, 3) tensor on %s"
+                             % (n_sub, n, self.device))
         buf = ctypes.create_string_buffer(thr, max(n_sub, 1))
         _check(self._lib.p3m_sr_force_batched(self._h, self._p(pos), self._p(mass),
                                               self._p(rung), n, n_sub,

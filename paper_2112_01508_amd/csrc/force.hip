@@ -94,7 +94,7 @@ struct BwdF64 {
     double wkx, wky, wkz, muk;
     __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
                                          const double4 &pj, int j, const PairArgs &a) {
-        const double4 wj = a.wa[j];
+        const double4 wj = a.wa[j];   // j may be wave-uniform or per lane
         double vx = pj.w * wkx - muk * wj.x;
         double vy = pj.w * wky - muk * wj.y;
         double vz = pj.w * wkz - muk * wj.z;
@@ -141,6 +141,55 @@ struct BwdF32 {
 
 // ---- supplier range loop ------------------------------------------------------
 
+// Pointer into the constant address space: loads through it at wave-uniform
+// addresses become scalar loads into SGPRs.  The supplier array is not
+// written by the pair kernels.
+template <class T>
+using ConstPtr = const __attribute__((address_space(4))) T *;
+
+__device__ __forceinline__ double4 load_uniform(const double4 *base, int j) {
+    ConstPtr<double> q = (ConstPtr<double>)base + 4 * (long long)j;
+    return make_double4(q[0], q[1], q[2], q[3]);
+}
+
+// A full cluster (G = 1): every lane tests the same supplier, read through
+// the scalar unit.  Two record sets alternate so that the load of the next
+// supplier is in flight while the current one is evaluated.
+template <bool SHIFT, class Body>
+__device__ __forceinline__ void test_pair(Body &body, double xi, double yi, double zi,
+                                          const double4 &pj, int j, bool valid, double shx,
+                                          double shy, double shz, const PairArgs &a,
+                                          int &n_acc) {
+    double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
+    if (SHIFT) {
+        dx -= shx;
+        dy -= shy;
+        dz -= shz;
+    }
+    const double r2 = dist2(dx, dy, dz);
+    if (valid & (r2 < a.g.rc2) & (r2 > 0.0)) {
+        ++n_acc;   // per-lane count of accepted pairs
+        body.pair(dx, dy, dz, r2, pj, j, a);
+    }
+}
+
+template <bool SHIFT, class Body>
+__device__ __forceinline__ void range_loop_full(Body &body, double xi, double yi, double zi,
+                                                int j0, int j1, double shx, double shy,
+                                                double shz, const PairArgs &a, int &n_acc) {
+    j0 = __builtin_amdgcn_readfirstlane(j0);
+    j1 = __builtin_amdgcn_readfirstlane(j1);
+    // the sorted array is padded by kSupplierPad records: the look-ahead
+    // loads past j1 stay inside the allocation
+    double4 A = load_uniform(a.sp, j0);
+    for (int j = j0; j < j1; j += 2) {
+        const double4 B = load_uniform(a.sp, j + 1);
+        test_pair<SHIFT>(body, xi, yi, zi, A, j, true, shx, shy, shz, a, n_acc);
+        A = load_uniform(a.sp, j + 2);
+        test_pair<SHIFT>(body, xi, yi, zi, B, j + 1, j + 1 < j1, shx, shy, shz, a, n_acc);
+    }
+}
+
 // The wave holds G copies ("groups") of the cluster's receivers; group g
 // takes suppliers j0 + g, j0 + g + G, ...  Lanes past the last group, and
 // groups past the end of the range, test a supplier that cannot pass.
@@ -148,6 +197,10 @@ template <bool SHIFT, class Body>
 __device__ __forceinline__ void range_loop(Body &body, double xi, double yi, double zi, int j0,
                                            int j1, int grp, int G, double shx, double shy,
                                            double shz, const PairArgs &a, int &n_acc) {
+    if (G == 1) {
+        range_loop_full<SHIFT>(body, xi, yi, zi, j0, j1, shx, shy, shz, a, n_acc);
+        return;
+    }
     const double rc2 = a.g.rc2;
     j0 = __builtin_amdgcn_readfirstlane(j0);
     const int len = __builtin_amdgcn_readfirstlane(j1) - j0;

@@ -57,3 +57,39 @@ def test_batched_uneven_thresholds(env):
             e = oracle.errors(out[k][act == 1], ref[act == 1], absum[act == 1])
             assert e["e_max_cond"] <= 1e-12
         assert np.all(out[k][act == 0] == 0)
+
+
+@pytest.fixture(scope="module")
+def clustered256():
+    print("generating clustered256 (N=256^3, k-NN rungs)", flush=True)
+    return make_workload("clustered256")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batched_clustered256_full(env, clustered256, prec):
+    """Full-size N=256^3 clustered set, 8 nested rung subsets in one launch:
+    256 receivers per rung (stratified, seeded) checked in every subset they
+    belong to against brute force over all N suppliers."""
+    torch, p3, ctx = env
+    wl = clustered256
+    thr = list(range(8))
+    out = ctx.force_batched(to_dev(torch, wl.pos), to_dev(torch, wl.mass), to_dev(torch, wl.rung),
+                            thr, box=1.0, x_s=wl.x_s, r_cut=wl.r_cut, precision=prec)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    print(prec, st, flush=True)
+    assert st["receivers"] == sum(int((wl.rung >= k).sum()) for k in thr)
+    idx = stratified_by_rung(wl.rung, 256, wl.config_id)
+    ref, cnt, absum, _ = oracle.force(wl.pos, wl.mass, 1.0, wl.x_s, wl.r_cut, recv=idx)
+    for k in thr:
+        sel = wl.rung[idx] >= k
+        got = out[k][torch.from_numpy(idx[sel]).to(out.device)].cpu().numpy()
+        e = oracle.errors(got, ref[sel], absum[sel])
+        print("subset", k, int(sel.sum()), e, flush=True)
+        assert e["e_l2"] <= TOL[prec] and e["e_max_cond"] <= TOL[prec], (k, e)
+        # rows outside the subset are zero
+        off = idx[~sel]
+        if off.size:
+            assert torch.count_nonzero(out[k][torch.from_numpy(off).to(out.device)]) == 0
+    del out
+    torch.cuda.empty_cache()
