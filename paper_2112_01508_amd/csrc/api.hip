@@ -175,6 +175,8 @@ Geom make_geom(double box, double x_s, double r_cut, int nt, int ns) {
     g.kb = 1.0 / (2.0 * 1.77245385090551602730 * x_s * x_s * x_s);
     g.k1f = (float)g.k1;
     g.kbf = (float)g.kb;
+    g.c2f = (float)(1.0 / (4.0 * x_s * x_s));
+    g.c3f = (float)(1.0 / (8.0 * x_s * x_s * x_s));
     return g;
 }
 
@@ -339,6 +341,7 @@ int run(p3m_sr_context *h, const Request &r) {
     a.part = (double *)h->part.p;
     a.counters = counters;
     a.n_items = n_items;
+    a.unit_mass = r.mass ? 0 : 1;
     a.g = g;
     if (h->blocks_per_cu[mode] == 0) h->blocks_per_cu[mode] = pairs_blocks_per_cu(mode);
     long long waves_wanted = (n_items + 0ll);

@@ -20,8 +20,10 @@
 // Precision: the separation r_ij, the squared distance and the cut-off
 // test are FP64 and bitwise the same as a plain FP64 evaluation, so both
 // paths accept exactly the same pairs.  The FP32 path then evaluates the
-// kernel shape in FP32 (hardware rsqrt and exp2 plus a degree-9 polynomial
-// for erfcx(u) + 2u/sqrt(pi)) and accumulates in FP64.
+// kernel shape in FP32 and accumulates in FP64: the forward force as
+// r^-3 + H(u^2) / (2 x_s)^3 (hardware rsqrt plus a degree-9 polynomial),
+// the adjoint with hardware rsqrt and exp2 and a degree-9 polynomial for
+// erfcx(u) + 2u/sqrt(pi).
 #include "p3msr_internal.hpp"
 #include "gpoly.inc"
 
@@ -40,6 +42,13 @@ __device__ inline float q_poly(float v) {
     return q;
 }
 
+__device__ inline float h_poly(float v) {
+    float h = kHpoly[P3M_HPOLY_DEGREE];
+#pragma unroll
+    for (int k = P3M_HPOLY_DEGREE - 1; k >= 0; --k) h = fmaf(h, v, kHpoly[k]);
+    return h;
+}
+
 __device__ inline float mu_f32(double w) {
     return __uint_as_float((unsigned int)(unsigned long long)__double_as_longlong(w));
 }
@@ -56,16 +65,19 @@ __device__ inline double dist2(double dx, double dy, double dz) {
 
 // ---- per-pair bodies ---------------------------------------------------------
 
+// Forward, FP32 shape: g(u)/r^3 = r^-3 + H(t) / (2 x_s)^3 with t = u^2 (one
+// hardware rsqrt and one polynomial, no exponential).  UNIT: every mass is 1.
+template <bool UNIT>
 struct FwdF32 {
     double ax = 0.0, ay = 0.0, az = 0.0;
     __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
                                          const double4 &pj, int, const PairArgs &a) {
         const Geom &g = a.g;
-        float r2f = (float)r2;
-        float ri = __builtin_amdgcn_rsqf(r2f);
-        float v = fmaf(r2f * ri, g.k1f, -P3M_GPOLY_C0);
-        float e = __builtin_amdgcn_exp2f((float)(r2 * g.k2));
-        float s = mu_f32(pj.w) * (e * q_poly(v)) * (ri * ri * ri);
+        const float r2f = (float)r2;
+        const float ri = __builtin_amdgcn_rsqf(r2f);
+        const float h = h_poly(fmaf(r2f, g.c2f, -P3M_HPOLY_T0));
+        const float sh = fmaf(g.c3f, h, ri * ri * ri);
+        const float s = UNIT ? sh : mu_f32(pj.w) * sh;
         double sd = (double)s;
         ax = fma(-sd, dx, ax);
         ay = fma(-sd, dy, ay);
@@ -73,6 +85,7 @@ struct FwdF32 {
     }
 };
 
+template <bool UNIT>
 struct FwdF64 {
     double ax = 0.0, ay = 0.0, az = 0.0;
     __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
@@ -80,7 +93,7 @@ struct FwdF64 {
         double r = sqrt(r2);
         double u = r * a.g.k1;
         double gu = erfc(u) + kTwoOverSqrtPi * u * exp(-u * u);
-        double s = pj.w * gu / (r2 * r);
+        double s = UNIT ? gu / (r2 * r) : pj.w * gu / (r2 * r);
         ax -= s * dx;
         ay -= s * dy;
         az -= s * dz;
@@ -159,7 +172,7 @@ template <bool SHIFT, class Body>
 __device__ __forceinline__ void test_pair(Body &body, double xi, double yi, double zi,
                                           const double4 &pj, int j, bool valid, double shx,
                                           double shy, double shz, const PairArgs &a,
-                                          int &n_acc) {
+                                          int &n_wave) {
     double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
     if (SHIFT) {
         dx -= shx;
@@ -168,7 +181,7 @@ __device__ __forceinline__ void test_pair(Body &body, double xi, double yi, doub
     }
     const double r2 = dist2(dx, dy, dz);
     if (valid & (r2 < a.g.rc2) & (r2 > 0.0)) {
-        ++n_acc;   // per-lane count of accepted pairs
+        ++n_wave;   // per-lane count of accepted pairs
         body.pair(dx, dy, dz, r2, pj, j, a);
     }
 }
@@ -176,7 +189,7 @@ __device__ __forceinline__ void test_pair(Body &body, double xi, double yi, doub
 template <bool SHIFT, class Body>
 __device__ __forceinline__ void range_loop_full(Body &body, double xi, double yi, double zi,
                                                 int j0, int j1, double shx, double shy,
-                                                double shz, const PairArgs &a, int &n_acc) {
+                                                double shz, const PairArgs &a, int &n_wave) {
     j0 = __builtin_amdgcn_readfirstlane(j0);
     j1 = __builtin_amdgcn_readfirstlane(j1);
     // the sorted array is padded by kSupplierPad records: the look-ahead
@@ -184,9 +197,9 @@ __device__ __forceinline__ void range_loop_full(Body &body, double xi, double yi
     double4 A = load_uniform(a.sp, j0);
     for (int j = j0; j < j1; j += 2) {
         const double4 B = load_uniform(a.sp, j + 1);
-        test_pair<SHIFT>(body, xi, yi, zi, A, j, true, shx, shy, shz, a, n_acc);
+        test_pair<SHIFT>(body, xi, yi, zi, A, j, true, shx, shy, shz, a, n_wave);
         A = load_uniform(a.sp, j + 2);
-        test_pair<SHIFT>(body, xi, yi, zi, B, j + 1, j + 1 < j1, shx, shy, shz, a, n_acc);
+        test_pair<SHIFT>(body, xi, yi, zi, B, j + 1, j + 1 < j1, shx, shy, shz, a, n_wave);
     }
 }
 
@@ -196,9 +209,10 @@ __device__ __forceinline__ void range_loop_full(Body &body, double xi, double yi
 template <bool SHIFT, class Body>
 __device__ __forceinline__ void range_loop(Body &body, double xi, double yi, double zi, int j0,
                                            int j1, int grp, int G, double shx, double shy,
-                                           double shz, const PairArgs &a, int &n_acc) {
+                                           double shz, const PairArgs &a, int &n_acc,
+                                           int &n_wave) {
     if (G == 1) {
-        range_loop_full<SHIFT>(body, xi, yi, zi, j0, j1, shx, shy, shz, a, n_acc);
+        range_loop_full<SHIFT>(body, xi, yi, zi, j0, j1, shx, shy, shz, a, n_wave);
         return;
     }
     const double rc2 = a.g.rc2;
@@ -233,7 +247,7 @@ template <class Body>
 __device__ __forceinline__ void walk_item(Body &body, const Item &item, const Cluster &cl,
                                           double xi, double yi, double zi, const double *lo,
                                           const double *hi, const PairArgs &a, int lane,
-                                          int grp, int G, int &n_acc,
+                                          int grp, int G, int &n_acc, int &n_wave,
                                           unsigned long long &n_cand,
                                           unsigned long long &n_steps) {
     const Geom &g = a.g;
@@ -281,10 +295,10 @@ __device__ __forceinline__ void walk_item(Body &body, const Item &item, const Cl
                     n_steps += (unsigned long long)((j1 - j0 + G - 1) / G);
                     if (shifted)
                         range_loop<true>(body, xi, yi, zi, j0, j1, grp, G, shx, shy, shz, a,
-                                         n_acc);
+                                         n_acc, n_wave);
                     else
                         range_loop<false>(body, xi, yi, zi, j0, j1, grp, G, 0.0, 0.0, 0.0, a,
-                                          n_acc);
+                                          n_acc, n_wave);
                 }
             }
         }
@@ -322,14 +336,15 @@ __device__ inline int next_item(const PairArgs &a, int lane, int &victim) {
     return -1;
 }
 
-template <int MODE>
+template <int MODE, bool UNIT>
 __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     int victim = 0;
     // statistics stay in registers until the wave has run out of work: a
     // contended atomic per item would also delay the next item's loads
     // (vector memory operations retire in order)
-    int n_acc = 0;
+    int n_acc = 0;    // per lane: accepted pairs of the strided (G > 1) loop
+    int n_wave = 0;   // per lane: accepted pairs of the full-cluster loop
     unsigned long long n_cand = 0, n_steps = 0;
     for (int it = next_item(a, lane, victim); it >= 0; it = next_item(a, lane, victim)) {
         const Item item = a.items[it];
@@ -346,27 +361,27 @@ __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
         const double xi = xp.x + far, yi = xp.y + far, zi = xp.z + far;
         double ax, ay, az;
         if constexpr (MODE == FWD_F32) {
-            FwdF32 b;
-            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_cand,
+            FwdF32<UNIT> b;
+            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_wave, n_cand,
                       n_steps);
             ax = b.ax; ay = b.ay; az = b.az;
         } else if constexpr (MODE == FWD_F64) {
-            FwdF64 b;
-            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_cand,
+            FwdF64<UNIT> b;
+            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_wave, n_cand,
                       n_steps);
             ax = b.ax; ay = b.ay; az = b.az;
         } else if constexpr (MODE == BWD_F64) {
             BwdF64 b;
             const double4 w = a.rwa[cl.begin + il];
             b.wkx = w.x; b.wky = w.y; b.wkz = w.z; b.muk = xp.w;
-            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_cand,
+            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_wave, n_cand,
                       n_steps);
             ax = b.ax; ay = b.ay; az = b.az;
         } else {
             BwdF32 b;
             const float4 w = reinterpret_cast<const float4 *>(a.rwa)[cl.begin + il];
             b.wkx = w.x; b.wky = w.y; b.wkz = w.z; b.muk = mu_f32(xp.w);
-            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_cand,
+            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_wave, n_cand,
                       n_steps);
             ax = b.ax; ay = b.ay; az = b.az;
         }
@@ -384,7 +399,7 @@ __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
             o[2 * kWave] = az;
         }
     }
-    unsigned long long tot = (unsigned long long)n_acc;
+    unsigned long long tot = (unsigned long long)(n_acc + n_wave);
     for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, kWave);
     if (lane == 0 && a.counters) {
         atomicAdd(&a.counters->interactions, tot);
@@ -423,7 +438,7 @@ __global__ __launch_bounds__(kWave) void k_reduce_items(const Cluster *__restric
 template <int MODE>
 int blocks_per_cu_of() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs<MODE>, kForceBlock, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs<MODE, false>, kForceBlock, 0) !=
         hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
@@ -444,10 +459,16 @@ hipError_t launch_pairs(int mode, const PairArgs &a, int grid, hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;
     dim3 gr((unsigned)grid), bl(kForceBlock);
     switch (mode) {
-    case FWD_F32: hipLaunchKernelGGL(k_pairs<FWD_F32>, gr, bl, 0, s, a); break;
-    case FWD_F64: hipLaunchKernelGGL(k_pairs<FWD_F64>, gr, bl, 0, s, a); break;
-    case BWD_F32: hipLaunchKernelGGL(k_pairs<BWD_F32>, gr, bl, 0, s, a); break;
-    default: hipLaunchKernelGGL(k_pairs<BWD_F64>, gr, bl, 0, s, a); break;
+    case FWD_F32:
+        if (a.unit_mass) hipLaunchKernelGGL((k_pairs<FWD_F32, true>), gr, bl, 0, s, a);
+        else hipLaunchKernelGGL((k_pairs<FWD_F32, false>), gr, bl, 0, s, a);
+        break;
+    case FWD_F64:
+        if (a.unit_mass) hipLaunchKernelGGL((k_pairs<FWD_F64, true>), gr, bl, 0, s, a);
+        else hipLaunchKernelGGL((k_pairs<FWD_F64, false>), gr, bl, 0, s, a);
+        break;
+    case BWD_F32: hipLaunchKernelGGL((k_pairs<BWD_F32, false>), gr, bl, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_pairs<BWD_F64, false>), gr, bl, 0, s, a); break;
     }
     return hipGetLastError();
 }
