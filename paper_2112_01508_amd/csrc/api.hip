@@ -26,6 +26,7 @@
 
 #include "../../include/p3msr.h"
 #include "p3msr_internal.hpp"
+#include "gpoly.inc"
 
 using namespace p3m;
 
@@ -175,8 +176,12 @@ Geom make_geom(double box, double x_s, double r_cut, int nt, int ns) {
     g.kb = 1.0 / (2.0 * 1.77245385090551602730 * x_s * x_s * x_s);
     g.k1f = (float)g.k1;
     g.kbf = (float)g.kb;
-    g.c2f = (float)(1.0 / (4.0 * x_s * x_s));
-    g.c3f = (float)(1.0 / (8.0 * x_s * x_s * x_s));
+    g.c2 = 1.0 / (4.0 * x_s * x_s);
+    g.c3 = 1.0 / (8.0 * x_s * x_s * x_s);
+    g.c2f = (float)g.c2;
+    g.c3f = (float)g.c3;
+    static_assert(P3M_H64_DEGREE + 1 <= (int)(sizeof(g.h64) / sizeof(double)), "H64 table");
+    for (int k = 0; k <= P3M_H64_DEGREE; ++k) g.h64[k] = kH64[k];
     return g;
 }
 

@@ -19,19 +19,19 @@
 //
 // Precision: the separation r_ij, the squared distance and the cut-off
 // test are FP64 and bitwise the same as a plain FP64 evaluation, so both
-// paths accept exactly the same pairs.  The FP32 path then evaluates the
-// kernel shape in FP32 and accumulates in FP64: the forward force as
-// r^-3 + H(u^2) / (2 x_s)^3 (hardware rsqrt plus a degree-9 polynomial),
-// the adjoint with hardware rsqrt and exp2 and a degree-9 polynomial for
-// erfcx(u) + 2u/sqrt(pi).
+// paths accept exactly the same pairs.  The kernel shape uses the identity
+// g(u)/r^3 = r^-3 + H(u^2) / (2 x_s)^3 (g - 1 has only odd powers of u from
+// u^3 on): the FP32 path with hardware rsqrt and a degree-9 polynomial, the
+// FP64 path with an FP64 rsqrt and a degree-17 polynomial (and its
+// derivative for the adjoint).  The FP32 adjoint uses hardware rsqrt and
+// exp2 and a degree-9 polynomial for erfcx(u) + 2u/sqrt(pi).  Accumulation
+// is FP64 everywhere.
 #include "p3msr_internal.hpp"
 #include "gpoly.inc"
 
 namespace p3m {
 
 namespace {
-
-constexpr double kTwoOverSqrtPi = 1.12837916709551257390;
 
 __device__ inline unsigned long long ballot64(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
@@ -46,6 +46,25 @@ __device__ inline float h_poly(float v) {
     float h = kHpoly[P3M_HPOLY_DEGREE];
 #pragma unroll
     for (int k = P3M_HPOLY_DEGREE - 1; k >= 0; --k) h = fmaf(h, v, kHpoly[k]);
+    return h;
+}
+
+// FP64 H and, optionally, dH/dv from one Horner pass; the coefficients come
+// from the kernel arguments (SGPRs) so each step is one v_fma_f64.
+__device__ inline double h64(double v, const double *c) {
+    double h = c[P3M_H64_DEGREE];
+#pragma unroll
+    for (int k = P3M_H64_DEGREE - 1; k >= 0; --k) h = fma(h, v, c[k]);
+    return h;
+}
+__device__ inline double h64_d(double v, const double *c, double &dh) {
+    double h = c[P3M_H64_DEGREE], d = 0.0;
+#pragma unroll
+    for (int k = P3M_H64_DEGREE - 1; k >= 0; --k) {
+        d = fma(d, v, h);
+        h = fma(h, v, c[k]);
+    }
+    dh = d;
     return h;
 }
 
@@ -85,15 +104,17 @@ struct FwdF32 {
     }
 };
 
+// Forward, FP64 shape: the same identity g(u)/r^3 = r^-3 + H(t) / (2 x_s)^3
+// with an FP64 rsqrt and a degree-17 polynomial (error 1.5e-15 in g).
 template <bool UNIT>
 struct FwdF64 {
     double ax = 0.0, ay = 0.0, az = 0.0;
     __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
                                          const double4 &pj, int, const PairArgs &a) {
-        double r = sqrt(r2);
-        double u = r * a.g.k1;
-        double gu = erfc(u) + kTwoOverSqrtPi * u * exp(-u * u);
-        double s = UNIT ? gu / (r2 * r) : pj.w * gu / (r2 * r);
+        const double ri = rsqrt(r2);
+        const double h = h64(fma(r2, a.g.c2, -P3M_H64_T0), a.g.h64);
+        const double sh = fma(a.g.c3, h, ri * ri * ri);
+        const double s = UNIT ? sh : pj.w * sh;
         ax -= s * dx;
         ay -= s * dy;
         az -= s * dz;
@@ -101,7 +122,9 @@ struct FwdF64 {
 };
 
 // Adjoint: grad_k -= J(r_kj) (mu_j wa_k - mu_k wa_j), wa = w * [active],
-// J = phi I - c r r^T, phi = g / r^3, c = 3 g / r^5 + exp(-u^2) / (2 sqrt(pi) x_s^3 r^2).
+// J = phi I - c r r^T with phi = g / r^3 = r^-3 + c3 H(t) and
+// c = -(dphi/dr)/r = 3 g / r^5 + exp(-u^2) / (2 sqrt(pi) x_s^3 r^2)
+//   = 3 r^-5 - 2 c2 c3 H'(t)   (t = r^2 c2).
 struct BwdF64 {
     double ax = 0.0, ay = 0.0, az = 0.0;
     double wkx, wky, wkz, muk;
@@ -111,12 +134,12 @@ struct BwdF64 {
         double vx = pj.w * wkx - muk * wj.x;
         double vy = pj.w * wky - muk * wj.y;
         double vz = pj.w * wkz - muk * wj.z;
-        double r = sqrt(r2);
-        double u = r * a.g.k1;
-        double e = exp(-u * u);
-        double gu = erfc(u) + kTwoOverSqrtPi * u * e;
-        double phi = gu / (r2 * r);
-        double c = 3.0 * gu / (r2 * r2 * r) + e * a.g.kb / r2;
+        const double ri = rsqrt(r2);
+        const double ri2 = ri * ri;
+        double dh;
+        const double h = h64_d(fma(r2, a.g.c2, -P3M_H64_T0), a.g.h64, dh);
+        const double phi = fma(a.g.c3, h, ri2 * ri);
+        const double c = fma(3.0 * ri2 * ri2, ri, -2.0 * a.g.c2 * a.g.c3 * dh);
         double rv = dx * vx + dy * vy + dz * vz;
         ax -= phi * vx - c * rv * dx;
         ay -= phi * vy - c * rv * dy;

@@ -13,6 +13,11 @@ H is fitted in t on [0, 2.25^2] as a degree-9 polynomial in v = t - 3
 (near-minimax in the absolute error of g), so the forward shape needs one
 hardware rsqrt and one polynomial, with no exponential.
 
+(3) H64(v): the same H for the FP64 path, degree 17 in v = t - 2.5, from
+Chebyshev interpolation at 60 digits (mpmath) converted to the shifted
+monomial basis at that precision and rounded to double; its derivative
+(for the adjoint) comes from the same Horner pass.
+
 The kernel shape of eq. p3m_gravity (section 2.1.3) is
     g(u) = erfc(u) + (2/sqrt(pi)) u exp(-u^2),   u = r / (2 x_s),
 evaluated only for r < r_cut = 4.5 x_s, i.e. u in [0, 2.25).  Factor out the
@@ -102,6 +107,59 @@ def fit_h(degree=H_DEGREE, t0=H_T0, n_grid=8001, iters=400):
     return coef, float(np.max(err)), g_err
 
 
+H64_DEGREE = 17
+H64_T0 = 2.5
+
+
+def fit_h64(degree=H64_DEGREE, t0=H64_T0):
+    """Chebyshev interpolant of H on [0, 2.25^2] in 60-digit arithmetic,
+    returned as double coefficients of the polynomial in v = t - t0, with the
+    largest absolute error of g = 1 + t^1.5 H over a check grid."""
+    mp.mp.dps = 60
+    tmax = mp.mpf(U_MAX) ** 2
+    t0m = mp.mpf(t0)
+
+    def h_exact(t):
+        if t == 0:
+            return -4 / (3 * mp.sqrt(mp.pi))
+        u = mp.sqrt(t)
+        return (mp.erfc(u) + 2 * u / mp.sqrt(mp.pi) * mp.exp(-u * u) - 1) / u ** 3
+
+    n = degree + 1
+    nodes = [tmax / 2 + tmax / 2 * mp.cos(mp.pi * (k + mp.mpf(1) / 2) / n) for k in range(n)]
+    vals = [h_exact(x) for x in nodes]
+    cheb = []
+    for j in range(n):
+        acc = sum(vals[k] * mp.cos(mp.pi * j * (k + mp.mpf(1) / 2) / n) for k in range(n))
+        cheb.append(2 * acc / n)
+    cheb[0] /= 2
+    # Chebyshev basis in x = 2t/tmax - 1 -> monomials in x -> monomials in v
+    tp = [[mp.mpf(1)], [mp.mpf(0), mp.mpf(1)]]
+    for j in range(2, n):
+        a = [mp.mpf(0)] + [2 * x for x in tp[-1]]
+        b = tp[-2] + [mp.mpf(0)] * (len(a) - len(tp[-2]))
+        tp.append([a[i] - b[i] for i in range(len(a))])
+    px = [mp.mpf(0)] * n
+    for j in range(n):
+        for i, co in enumerate(tp[j]):
+            px[i] += cheb[j] * co
+    alpha, beta = 2 / tmax, 2 * t0m / tmax - 1
+    res = [mp.mpf(0)] * n
+    for i in range(n):
+        for k in range(i + 1):
+            res[k] += px[i] * mp.binomial(i, k) * alpha ** k * beta ** (i - k)
+    coef = [float(x) for x in res]
+    worst = mp.mpf(0)
+    for m in range(0, 1001):
+        t = tmax * m / 1000
+        v = float(t - t0m)
+        acc = coef[-1]
+        for a_ in coef[-2::-1]:
+            acc = acc * v + a_
+        worst = max(worst, abs((mp.mpf(acc) - h_exact(t)) * t ** mp.mpf(1.5)))
+    return coef, float(worst)
+
+
 def main():
     coef, e_fit, e32 = fit()
     out = sys.stdout
@@ -124,6 +182,16 @@ def main():
     out.write("static constexpr float kHpoly[P3M_HPOLY_DEGREE + 1] = {\n")
     for k, a in enumerate(hc):
         out.write("    %sf,%s\n" % (float(a).hex(), "  // v^%d" % k))
+    out.write("};\n")
+    h64, e64 = fit_h64()
+    out.write("// H(t) for the FP64 path: degree-%d polynomial in v = t - %.17g (Chebyshev\n"
+              "// interpolant at 60 digits); FP64 Horner error %.2e (absolute, in units of g).\n"
+              % (H64_DEGREE, H64_T0, e64))
+    out.write("#define P3M_H64_DEGREE %d\n" % H64_DEGREE)
+    out.write("#define P3M_H64_T0 %s\n" % float(H64_T0).hex())
+    out.write("static constexpr double kH64[P3M_H64_DEGREE + 1] = {\n")
+    for k, a in enumerate(h64):
+        out.write("    %s,%s\n" % (float(a).hex(), "  // v^%d" % k))
     out.write("};\n")
 
 

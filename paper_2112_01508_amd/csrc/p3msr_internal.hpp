@@ -44,6 +44,8 @@ struct Geom {
     float k1f, kbf;    // FP32 copies of k1 and kb
     float c2f;         // 1 / (4 x_s^2): t = u^2 = r^2 c2
     float c3f;         // 1 / (8 x_s^3): g(u) / r^3 = r^-3 + H(t) c3
+    double c2, c3;     // FP64 copies of c2f and c3f
+    double h64[18];    // FP64 H coefficients (kernel argument, so they sit in SGPRs)
 };
 
 struct Cluster {
