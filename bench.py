@@ -38,6 +38,10 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--ns", type=int, default=0, help="fixed subtiles per tile (0 = autotune)")
     ap.add_argument("--target", type=int, default=0, help="fixed work-item size (0 = autotune)")
+    ap.add_argument("--csize", type=int, default=0,
+                    help="fixed cluster size 8/16/32/64 (0 = autotune)")
+    ap.add_argument("--screen", type=int, default=-1,
+                    help="fixed per-supplier box screen 0/1 (-1 = autotune)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device copy (HBM counter calibration)")
     ap.add_argument("--no-fp64", action="store_true")
@@ -111,7 +115,7 @@ def adjoint_leg(torch, ctx, pos, mass, wl, steps, warmup):
     return out
 
 
-def batched_leg(torch, p3, name, steps, warmup):
+def batched_leg(torch, p3, name, steps, warmup, autotune=True):
     """All 8 nested rung subsets (rung >= k, k = 0..7) in one persistent launch."""
     from workloads import make_workload
     log("generating", name, "with rungs")
@@ -123,6 +127,11 @@ def batched_leg(torch, p3, name, steps, warmup):
     ctx = p3.Context(0)
     thr = list(range(8))
     out = torch.empty((8, wl.n, 3), dtype=torch.float64, device=dev)
+    if autotune:
+        for prec in ("fp32", "fp64"):
+            log("autotuning batched", prec)
+            ctx.autotune(pos, mass, None, box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut,
+                         precision=prec, level=1, out=out[0])
     res = {"workload": "%s: N=%d clustered, PM grid %d^3, k-NN density rungs 0-7, 8 nested "
                        "subsets rung>=k in one launch" % (name, wl.n, wl.n_pm),
            "subset_sizes": [int((wl.rung >= k).sum()) for k in thr]}
@@ -137,13 +146,14 @@ def batched_leg(torch, p3, name, steps, warmup):
         res[prec] = {"ms_per_call": wall * 1e3, "pair_kernel_ms": st["ms_pairs"],
                      "interactions": st["interactions"], "value": st["interactions"] / wall,
                      "achieved_tflops": 40 * st["interactions"] / (st["ms_pairs"] * 1e-3) / 1e12,
-                     "subtiles_per_dim": st["subtiles_per_dim"], "items": st["items"]}
+                     "subtiles_per_dim": st["subtiles_per_dim"], "items": st["items"],
+                     "cluster_size": st["cluster_size"], "screen": st["screen"]}
         log("batched", prec, "%.3f ms  interactions %d" % (wall * 1e3, st["interactions"]))
     ctx.close()
     return res
 
 
-def profiled_traffic(name, ns, target):
+def profiled_traffic(name, st):
     """HBM bytes per launch of the pair kernel from the committed rocprofv3
     counter runs (profiles/traffic.json), or None when the kernel sources or
     the decomposition differ from the ones the counters were taken with."""
@@ -156,8 +166,8 @@ def profiled_traffic(name, ns, target):
     for f in ("force.hip", "p3msr_internal.hpp", "gpoly.inc"):
         with open(os.path.join(ROOT, "paper_2112_01508_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if (h.hexdigest() != rec.get("kernel_sources_sha256") or rec.get("subtiles_per_dim") != ns
-            or rec.get("item_target") != target):
+    keys = ("subtiles_per_dim", "item_target", "cluster_size", "screen")
+    if h.hexdigest() != rec.get("kernel_sources_sha256") or any(rec.get(k) != st[k] for k in keys):
         return None
     return rec["traffic_bytes"]
 
@@ -197,10 +207,11 @@ def main():
     ctx = p3.Context(0)
 
     results = {}
-    if args.ns or args.target:
-        ctx.set_config(args.ns, args.target)
+    fixed = bool(args.ns or args.target or args.csize or args.screen >= 0)
+    if fixed:
+        ctx.set_config(args.ns, args.target, args.csize, args.screen)
     for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
-        if not args.no_autotune and not (args.ns or args.target):
+        if not args.no_autotune and not fixed:
             log("autotuning", prec)
             ctx.autotune(pos, mass, None, box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut,
                          precision=prec, level=2)
@@ -209,9 +220,10 @@ def main():
                                                        args.steps, args.warmup)
         results[prec] = dict(out=out.cpu().numpy(), wall=wall, stats=st, pairs_ms=pairs_ms,
                              build_ms=build_ms)
-        log(prec, "ms/step %.3f  pairs %.3f ms  build %.3f ms  interactions %d  ns %d target %d"
-            % (wall * 1e3, pairs_ms, build_ms, st["interactions"], st["subtiles_per_dim"],
-               st["item_target"]))
+        log(prec, "ms/step %.3f  pairs %.3f ms  build %.3f ms  interactions %d  ns %d target %d "
+            "csize %d screen %d steps %d" % (wall * 1e3, pairs_ms, build_ms, st["interactions"],
+                                             st["subtiles_per_dim"], st["item_target"],
+                                             st["cluster_size"], st["screen"], st["steps"]))
 
     r32 = results["fp32"]
     inter = r32["stats"]["interactions"]
@@ -238,12 +250,13 @@ def main():
                    "n": wl.n, "interactions_per_step": inter,
                    "tiles_per_dim": r32["stats"]["tiles_per_dim"],
                    "subtiles_per_dim": r32["stats"]["subtiles_per_dim"],
-                   "item_target": r32["stats"]["item_target"]},
+                   "item_target": r32["stats"]["item_target"],
+                   "cluster_size": r32["stats"]["cluster_size"],
+                   "screen": r32["stats"]["screen"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": profiled_traffic("k_pairs_fwd_fp32_%s" % args.workload,
-                                                 r32["stats"]["subtiles_per_dim"],
-                                                 r32["stats"]["item_target"])},
+                                                 r32["stats"])},
         "pair_kernel_ms": r32["pairs_ms"],
         "build_ms": r32["build_ms"],
     }
@@ -252,13 +265,16 @@ def main():
         a64 = FLOPS_PER_INTERACTION * r64["stats"]["interactions"] / (r64["pairs_ms"] * 1e-3) / 1e12
         line["fp64"] = {"value": r64["stats"]["interactions"] / r64["wall"],
                         "ms_per_step": r64["wall"] * 1e3, "pair_kernel_ms": r64["pairs_ms"],
-                        "achieved_tflops": a64, "frac_fp64_peak": a64 / PEAK_FP64_TFLOPS}
+                        "achieved_tflops": a64, "frac_fp64_peak": a64 / PEAK_FP64_TFLOPS,
+                        "layout": {k: r64["stats"][k] for k in
+                                   ("subtiles_per_dim", "item_target", "cluster_size", "screen")}}
 
     legs = [l for l in args.legs.split(",") if l]
     if "adjoint" in legs:
         line["adjoint"] = adjoint_leg(torch, ctx, pos, mass, wl, args.steps, args.warmup)
     if "batched" in legs:
-        line["batched"] = batched_leg(torch, p3, args.batched_workload, args.steps, args.warmup)
+        line["batched"] = batched_leg(torch, p3, args.batched_workload, args.steps, args.warmup,
+                                      autotune=not args.no_autotune)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -64,8 +64,8 @@ typedef struct {
     int64_t n;               /* particles */
     int64_t receivers;       /* receiver rows summed over subsets */
     int64_t interactions;    /* accepted ordered pairs (i receiver, j != i, r < r_cut) */
-    int64_t candidates;      /* (receiver lane, supplier) pairs tested after culling */
-    int64_t clusters;        /* receiver groups of <= 64 */
+    int64_t candidates;      /* (receiver, supplier) pairs handed to the pair loop */
+    int64_t clusters;        /* receiver groups of <= cluster_size */
     int64_t items;           /* work items of the persistent launch */
     int64_t steps;           /* wavefront steps over suppliers (64 lane-slots each) */
     int32_t tiles_per_dim;   /* tiles per dimension (>= 3) */
@@ -75,7 +75,10 @@ typedef struct {
     float ms_build;          /* sort + compaction + planning, when timing is on, else -1 */
     float ms_pairs;          /* the persistent pair-kernel launch, when timing is on, else -1 */
     float ms_total;          /* whole call (GPU side), when timing is on, else -1 */
+    int32_t cluster_size;    /* receivers per cluster: 8, 16, 32 or 64 */
+    int32_t screen;          /* 1: suppliers screened against each cluster's box */
     int32_t pad;
+    int64_t screened;        /* supplier records tested by the screen (0 without it) */
 } p3m_sr_stats;
 
 /* Create a context on HIP device `device`.  *h receives the handle. */
@@ -136,8 +139,9 @@ int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
  * Measure-and-keep autotuning (the paper's automatic subtile refinement,
  * section 2.1.3 "Subtiles": try a finer subdivision, time it, keep it if
  * faster).  Times p3m_sr_force on these inputs for candidate subtile counts
- * per dimension (and, at level >= 2, work-item sizes) and stores the fastest
- * in the handle; later calls on the same particle count and geometry use it.
+ * per dimension crossed with cluster layouts (cluster size, screening) and,
+ * at level >= 2, work-item sizes around the winner; stores the fastest in the
+ * handle; later calls on the same particle count and geometry use it.
  * acc_scratch is an n x 3 FP64 device buffer the trials write into.
  * level: 1 = subtiles only, 2 = subtiles and item size.  Synchronises.
  */
@@ -146,11 +150,26 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass,
                     int precision, int level, double *acc_scratch, void *stream);
 
 /*
- * Fix the decomposition instead of autotuning: subtiles per tile per
- * dimension (1..16, 0 = automatic) and work-item target size in supplier
- * candidates (64..1<<20, 0 = automatic).  EINVAL outside those ranges.
+ * Fix the decomposition instead of autotuning (0 / -1 = automatic):
+ *   subtiles_per_dim  subtiles per tile per dimension, 1..16 (section 2.1.3
+ *                     "Subtiles");
+ *   item_target       work-item target size in supplier candidates, 64..1<<20;
+ *   cluster_size      receivers per cluster, 8, 16, 32 or 64.  Particles are
+ *                     kept in tile -> subtile order (section 2.1.3) and, inside
+ *                     each dense subtile, in the Morton order of an 8^3 grid of
+ *                     sub-cells, so a cluster of consecutive receivers is
+ *                     spatially compact; a wavefront carries 64 / cluster_size
+ *                     copies of a cluster that walk different suppliers;
+ *   screen            1: forward calls test each supplier of the surviving
+ *                     subtiles against the cluster's bounding box before the
+ *                     pair loop (the subtile-pair culling of section 2.1.3
+ *                     carried down to single suppliers); 0: no screening;
+ *                     -1: automatic.  The adjoint never screens.
+ * EINVAL outside those ranges.  Results do not depend on these settings
+ * beyond FP64 summation order.
  */
-int p3m_sr_set_config(p3m_sr_handle h, int subtiles_per_dim, int item_target);
+int p3m_sr_set_config(p3m_sr_handle h, int subtiles_per_dim, int item_target,
+                      int cluster_size, int screen);
 
 /*
  * Record HIP events on the call's stream around the build phase and the

@@ -47,7 +47,9 @@ class Stats(ctypes.Structure):
                 ("tiles_per_dim", ctypes.c_int32), ("subtiles_per_dim", ctypes.c_int32),
                 ("item_target", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("ms_build", ctypes.c_float), ("ms_pairs", ctypes.c_float),
-                ("ms_total", ctypes.c_float), ("pad", ctypes.c_int32)]
+                ("ms_total", ctypes.c_float), ("cluster_size", ctypes.c_int32),
+                ("screen", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("screened", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -69,7 +71,7 @@ EXPORTS = {
     "p3m_sr_force_backward": ([_P, _P, _P, _P, _I64, _D, _D, _D, _I, _P, _P, _P], _I),
     "p3m_sr_force_batched": ([_P, _P, _P, _P, _I64, _I, _P, _D, _D, _D, _I, _P, _P], _I),
     "p3m_sr_autotune": ([_P, _P, _P, _P, _I64, _D, _D, _D, _I, _I, _P, _P], _I),
-    "p3m_sr_set_config": ([_P, _I, _I], _I),
+    "p3m_sr_set_config": ([_P, _I, _I, _I, _I], _I),
     "p3m_sr_set_timing": ([_P, _I], _I),
     "p3m_sr_get_stats": ([_P, ctypes.POINTER(Stats)], _I),
 }
@@ -167,13 +169,19 @@ class Context:
     def _p(t):
         return None if t is None else ctypes.c_void_p(t.data_ptr())
 
+    def _out(self, out, n):
+        """An n x 3 FP64 output on this device: the caller's (checked) or new."""
+        if out is None:
+            return torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        _dev_ptr(out, torch.float64, (3,), "out", self.device)
+        if out.shape[0] != n:
+            raise ValueError("out must have %d rows (got %d)" % (n, out.shape[0]))
+        return out
+
     # -- entry points ------------------------------------------------------------
     def force(self, pos, mass=None, active=None, *, box, x_s, r_cut, precision="fp32", out=None):
         pos, mass, active, n = self._inputs(pos, mass, active, "active")
-        if out is None:
-            out = torch.empty((n, 3), dtype=torch.float64, device=self.device)
-        else:
-            _dev_ptr(out, torch.float64, (3,), "out", self.device)
+        out = self._out(out, n)
         _check(self._lib.p3m_sr_force(self._h, self._p(pos), self._p(mass), self._p(active), n,
                                       float(box), float(x_s), float(r_cut), _prec(precision),
                                       self._p(out), _stream_ptr(self.device)))
@@ -209,16 +217,20 @@ class Context:
         return out
 
     def autotune(self, pos, mass=None, active=None, *, box, x_s, r_cut, precision="fp32",
-                 level=1):
+                 level=1, out=None):
+        """Measure-and-keep tuning of the decomposition for these inputs;
+        `out` (n x 3 FP64 on the device) is optional scratch for the trials."""
         pos, mass, active, n = self._inputs(pos, mass, active, "active")
-        scratch = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        scratch = self._out(out, n)
         _check(self._lib.p3m_sr_autotune(self._h, self._p(pos), self._p(mass), self._p(active),
                                          n, float(box), float(x_s), float(r_cut),
                                          _prec(precision), int(level), self._p(scratch),
                                          _stream_ptr(self.device)))
 
-    def set_config(self, subtiles_per_dim=0, item_target=0):
-        _check(self._lib.p3m_sr_set_config(self._h, int(subtiles_per_dim), int(item_target)))
+    def set_config(self, subtiles_per_dim=0, item_target=0, cluster_size=0, screen=-1):
+        """Fix the decomposition (0 / -1 = automatic); see p3m_sr_set_config."""
+        _check(self._lib.p3m_sr_set_config(self._h, int(subtiles_per_dim), int(item_target),
+                                           int(cluster_size), int(screen)))
 
     def set_timing(self, enable=True):
         _check(self._lib.p3m_sr_set_timing(self._h, 1 if enable else 0))

@@ -7,7 +7,8 @@
 //   scatter   particles into tile -> subtile order (section 2.1.3, memory
 //             reorder of "Other optimisations")
 //   flags     receiver flags per subset, scan, compaction
-//   clusters  <= 64 receivers of one tile per cluster
+//   fine      inside dense subtiles, particles reordered by fine sub-cell
+//   clusters  <= csize (8..64) consecutive receivers of one tile per cluster
 //   items     clusters split over their 27 neighbour tiles (work estimate)
 //   [read back the cluster and item totals: the only host synchronisation]
 //   pairs     one persistent launch over all items, per-item partial sums
@@ -68,6 +69,8 @@ struct TuneKey {
 struct TuneVal {
     int ns;
     int target;
+    int csize;
+    int screen;
 };
 
 }  // namespace
@@ -75,10 +78,10 @@ struct TuneVal {
 struct p3m_sr_context {
     int device = 0;
     int n_cu = 0;
-    int blocks_per_cu[4] = {0, 0, 0, 0};
-    DevBuf key, rank, cells, sp, perm, sel, flags, actpos, ncl, clusters, itemcnt, items, bsum,
-        counters, wa, scal, part, rp, rperm, rwa;
-    int cfg_ns = 0, cfg_target = 0;
+    int blocks_per_cu[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    DevBuf key, rank, cells, sp, perm, sel, sp2, perm2, sel2, flags, actpos, ncl, clusters,
+        itemcnt, items, bsum, counters, wa, scal, part, rp, rperm, rwa;
+    int cfg_ns = 0, cfg_target = 0, cfg_csize = 0, cfg_screen = -1;
     std::map<TuneKey, TuneVal> tuned;
     p3m_sr_stats stats{};
     hipStream_t last_stream = nullptr;
@@ -201,7 +204,15 @@ struct Request {
     hipStream_t stream;
     int force_ns;            // >0: override subtiles (autotune trials)
     int force_target;
+    int force_csize;         // >0: override the cluster size
+    int force_screen;        // 0: not forced, 1: screening off, 2: on
 };
+
+// Default layout before tuning: full 64-receiver clusters without screening.
+constexpr int kDefaultCsize = 64;
+constexpr int kDefaultScreen = 0;
+
+bool valid_csize(int c) { return c == 8 || c == 16 || c == 32 || c == 64; }
 
 int run(p3m_sr_context *h, const Request &r) {
     hipStream_t s = r.stream;
@@ -211,19 +222,28 @@ int run(p3m_sr_context *h, const Request &r) {
     const int nt = tiles_per_dim(r.box, r.r_cut);
 
     // decomposition: explicit override > user config > autotuned > default
-    int ns = 0, target = 0;
+    int ns = 0, target = 0, csize = 0, screen = -1;
     const int mode = (r.backward ? 2 : 0) + (fp32 ? 0 : 1);
     auto it = h->tuned.find(TuneKey{r.n, nt, r.precision, r.backward ? 1 : 0});
     if (it != h->tuned.end()) {
         ns = it->second.ns;
         target = it->second.target;
+        csize = it->second.csize;
+        screen = it->second.screen;
     }
     if (h->cfg_ns > 0) ns = h->cfg_ns;
     if (h->cfg_target > 0) target = h->cfg_target;
+    if (h->cfg_csize > 0) csize = h->cfg_csize;
+    if (h->cfg_screen >= 0) screen = h->cfg_screen;
     if (r.force_ns > 0) ns = r.force_ns;
     if (r.force_target > 0) target = r.force_target;
+    if (r.force_csize > 0) csize = r.force_csize;
+    if (r.force_screen > 0) screen = r.force_screen - 1;
     ns = pick_subtiles(nt, r.n, ns);
     if (target <= 0) target = 1024;
+    if (!valid_csize(csize)) csize = kDefaultCsize;
+    if (screen < 0) screen = kDefaultScreen;
+    if (r.backward) screen = 0;   // the adjoint streams suppliers directly
     const Geom g = make_geom(r.box, r.x_s, r.r_cut, nt, ns);
     const size_t ncells = (size_t)g.nt3 * g.ns3;
 
@@ -233,6 +253,8 @@ int run(p3m_sr_context *h, const Request &r) {
     st.subtiles_per_dim = ns;
     st.item_target = target;
     st.precision = r.precision;
+    st.cluster_size = csize;
+    st.screen = screen;
     st.ms_build = st.ms_pairs = st.ms_total = -1.0f;
     h->last_stream = s;
     h->timed_last = false;
@@ -251,7 +273,7 @@ int run(p3m_sr_context *h, const Request &r) {
     // ---- workspace ----
     const size_t nflags = (size_t)n * n_sub;
     const size_t ncl_len = (size_t)n_sub * g.nt3;
-    const size_t cl_bound = ncl_len + (nflags + kWave - 1) / kWave;
+    const size_t cl_bound = ncl_len + (nflags + csize - 1) / csize;
     const size_t scan_max = std::max(std::max(ncells, nflags), std::max(ncl_len, cl_bound));
     int rc;
     if ((rc = ensure(h, h->key, sizeof(int) * n, s))) return rc;
@@ -260,6 +282,9 @@ int run(p3m_sr_context *h, const Request &r) {
     if ((rc = ensure(h, h->sp, sizeof(double4) * ((size_t)n + kSupplierPad), s))) return rc;
     if ((rc = ensure(h, h->perm, sizeof(int) * n, s))) return rc;
     if ((rc = ensure(h, h->sel, (size_t)n, s))) return rc;
+    if ((rc = ensure(h, h->sp2, sizeof(double4) * ((size_t)n + kSupplierPad), s))) return rc;
+    if ((rc = ensure(h, h->perm2, sizeof(int) * n, s))) return rc;
+    if ((rc = ensure(h, h->sel2, (size_t)n, s))) return rc;
     if ((rc = ensure(h, h->flags, sizeof(int) * (nflags + 1), s))) return rc;
     if ((rc = ensure(h, h->actpos, sizeof(int) * (nflags + 1), s))) return rc;
     if ((rc = ensure(h, h->ncl, sizeof(int) * (ncl_len + 1), s))) return rc;
@@ -291,6 +316,16 @@ int run(p3m_sr_context *h, const Request &r) {
     const uint8_t *sel_src = (r.sel_kind == SEL_ALL && !r.backward) ? nullptr : r.sel;
     P3M_HIP(launch_scatter(r.pos, r.mass, sel_src, n, g, key, rank, cells, fp32 ? 1 : 0, sp, perm,
                            sel_s, s));
+    // fine order inside dense subtiles (key/rank are free again as scratch)
+    {
+        double4 *sp_f = (double4 *)h->sp2.p;
+        int *perm_f = (int *)h->perm2.p;
+        uint8_t *sel_f = (uint8_t *)h->sel2.p;
+        P3M_HIP(launch_fine_order(sp, perm, sel_s, cells, g, key, rank, sp_f, perm_f, sel_f, s));
+        sp = sp_f;
+        perm = perm_f;
+        sel_s = sel_f;
+    }
     P3M_HIP(launch_fill_i32((int *)(sp + n), 0, kSupplierPad * sizeof(double4) / sizeof(int), s));
 
     // ---- receivers -> clusters -> items ----
@@ -300,9 +335,9 @@ int run(p3m_sr_context *h, const Request &r) {
     P3M_HIP(launch_flags(sel_s, n, n_sub, kind, r.thr, flags, s));
     P3M_HIP(launch_scan(flags, flags, nflags, bsum, s));
     P3M_HIP(launch_compact(flags, n, n_sub, actpos, s));
-    P3M_HIP(launch_cluster_count(cells, flags, n, n_sub, g, ncl, s));
+    P3M_HIP(launch_cluster_count(cells, flags, n, n_sub, g, csize, ncl, s));
     P3M_HIP(launch_scan(ncl, ncl, ncl_len, bsum, s));
-    P3M_HIP(launch_cluster_write(cells, flags, ncl, n, n_sub, g, clusters, s));
+    P3M_HIP(launch_cluster_write(cells, flags, ncl, n, n_sub, g, csize, clusters, s));
     P3M_HIP(launch_item_count(clusters, ncl + ncl_len, (int)cl_bound, cells, g, target, itemcnt,
                               s));
     P3M_HIP(launch_scan(itemcnt, itemcnt, cl_bound, bsum, s));
@@ -319,7 +354,7 @@ int run(p3m_sr_context *h, const Request &r) {
 
     if ((rc = ensure(h, h->items, sizeof(Item) * (size_t)(n_items > 0 ? n_items : 1), s)))
         return rc;
-    if ((rc = ensure(h, h->part, sizeof(double) * 3 * kWave * (size_t)(n_items > 0 ? n_items : 1),
+    if ((rc = ensure(h, h->part, sizeof(double) * 3 * csize * (size_t)(n_items > 0 ? n_items : 1),
                      s)))
         return rc;
     Item *items = (Item *)h->items.p;
@@ -347,20 +382,21 @@ int run(p3m_sr_context *h, const Request &r) {
     a.counters = counters;
     a.n_items = n_items;
     a.unit_mass = r.mass ? 0 : 1;
+    a.csize = csize;
     a.g = g;
-    if (h->blocks_per_cu[mode] == 0) h->blocks_per_cu[mode] = pairs_blocks_per_cu(mode);
+    int &bpc = h->blocks_per_cu[mode][screen];
+    if (bpc == 0) bpc = pairs_blocks_per_cu(mode, screen);
     long long waves_wanted = (n_items + 0ll);
-    long long grid = std::min<long long>((waves_wanted + 3) / 4,
-                                         (long long)h->n_cu * h->blocks_per_cu[mode]);
+    long long grid = std::min<long long>((waves_wanted + 3) / 4, (long long)h->n_cu * bpc);
     if (grid < 1) grid = 1;
     if (h->timing) P3M_HIP(hipEventRecord(h->ev[1], s));
-    P3M_HIP(launch_pairs(mode, a, (int)grid, s));
+    P3M_HIP(launch_pairs(mode, screen, a, (int)grid, s));
     if (h->timing) {
         P3M_HIP(hipEventRecord(h->ev[2], s));
         h->timed_last = true;
     }
     P3M_HIP(launch_reduce_items(clusters, n_clusters, itemcnt, (const int *)h->rperm.p,
-                                (double *)h->part.p, r.out, 3ll * n, s));
+                                (double *)h->part.p, csize, r.out, 3ll * n, s));
     if (h->timing) P3M_HIP(hipEventRecord(h->ev[3], s));
     h->stats = st;
     return P3M_OK;
@@ -408,10 +444,11 @@ int p3m_sr_destroy(p3m_sr_handle h) {
     if (!h) return P3M_OK;
     (void)hipSetDevice(h->device);
     (void)hipDeviceSynchronize();
-    DevBuf *bufs[] = {&h->key,      &h->rank,    &h->cells,   &h->sp,    &h->perm,
-                      &h->sel,      &h->flags,   &h->actpos,  &h->ncl,   &h->clusters,
-                      &h->itemcnt,  &h->items,   &h->bsum,    &h->counters, &h->wa,
-                      &h->scal,     &h->part,    &h->rp,      &h->rperm, &h->rwa};
+    DevBuf *bufs[] = {&h->key,     &h->rank,     &h->cells,  &h->sp,    &h->perm,
+                      &h->sel,     &h->sp2,      &h->perm2,  &h->sel2,  &h->flags,
+                      &h->actpos,  &h->ncl,      &h->clusters, &h->itemcnt, &h->items,
+                      &h->bsum,    &h->counters, &h->wa,     &h->scal,  &h->part,
+                      &h->rp,      &h->rperm,    &h->rwa};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : h->ev)
@@ -515,15 +552,21 @@ int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
     return run(h, r);
 }
 
-int p3m_sr_set_config(p3m_sr_handle h, int subtiles_per_dim, int item_target) {
+int p3m_sr_set_config(p3m_sr_handle h, int subtiles_per_dim, int item_target, int cluster_size,
+                      int screen) {
     int rc;
-    if ((rc = check_handle(h))) return rc;
     if (subtiles_per_dim < 0 || subtiles_per_dim > 16)
         return set_error(P3M_EINVAL, "subtiles_per_dim must be in 0..16");
     if (item_target != 0 && (item_target < 64 || item_target > (1 << 20)))
         return set_error(P3M_EINVAL, "item_target must be 0 or in 64..2^20");
+    if (cluster_size != 0 && !valid_csize(cluster_size))
+        return set_error(P3M_EINVAL, "cluster_size must be 0, 8, 16, 32 or 64");
+    if (screen < -1 || screen > 1) return set_error(P3M_EINVAL, "screen must be -1, 0 or 1");
+    if ((rc = check_handle(h))) return rc;
     h->cfg_ns = subtiles_per_dim;
     h->cfg_target = item_target;
+    h->cfg_csize = cluster_size;
+    h->cfg_screen = screen;
     return P3M_OK;
 }
 
@@ -554,36 +597,49 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     r.out = acc_scratch;
     r.stream = s;
     const int nt = tiles_per_dim(box, r_cut);
+    // level 1: subtiles x layout (cluster size, screening) at the default
+    // item size; level 2 also sweeps the item size around the level-1 winner
     std::vector<int> ns_list = {1, 2, 3, 4, 5, 6};
-    std::vector<int> tg_list = {1024};
-    if (level >= 2) tg_list = {256, 512, 1024, 2048, 4096};
+    const std::pair<int, int> layouts[] = {{64, 0}, {64, 1}, {32, 1}, {16, 1}, {8, 1}, {16, 0},
+                                           {8, 0}};
     hipEvent_t e0, e1;
     P3M_HIP(hipEventCreate(&e0));
     P3M_HIP(hipEventCreate(&e1));
     float best = 1e30f;
-    TuneVal best_v{pick_subtiles(nt, n, 0), 1024};
+    TuneVal best_v{pick_subtiles(nt, n, 0), 1024, kDefaultCsize, kDefaultScreen};
+    auto trial = [&](const TuneVal &v) -> int {
+        r.force_ns = v.ns;
+        r.force_target = v.target;
+        r.force_csize = v.csize;
+        r.force_screen = v.screen + 1;
+        int rc2;
+        if ((rc2 = run(h, r))) return rc2;   // warm-up (also grows the workspace)
+        float tot = 0;
+        const int reps = 3;
+        for (int k = 0; k < reps; ++k) {
+            P3M_HIP(hipEventRecord(e0, s));
+            if ((rc2 = run(h, r))) return rc2;
+            P3M_HIP(hipEventRecord(e1, s));
+            P3M_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            P3M_HIP(hipEventElapsedTime(&ms, e0, e1));
+            tot += ms;
+        }
+        if (tot < best) {
+            best = tot;
+            best_v = v;
+        }
+        return P3M_OK;
+    };
     for (int ns : ns_list) {
         if (pick_subtiles(nt, n, ns) != ns) continue;
-        for (int tg : tg_list) {
-            r.force_ns = ns;
-            r.force_target = tg;
-            if ((rc = run(h, r))) return rc;   // warm-up (also grows the workspace)
-            float tot = 0;
-            const int reps = 3;
-            for (int k = 0; k < reps; ++k) {
-                P3M_HIP(hipEventRecord(e0, s));
-                if ((rc = run(h, r))) return rc;
-                P3M_HIP(hipEventRecord(e1, s));
-                P3M_HIP(hipEventSynchronize(e1));
-                float ms = 0;
-                P3M_HIP(hipEventElapsedTime(&ms, e0, e1));
-                tot += ms;
-            }
-            if (tot < best) {
-                best = tot;
-                best_v = TuneVal{ns, tg};
-            }
-        }
+        for (const auto &l : layouts)
+            if ((rc = trial(TuneVal{ns, 1024, l.first, l.second}))) return rc;
+    }
+    if (level >= 2) {
+        const TuneVal base = best_v;
+        for (int tg : {256, 512, 2048, 4096, 8192})
+            if ((rc = trial(TuneVal{base.ns, tg, base.csize, base.screen}))) return rc;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -612,6 +668,7 @@ int p3m_sr_get_stats(p3m_sr_handle h, p3m_sr_stats *out) {
         st.interactions = (int64_t)c.interactions;
         st.candidates = (int64_t)c.candidates;
         st.steps = (int64_t)c.steps;
+        st.screened = (int64_t)c.screened;
     }
     if (h->timed_last) {
         float a = 0, b = 0, t = 0;

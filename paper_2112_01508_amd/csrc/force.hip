@@ -88,6 +88,7 @@ __device__ inline double dist2(double dx, double dy, double dz) {
 // hardware rsqrt and one polynomial, no exponential).  UNIT: every mass is 1.
 template <bool UNIT>
 struct FwdF32 {
+    static constexpr bool kNeedW = !UNIT;
     double ax = 0.0, ay = 0.0, az = 0.0;
     __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
                                          const double4 &pj, int, const PairArgs &a) {
@@ -108,6 +109,7 @@ struct FwdF32 {
 // with an FP64 rsqrt and a degree-17 polynomial (error 1.5e-15 in g).
 template <bool UNIT>
 struct FwdF64 {
+    static constexpr bool kNeedW = !UNIT;
     double ax = 0.0, ay = 0.0, az = 0.0;
     __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
                                          const double4 &pj, int, const PairArgs &a) {
@@ -126,6 +128,7 @@ struct FwdF64 {
 // c = -(dphi/dr)/r = 3 g / r^5 + exp(-u^2) / (2 sqrt(pi) x_s^3 r^2)
 //   = 3 r^-5 - 2 c2 c3 H'(t)   (t = r^2 c2).
 struct BwdF64 {
+    static constexpr bool kNeedW = true;
     double ax = 0.0, ay = 0.0, az = 0.0;
     double wkx, wky, wkz, muk;
     __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
@@ -148,6 +151,7 @@ struct BwdF64 {
 };
 
 struct BwdF32 {
+    static constexpr bool kNeedW = true;
     double ax = 0.0, ay = 0.0, az = 0.0;
     float wkx, wky, wkz, muk;
     __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
@@ -188,14 +192,13 @@ __device__ __forceinline__ double4 load_uniform(const double4 *base, int j) {
     return make_double4(q[0], q[1], q[2], q[3]);
 }
 
-// A full cluster (G = 1): every lane tests the same supplier, read through
-// the scalar unit.  Two record sets alternate so that the load of the next
-// supplier is in flight while the current one is evaluated.
+// One receiver lane against one supplier: the separation (with the tile's
+// periodic image), the squared distance and the strict cut-off test in FP64,
+// then the pair body.
 template <bool SHIFT, class Body>
 __device__ __forceinline__ void test_pair(Body &body, double xi, double yi, double zi,
                                           const double4 &pj, int j, bool valid, double shx,
-                                          double shy, double shz, const PairArgs &a,
-                                          int &n_wave) {
+                                          double shy, double shz, const PairArgs &a, int &n_ok) {
     double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
     if (SHIFT) {
         dx -= shx;
@@ -204,15 +207,18 @@ __device__ __forceinline__ void test_pair(Body &body, double xi, double yi, doub
     }
     const double r2 = dist2(dx, dy, dz);
     if (valid & (r2 < a.g.rc2) & (r2 > 0.0)) {
-        ++n_wave;   // per-lane count of accepted pairs
+        ++n_ok;   // per-lane count of accepted pairs
         body.pair(dx, dy, dz, r2, pj, j, a);
     }
 }
 
+// A full cluster (G = 1): every lane tests the same supplier, read through
+// the scalar unit.  Two record sets alternate so that the load of the next
+// supplier is in flight while the current one is evaluated.
 template <bool SHIFT, class Body>
 __device__ __forceinline__ void range_loop_full(Body &body, double xi, double yi, double zi,
                                                 int j0, int j1, double shx, double shy,
-                                                double shz, const PairArgs &a, int &n_wave) {
+                                                double shz, const PairArgs &a, int &n_ok) {
     j0 = __builtin_amdgcn_readfirstlane(j0);
     j1 = __builtin_amdgcn_readfirstlane(j1);
     // the sorted array is padded by kSupplierPad records: the look-ahead
@@ -220,9 +226,9 @@ __device__ __forceinline__ void range_loop_full(Body &body, double xi, double yi
     double4 A = load_uniform(a.sp, j0);
     for (int j = j0; j < j1; j += 2) {
         const double4 B = load_uniform(a.sp, j + 1);
-        test_pair<SHIFT>(body, xi, yi, zi, A, j, true, shx, shy, shz, a, n_wave);
+        test_pair<SHIFT>(body, xi, yi, zi, A, j, true, shx, shy, shz, a, n_ok);
         A = load_uniform(a.sp, j + 2);
-        test_pair<SHIFT>(body, xi, yi, zi, B, j + 1, j + 1 < j1, shx, shy, shz, a, n_wave);
+        test_pair<SHIFT>(body, xi, yi, zi, B, j + 1, j + 1 < j1, shx, shy, shz, a, n_ok);
     }
 }
 
@@ -232,10 +238,9 @@ __device__ __forceinline__ void range_loop_full(Body &body, double xi, double yi
 template <bool SHIFT, class Body>
 __device__ __forceinline__ void range_loop(Body &body, double xi, double yi, double zi, int j0,
                                            int j1, int grp, int G, double shx, double shy,
-                                           double shz, const PairArgs &a, int &n_acc,
-                                           int &n_wave) {
+                                           double shz, const PairArgs &a, int &n_ok) {
     if (G == 1) {
-        range_loop_full<SHIFT>(body, xi, yi, zi, j0, j1, shx, shy, shz, a, n_wave);
+        range_loop_full<SHIFT>(body, xi, yi, zi, j0, j1, shx, shy, shz, a, n_ok);
         return;
     }
     const double rc2 = a.g.rc2;
@@ -258,23 +263,201 @@ __device__ __forceinline__ void range_loop(Body &body, double xi, double yi, dou
         }
         const double r2 = dist2(dx, dy, dz);
         if (ok & (r2 < rc2) & (r2 > 0.0)) {
-            ++n_acc;   // per-lane count of accepted pairs
+            ++n_ok;   // per-lane count of accepted pairs
             body.pair(dx, dy, dz, r2, pj, j0 + k + grp, a);
         }
     }
 }
 
-// One work item: the cluster's receivers against the suppliers of its
-// neighbour-tile / subtile range, with subtile culling by bounding box.
+// Screened suppliers in LDS: group g takes list entries g, g + G, ...; all
+// lanes of a group read the same record (an LDS broadcast).  `p` is this
+// lane's view of the list (list + min(grp, G)).  The G records after the
+// last entry hold far-away points, so a step needs no bounds test; two
+// record sets alternate so that the next read is in flight while the
+// current record is evaluated.  G is a compile-time constant (64 / csize),
+// so the reads use immediate offsets.
+template <bool NEED_W>
+__device__ __forceinline__ double4 list_read(const double4 *p) {
+    if constexpr (NEED_W) {
+        return *p;
+    } else {
+        const double2 xy = *reinterpret_cast<const double2 *>(p);
+        return make_double4(xy.x, xy.y, p->z, 0.0);
+    }
+}
+
+template <bool NEED_W>
+__device__ __forceinline__ void list_write(double4 *p, const double4 &v) {
+    if constexpr (NEED_W) {
+        *p = v;
+    } else {
+        *reinterpret_cast<double2 *>(p) = make_double2(v.x, v.y);
+        p->z = v.z;
+    }
+}
+
+template <int G, bool SHIFT, class Body>
+__device__ __forceinline__ void list_loop(Body &body, const double4 *p, int n_list, double xi,
+                                          double yi, double zi, double shx, double shy,
+                                          double shz, const PairArgs &a, int &n_ok) {
+    constexpr bool W = Body::kNeedW;
+    double4 A = list_read<W>(p);
+    for (int k = 0; k < n_list; k += 2 * G) {
+        const double4 *q = p + k;
+        const double4 B = list_read<W>(q + G);
+        test_pair<SHIFT>(body, xi, yi, zi, A, 0, true, shx, shy, shz, a, n_ok);
+        A = list_read<W>(q + 2 * G);
+        if (k + G < n_list) test_pair<SHIFT>(body, xi, yi, zi, B, 0, true, shx, shy, shz, a, n_ok);
+    }
+}
+
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Per-wave statistics, kept in registers until the wave runs out of work: a
+// contended atomic per item would also delay the next item's loads (vector
+// memory operations retire in order).
+struct WaveCounts {
+    int n_ok = 0;                       // per lane: accepted pairs
+    unsigned long long cand = 0;        // receiver x supplier pairs handed to the pair loop
+    unsigned long long steps = 0;       // wave steps of the pair loop
+    unsigned long long screened = 0;    // supplier records tested against the cluster box
+};
+
+// Shared state of one work item for the visitors below.
+struct ItemCtx {
+    double xi, yi, zi;     // this lane's receiver (far away for idle lanes)
+    const double *lo, *hi; // the cluster's bounding box
+    int lane, grp, G, cnt;
+    int rgrp;              // screened loop: min(grp, G)
+};
+
+// Direct visitor: every supplier of every surviving subtile run goes to the
+// pair loop.
 template <class Body>
-__device__ __forceinline__ void walk_item(Body &body, const Item &item, const Cluster &cl,
-                                          double xi, double yi, double zi, const double *lo,
-                                          const double *hi, const PairArgs &a, int lane,
-                                          int grp, int G, int &n_acc, int &n_wave,
-                                          unsigned long long &n_cand,
-                                          unsigned long long &n_steps) {
+struct DirectVisit {
+    Body &body;
+    const ItemCtx &c;
+    const PairArgs &a;
+    WaveCounts &wc;
+    bool shifted = false;
+    double shx = 0.0, shy = 0.0, shz = 0.0;
+    __device__ __forceinline__ void tile(int, bool sh, double x, double y, double z) {
+        shifted = sh;
+        shx = x;
+        shy = y;
+        shz = z;
+    }
+    __device__ __forceinline__ void run(int j0, int j1) {
+        wc.cand += (unsigned long long)(j1 - j0) * (unsigned long long)c.cnt;
+        wc.steps += (unsigned long long)((j1 - j0 + c.G - 1) / c.G);
+        if (shifted)
+            range_loop<true>(body, c.xi, c.yi, c.zi, j0, j1, c.grp, c.G, shx, shy, shz, a, wc.n_ok);
+        else
+            range_loop<false>(body, c.xi, c.yi, c.zi, j0, j1, c.grp, c.G, 0.0, 0.0, 0.0, a,
+                              wc.n_ok);
+    }
+    __device__ __forceinline__ void finish() {}
+};
+
+// Screening visitor: each lane tests one supplier of the run against the
+// cluster's bounding box (distance from the box below r_cut, conservative by
+// the culling margin), the survivors are appended to the wave's LDS list,
+// and the list goes to the pair loop when it is nearly full, when the next
+// tile has another periodic image, and at the end of the item.  G = 64 /
+// csize copies of the cluster share the wave.
+template <int G, class Body>
+struct ScreenVisit {
+    static constexpr bool W = Body::kNeedW;
+    Body &body;
+    const ItemCtx &c;
+    const PairArgs &a;
+    WaveCounts &wc;
+    double4 *list;
+    int n_list = 0;
+    int code = -1;   // periodic image of the records in the list
+    double shx = 0.0, shy = 0.0, shz = 0.0;
+    __device__ __forceinline__ void flush() {
+        if (n_list == 0) return;
+        // far-away records after the last entry: the pair loop's reads past
+        // n_list (at most G of them) cannot pass the cut-off
+        if (c.lane < 2 * G)
+            list_write<W>(list + n_list + c.lane, make_double4(-1.0e300, -1.0e300, -1.0e300, 0.0));
+        wave_lds_sync();
+        wc.cand += (unsigned long long)n_list * (unsigned long long)c.cnt;
+        wc.steps += (unsigned long long)((n_list + G - 1) / G);
+        const double4 *p = list + c.rgrp;
+        if (code != 13)
+            list_loop<G, true>(body, p, n_list, c.xi, c.yi, c.zi, shx, shy, shz, a, wc.n_ok);
+        else
+            list_loop<G, false>(body, p, n_list, c.xi, c.yi, c.zi, 0.0, 0.0, 0.0, a, wc.n_ok);
+        wave_lds_sync();
+        n_list = 0;
+    }
+    __device__ __forceinline__ void tile(int img, bool, double x, double y, double z) {
+        if (img != code) {
+            flush();
+            code = img;
+            shx = x;
+            shy = y;
+            shz = z;
+        }
+    }
+    __device__ __forceinline__ double4 load(const double4 *q) const {
+        if constexpr (W) {
+            return q[c.lane];
+        } else {
+            const double4 *r = q + c.lane;
+            const double2 xy = *reinterpret_cast<const double2 *>(r);
+            return make_double4(xy.x, xy.y, r->z, 0.0);
+        }
+    }
+    __device__ __forceinline__ void run(int j0, int j1) {
+        const double cull2 = a.g.cull2;
+        const double lx = c.lo[0], ly = c.lo[1], lz = c.lo[2];
+        const double hx = c.hi[0], hy = c.hi[1], hz = c.hi[2];
+        j0 = __builtin_amdgcn_readfirstlane(j0);
+        j1 = __builtin_amdgcn_readfirstlane(j1);
+        wc.screened += (unsigned long long)(j1 - j0);
+        // the sorted array is padded by kSupplierPad >= 128 records: the
+        // reads of the last chunk and the look-ahead after it stay inside
+        double4 nxt = load(a.sp + j0);
+        for (int base = j0; base < j1; base += kWave) {
+            const double4 p = nxt;
+            nxt = load(a.sp + base + kWave);
+            const double px = p.x + shx, py = p.y + shy, pz = p.z + shz;
+            const double gx = fmax(0.0, fmax(lx - px, px - hx));
+            const double gy = fmax(0.0, fmax(ly - py, py - hy));
+            const double gz = fmax(0.0, fmax(lz - pz, pz - hz));
+            const bool keep = gx * gx + gy * gy + gz * gz < cull2;
+            // lanes past the run end may pass too: they are left out of the
+            // count, and what they write lies past the list's last entry
+            const int left = j1 - base;
+            const unsigned long long tail = left >= kWave ? ~0ull : ((1ull << left) - 1ull);
+            const unsigned long long m = ballot64(keep) & tail;
+            const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            if (keep) list_write<W>(list + n_list + off, p);
+            n_list += __builtin_popcountll(m);
+            if (n_list > kListCap - kWave) flush();   // keeps n_list <= kListCap
+        }
+    }
+    __device__ __forceinline__ void finish() { flush(); }
+};
+
+// One work item: the cluster's receivers against the suppliers of its
+// neighbour-tile / subtile range.  Per neighbour tile the periodic image is
+// fixed; one lane per subtile tests the subtile box against the cluster's
+// bounding box, a ballot gives the surviving subtiles, and consecutive
+// survivors merge into supplier ranges handed to the visitor.
+template <class Visit>
+__device__ __forceinline__ void walk_item(Visit &v, const Item &item, const Cluster &cl,
+                                          const PairArgs &a, int lane) {
     const Geom &g = a.g;
     const int *__restrict__ cs = a.cell_start;
+    const double *lo = cl.lo, *hi = cl.hi;
     const int tx = cl.tile / (g.nt * g.nt), ty = (cl.tile / g.nt) % g.nt, tz = cl.tile % g.nt;
     const int t0 = item.tiles & 0xff, t1 = (item.tiles >> 8) & 0xff;
     const int s0 = item.subs & 0xffff, s1 = (item.subs >> 16) & 0xffff;
@@ -286,7 +469,7 @@ __device__ __forceinline__ void walk_item(Body &body, const Item &item, const Cl
         if (ny < 0) { ny += g.nt; iy = -1; } else if (ny >= g.nt) { ny -= g.nt; iy = 1; }
         if (nz < 0) { nz += g.nt; iz = -1; } else if (nz >= g.nt) { nz -= g.nt; iz = 1; }
         const double shx = ix * g.box, shy = iy * g.box, shz = iz * g.box;
-        const bool shifted = (ix | iy | iz) != 0;
+        v.tile((ix + 1) * 9 + (iy + 1) * 3 + (iz + 1), (ix | iy | iz) != 0, shx, shy, shz);
         // origin of the supplier tile's image
         const double ox = nx * g.tile + shx, oy = ny * g.tile + shy, oz = nz * g.tile + shz;
         const int cbase = ((nx * g.nt + ny) * g.nt + nz) * g.ns3;
@@ -313,19 +496,11 @@ __device__ __forceinline__ void walk_item(Body &body, const Item &item, const Cl
                 const int j1 = rb < nvalid ? __builtin_amdgcn_readlane(cstart, rb)
                                            : cs[cbase + base + rb];
                 m = rb >= kWave ? 0ull : (m & (~0ull << rb));
-                if (j1 > j0) {
-                    n_cand += (unsigned long long)(j1 - j0) * (unsigned long long)cl.count;
-                    n_steps += (unsigned long long)((j1 - j0 + G - 1) / G);
-                    if (shifted)
-                        range_loop<true>(body, xi, yi, zi, j0, j1, grp, G, shx, shy, shz, a,
-                                         n_acc, n_wave);
-                    else
-                        range_loop<false>(body, xi, yi, zi, j0, j1, grp, G, 0.0, 0.0, 0.0, a,
-                                          n_acc, n_wave);
-                }
+                if (j1 > j0) v.run(j0, j1);
             }
         }
     }
+    v.finish();
 }
 
 // Sum a value over the G copies of each receiver: after the loop, lane
@@ -359,75 +534,95 @@ __device__ inline int next_item(const PairArgs &a, int lane, int &victim) {
     return -1;
 }
 
-template <int MODE, bool UNIT>
+template <int SG, class Body>
+__device__ __forceinline__ void visit_item(Body &body, const Item &item, const Cluster &cl,
+                                           const ItemCtx &c, const PairArgs &a, WaveCounts &wc,
+                                           double4 *list) {
+    if constexpr (SG > 0) {
+        ScreenVisit<SG, Body> v{body, c, a, wc, list};
+        walk_item(v, item, cl, a, c.lane);
+    } else {
+        DirectVisit<Body> v{body, c, a, wc};
+        walk_item(v, item, cl, a, c.lane);
+    }
+}
+
+// The persistent pair kernel.  SG > 0 (forward modes only): suppliers are
+// screened against the cluster's box into LDS before the pair loop, with SG =
+// 64 / csize copies of each cluster per wave; SG = 0: suppliers stream
+// directly, with 64 / count copies.
+template <int MODE, bool UNIT, int SG>
 __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
+    constexpr bool SCREEN = SG > 0;
+    __shared__ double4 lists[SCREEN ? kForceBlock / kWave : 1][SCREEN ? kListCap + kListSlack : 1];
     const int lane = threadIdx.x & (kWave - 1);
+    double4 *list = lists[SCREEN ? threadIdx.x / kWave : 0];
     int victim = 0;
-    // statistics stay in registers until the wave has run out of work: a
-    // contended atomic per item would also delay the next item's loads
-    // (vector memory operations retire in order)
-    int n_acc = 0;    // per lane: accepted pairs of the strided (G > 1) loop
-    int n_wave = 0;   // per lane: accepted pairs of the full-cluster loop
-    unsigned long long n_cand = 0, n_steps = 0;
+    WaveCounts wc;
     for (int it = next_item(a, lane, victim); it >= 0; it = next_item(a, lane, victim)) {
         const Item item = a.items[it];
         const Cluster cl = a.clusters[item.cluster];
         // receivers replicated over G lane groups; lanes past G*cnt are idle
-        const int cnt = __builtin_amdgcn_readfirstlane(cl.count);
-        const int G = __builtin_amdgcn_readfirstlane(kWave / cnt);
-        const int grp = lane / cnt;
-        const int il = lane - grp * cnt;
-        const bool live = grp < G;
+        ItemCtx c;
+        c.cnt = __builtin_amdgcn_readfirstlane(cl.count);
+        // the screened loop carries exactly SG copies (count <= csize)
+        c.G = SCREEN ? SG : __builtin_amdgcn_readfirstlane(kWave / c.cnt);
+        c.lane = lane;
+        c.grp = lane / c.cnt;
+        c.rgrp = min(c.grp, c.G);
+        c.lo = cl.lo;
+        c.hi = cl.hi;
+        const int il = lane - c.grp * c.cnt;
+        const bool live = c.grp < c.G;
         const double4 xp = a.rp[cl.begin + il];
         // idle lanes sit far outside the box: no pair passes r < r_cut
         const double far = live ? 0.0 : 1.0e300;
-        const double xi = xp.x + far, yi = xp.y + far, zi = xp.z + far;
+        c.xi = xp.x + far;
+        c.yi = xp.y + far;
+        c.zi = xp.z + far;
         double ax, ay, az;
         if constexpr (MODE == FWD_F32) {
             FwdF32<UNIT> b;
-            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_wave, n_cand,
-                      n_steps);
+            visit_item<SG>(b, item, cl, c, a, wc, list);
             ax = b.ax; ay = b.ay; az = b.az;
         } else if constexpr (MODE == FWD_F64) {
             FwdF64<UNIT> b;
-            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_wave, n_cand,
-                      n_steps);
+            visit_item<SG>(b, item, cl, c, a, wc, list);
             ax = b.ax; ay = b.ay; az = b.az;
         } else if constexpr (MODE == BWD_F64) {
             BwdF64 b;
             const double4 w = a.rwa[cl.begin + il];
             b.wkx = w.x; b.wky = w.y; b.wkz = w.z; b.muk = xp.w;
-            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_wave, n_cand,
-                      n_steps);
+            visit_item<0>(b, item, cl, c, a, wc, list);
             ax = b.ax; ay = b.ay; az = b.az;
         } else {
             BwdF32 b;
             const float4 w = reinterpret_cast<const float4 *>(a.rwa)[cl.begin + il];
             b.wkx = w.x; b.wky = w.y; b.wkz = w.z; b.muk = mu_f32(xp.w);
-            walk_item(b, item, cl, xi, yi, zi, cl.lo, cl.hi, a, lane, grp, G, n_acc, n_wave, n_cand,
-                      n_steps);
+            visit_item<0>(b, item, cl, c, a, wc, list);
             ax = b.ax; ay = b.ay; az = b.az;
         }
-        if (G > 1) {
-            ax = group_sum(ax, lane, grp, cnt, G);
-            ay = group_sum(ay, lane, grp, cnt, G);
-            az = group_sum(az, lane, grp, cnt, G);
+        if (c.G > 1) {
+            ax = group_sum(ax, lane, c.grp, c.cnt, c.G);
+            ay = group_sum(ay, lane, c.grp, c.cnt, c.G);
+            az = group_sum(az, lane, c.grp, c.cnt, c.G);
         }
         // per-item partial sums (group 0 holds them); a separate pass adds
         // the items of each cluster in a fixed order
-        if (grp == 0) {
-            double *o = a.part + (long long)it * (3 * kWave) + il;
+        if (c.grp == 0) {
+            double *o = a.part + (long long)it * (3 * a.csize) + il;
             o[0] = ax;
-            o[kWave] = ay;
-            o[2 * kWave] = az;
+            o[a.csize] = ay;
+            o[2 * a.csize] = az;
         }
     }
-    unsigned long long tot = (unsigned long long)(n_acc + n_wave);
+    unsigned long long tot = (unsigned long long)wc.n_ok;
     for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, kWave);
     if (lane == 0 && a.counters) {
         atomicAdd(&a.counters->interactions, tot);
-        atomicAdd(&a.counters->candidates, n_cand);
-        atomicAdd(&a.counters->steps, n_steps);
+        atomicAdd(&a.counters->candidates, wc.cand);
+        atomicAdd(&a.counters->steps, wc.steps);
+        atomicAdd(&a.counters->screened, wc.screened);
     }
 }
 
@@ -438,7 +633,7 @@ __global__ __launch_bounds__(kWave) void k_reduce_items(const Cluster *__restric
                                                         const int *__restrict__ item_off,
                                                         const int *__restrict__ rperm,
                                                         const double *__restrict__ part,
-                                                        double *__restrict__ out,
+                                                        int csize, double *__restrict__ out,
                                                         long long out_stride) {
     const int c = blockIdx.x;
     const Cluster cl = clusters[c];
@@ -447,10 +642,10 @@ __global__ __launch_bounds__(kWave) void k_reduce_items(const Cluster *__restric
     const int i0 = item_off[c], i1 = item_off[c + 1];
     double x = 0.0, y = 0.0, z = 0.0;
     for (int it = i0; it < i1; ++it) {
-        const double *q = part + (long long)it * (3 * kWave) + il;
+        const double *q = part + (long long)it * (3 * csize) + il;
         x += q[0];
-        y += q[kWave];
-        z += q[2 * kWave];
+        y += q[csize];
+        z += q[2 * csize];
     }
     double *o = out + (long long)cl.subset * out_stride + 3ll * rperm[cl.begin + il];
     o[0] = x;
@@ -458,50 +653,68 @@ __global__ __launch_bounds__(kWave) void k_reduce_items(const Cluster *__restric
     o[2] = z;
 }
 
-template <int MODE>
+template <int MODE, int SG>
 int blocks_per_cu_of() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs<MODE, false>, kForceBlock, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs<MODE, false, SG>, kForceBlock,
+                                                     0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
+template <int MODE, bool UNIT>
+void launch_fwd(int sg, const PairArgs &a, dim3 gr, dim3 bl, hipStream_t s) {
+    switch (sg) {
+    case 1: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 1>), gr, bl, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 2>), gr, bl, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 4>), gr, bl, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 8>), gr, bl, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 0>), gr, bl, 0, s, a); break;
+    }
+}
+
+// screen groups: 64 / csize when screening (csize in {8, 16, 32, 64}), else 0
+inline int screen_groups(int screen, int csize) { return screen ? kWave / csize : 0; }
+
 }  // namespace
 
 hipError_t launch_reduce_items(const Cluster *clusters, int n_clusters, const int *item_off,
-                               const int *rperm, const double *part, double *out,
+                               const int *rperm, const double *part, int csize, double *out,
                                long long out_stride, hipStream_t s) {
     if (n_clusters <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_reduce_items, dim3((unsigned)n_clusters), dim3(kWave), 0, s, clusters,
-                       item_off, rperm, part, out, out_stride);
+                       item_off, rperm, part, csize, out, out_stride);
     return hipGetLastError();
 }
 
-hipError_t launch_pairs(int mode, const PairArgs &a, int grid, hipStream_t s) {
+hipError_t launch_pairs(int mode, int screen, const PairArgs &a, int grid, hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;
+    if (a.csize != 8 && a.csize != 16 && a.csize != 32 && a.csize != 64) return hipErrorInvalidValue;
     dim3 gr((unsigned)grid), bl(kForceBlock);
+    const int sg = screen_groups(screen, a.csize);
     switch (mode) {
     case FWD_F32:
-        if (a.unit_mass) hipLaunchKernelGGL((k_pairs<FWD_F32, true>), gr, bl, 0, s, a);
-        else hipLaunchKernelGGL((k_pairs<FWD_F32, false>), gr, bl, 0, s, a);
+        if (a.unit_mass) launch_fwd<FWD_F32, true>(sg, a, gr, bl, s);
+        else launch_fwd<FWD_F32, false>(sg, a, gr, bl, s);
         break;
     case FWD_F64:
-        if (a.unit_mass) hipLaunchKernelGGL((k_pairs<FWD_F64, true>), gr, bl, 0, s, a);
-        else hipLaunchKernelGGL((k_pairs<FWD_F64, false>), gr, bl, 0, s, a);
+        if (a.unit_mass) launch_fwd<FWD_F64, true>(sg, a, gr, bl, s);
+        else launch_fwd<FWD_F64, false>(sg, a, gr, bl, s);
         break;
-    case BWD_F32: hipLaunchKernelGGL((k_pairs<BWD_F32, false>), gr, bl, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_pairs<BWD_F64, false>), gr, bl, 0, s, a); break;
+    case BWD_F32: hipLaunchKernelGGL((k_pairs<BWD_F32, false, 0>), gr, bl, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_pairs<BWD_F64, false, 0>), gr, bl, 0, s, a); break;
     }
     return hipGetLastError();
 }
 
-int pairs_blocks_per_cu(int mode) {
+int pairs_blocks_per_cu(int mode, int screen) {
+    // every screened variant has the same LDS footprint; use G = 8's count
+    const bool sc = screen != 0 && (mode == FWD_F32 || mode == FWD_F64);
     switch (mode) {
-    case FWD_F32: return blocks_per_cu_of<FWD_F32>();
-    case FWD_F64: return blocks_per_cu_of<FWD_F64>();
-    case BWD_F32: return blocks_per_cu_of<BWD_F32>();
-    default: return blocks_per_cu_of<BWD_F64>();
+    case FWD_F32: return sc ? blocks_per_cu_of<FWD_F32, 8>() : blocks_per_cu_of<FWD_F32, 0>();
+    case FWD_F64: return sc ? blocks_per_cu_of<FWD_F64, 8>() : blocks_per_cu_of<FWD_F64, 0>();
+    case BWD_F32: return blocks_per_cu_of<BWD_F32, 0>();
+    default: return blocks_per_cu_of<BWD_F64, 0>();
     }
 }
 

@@ -9,7 +9,7 @@
 //   cell_start[c] first sorted index of fine cell c (c = tile*ns^3 + subtile),
 //                cell_start[ncells] = n
 //   act_pos[]    sorted indices of the receivers, subset-major, tile order
-//   clusters[]   receiver groups of <= 64 particles inside one tile
+//   clusters[]   receiver groups of <= csize (8..64) particles inside one tile
 //   items[]      (cluster, neighbour-tile range, subtile range) work units
 #pragma once
 
@@ -26,6 +26,11 @@ constexpr int kScanPerThread = 16;          // elements per scan thread
 constexpr int kScanTile = kScanBlock * kScanPerThread;
 constexpr int kForceBlock = 256;            // 4 waves, each with its own work item
 constexpr int kSupplierPad = 128;           // zeroed records after the sorted particles
+constexpr int kFineSide = 8;                // fine order: 8x8x8 sub-cells per subtile
+constexpr int kFineBins = kFineSide * kFineSide * kFineSide;
+constexpr int kFineMin = 8;                 // subtiles with at most this many keep their order
+constexpr int kListCap = 224;               // screened supplier records per wave (LDS)
+constexpr int kListSlack = 32;              // records past the cap for look-ahead reads (3*8 used)
 
 // Geometry of one call.  Tiles are cubes of side box/nt >= r_cut; each tile
 // holds ns^3 subtiles; fine cells are the subtiles, nc = nt*ns per dimension.
@@ -52,7 +57,7 @@ struct Cluster {
     int tile;     // tile index (tx*nt + ty)*nt + tz
     int subset;   // receiver subset (batched calls)
     int begin;    // first entry in act_pos / rp / rperm
-    int count;    // 1..64 receivers
+    int count;    // 1..csize receivers
     double lo[3]; // bounding box of the receivers (wrapped positions)
     double hi[3];
 };
@@ -71,7 +76,8 @@ struct Counters {
     unsigned long long interactions;
     unsigned long long candidates;
     unsigned long long steps;        // wave steps over suppliers
-    unsigned long long pad[5];
+    unsigned long long screened;     // supplier records tested against cluster boxes
+    unsigned long long pad[4];
 };
 
 enum SelKind { SEL_ALL = 0, SEL_MASK = 1, SEL_RUNG = 2 };
@@ -91,13 +97,18 @@ hipError_t launch_scatter(const double *pos, const double *mass, const uint8_t *
                           const Geom &g, const int *key, const int *rank,
                           const int *cell_start, int fp32, double4 *sp, int *perm,
                           uint8_t *sel_s, hipStream_t s);
+// reorder the particles of every subtile by the Morton index of their fine
+// sub-cell (sp/perm/sel -> sp2/perm2/sel2; fkey/frank: n ints of scratch)
+hipError_t launch_fine_order(const double4 *sp, const int *perm, const uint8_t *sel,
+                             const int *cell_start, const Geom &g, int *fkey, int *frank,
+                             double4 *sp2, int *perm2, uint8_t *sel2, hipStream_t s);
 hipError_t launch_flags(const uint8_t *sel_s, int n, int n_sub, int kind,
                         const uint8_t *thr_host, int *flags, hipStream_t s);
 hipError_t launch_compact(const int *scan, int n, int n_sub, int *act_pos, hipStream_t s);
 hipError_t launch_cluster_count(const int *cell_start, const int *scan, int n, int n_sub,
-                                const Geom &g, int *ncl, hipStream_t s);
+                                const Geom &g, int csize, int *ncl, hipStream_t s);
 hipError_t launch_cluster_write(const int *cell_start, const int *scan, const int *cl_off,
-                                int n, int n_sub, const Geom &g, Cluster *clusters,
+                                int n, int n_sub, const Geom &g, int csize, Cluster *clusters,
                                 hipStream_t s);
 hipError_t launch_item_count(const Cluster *clusters, const int *n_clusters_dev,
                              int cluster_bound, const int *cell_start, const Geom &g,
@@ -126,16 +137,19 @@ struct PairArgs {
     const Item *items;
     const double4 *wa;       // backward: suppliers' w * [active], sorted (FP32: float4 bits)
     int *queue;              // kXcds work counters, zero at launch
-    double *part;            // per-item partial sums, n_items x 3 x 64
+    double *part;            // per-item partial sums, n_items x 3 x csize
     Counters *counters;
     int n_items;
     int unit_mass;           // no mass array: every mu_j is 1 (forward kernels specialise)
+    int csize;               // cluster size (receivers per cluster, 8..64); partial-sum stride
     Geom g;
 };
-hipError_t launch_pairs(int mode, const PairArgs &a, int grid, hipStream_t s);
+// screen != 0: forward modes test every supplier against the cluster's box
+// first and stream the survivors from LDS
+hipError_t launch_pairs(int mode, int screen, const PairArgs &a, int grid, hipStream_t s);
 hipError_t launch_reduce_items(const Cluster *clusters, int n_clusters, const int *item_off,
-                               const int *rperm, const double *part, double *out,
+                               const int *rperm, const double *part, int csize, double *out,
                                long long out_stride, hipStream_t s);
-int pairs_blocks_per_cu(int mode);
+int pairs_blocks_per_cu(int mode, int screen);
 
 }  // namespace p3m

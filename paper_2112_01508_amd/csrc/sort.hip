@@ -11,6 +11,8 @@
 // work of clustered particle sets.
 #include "p3msr_internal.hpp"
 
+#include <algorithm>
+
 namespace p3m {
 
 namespace {
@@ -166,6 +168,101 @@ __global__ void k_scatter(const double *__restrict__ pos, const double *__restri
     sel_s[dst] = sel ? sel[i] : (uint8_t)1;
 }
 
+// ---- fine order inside subtiles -------------------------------------------------
+
+// Morton index of the particle's 8x8x8 sub-cell inside its subtile.
+__device__ inline int fine_key(const double4 &p, const Geom &g) {
+    int f[3];
+    const double w[3] = {p.x, p.y, p.z};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double u = w[d] * g.inv_cell;
+        int c = (int)u;
+        c = c < 0 ? 0 : (c >= g.nc ? g.nc - 1 : c);
+        int q = (int)((u - c) * kFineSide);
+        f[d] = q < 0 ? 0 : (q >= kFineSide ? kFineSide - 1 : q);
+    }
+    int k = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+        k |= (((f[0] >> b) & 1) << (3 * b + 2)) | (((f[1] >> b) & 1) << (3 * b + 1)) |
+             (((f[2] >> b) & 1) << (3 * b));
+    return k;
+}
+
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// One wave per tile.  Inside every subtile holding more than kFineMin
+// particles the particles are reordered by fine_key (a counting sort over
+// kFineBins bins in LDS); smaller subtiles are copied as they are.  Reads
+// sp/perm/sel and writes sp2/perm2/sel2; fkey/frank are scratch indexed by
+// sorted position.  Consecutive receivers then lie close together, so small
+// clusters have small bounding boxes.
+__global__ __launch_bounds__(kWave) void k_fine_order(const double4 *__restrict__ sp,
+                                                      const int *__restrict__ perm,
+                                                      const uint8_t *__restrict__ sel,
+                                                      const int *__restrict__ cs, Geom g,
+                                                      int *__restrict__ fkey,
+                                                      int *__restrict__ frank,
+                                                      double4 *__restrict__ sp2,
+                                                      int *__restrict__ perm2,
+                                                      uint8_t *__restrict__ sel2) {
+    __shared__ int hist[kFineBins];
+    const int lane = threadIdx.x;
+    for (long long tile = blockIdx.x; tile < g.nt3; tile += gridDim.x) {
+        const int *c = cs + tile * g.ns3;
+        for (int s = 0; s < g.ns3; ++s) {
+            const int a0 = c[s], a1 = c[s + 1];
+            if (a1 - a0 <= kFineMin) {
+                for (int i = a0 + lane; i < a1; i += kWave) {
+                    sp2[i] = sp[i];
+                    perm2[i] = perm[i];
+                    sel2[i] = sel[i];
+                }
+                continue;
+            }
+            for (int b = lane; b < kFineBins; b += kWave) hist[b] = 0;
+            wave_lds_sync();
+            for (int i = a0 + lane; i < a1; i += kWave) {
+                const int k = fine_key(sp[i], g);
+                fkey[i] = k;
+                frank[i] = atomicAdd(&hist[k], 1);
+            }
+            wave_lds_sync();
+            // exclusive scan of the bins: lane l owns bins [l*P, l*P + P)
+            constexpr int P = kFineBins / kWave;
+            int v[P], sum = 0;
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                v[q] = hist[lane * P + q];
+                sum += v[q];
+            }
+            int incl = sum;
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int y = __shfl_up(incl, off, kWave);
+                if (lane >= off) incl += y;
+            }
+            int run = incl - sum;
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                hist[lane * P + q] = run;
+                run += v[q];
+            }
+            wave_lds_sync();
+            for (int i = a0 + lane; i < a1; i += kWave) {
+                const int dst = a0 + hist[fkey[i]] + frank[i];
+                sp2[dst] = sp[i];
+                perm2[dst] = perm[i];
+                sel2[dst] = sel[i];
+            }
+            wave_lds_sync();
+        }
+    }
+}
+
 // ---- receiver selection and compaction ---------------------------------------
 
 struct Thresholds { uint8_t t[64]; };
@@ -196,7 +293,7 @@ __global__ void k_compact(const int *__restrict__ scan, int n, int n_sub, int *_
 }
 
 __global__ void k_cluster_count(const int *__restrict__ cs, const int *__restrict__ scan, int n,
-                                int n_sub, Geom g, int *__restrict__ ncl) {
+                                int n_sub, Geom g, int csize, int *__restrict__ ncl) {
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n_sub * g.nt3) return;
     int k = idx / g.nt3;
@@ -204,11 +301,11 @@ __global__ void k_cluster_count(const int *__restrict__ cs, const int *__restric
     size_t off = (size_t)k * n;
     int a0 = scan[off + cs[(size_t)t * g.ns3]];
     int a1 = scan[off + cs[(size_t)(t + 1) * g.ns3]];
-    ncl[idx] = (a1 - a0 + kWave - 1) / kWave;
+    ncl[idx] = (a1 - a0 + csize - 1) / csize;
 }
 
 __global__ void k_cluster_write(const int *__restrict__ cs, const int *__restrict__ scan, int n,
-                                int n_sub, Geom g, const int *__restrict__ cl_off,
+                                int n_sub, Geom g, int csize, const int *__restrict__ cl_off,
                                 Cluster *__restrict__ clusters) {
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n_sub * g.nt3) return;
@@ -218,12 +315,12 @@ __global__ void k_cluster_write(const int *__restrict__ cs, const int *__restric
     int a0 = scan[off + cs[(size_t)t * g.ns3]];
     int a1 = scan[off + cs[(size_t)(t + 1) * g.ns3]];
     int o = cl_off[idx];
-    for (int b = a0; b < a1; b += kWave) {
+    for (int b = a0; b < a1; b += csize) {
         Cluster c{};
         c.tile = t;
         c.subset = k;
         c.begin = b;
-        c.count = min(kWave, a1 - b);
+        c.count = min(csize, a1 - b);
         clusters[o++] = c;
     }
 }
@@ -418,6 +515,15 @@ hipError_t launch_scatter(const double *pos, const double *mass, const uint8_t *
     return hipGetLastError();
 }
 
+hipError_t launch_fine_order(const double4 *sp, const int *perm, const uint8_t *sel,
+                             const int *cell_start, const Geom &g, int *fkey, int *frank,
+                             double4 *sp2, int *perm2, uint8_t *sel2, hipStream_t s) {
+    long long grid = std::min<long long>(g.nt3, 1ll << 20);
+    hipLaunchKernelGGL(k_fine_order, dim3((unsigned)grid), dim3(kWave), 0, s, sp, perm, sel,
+                       cell_start, g, fkey, frank, sp2, perm2, sel2);
+    return hipGetLastError();
+}
+
 hipError_t launch_flags(const uint8_t *sel_s, int n, int n_sub, int kind, const uint8_t *thr_host,
                         int *flags, hipStream_t s) {
     size_t total = (size_t)n * n_sub;
@@ -439,18 +545,19 @@ hipError_t launch_compact(const int *scan, int n, int n_sub, int *act_pos, hipSt
 }
 
 hipError_t launch_cluster_count(const int *cs, const int *scan, int n, int n_sub, const Geom &g,
-                                int *ncl, hipStream_t s) {
+                                int csize, int *ncl, hipStream_t s) {
     size_t total = (size_t)n_sub * g.nt3;
     hipLaunchKernelGGL(k_cluster_count, dim3(grid_for(total, 256)), dim3(256), 0, s, cs, scan, n,
-                       n_sub, g, ncl);
+                       n_sub, g, csize, ncl);
     return hipGetLastError();
 }
 
 hipError_t launch_cluster_write(const int *cs, const int *scan, const int *cl_off, int n,
-                                int n_sub, const Geom &g, Cluster *clusters, hipStream_t s) {
+                                int n_sub, const Geom &g, int csize, Cluster *clusters,
+                                hipStream_t s) {
     size_t total = (size_t)n_sub * g.nt3;
     hipLaunchKernelGGL(k_cluster_write, dim3(grid_for(total, 256)), dim3(256), 0, s, cs, scan, n,
-                       n_sub, g, cl_off, clusters);
+                       n_sub, g, csize, cl_off, clusters);
     return hipGetLastError();
 }
 

@@ -73,7 +73,12 @@ def test_batched_and_config_checks(lib):
     assert lib.p3m_sr_force_batched(None, ctypes.c_void_p(8), None, ctypes.c_void_p(8), 10, 0,
                                     None, 1.0, 0.01, 0.045, 1, ctypes.c_void_p(8), None) == -1
     assert "n_sub" in lib.p3m_sr_last_error().decode()
-    assert lib.p3m_sr_set_config(None, 2, 0) == -1
+    assert lib.p3m_sr_set_config(None, 2, 0, 0, -1) == -1
+    assert "NULL handle" in lib.p3m_sr_last_error().decode()
+    for args, msg in (((17, 0, 0, -1), "subtiles"), ((2, 5, 0, -1), "item_target"),
+                      ((2, 0, 12, -1), "cluster_size"), ((2, 0, 8, 2), "screen")):
+        assert lib.p3m_sr_set_config(None, *args) == -1
+        assert msg in lib.p3m_sr_last_error().decode()
     h = ctypes.c_void_p(0)
     # no GPU in the build container: create must fail cleanly, not crash
     if os.environ.get("HIP_VISIBLE_DEVICES", "x") == "":

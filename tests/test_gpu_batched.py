@@ -16,10 +16,20 @@ def env():
     return torch, p3, p3.Context(0)
 
 
+@pytest.mark.parametrize("csize,screen", [(64, 0), (8, 1), (32, 1)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batched_matches_oracle_and_single_calls(env, prec):
+def test_batched_matches_oracle_and_single_calls(env, prec, csize, screen):
     torch, p3, ctx = env
-    print("clustered256 recipe at n_side=48 with rungs", prec, flush=True)
+    print("clustered256 recipe at n_side=48 with rungs", prec, csize, screen, flush=True)
+    ctx.set_config(cluster_size=csize, screen=screen)
+    try:
+        _batched_vs_oracle(env, prec)
+    finally:
+        ctx.set_config()
+
+
+def _batched_vs_oracle(env, prec):
+    torch, p3, ctx = env
     wl = make_workload("clustered256", n_side=48)
     thr = list(range(8))
     pos, mass, rung = to_dev(torch, wl.pos), to_dev(torch, wl.mass), to_dev(torch, wl.rung)

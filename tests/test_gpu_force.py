@@ -32,7 +32,7 @@ def run_force(env, pos, mass, active, box, x_s, r_cut, prec, **cfg):
         return acc.cpu().numpy(), ctx.stats()
     finally:
         if cfg:
-            ctx.set_config(0, 0)
+            ctx.set_config()
 
 
 def check(acc, st, ref, cnt, absum, prec, active=None):
@@ -84,6 +84,59 @@ def test_decompositions_agree(env, ns, target):
     check(acc, st, ref, cnt, absum, "fp64")
 
 
+LAYOUTS = [(64, 0), (64, 1), (32, 1), (16, 1), (8, 1), (16, 0), (8, 0)]
+
+
+@pytest.mark.parametrize("csize,screen", LAYOUTS)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_layouts_agree(env, csize, screen, prec):
+    """Every cluster size, with and without the per-supplier box screen,
+    gives the oracle's force and its exact pair count (the layout changes
+    only which lanes evaluate a pair and the FP64 summation order)."""
+    print("clustered n_side=24 csize=%d screen=%d" % (csize, screen), prec, flush=True)
+    wl = make_workload("diff64", n_side=24)
+    ref, cnt, absum = oracle.force_full(wl.pos, wl.mass, 1.0, wl.x_s, wl.r_cut, method="tiled")
+    for ns in (1, 3):
+        acc, st = run_force(env, wl.pos, wl.mass, None, 1.0, wl.x_s, wl.r_cut, prec,
+                            subtiles_per_dim=ns, item_target=512, cluster_size=csize,
+                            screen=screen)
+        assert st["cluster_size"] == csize and st["screen"] == screen
+        assert (st["screened"] > 0) == (screen == 1)
+        check(acc, st, ref, cnt, absum, prec)
+
+
+@pytest.mark.parametrize("csize,screen", [(8, 1), (16, 1), (64, 1), (8, 0)])
+@pytest.mark.parametrize("n", [1, 2, 9, 63, 1000, 4097])
+def test_layouts_ragged_masses_and_mask(env, n, csize, screen):
+    """Small and ragged inputs with masses and an active mask on the
+    screened / small-cluster layouts (partial clusters, empty lists)."""
+    print("random n=%d csize=%d screen=%d" % (n, csize, screen), flush=True)
+    pos, mass, active = random_particles(n, seed=200 + n, active_frac=0.6)
+    if n <= 2:
+        pos[:] = [0.5, 0.5, 0.5]
+        pos[-1] = [0.52, 0.49, 0.5]
+    x_s = 1.25 / 24
+    r_cut = 4.5 * x_s
+    ref, cnt, absum = oracle.force_full(pos, mass, 1.0, x_s, r_cut, active=active, method="brute")
+    for prec in ("fp64", "fp32"):
+        acc, st = run_force(env, pos, mass, active, 1.0, x_s, r_cut, prec, cluster_size=csize,
+                            screen=screen)
+        check(acc, st, ref, cnt, absum, prec, active)
+        # unit masses take the specialised kernels
+        ref1, cnt1, absum1 = oracle.force_full(pos, np.ones(n), 1.0, x_s, r_cut, active=active,
+                                               method="brute")
+        torch, p3, ctx = env
+        ctx.set_config(cluster_size=csize, screen=screen)
+        try:
+            acc1 = ctx.force(to_dev(torch, pos), None, to_dev(torch, active), box=1.0, x_s=x_s,
+                             r_cut=r_cut, precision=prec)
+            torch.cuda.synchronize()
+            st1 = ctx.stats()
+        finally:
+            ctx.set_config()
+        check(acc1.cpu().numpy(), st1, ref1, cnt1, absum1, prec, active)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_diff64_clustered_full(env, prec):
     print("diff64 N=64^3 clustered", prec, flush=True)
@@ -93,13 +146,16 @@ def test_diff64_clustered_full(env, prec):
     print(check(acc, st, ref, cnt, absum, prec), flush=True)
 
 
+@pytest.mark.parametrize("csize,screen", [(64, 0), (8, 1), (16, 1)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_clustered128_sampled(env, prec):
-    """Full-size N=128^3 clustered set, default launch configuration; 512
-    seeded receivers checked one by one against brute force over all N."""
-    print("clustered128 N=128^3", prec, flush=True)
+def test_clustered128_sampled(env, prec, csize, screen):
+    """Full-size N=128^3 clustered set in the layouts the autotuner picks
+    from; 512 seeded receivers checked one by one against brute force over
+    all N."""
+    print("clustered128 N=128^3", prec, csize, screen, flush=True)
     wl = make_workload("clustered128", with_rungs=False)
-    acc, st = run_force(env, wl.pos, wl.mass, None, 1.0, wl.x_s, wl.r_cut, prec)
+    acc, st = run_force(env, wl.pos, wl.mass, None, 1.0, wl.x_s, wl.r_cut, prec,
+                        subtiles_per_dim=2, cluster_size=csize, screen=screen)
     idx = sample_indices(wl.n, 512, wl.config_id)
     ref, cnt, absum, _ = oracle.force(wl.pos, wl.mass, 1.0, wl.x_s, wl.r_cut, recv=idx)
     e = oracle.errors(acc[idx], ref, absum)
