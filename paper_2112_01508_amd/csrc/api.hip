@@ -389,6 +389,8 @@ int run(p3m_sr_context *h, const Request &r) {
     long long waves_wanted = (n_items + 0ll);
     long long grid = std::min<long long>((waves_wanted + 3) / 4, (long long)h->n_cu * bpc);
     if (grid < 1) grid = 1;
+    // items per queue atomic: about 32 claims per wave, at most 8 items each
+    a.batch = (int)std::max<long long>(1, std::min<long long>(8, n_items / (grid * 4 * 32)));
     if (h->timing) P3M_HIP(hipEventRecord(h->ev[1], s));
     P3M_HIP(launch_pairs(mode, screen, a, (int)grid, s));
     if (h->timing) {

@@ -362,12 +362,14 @@ struct DirectVisit {
     __device__ __forceinline__ void finish() {}
 };
 
-// Screening visitor: each lane tests one supplier of the run against the
+// Screening visitor.  Supplier runs are packed into chunks of 64 records
+// (one per lane, several runs per chunk, so short runs do not leave lanes
+// idle); each full chunk is screened: every lane tests its record against the
 // cluster's bounding box (distance from the box below r_cut, conservative by
-// the culling margin), the survivors are appended to the wave's LDS list,
-// and the list goes to the pair loop when it is nearly full, when the next
-// tile has another periodic image, and at the end of the item.  G = 64 /
-// csize copies of the cluster share the wave.
+// the culling margin) and the survivors are appended to the wave's LDS list.
+// The list goes to the pair loop when it is nearly full, when the next tile
+// has another periodic image, and at the end of the item.  G = 64 / csize
+// copies of the cluster share the wave.
 template <int G, class Body>
 struct ScreenVisit {
     static constexpr bool W = Body::kNeedW;
@@ -377,8 +379,11 @@ struct ScreenVisit {
     WaveCounts &wc;
     double4 *list;
     int n_list = 0;
-    int code = -1;   // periodic image of the records in the list
+    int code = -1;   // periodic image of the records in the list and the open chunk
     double shx = 0.0, shy = 0.0, shz = 0.0;
+    int fill = 0;    // records in the open chunk: lanes [0, fill)
+    int jj = 0;      // per lane: its record is a.sp[jj + lane]
+
     __device__ __forceinline__ void flush() {
         if (n_list == 0) return;
         // far-away records after the last entry: the pair loop's reads past
@@ -396,8 +401,38 @@ struct ScreenVisit {
         wave_lds_sync();
         n_list = 0;
     }
+    __device__ __forceinline__ double4 load(const double4 *r) const {
+        if constexpr (W) {
+            return *r;
+        } else {
+            const double2 xy = *reinterpret_cast<const double2 *>(r);
+            return make_double4(xy.x, xy.y, r->z, 0.0);
+        }
+    }
+    // Screen the open chunk.  Lanes past `fill` read a record at most 63
+    // past the end of the last run (inside the padded sorted array); they
+    // are left out of the count, and what they write lies past the list's
+    // last entry.
+    __device__ __forceinline__ void screen_chunk() {
+        if (fill == 0) return;
+        const double4 p = load(a.sp + (jj + c.lane));
+        const double px = p.x + shx, py = p.y + shy, pz = p.z + shz;
+        const double gx = fmax(0.0, fmax(c.lo[0] - px, px - c.hi[0]));
+        const double gy = fmax(0.0, fmax(c.lo[1] - py, py - c.hi[1]));
+        const double gz = fmax(0.0, fmax(c.lo[2] - pz, pz - c.hi[2]));
+        const bool keep = gx * gx + gy * gy + gz * gz < a.g.cull2;
+        const unsigned long long tail = fill >= kWave ? ~0ull : ((1ull << fill) - 1ull);
+        const unsigned long long m = ballot64(keep) & tail;
+        const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        if (keep) list_write<W>(list + n_list + off, p);
+        n_list += __builtin_popcountll(m);
+        fill = 0;
+        if (n_list > kListCap - kWave) flush();   // keeps n_list <= kListCap
+    }
     __device__ __forceinline__ void tile(int img, bool, double x, double y, double z) {
         if (img != code) {
+            screen_chunk();
             flush();
             code = img;
             shx = x;
@@ -405,53 +440,42 @@ struct ScreenVisit {
             shz = z;
         }
     }
-    __device__ __forceinline__ double4 load(const double4 *q) const {
-        if constexpr (W) {
-            return q[c.lane];
-        } else {
-            const double4 *r = q + c.lane;
-            const double2 xy = *reinterpret_cast<const double2 *>(r);
-            return make_double4(xy.x, xy.y, r->z, 0.0);
-        }
-    }
     __device__ __forceinline__ void run(int j0, int j1) {
-        const double cull2 = a.g.cull2;
-        const double lx = c.lo[0], ly = c.lo[1], lz = c.lo[2];
-        const double hx = c.hi[0], hy = c.hi[1], hz = c.hi[2];
         j0 = __builtin_amdgcn_readfirstlane(j0);
         j1 = __builtin_amdgcn_readfirstlane(j1);
         wc.screened += (unsigned long long)(j1 - j0);
-        // the sorted array is padded by kSupplierPad >= 128 records: the
-        // reads of the last chunk and the look-ahead after it stay inside
-        double4 nxt = load(a.sp + j0);
-        for (int base = j0; base < j1; base += kWave) {
-            const double4 p = nxt;
-            nxt = load(a.sp + base + kWave);
-            const double px = p.x + shx, py = p.y + shy, pz = p.z + shz;
-            const double gx = fmax(0.0, fmax(lx - px, px - hx));
-            const double gy = fmax(0.0, fmax(ly - py, py - hy));
-            const double gz = fmax(0.0, fmax(lz - pz, pz - hz));
-            const bool keep = gx * gx + gy * gy + gz * gz < cull2;
-            // lanes past the run end may pass too: they are left out of the
-            // count, and what they write lies past the list's last entry
-            const int left = j1 - base;
-            const unsigned long long tail = left >= kWave ? ~0ull : ((1ull << left) - 1ull);
-            const unsigned long long m = ballot64(keep) & tail;
-            const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-            if (keep) list_write<W>(list + n_list + off, p);
-            n_list += __builtin_popcountll(m);
-            if (n_list > kListCap - kWave) flush();   // keeps n_list <= kListCap
+        while (j0 < j1) {
+            // lanes [fill, fill + take) take records j0, j0 + 1, ...; lanes
+            // past them keep the same offset (their reads stay near the run)
+            if (c.lane >= fill) jj = j0 - fill;
+            const int take = min(j1 - j0, kWave - fill);
+            j0 += take;
+            fill += take;
+            if (fill == kWave) screen_chunk();
         }
     }
-    __device__ __forceinline__ void finish() { flush(); }
+    __device__ __forceinline__ void finish() {
+        screen_chunk();
+        flush();
+    }
 };
 
+// Floor of (i + 0.5) * inv for 0 <= i < 2^20, inv = 1/d rounded to float, d <= 4096:
+// exact, since (i + 0.5) / d is at least 0.5/d away from an integer and the
+// float product is off by far less.
+__device__ __forceinline__ int div_small(int i, float inv) {
+    return (int)(((float)i + 0.5f) * inv);
+}
+
 // One work item: the cluster's receivers against the suppliers of its
-// neighbour-tile / subtile range.  Per neighbour tile the periodic image is
-// fixed; one lane per subtile tests the subtile box against the cluster's
-// bounding box, a ballot gives the surviving subtiles, and consecutive
-// survivors merge into supplier ranges handed to the visitor.
+// neighbour-tile / subtile range.  The item's (tile, subtile) entries are
+// tested 64 at a time, one lane each: the subtile box (in the unwrapped
+// frame of the tile's periodic image) against the cluster's bounding box,
+// the subtile-pair culling of section 2.1.3 done against the receivers'
+// actual extent (conservative by the culling margin, so rounding in the box
+// corners cannot drop a pair).  Each lane also loads its subtile's cell
+// range.  Per neighbour tile of the pass, the image is fixed and consecutive
+// surviving subtiles merge into supplier ranges handed to the visitor.
 template <class Visit>
 __device__ __forceinline__ void walk_item(Visit &v, const Item &item, const Cluster &cl,
                                           const PairArgs &a, int lane) {
@@ -461,40 +485,63 @@ __device__ __forceinline__ void walk_item(Visit &v, const Item &item, const Clus
     const int tx = cl.tile / (g.nt * g.nt), ty = (cl.tile / g.nt) % g.nt, tz = cl.tile % g.nt;
     const int t0 = item.tiles & 0xff, t1 = (item.tiles >> 8) & 0xff;
     const int s0 = item.subs & 0xffff, s1 = (item.subs >> 16) & 0xffff;
+    const int S = s1 - s0;                 // subtiles of each tile in this item
+    const int E = (t1 - t0) * S;           // (tile, subtile) entries
     const int nss = g.ns * g.ns;
-    for (int t = t0; t < t1; ++t) {
-        int nx = tx + t / 9 - 1, ny = ty + (t / 3) % 3 - 1, nz = tz + t % 3 - 1;
-        int ix = 0, iy = 0, iz = 0;   // image of the supplier tile, in box lengths
-        if (nx < 0) { nx += g.nt; ix = -1; } else if (nx >= g.nt) { nx -= g.nt; ix = 1; }
-        if (ny < 0) { ny += g.nt; iy = -1; } else if (ny >= g.nt) { ny -= g.nt; iy = 1; }
-        if (nz < 0) { nz += g.nt; iz = -1; } else if (nz >= g.nt) { nz -= g.nt; iz = 1; }
-        const double shx = ix * g.box, shy = iy * g.box, shz = iz * g.box;
-        v.tile((ix + 1) * 9 + (iy + 1) * 3 + (iz + 1), (ix | iy | iz) != 0, shx, shy, shz);
-        // origin of the supplier tile's image
-        const double ox = nx * g.tile + shx, oy = ny * g.tile + shy, oz = nz * g.tile + shz;
-        const int cbase = ((nx * g.nt + ny) * g.nt + nz) * g.ns3;
-        for (int base = s0; base < s1; base += kWave) {
-            const int s = base + lane;
-            const int nvalid = min(kWave, s1 - base);
-            bool keep = false;
-            int cstart = 0;
-            if (s < s1) {
-                const int sa = s / nss, sb = (s / g.ns) % g.ns, sc = s % g.ns;
-                const double bx0 = ox + sa * g.sub, by0 = oy + sb * g.sub, bz0 = oz + sc * g.sub;
-                const double gx = fmax(0.0, fmax(bx0 - hi[0], lo[0] - (bx0 + g.sub)));
-                const double gy = fmax(0.0, fmax(by0 - hi[1], lo[1] - (by0 + g.sub)));
-                const double gz = fmax(0.0, fmax(bz0 - hi[2], lo[2] - (bz0 + g.sub)));
-                keep = gx * gx + gy * gy + gz * gz < g.cull2;
-                cstart = cs[cbase + s];
-            }
-            unsigned long long m = ballot64(keep);
+    const float inv_S = 1.0f / (float)S;
+    const float inv_nss = 1.0f / (float)nss;
+    const float inv_ns = 1.0f / (float)g.ns;
+    for (int e0 = 0; e0 < E; e0 += kWave) {
+        const int e = e0 + lane;
+        bool keep = false;
+        int cst = 0, cen = 0;
+        if (e < E) {
+            const int q = div_small(e, inv_S);
+            const int s = s0 + e - q * S;
+            const int t = t0 + q;
+            const int sa = div_small(s, inv_nss);
+            const int r = s - sa * nss;
+            const int sb = div_small(r, inv_ns);
+            const int sc = r - sb * g.ns;
+            // unwrapped tile coordinates of the neighbour tile
+            const int ux = tx + t / 9 - 1, uy = ty + (t / 3) % 3 - 1, uz = tz + t % 3 - 1;
+            const double bx0 = (double)(ux * g.ns + sa) * g.sub;
+            const double by0 = (double)(uy * g.ns + sb) * g.sub;
+            const double bz0 = (double)(uz * g.ns + sc) * g.sub;
+            const double gx = fmax(0.0, fmax(bx0 - hi[0], lo[0] - (bx0 + g.sub)));
+            const double gy = fmax(0.0, fmax(by0 - hi[1], lo[1] - (by0 + g.sub)));
+            const double gz = fmax(0.0, fmax(bz0 - hi[2], lo[2] - (bz0 + g.sub)));
+            keep = gx * gx + gy * gy + gz * gz < g.cull2;
+            const int wx = ux < 0 ? ux + g.nt : (ux >= g.nt ? ux - g.nt : ux);
+            const int wy = uy < 0 ? uy + g.nt : (uy >= g.nt ? uy - g.nt : uy);
+            const int wz = uz < 0 ? uz + g.nt : (uz >= g.nt ? uz - g.nt : uz);
+            const int c = ((wx * g.nt + wy) * g.nt + wz) * g.ns3 + s;
+            cst = cs[c];
+            cen = cs[c + 1];
+        }
+        const unsigned long long mask = ballot64(keep);
+        if (!mask) continue;
+        // the neighbour tiles whose entries lie in this pass
+        const int e1 = min(E, e0 + kWave);
+        for (int q = e0 / S; q * S < e1; ++q) {
+            const int la = max(q * S - e0, 0), lb = min((q + 1) * S - e0, kWave);
+            const unsigned long long range =
+                (lb >= kWave ? ~0ull : ((1ull << lb) - 1ull)) & ~((1ull << la) - 1ull);
+            unsigned long long m = mask & range;
+            if (!m) continue;
+            const int t = t0 + q;
+            int nx = tx + t / 9 - 1, ny = ty + (t / 3) % 3 - 1, nz = tz + t % 3 - 1;
+            const int ix = nx < 0 ? -1 : (nx >= g.nt ? 1 : 0);
+            const int iy = ny < 0 ? -1 : (ny >= g.nt ? 1 : 0);
+            const int iz = nz < 0 ? -1 : (nz >= g.nt ? 1 : 0);
+            v.tile((ix + 1) * 9 + (iy + 1) * 3 + (iz + 1), (ix | iy | iz) != 0, ix * g.box,
+                   iy * g.box, iz * g.box);
             while (m) {
                 const int ra = __builtin_ctzll(m);
                 const unsigned long long rest = ~(m >> ra);
                 const int rb = rest ? ra + __builtin_ctzll(rest) : kWave;   // run [ra, rb)
-                const int j0 = __builtin_amdgcn_readlane(cstart, ra);
-                const int j1 = rb < nvalid ? __builtin_amdgcn_readlane(cstart, rb)
-                                           : cs[cbase + base + rb];
+                const int j0 = __builtin_amdgcn_readlane(cst, ra);
+                const int j1 = __builtin_amdgcn_readlane(cen, rb - 1);
                 m = rb >= kWave ? 0ull : (m & (~0ull << rb));
                 if (j1 > j0) v.run(j0, j1);
             }
@@ -518,18 +565,30 @@ __device__ inline double group_sum(double v, int lane, int grp, int cnt, int G) 
 // the box); the workgroups of XCD x (blockIdx % kXcds, the round-robin
 // dispatch order) draw from chunk x through its own counter, so that XCD's
 // L2 serves a compact set of suppliers, and steal from the other chunks once
-// theirs is empty.  Returns -1 when every chunk is exhausted.
-__device__ inline int next_item(const PairArgs &a, int lane, int &victim) {
+// theirs is empty.  A wave claims a.batch consecutive items per atomic: the
+// counters are device-wide, and one atomic per item would serialise on them.
+// Returns -1 when every chunk is exhausted.
+struct ItemCursor {
+    int cur = 0, end = 0;   // claimed items [cur, end)
+    int victim = 0;         // chunks tried so far, from the home chunk on
+};
+
+__device__ inline int next_item(const PairArgs &a, int lane, ItemCursor &q) {
+    if (q.cur < q.end) return q.cur++;
     const int home = (int)(blockIdx.x % kXcds);
-    while (victim < kXcds) {
-        const int x = (home + victim) % kXcds;
+    while (q.victim < kXcds) {
+        const int x = (home + q.victim) % kXcds;
         const int c0 = (int)((long long)a.n_items * x / kXcds);
         const int c1 = (int)((long long)a.n_items * (x + 1) / kXcds);
         int got = 0;
-        if (lane == 0) got = atomicAdd(&a.queue[x], 1);
+        if (lane == 0) got = atomicAdd(&a.queue[x], a.batch);
         got = __builtin_amdgcn_readfirstlane(got);
-        if (c0 + got < c1) return c0 + got;
-        ++victim;
+        if (c0 + got < c1) {
+            q.cur = c0 + got;
+            q.end = min(c0 + got + a.batch, c1);
+            return q.cur++;
+        }
+        ++q.victim;
     }
     return -1;
 }
@@ -557,9 +616,9 @@ __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
     __shared__ double4 lists[SCREEN ? kForceBlock / kWave : 1][SCREEN ? kListCap + kListSlack : 1];
     const int lane = threadIdx.x & (kWave - 1);
     double4 *list = lists[SCREEN ? threadIdx.x / kWave : 0];
-    int victim = 0;
+    ItemCursor cursor;
     WaveCounts wc;
-    for (int it = next_item(a, lane, victim); it >= 0; it = next_item(a, lane, victim)) {
+    for (int it = next_item(a, lane, cursor); it >= 0; it = next_item(a, lane, cursor)) {
         const Item item = a.items[it];
         const Cluster cl = a.clusters[item.cluster];
         // receivers replicated over G lane groups; lanes past G*cnt are idle

@@ -140,6 +140,7 @@ struct PairArgs {
     double *part;            // per-item partial sums, n_items x 3 x csize
     Counters *counters;
     int n_items;
+    int batch;               // items a wave claims per queue atomic (>= 1)
     int unit_mass;           // no mass array: every mu_j is 1 (forward kernels specialise)
     int csize;               // cluster size (receivers per cluster, 8..64); partial-sum stride
     Geom g;
