@@ -115,8 +115,11 @@ def adjoint_leg(torch, ctx, pos, mass, wl, steps, warmup):
     return out
 
 
-def batched_leg(torch, p3, name, steps, warmup, autotune=True):
-    """All 8 nested rung subsets (rung >= k, k = 0..7) in one persistent launch."""
+def batched_leg(torch, p3, name, steps, warmup, layouts=None):
+    """All 8 nested rung subsets (rung >= k, k = 0..7) in one persistent launch.
+    `layouts` maps precision to the (subtiles, item target, cluster size,
+    screen) the main workload's autotuner chose: tiles hold the same number
+    of particles at every configuration (the PM grid scales with N)."""
     from workloads import make_workload
     log("generating", name, "with rungs")
     wl = make_workload(name)
@@ -127,16 +130,13 @@ def batched_leg(torch, p3, name, steps, warmup, autotune=True):
     ctx = p3.Context(0)
     thr = list(range(8))
     out = torch.empty((8, wl.n, 3), dtype=torch.float64, device=dev)
-    if autotune:
-        for prec in ("fp32", "fp64"):
-            log("autotuning batched", prec)
-            ctx.autotune(pos, mass, None, box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut,
-                         precision=prec, level=1, out=out[0])
     res = {"workload": "%s: N=%d clustered, PM grid %d^3, k-NN density rungs 0-7, 8 nested "
                        "subsets rung>=k in one launch" % (name, wl.n, wl.n_pm),
            "subset_sizes": [int((wl.rung >= k).sum()) for k in thr]}
     for prec in ("fp32", "fp64"):
         kw = dict(box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut, precision=prec)
+        if layouts and prec in layouts:
+            ctx.set_config(*layouts[prec])
         wall = time_calls(torch, lambda: ctx.force_batched(pos, mass, rung, thr, out=out, **kw),
                           max(2, steps // 5), 1)
         ctx.set_timing(True)
@@ -273,8 +273,11 @@ def main():
     if "adjoint" in legs:
         line["adjoint"] = adjoint_leg(torch, ctx, pos, mass, wl, args.steps, args.warmup)
     if "batched" in legs:
+        layouts = {p: tuple(results[p]["stats"][k] for k in
+                            ("subtiles_per_dim", "item_target", "cluster_size", "screen"))
+                   for p in results}
         line["batched"] = batched_leg(torch, p3, args.batched_workload, args.steps, args.warmup,
-                                      autotune=not args.no_autotune)
+                                      layouts=layouts)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -599,16 +599,17 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     r.out = acc_scratch;
     r.stream = s;
     const int nt = tiles_per_dim(box, r_cut);
-    // level 1: subtiles x layout (cluster size, screening) at the default
-    // item size; level 2 also sweeps the item size around the level-1 winner
-    std::vector<int> ns_list = {1, 2, 3, 4, 5, 6};
+    // level 1: subtiles x layout (cluster size, screening) x two item sizes;
+    // level 2 also sweeps the item size around the level-1 winner
+    std::vector<int> ns_list = {1, 2, 3, 4};
     const std::pair<int, int> layouts[] = {{64, 0}, {64, 1}, {32, 1}, {16, 1}, {8, 1}, {16, 0},
                                            {8, 0}};
     hipEvent_t e0, e1;
     P3M_HIP(hipEventCreate(&e0));
     P3M_HIP(hipEventCreate(&e1));
-    float best = 1e30f;
+    float best = 1e30f, best_direct = 1e30f;
     TuneVal best_v{pick_subtiles(nt, n, 0), 1024, kDefaultCsize, kDefaultScreen};
+    TuneVal best_direct_v = best_v;   // fastest unscreened layout (the adjoint's)
     auto trial = [&](const TuneVal &v) -> int {
         r.force_ns = v.ns;
         r.force_target = v.target;
@@ -631,22 +632,29 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
             best = tot;
             best_v = v;
         }
+        if (v.screen == 0 && tot < best_direct) {
+            best_direct = tot;
+            best_direct_v = v;
+        }
         return P3M_OK;
     };
     for (int ns : ns_list) {
         if (pick_subtiles(nt, n, ns) != ns) continue;
         for (const auto &l : layouts)
-            if ((rc = trial(TuneVal{ns, 1024, l.first, l.second}))) return rc;
+            for (int tg : {1024, 4096})
+                if ((rc = trial(TuneVal{ns, tg, l.first, l.second}))) return rc;
     }
     if (level >= 2) {
         const TuneVal base = best_v;
-        for (int tg : {256, 512, 2048, 4096, 8192})
+        for (int tg : {256, 512, 2048, 8192, 16384})
             if ((rc = trial(TuneVal{base.ns, tg, base.csize, base.screen}))) return rc;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    // the adjoint streams suppliers directly (no screen): it takes the
+    // fastest unscreened layout of the forward trials
     h->tuned[TuneKey{n, nt, precision, 0}] = best_v;
-    h->tuned[TuneKey{n, nt, precision, 1}] = best_v;
+    h->tuned[TuneKey{n, nt, precision, 1}] = best_direct_v;
     return P3M_OK;
 }
 
