@@ -11,8 +11,8 @@
 //   clusters  <= csize (8..64) consecutive receivers of one tile per cluster
 //   items     clusters split over their 27 neighbour tiles (work estimate)
 //   [read back the cluster and item totals: the only host synchronisation]
-//   pairs     one persistent launch over all items, per-item partial sums
-//   reduce    partial sums of each cluster's items added in item order
+//   pairs     one persistent launch over all items; an item's sums are stored
+//             (sole item of its cluster) or added with FP64 atomics
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -80,7 +80,7 @@ struct p3m_sr_context {
     int n_cu = 0;
     int blocks_per_cu[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
     DevBuf key, rank, cells, sp, perm, sel, sp2, perm2, sel2, flags, actpos, ncl, clusters,
-        itemcnt, items, bsum, counters, wa, scal, part, rp, rperm, rwa;
+        itemcnt, items, bsum, counters, wa, scal, rp, rperm, rwa;
     int cfg_ns = 0, cfg_target = 0, cfg_csize = 0, cfg_screen = -1;
     std::map<TuneKey, TuneVal> tuned;
     p3m_sr_stats stats{};
@@ -354,9 +354,6 @@ int run(p3m_sr_context *h, const Request &r) {
 
     if ((rc = ensure(h, h->items, sizeof(Item) * (size_t)(n_items > 0 ? n_items : 1), s)))
         return rc;
-    if ((rc = ensure(h, h->part, sizeof(double) * 3 * csize * (size_t)(n_items > 0 ? n_items : 1),
-                     s)))
-        return rc;
     Item *items = (Item *)h->items.p;
     P3M_HIP(launch_item_write(clusters, n_clusters, cells, g, target, itemcnt, items, s));
     double4 *wa = r.backward ? (double4 *)h->wa.p : nullptr;
@@ -378,7 +375,9 @@ int run(p3m_sr_context *h, const Request &r) {
     a.items = items;
     a.wa = wa;
     a.queue = queue;
-    a.part = (double *)h->part.p;
+    a.rperm = (const int *)h->rperm.p;
+    a.out = r.out;
+    a.out_stride = 3ll * n;
     a.counters = counters;
     a.n_items = n_items;
     a.unit_mass = r.mass ? 0 : 1;
@@ -397,8 +396,6 @@ int run(p3m_sr_context *h, const Request &r) {
         P3M_HIP(hipEventRecord(h->ev[2], s));
         h->timed_last = true;
     }
-    P3M_HIP(launch_reduce_items(clusters, n_clusters, itemcnt, (const int *)h->rperm.p,
-                                (double *)h->part.p, csize, r.out, 3ll * n, s));
     if (h->timing) P3M_HIP(hipEventRecord(h->ev[3], s));
     h->stats = st;
     return P3M_OK;
@@ -449,7 +446,7 @@ int p3m_sr_destroy(p3m_sr_handle h) {
     DevBuf *bufs[] = {&h->key,     &h->rank,     &h->cells,  &h->sp,    &h->perm,
                       &h->sel,     &h->sp2,      &h->perm2,  &h->sel2,  &h->flags,
                       &h->actpos,  &h->ncl,      &h->clusters, &h->itemcnt, &h->items,
-                      &h->bsum,    &h->counters, &h->wa,     &h->scal,  &h->part,
+                      &h->bsum,    &h->counters, &h->wa,     &h->scal,
                       &h->rp,      &h->rperm,    &h->rwa};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);

@@ -666,13 +666,19 @@ __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
             ay = group_sum(ay, lane, c.grp, c.cnt, c.G);
             az = group_sum(az, lane, c.grp, c.cnt, c.G);
         }
-        // per-item partial sums (group 0 holds them); a separate pass adds
-        // the items of each cluster in a fixed order
+        // group 0 holds the item's sums: stored when the item is its
+        // cluster's only one, else added (FP64 atomics) into the zeroed output
         if (c.grp == 0) {
-            double *o = a.part + (long long)it * (3 * a.csize) + il;
-            o[0] = ax;
-            o[a.csize] = ay;
-            o[2 * a.csize] = az;
+            double *o = a.out + (long long)cl.subset * a.out_stride + 3ll * a.rperm[cl.begin + il];
+            if (item.sole) {
+                o[0] = ax;
+                o[1] = ay;
+                o[2] = az;
+            } else {
+                atomicAdd(o, ax);
+                atomicAdd(o + 1, ay);
+                atomicAdd(o + 2, az);
+            }
         }
     }
     unsigned long long tot = (unsigned long long)wc.n_ok;
@@ -683,33 +689,6 @@ __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
         atomicAdd(&a.counters->steps, wc.steps);
         atomicAdd(&a.counters->screened, wc.screened);
     }
-}
-
-// acc_out[subset][original index] = sum over the cluster's items of their
-// partials, added in item order (deterministic).  One 64-thread block per
-// cluster.
-__global__ __launch_bounds__(kWave) void k_reduce_items(const Cluster *__restrict__ clusters,
-                                                        const int *__restrict__ item_off,
-                                                        const int *__restrict__ rperm,
-                                                        const double *__restrict__ part,
-                                                        int csize, double *__restrict__ out,
-                                                        long long out_stride) {
-    const int c = blockIdx.x;
-    const Cluster cl = clusters[c];
-    const int il = threadIdx.x;
-    if (il >= cl.count) return;
-    const int i0 = item_off[c], i1 = item_off[c + 1];
-    double x = 0.0, y = 0.0, z = 0.0;
-    for (int it = i0; it < i1; ++it) {
-        const double *q = part + (long long)it * (3 * csize) + il;
-        x += q[0];
-        y += q[csize];
-        z += q[2 * csize];
-    }
-    double *o = out + (long long)cl.subset * out_stride + 3ll * rperm[cl.begin + il];
-    o[0] = x;
-    o[1] = y;
-    o[2] = z;
 }
 
 template <int MODE, int SG>
@@ -736,15 +715,6 @@ void launch_fwd(int sg, const PairArgs &a, dim3 gr, dim3 bl, hipStream_t s) {
 inline int screen_groups(int screen, int csize) { return screen ? kWave / csize : 0; }
 
 }  // namespace
-
-hipError_t launch_reduce_items(const Cluster *clusters, int n_clusters, const int *item_off,
-                               const int *rperm, const double *part, int csize, double *out,
-                               long long out_stride, hipStream_t s) {
-    if (n_clusters <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_items, dim3((unsigned)n_clusters), dim3(kWave), 0, s, clusters,
-                       item_off, rperm, part, csize, out, out_stride);
-    return hipGetLastError();
-}
 
 hipError_t launch_pairs(int mode, int screen, const PairArgs &a, int grid, hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;

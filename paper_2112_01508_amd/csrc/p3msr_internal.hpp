@@ -10,7 +10,8 @@
 //                cell_start[ncells] = n
 //   act_pos[]    sorted indices of the receivers, subset-major, tile order
 //   clusters[]   receiver groups of <= csize (8..64) particles inside one tile
-//   items[]      (cluster, neighbour-tile range, subtile range) work units
+//   items[]      (cluster, neighbour-tile range, subtile range) work units,
+//                the items of one cluster consecutive
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -69,7 +70,7 @@ struct Item {
     int cluster;
     int tiles;    // t0 | t1 << 8
     int subs;     // s0 | s1 << 16
-    int pad;
+    int sole;     // 1: the only item of its cluster (its sums are stored, not added)
 };
 
 struct Counters {
@@ -137,20 +138,19 @@ struct PairArgs {
     const Item *items;
     const double4 *wa;       // backward: suppliers' w * [active], sorted (FP32: float4 bits)
     int *queue;              // kXcds work counters, zero at launch
-    double *part;            // per-item partial sums, n_items x 3 x csize
+    const int *rperm;        // original index of each receiver row (indexed like act_pos)
+    double *out;             // n_sub x n x 3, zeroed before the launch
+    long long out_stride;    // elements per subset in out (3 n)
     Counters *counters;
     int n_items;
     int batch;               // items a wave claims per queue atomic (>= 1)
     int unit_mass;           // no mass array: every mu_j is 1 (forward kernels specialise)
-    int csize;               // cluster size (receivers per cluster, 8..64); partial-sum stride
+    int csize;               // cluster size (receivers per cluster, 8..64)
     Geom g;
 };
 // screen != 0: forward modes test every supplier against the cluster's box
 // first and stream the survivors from LDS
 hipError_t launch_pairs(int mode, int screen, const PairArgs &a, int grid, hipStream_t s);
-hipError_t launch_reduce_items(const Cluster *clusters, int n_clusters, const int *item_off,
-                               const int *rperm, const double *part, int csize, double *out,
-                               long long out_stride, hipStream_t s);
 int pairs_blocks_per_cu(int mode, int screen);
 
 }  // namespace p3m

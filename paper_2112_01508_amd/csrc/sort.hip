@@ -341,7 +341,7 @@ __device__ inline int neighbour_tile(int tile, int t, const Geom &g) {
 // `target` particles is split by subtile ranges.  Returns the item count and
 // writes the items when `out` is non-null.
 __device__ int plan_items(int cidx, const Cluster &cl, const int *__restrict__ cs, const Geom &g,
-                          int target, Item *out) {
+                          int target, Item *out, int sole = 0) {
     int n = 0, acc = 0, t0 = 0;
     auto emit = [&](int a, int b, int s0, int s1) {
         if (out) {
@@ -349,7 +349,7 @@ __device__ int plan_items(int cidx, const Cluster &cl, const int *__restrict__ c
             it.cluster = cidx;
             it.tiles = a | (b << 8);
             it.subs = s0 | (s1 << 16);
-            it.pad = 0;
+            it.sole = sole;
             out[n] = it;
         }
         ++n;
@@ -390,7 +390,8 @@ __global__ void k_item_write(const Cluster *__restrict__ clusters, int n_cluster
                              const int *__restrict__ item_off, Item *__restrict__ items) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_clusters) return;
-    plan_items(c, clusters[c], cs, g, target, items + item_off[c]);
+    plan_items(c, clusters[c], cs, g, target, items + item_off[c],
+               item_off[c + 1] - item_off[c] == 1 ? 1 : 0);
 }
 
 __global__ void k_gather_weights(const double *__restrict__ w, const uint8_t *__restrict__ sel_s,

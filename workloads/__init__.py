@@ -6,7 +6,8 @@ Five particle sets, one per measured configuration:
   clustered128     N = 128^3 clustered (200 halos hold 30%), PM grid 256^3
   clustered256     N = 256^3 clustered, PM grid 512^3, rungs 0-7 from density
   diff64           N = 64^3 clustered, PM grid 128^3, Gaussian loss weights
-  scale512         N = 512^3, 1000 halos hold 50%, PM grid 1024^3, rungs
+  scale512         N = 512^3, 1000 halos hold 50%, PM grid 1024^3, rungs 0-7 from
+                   grid counts
 
 Every set lives in a unit periodic box with G*m = 1, x_s = 1.25 cells and
 r_cut = 4.5 x_s.  Nothing here computes forces.
@@ -15,7 +16,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .generators import (Workload, clustered_positions, gaussian_weights, knn_rungs,
+from .generators import (Workload, clustered_positions, gaussian_weights, grid_rungs, knn_rungs,
                          p3m_scales, rng_for, sample_indices, stratified_by_rung,
                          uniform_positions, wrap_unit, STREAM_LATTICE)
 
@@ -28,7 +29,7 @@ CONFIGS = {
     "diff64": dict(config_id=4, n_side=64, n_pm=128, kind="clustered",
                    n_halos=200, halo_frac=0.30, weights=True),
     "scale512": dict(config_id=5, n_side=512, n_pm=1024, kind="clustered",
-                     n_halos=1000, halo_frac=0.50, rungs=True),
+                     n_halos=1000, halo_frac=0.50, rungs=True, rung_grid=True),
 }
 
 
@@ -52,7 +53,9 @@ def make_workload(name: str, *, n_side: int | None = None, with_rungs: bool | No
                   pos=pos, mass=mass, meta=meta)
     want_rungs = spec.get("rungs", False) if with_rungs is None else with_rungs
     if want_rungs:
-        wl.rung = knn_rungs(pos)
+        # k-NN density for the sets up to 256^3; at 512^3 a k-d tree takes too
+        # long, so counts on an n_side^3 grid summed over 3x3x3 cells are used
+        wl.rung = grid_rungs(pos, n_grid=ns) if spec.get("rung_grid") else knn_rungs(pos)
     if spec.get("weights", False):
         wl.weights = gaussian_weights(n, cid)
     return wl

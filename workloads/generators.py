@@ -82,19 +82,22 @@ def _nfw_mass_profile(x: np.ndarray) -> np.ndarray:
 
 
 def nfw_radii(u: np.ndarray, conc: np.ndarray) -> np.ndarray:
-    """Solve mu(x) = u * mu(c) for x in [0, c] (bisection, vectorised).
+    """Solve mu(x) = u * mu(c) for x in [0, c], mu(x) = ln(1+x) - x/(1+x).
 
-    Returns x/c, the radius in units of the truncation radius R.
+    A tabulated inverse of mu gives the starting point; Newton steps
+    (mu'(x) = x / (1+x)^2) then converge to double precision.  Returns x/c,
+    the radius in units of the truncation radius R.
     """
     target = u * _nfw_mass_profile(conc)
-    lo = np.zeros_like(conc)
-    hi = conc.copy()
-    for _ in range(60):
-        mid = 0.5 * (lo + hi)
-        below = _nfw_mass_profile(mid) < target
-        lo = np.where(below, mid, lo)
-        hi = np.where(below, hi, mid)
-    return 0.5 * (lo + hi) / conc
+    t = np.linspace(0.0, 1.0, 8193)
+    x_tab = float(conc.max()) * t * t                  # denser near 0, where mu ~ x^2/2
+    mu_tab = _nfw_mass_profile(x_tab)
+    x = np.interp(target, mu_tab, x_tab)
+    for _ in range(4):
+        d = x / ((1.0 + x) * (1.0 + x))
+        step = np.where(d > 0, (_nfw_mass_profile(x) - target) / np.where(d > 0, d, 1.0), 0.0)
+        x = np.clip(x - step, 0.0, conc)
+    return x / conc
 
 
 @dataclass
@@ -186,6 +189,28 @@ def knn_rungs(pos: np.ndarray, k: int = 32, box: float = 1.0, max_rung: int = 7,
     dk = d[:, 0]
     ratio = k / ((4.0 / 3.0) * math.pi * dk ** 3 * n / box ** 3)
     rung = np.floor(np.log2(ratio) / exponent_step)
+    return np.clip(rung, 0, max_rung).astype(np.uint8)
+
+
+def grid_rungs(pos: np.ndarray, n_grid: int, box: float = 1.0, max_rung: int = 7,
+               exponent_step: float = 1.5) -> np.ndarray:
+    """Rung from local density for very large sets: clamp(floor(log2(rho/rho_bar)/1.5), 0, 7)
+    with rho/rho_bar estimated from particle counts on an n_grid^3 grid summed
+    over the periodic 3x3x3 block of cells around each particle's cell."""
+    n = pos.shape[0]
+    cell = np.minimum((pos * (n_grid / box)).astype(np.int64), n_grid - 1)
+    flat = (cell[:, 0] * n_grid + cell[:, 1]) * n_grid + cell[:, 2]
+    del cell
+    counts = np.bincount(flat, minlength=n_grid ** 3).astype(np.float32)
+    counts = counts.reshape(n_grid, n_grid, n_grid)
+    block = counts
+    for axis in range(3):
+        block = np.roll(block, 1, axis) + block + np.roll(block, -1, axis)
+    del counts
+    mean = 27.0 * n / float(n_grid) ** 3
+    ratio = block.reshape(-1)[flat] / mean
+    del block, flat
+    rung = np.floor(np.log2(np.maximum(ratio, 1e-30)) / exponent_step)
     return np.clip(rung, 0, max_rung).astype(np.uint8)
 
 
