@@ -45,21 +45,30 @@ def _load():
         build(force=False)
     lib = ctypes.CDLL(_LIB)
     lib.p3o_threads.restype = ctypes.c_int
-    lib.p3o_force.argtypes = [_I64, _P, _P, _D, _D, _D, _I64, _P, _P, _P, _P]
+    lib.p3o_force.argtypes = [_I64, _P, _P, _D, _D, _D, _D, _I64, _P, _P, _P, _P]
     lib.p3o_force.restype = None
-    lib.p3o_force_tiled.argtypes = [_I64, _P, _P, _D, _D, _D, _I64, _P, _P, _P, _P]
+    lib.p3o_force_tiled.argtypes = [_I64, _P, _P, _D, _D, _D, _D, _I64, _P, _P, _P, _P]
     lib.p3o_force_tiled.restype = ctypes.c_int
     lib.p3o_cell_census.argtypes = [_I64, _P, _D, _D, _P, _P]
     lib.p3o_cell_census.restype = ctypes.c_int
-    lib.p3o_vjp.argtypes = [_I64, _P, _P, _P, _P, _D, _D, _D, _I64, _P, _P]
+    lib.p3o_vjp.argtypes = [_I64, _P, _P, _P, _P, _D, _D, _D, _D, _I64, _P, _P]
     lib.p3o_vjp.restype = None
-    lib.p3o_vjp_tiled.argtypes = [_I64, _P, _P, _P, _P, _D, _D, _D, _I64, _P, _P]
+    lib.p3o_vjp_tiled.argtypes = [_I64, _P, _P, _P, _P, _D, _D, _D, _D, _I64, _P, _P]
     lib.p3o_vjp_tiled.restype = ctypes.c_int
-    lib.p3o_fd_grad.argtypes = [_I64, _P, _P, _P, _P, _D, _D, _D, _D, ctypes.c_int, _I64, _P,
-                                _P, _P]
+    lib.p3o_fd_grad.argtypes = [_I64, _P, _P, _P, _P, _D, _D, _D, _D, _D, ctypes.c_int, _I64,
+                                _P, _P, _P]
     lib.p3o_fd_grad.restype = None
     _lib = lib
     return lib
+
+
+# B-spline softening length from the Plummer-equivalent softening length
+# (section 2.1.1, below eq. bspline_force: eps_B = 2.8 eps).
+BSPLINE_PER_PLUMMER = 2.8
+
+
+def eps_b_of(eps: float) -> float:
+    return BSPLINE_PER_PLUMMER * float(eps)
 
 
 def threads() -> int:
@@ -87,7 +96,7 @@ def _receivers(n, active, recv):
     return np.nonzero(active)[0].astype(np.int64)
 
 
-def force(pos, mass, box, x_s, r_cut, recv=None, active=None, method="brute"):
+def force(pos, mass, box, x_s, r_cut, recv=None, active=None, method="brute", eps=0.0):
     """Short-range acceleration of receivers.
 
     Receivers are `recv` (indices) if given, else the particles with a
@@ -95,6 +104,7 @@ def force(pos, mass, box, x_s, r_cut, recv=None, active=None, method="brute"):
     absum[n_recv], recv) where count is the number of accepted pairs and
     absum = sum_j |pair acceleration|.  method "tiled" uses the cell list
     and falls back to brute force when the box holds fewer than 3 cells.
+    eps > 0 adds the B-spline softening bracket with eps_B = 2.8 eps.
     """
     pos, mass, active = _prep(pos, mass, active)
     n = pos.shape[0]
@@ -103,8 +113,8 @@ def force(pos, mass, box, x_s, r_cut, recv=None, active=None, method="brute"):
     cnt = np.zeros(r.size, dtype=np.int64)
     absum = np.zeros(r.size)
     lib = _load()
-    args = (n, _ptr(pos), _ptr(mass), box, x_s, r_cut, r.size, _ptr(r), _ptr(acc), _ptr(cnt),
-            _ptr(absum))
+    args = (n, _ptr(pos), _ptr(mass), box, x_s, r_cut, eps_b_of(eps), r.size, _ptr(r), _ptr(acc),
+            _ptr(cnt), _ptr(absum))
     if method == "tiled" and lib.p3o_force_tiled(*args) == 0:
         pass
     else:
@@ -112,11 +122,12 @@ def force(pos, mass, box, x_s, r_cut, recv=None, active=None, method="brute"):
     return acc, cnt, absum, r
 
 
-def force_full(pos, mass, box, x_s, r_cut, active=None, method="tiled"):
+def force_full(pos, mass, box, x_s, r_cut, active=None, method="tiled", eps=0.0):
     """acc for every particle (zero rows for inactive ones), count, absum."""
     pos, mass, active = _prep(pos, mass, active)
     n = pos.shape[0]
-    acc_r, cnt_r, abs_r, r = force(pos, mass, box, x_s, r_cut, active=active, method=method)
+    acc_r, cnt_r, abs_r, r = force(pos, mass, box, x_s, r_cut, active=active, method=method,
+                                   eps=eps)
     acc = np.zeros((n, 3))
     cnt = np.zeros(n, dtype=np.int64)
     absum = np.zeros(n)
@@ -136,7 +147,7 @@ def cell_census(pos, box, r_cut):
     return c, a
 
 
-def vjp(pos, mass, active, w, box, x_s, r_cut, kidx=None, method="brute"):
+def vjp(pos, mass, active, w, box, x_s, r_cut, kidx=None, method="brute", eps=0.0):
     """dL/dx_k for L = sum_{i active} w_i . a_i at listed k (default all)."""
     pos, mass, active = _prep(pos, mass, active)
     w = np.ascontiguousarray(w, dtype=np.float64)
@@ -144,8 +155,8 @@ def vjp(pos, mass, active, w, box, x_s, r_cut, kidx=None, method="brute"):
     k = np.arange(n, dtype=np.int64) if kidx is None else np.ascontiguousarray(kidx, np.int64)
     g = np.zeros((k.size, 3))
     lib = _load()
-    args = (n, _ptr(pos), _ptr(mass), _ptr(active), _ptr(w), box, x_s, r_cut, k.size, _ptr(k),
-            _ptr(g))
+    args = (n, _ptr(pos), _ptr(mass), _ptr(active), _ptr(w), box, x_s, r_cut, eps_b_of(eps), k.size,
+            _ptr(k), _ptr(g))
     if method == "tiled" and lib.p3o_vjp_tiled(*args) == 0:
         pass
     else:
@@ -153,7 +164,7 @@ def vjp(pos, mass, active, w, box, x_s, r_cut, kidx=None, method="brute"):
     return g
 
 
-def fd_grad(pos, mass, active, w, box, x_s, r_cut, kidx, h=1e-6, mode="fixed"):
+def fd_grad(pos, mass, active, w, box, x_s, r_cut, kidx, h=1e-6, mode="fixed", eps=0.0):
     """Central finite-difference dL/dx_k; returns (grad[n_k,3], straddle[n_k])."""
     pos, mass, active = _prep(pos, mass, active)
     w = np.ascontiguousarray(w, dtype=np.float64)
@@ -161,8 +172,8 @@ def fd_grad(pos, mass, active, w, box, x_s, r_cut, kidx, h=1e-6, mode="fixed"):
     g = np.zeros((k.size, 3))
     st = np.zeros(k.size, dtype=np.uint8)
     _load().p3o_fd_grad(pos.shape[0], _ptr(pos), _ptr(mass), _ptr(active), _ptr(w), box, x_s,
-                        r_cut, h, 0 if mode == "fixed" else 1, k.size, _ptr(k), _ptr(g),
-                        _ptr(st))
+                        r_cut, eps_b_of(eps), h, 0 if mode == "fixed" else 1, k.size, _ptr(k),
+                        _ptr(g), _ptr(st))
     return g, st
 
 

@@ -7,10 +7,19 @@
  * GPU library.
  *
  * What it computes (paper section 2.1.3, lower "short-range" half of
- * eq. p3m_gravity, point-particle shape so the softening bracket vanishes):
+ * eq. p3m_gravity):
  *
- *   a_i = - sum_{j != i, |r_ij| < r_cut} mu_j * g(|r_ij| / (2 x_s)) * r_ij / |r_ij|^3
+ *   a_i = - sum_{j != i, |r_ij| < r_cut} mu_j * phi(|r_ij|) * r_ij
+ *   phi(r) = g(r / (2 x_s)) / r^3  +  [r < eps_b] (|r|_B^-3 - r^-3)
  *   g(u) = erfc(u) + (2/sqrt(pi)) u exp(-u^2)
+ *
+ * The second term is the softening bracket of eq. p3m_gravity with the
+ * B-spline shape (section 2.1.1, eq. bspline_force; eps_b = 2.8 eps, zero
+ * for point particles, where the bracket vanishes).  For r < eps_b the
+ * difference g/r^3 - r^-3 cancels to O(u^3), so it is evaluated as
+ * (g - 1)/r^3 with g - 1 = (2/sqrt(pi)) u exp(-u^2) - erf(u), from its
+ * Maclaurin series for u < 1/2 and in long double above (the same quantity,
+ * written without the cancelling r^-3 terms).
  *
  * where mu_j = G m_j and r_ij = x_i - x_j is taken to the nearest periodic
  * image (the single image n' of eq. p3m_gravity; minimum image per
@@ -56,6 +65,52 @@ static inline double g_sr(double u) {
     return erfc(u) + ORACLE_2_SQRTPI * u * exp(-u * u);
 }
 
+/* |r|_B^-3 of eq. bspline_force, x = r / eps_b < 1. */
+static double bspline_rm3(double x, double eps_b) {
+    const double k = 32.0 / (eps_b * eps_b * eps_b);
+    if (x < 0.5) return k * (x * x * x - 6.0 / 5.0 * x * x + 1.0 / 3.0);
+    return k * (-x * x * x / 3.0 + 6.0 / 5.0 * x * x - 1.5 * x + 2.0 / 3.0
+                - 1.0 / (480.0 * x * x * x));
+}
+
+/* d|r|_B^-3 / dr, x = r / eps_b < 1 (derivative of the expression above). */
+static double bspline_rm3_dr(double x, double eps_b) {
+    const double k = 32.0 / (eps_b * eps_b * eps_b * eps_b);
+    if (x < 0.5) return k * (3.0 * x * x - 12.0 / 5.0 * x);
+    return k * (-x * x + 12.0 / 5.0 * x - 1.5 + 3.0 / (480.0 * x * x * x * x));
+}
+
+/* (g(u) - 1) / r^3 for the softened range, without the cancelling terms.
+ * g - 1 = (2/sqrt(pi)) u exp(-u^2) - erf(u); subtracting the Maclaurin
+ * series of erf(u) = (2/sqrt(pi)) sum_n (-1)^n u^(2n+1) / (n! (2n+1)) from
+ * that of (2/sqrt(pi)) u exp(-u^2) = (2/sqrt(pi)) sum_n (-1)^n u^(2n+1) / n!
+ * term by term gives
+ *   (g - 1) / u^3 = (2/sqrt(pi)) sum_{n>=1} (-1)^n 2n u^(2n-2) / (n! (2n+1)),
+ * used for u < 1/2 (where the direct difference loses the u^3 term to
+ * rounding); above that the direct difference in long double is accurate. */
+static double gm1_over_r3(double r, double x_s) {
+    long double u = (long double)r / (2.0L * (long double)x_s);
+    long double rl = r;
+    if (u < 0.5L) {
+        long double u2 = u * u, term = 1.0L, sum = 0.0L;   /* term = u^(2n-2) / n! */
+        for (int n = 1; n <= 30; ++n) {
+            term = (n == 1) ? 1.0L : term * u2 / n;
+            long double t = (long double)(2 * n) * term / (long double)(2 * n + 1);
+            sum += (n & 1) ? -t : t;
+        }
+        long double h = 1.12837916709551257389615890312154517L * sum;   /* (g-1)/u^3 */
+        return (double)(h / (8.0L * (long double)x_s * x_s * x_s));
+    }
+    long double gm1 = 1.12837916709551257389615890312154517L * u * expl(-u * u) - erfl(u);
+    return (double)(gm1 / (rl * rl * rl));
+}
+
+/* phi(r) of the header: the pair factor of a_i = -sum mu_j phi r_ij. */
+static double pair_phi(double r, double r2, double x_s, double eps_b) {
+    if (eps_b > 0.0 && r < eps_b) return gm1_over_r3(r, x_s) + bspline_rm3(r / eps_b, eps_b);
+    return g_sr(r / (2.0 * x_s)) / (r2 * r);
+}
+
 /* Nearest periodic image of a coordinate difference. */
 static inline double min_image(double d, double box) {
     return d - box * rint(d / box);
@@ -76,10 +131,9 @@ int p3o_threads(void) {
  *   absum  n_recv out: sum_j |pair force| (may be NULL).
  */
 void p3o_force(int64_t n, const double *pos, const double *mass, double box, double x_s,
-               double r_cut, int64_t n_recv, const int64_t *recv, double *acc, int64_t *cnt,
-               double *absum) {
+               double r_cut, double eps_b, int64_t n_recv, const int64_t *recv, double *acc,
+               int64_t *cnt, double *absum) {
     const double rc2 = r_cut * r_cut;
-    const double inv2xs = 1.0 / (2.0 * x_s);
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t q = 0; q < n_recv; ++q) {
         const int64_t i = recv[q];
@@ -95,7 +149,7 @@ void p3o_force(int64_t n, const double *pos, const double *mass, double box, dou
             if (r2 >= rc2 || r2 == 0.0) continue;
             double r = sqrt(r2);
             double mu = mass ? mass[j] : 1.0;
-            double s = mu * g_sr(r * inv2xs) / (r2 * r);
+            double s = mu * pair_phi(r, r2, x_s, eps_b);
             nsum_add(&ax, -s * dx);
             nsum_add(&ay, -s * dy);
             nsum_add(&az, -s * dz);
@@ -162,13 +216,12 @@ static void free_cells(cell_list *cl) {
 }
 
 int p3o_force_tiled(int64_t n, const double *pos, const double *mass, double box, double x_s,
-                    double r_cut, int64_t n_recv, const int64_t *recv, double *acc, int64_t *cnt,
-                    double *absum) {
+                    double r_cut, double eps_b, int64_t n_recv, const int64_t *recv, double *acc,
+                    int64_t *cnt, double *absum) {
     cell_list cl;
     if (build_cells(&cl, n, pos, box, r_cut) != 0) return -1;
     const int nc = cl.nc;
     const double rc2 = r_cut * r_cut;
-    const double inv2xs = 1.0 / (2.0 * x_s);
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t q = 0; q < n_recv; ++q) {
         const int64_t i = recv[q];
@@ -191,7 +244,7 @@ int p3o_force_tiled(int64_t n, const double *pos, const double *mass, double box
                 if (r2 >= rc2 || r2 == 0.0) continue;
                 double r = sqrt(r2);
                 double mu = mass ? mass[j] : 1.0;
-                double s = mu * g_sr(r * inv2xs) / (r2 * r);
+                double s = mu * pair_phi(r, r2, x_s, eps_b);
                 nsum_add(&ax, -s * dx);
                 nsum_add(&ay, -s * dy);
                 nsum_add(&az, -s * dz);
@@ -259,21 +312,32 @@ int p3o_cell_census(int64_t n, const double *pos, double box, double r_cut,
 /* Vector-Jacobian product of the force above with respect to positions.
  *
  * Loss L = sum_{i active} w_i . a_i.  Writing a_i = -sum_j mu_j F(r_ij) with
- * F(r) = phi(|r|) r, phi(r) = g(u)/r^3, u = r/(2 x_s), the Jacobian
- * J(r) = dF/dr = phi I + (phi'(r)/r) r r^T is symmetric and even in r, and
+ * F(r) = phi(|r|) r, the Jacobian J(r) = dF/dr = phi I + (phi'(r)/r) r r^T is
+ * symmetric and even in r, and
  *   dL/dx_k = - sum_{j != k, |r_kj| < r_cut} J(r_kj) (mu_j w_k [k act] - mu_k w_j [j act]).
- * With g'(u) = -(4/sqrt(pi)) u^2 exp(-u^2):
- *   phi'(r)/r = -3 g / r^5 - exp(-u^2) / (2 sqrt(pi) x_s^3 r^2).
- * The pair set is the one of the forward sum (fixed at these positions).
- */
+ * With g'(u) = -(4/sqrt(pi)) u^2 exp(-u^2) and phi = g/r^3:
+ *   phi'(r)/r = -3 g / r^5 - exp(-u^2) / (2 sqrt(pi) x_s^3 r^2);
+ * inside the softening length phi = (g - 1)/r^3 + |r|_B^-3, whose derivative
+ * adds d|r|_B^-3/dr / r + 3 / r^5 (the -3 g / r^5 and +3 / r^5 terms are
+ * combined as -3 (g - 1) / r^5).
+ * The pair set is the one of the forward sum (fixed at these positions). */
 static inline void pair_jvp(double dx, double dy, double dz, double r2, double x_s,
-                            double vx, double vy, double vz, double *ox, double *oy, double *oz) {
+                            double eps_b, double vx, double vy, double vz, double *ox,
+                            double *oy, double *oz) {
     double r = sqrt(r2);
     double u = r / (2.0 * x_s);
     double e = exp(-u * u);
-    double g = erfc(u) + ORACLE_2_SQRTPI * u * e;
-    double phi = g / (r2 * r);
-    double c = 3.0 * g / (r2 * r2 * r) + e / (2.0 * ORACLE_SQRTPI * x_s * x_s * x_s * r2);
+    double gauss = e / (2.0 * ORACLE_SQRTPI * x_s * x_s * x_s * r2);
+    double phi, c;   /* c = -phi'(r) / r */
+    if (eps_b > 0.0 && r < eps_b) {
+        double gm1r3 = gm1_over_r3(r, x_s);
+        phi = gm1r3 + bspline_rm3(r / eps_b, eps_b);
+        c = 3.0 * gm1r3 / r2 + gauss - bspline_rm3_dr(r / eps_b, eps_b) / r;
+    } else {
+        double g = erfc(u) + ORACLE_2_SQRTPI * u * e;
+        phi = g / (r2 * r);
+        c = 3.0 * g / (r2 * r2 * r) + gauss;
+    }
     double rv = dx * vx + dy * vy + dz * vz;
     *ox = phi * vx - c * rv * dx;
     *oy = phi * vy - c * rv * dy;
@@ -281,7 +345,7 @@ static inline void pair_jvp(double dx, double dy, double dz, double r2, double x
 }
 
 void p3o_vjp(int64_t n, const double *pos, const double *mass, const uint8_t *active,
-             const double *w, double box, double x_s, double r_cut, int64_t n_k,
+             const double *w, double box, double x_s, double r_cut, double eps_b, int64_t n_k,
              const int64_t *kidx, double *grad) {
     const double rc2 = r_cut * r_cut;
     #pragma omp parallel for schedule(dynamic, 16)
@@ -304,7 +368,7 @@ void p3o_vjp(int64_t n, const double *pos, const double *mass, const uint8_t *ac
             if (ak) { vx += muj * w[3 * k]; vy += muj * w[3 * k + 1]; vz += muj * w[3 * k + 2]; }
             if (aj) { vx -= muk * w[3 * j]; vy -= muk * w[3 * j + 1]; vz -= muk * w[3 * j + 2]; }
             double ox, oy, oz;
-            pair_jvp(dx, dy, dz, r2, x_s, vx, vy, vz, &ox, &oy, &oz);
+            pair_jvp(dx, dy, dz, r2, x_s, eps_b, vx, vy, vz, &ox, &oy, &oz);
             nsum_add(&gx, -ox);
             nsum_add(&gy, -oy);
             nsum_add(&gz, -oz);
@@ -316,8 +380,8 @@ void p3o_vjp(int64_t n, const double *pos, const double *mass, const uint8_t *ac
 }
 
 int p3o_vjp_tiled(int64_t n, const double *pos, const double *mass, const uint8_t *active,
-                  const double *w, double box, double x_s, double r_cut, int64_t n_k,
-                  const int64_t *kidx, double *grad) {
+                  const double *w, double box, double x_s, double r_cut, double eps_b,
+                  int64_t n_k, const int64_t *kidx, double *grad) {
     cell_list cl;
     if (build_cells(&cl, n, pos, box, r_cut) != 0) return -1;
     const int nc = cl.nc;
@@ -350,7 +414,7 @@ int p3o_vjp_tiled(int64_t n, const double *pos, const double *mass, const uint8_
                 if (ak) { vx += muj * w[3 * k]; vy += muj * w[3 * k + 1]; vz += muj * w[3 * k + 2]; }
                 if (aj) { vx -= muk * w[3 * j]; vy -= muk * w[3 * j + 1]; vz -= muk * w[3 * j + 2]; }
                 double ox, oy, oz;
-                pair_jvp(dx, dy, dz, r2, x_s, vx, vy, vz, &ox, &oy, &oz);
+                pair_jvp(dx, dy, dz, r2, x_s, eps_b, vx, vy, vz, &ox, &oy, &oz);
                 nsum_add(&gx, -ox);
                 nsum_add(&gy, -oy);
                 nsum_add(&gz, -oz);
@@ -376,10 +440,9 @@ int p3o_vjp_tiled(int64_t n, const double *pos, const double *mass, const uint8_
  *                   straddle[q] = 1 when any pair of k changes membership
  *                   between the -h, 0 and +h positions. */
 static double local_loss(int64_t n, const double *pos, const double *mass, const uint8_t *active,
-                         const double *w, double box, double x_s, double r_cut, int64_t k,
-                         const double *y, int mode, int *flip) {
+                         const double *w, double box, double x_s, double r_cut, double eps_b,
+                         int64_t k, const double *y, int mode, int *flip) {
     const double rc2 = r_cut * r_cut;
-    const double inv2xs = 1.0 / (2.0 * x_s);
     const int ak = active ? (active[k] != 0) : 1;
     const double muk = mass ? mass[k] : 1.0;
     nsum L = {0, 0};
@@ -401,7 +464,7 @@ static double local_loss(int64_t n, const double *pos, const double *mass, const
         int use = mode == 0 ? in0 : in1;
         if (!use || r2 == 0.0) continue;
         double r = sqrt(r2);
-        double phi = g_sr(r * inv2xs) / (r2 * r);
+        double phi = pair_phi(r, r2, x_s, eps_b);
         double muj = mass ? mass[j] : 1.0;
         /* F(x_k - x_j) = phi * d, contributes -mu_j F to a_k and +mu_k F to a_j */
         if (ak) nsum_add(&L, -muj * phi * (w[3 * k] * dx + w[3 * k + 1] * dy + w[3 * k + 2] * dz));
@@ -411,8 +474,8 @@ static double local_loss(int64_t n, const double *pos, const double *mass, const
 }
 
 void p3o_fd_grad(int64_t n, const double *pos, const double *mass, const uint8_t *active,
-                 const double *w, double box, double x_s, double r_cut, double h, int mode,
-                 int64_t n_k, const int64_t *kidx, double *grad, uint8_t *straddle) {
+                 const double *w, double box, double x_s, double r_cut, double eps_b, double h,
+                 int mode, int64_t n_k, const int64_t *kidx, double *grad, uint8_t *straddle) {
     #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t q = 0; q < n_k; ++q) {
         const int64_t k = kidx[q];
@@ -422,8 +485,10 @@ void p3o_fd_grad(int64_t n, const double *pos, const double *mass, const uint8_t
             double ym[3] = {yp[0], yp[1], yp[2]};
             yp[d] += h;
             ym[d] -= h;
-            double lp = local_loss(n, pos, mass, active, w, box, x_s, r_cut, k, yp, mode, &flip);
-            double lm = local_loss(n, pos, mass, active, w, box, x_s, r_cut, k, ym, mode, &flip);
+            double lp = local_loss(n, pos, mass, active, w, box, x_s, r_cut, eps_b, k, yp, mode,
+                                   &flip);
+            double lm = local_loss(n, pos, mass, active, w, box, x_s, r_cut, eps_b, k, ym, mode,
+                                   &flip);
             grad[3 * q + d] = (lp - lm) / (2.0 * h);
         }
         if (straddle) straddle[q] = (uint8_t)flip;
