@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="adjoint,batched",
+    ap.add_argument("--legs", default="adjoint,batched,softened",
                     help="extra measured legs beside the forward force: adjoint, batched")
     ap.add_argument("--batched-workload", default="clustered256")
     return ap.parse_args()
@@ -112,6 +112,27 @@ def adjoint_leg(torch, ctx, pos, mass, wl, steps, warmup):
                      "value": st["interactions"] / wall,
                      "achieved_tflops": 60 * st["interactions"] / (st["ms_pairs"] * 1e-3) / 1e12}
         log("adjoint", prec, "%.3f ms" % (wall * 1e3))
+    return out
+
+
+def softened_leg(torch, ctx, pos, mass, wl, steps, warmup):
+    """The B-spline softened force (eps = 0.03 L / cbrt(N), eps_B = 2.8 eps) on
+    the main workload, with the layouts the autotuner chose."""
+    eps = 0.03 / round(wl.n ** (1.0 / 3.0))
+    out = {"eps": eps, "eps_b": 2.8 * eps}
+    ctx.set_softening(eps)
+    try:
+        for prec in ("fp32", "fp64"):
+            _, wall, st, pairs_ms, _ = time_steps(torch, ctx, pos, mass, wl, prec,
+                                                  max(2, steps // 2), warmup)
+            out[prec] = {"ms_per_step": wall * 1e3, "pair_kernel_ms": pairs_ms,
+                         "interactions": st["interactions"],
+                         "value": st["interactions"] / wall,
+                         "achieved_tflops": FLOPS_PER_INTERACTION * st["interactions"]
+                         / (pairs_ms * 1e-3) / 1e12}
+            log("softened", prec, "%.3f ms/step  pairs %.3f ms" % (wall * 1e3, pairs_ms))
+    finally:
+        ctx.set_softening(0.0)
     return out
 
 
@@ -272,6 +293,8 @@ def main():
     legs = [l for l in args.legs.split(",") if l]
     if "adjoint" in legs:
         line["adjoint"] = adjoint_leg(torch, ctx, pos, mass, wl, args.steps, args.warmup)
+    if "softened" in legs:
+        line["softened"] = softened_leg(torch, ctx, pos, mass, wl, args.steps, args.warmup)
     if "batched" in legs:
         layouts = {p: tuple(results[p]["stats"][k] for k in
                             ("subtiles_per_dim", "item_target", "cluster_size", "screen"))

@@ -3,12 +3,15 @@
  *
  * The library computes the short-range ("particle-particle") half of the
  * P3M gravity of the CONCEPT 1.0 paper (arXiv:2112.01508), section 2.1.3,
- * lower half of eq. p3m_gravity with point-particle shape (no softening):
+ * lower half of eq. p3m_gravity, for point particles by default:
  *
  *   a_i = - sum_{j != i, |r_ij| < r_cut} mu_j g(|r_ij| / (2 x_s)) r_ij / |r_ij|^3,
  *   g(u) = erfc(u) + (2 / sqrt(pi)) u exp(-u^2),
  *
- * with mu_j = G m_j and r_ij the separation to the nearest periodic image of
+ * and with the B-spline softening bracket of the same equation when a
+ * softening length is set (p3m_sr_set_softening): mu_j (|r|_B^-3 - |r|^-3) r_ij
+ * is then added for |r_ij| < eps_B.  Here mu_j = G m_j and r_ij is the
+ * separation to the nearest periodic image of
  * j (the single image n' of eq. p3m_gravity).  The sum is strict
  * (|r| < r_cut); a pair at zero separation contributes nothing.  Receivers
  * are the active particles only; every particle is a supplier (section
@@ -79,6 +82,7 @@ typedef struct {
     int32_t screen;          /* 1: suppliers screened against each cluster's box */
     int32_t pad;
     int64_t screened;        /* supplier records tested by the screen (0 without it) */
+    double eps_b;            /* B-spline softening length of the call (0: none) */
 } p3m_sr_stats;
 
 /* Create a context on HIP device `device`.  *h receives the handle. */
@@ -94,7 +98,8 @@ const char *p3m_sr_last_error(void);
 const char *p3m_sr_version(void);
 
 /*
- * Short-range acceleration (section 2.1.3, lower half of eq. p3m_gravity).
+ * Short-range acceleration (section 2.1.3, lower half of eq. p3m_gravity;
+ * with softening when p3m_sr_set_softening set eps > 0).
  *   active  n uint8 (nonzero = receiver) or NULL (all receive).
  *   acc_out n x 3 FP64; rows of non-receivers are set to 0.
  * Ownership: caller owns every array.  Errors: EINVAL for bad geometry,
@@ -170,6 +175,17 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass,
  */
 int p3m_sr_set_config(p3m_sr_handle h, int subtiles_per_dim, int item_target,
                       int cluster_size, int screen);
+
+/*
+ * Softening (section 2.1.1 and the softening bracket of eq. p3m_gravity):
+ * every following force, backward and batched call on this handle adds
+ * mu_j (|r|_B^-3 - |r|^-3) r_ij to the pair force for |r_ij| < eps_B, with
+ * the B-spline |r|_B^-3 of eq. bspline_force and eps_B = 2.8 eps (eps is the
+ * Plummer-equivalent softening length; the paper's choice of eps_B).  The
+ * adjoint differentiates the softened force.  eps = 0 (the default) gives
+ * point particles.  EINVAL for a negative or non-finite eps.
+ */
+int p3m_sr_set_softening(p3m_sr_handle h, double eps);
 
 /*
  * Record HIP events on the call's stream around the build phase and the

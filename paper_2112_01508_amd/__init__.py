@@ -49,7 +49,7 @@ class Stats(ctypes.Structure):
                 ("ms_build", ctypes.c_float), ("ms_pairs", ctypes.c_float),
                 ("ms_total", ctypes.c_float), ("cluster_size", ctypes.c_int32),
                 ("screen", ctypes.c_int32), ("pad", ctypes.c_int32),
-                ("screened", ctypes.c_int64)]
+                ("screened", ctypes.c_int64), ("eps_b", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -73,6 +73,7 @@ EXPORTS = {
     "p3m_sr_autotune": ([_P, _P, _P, _P, _I64, _D, _D, _D, _I, _I, _P, _P], _I),
     "p3m_sr_set_config": ([_P, _I, _I, _I, _I], _I),
     "p3m_sr_set_timing": ([_P, _I], _I),
+    "p3m_sr_set_softening": ([_P, ctypes.c_double], _I),
     "p3m_sr_get_stats": ([_P, ctypes.POINTER(Stats)], _I),
 }
 
@@ -231,6 +232,11 @@ class Context:
         """Fix the decomposition (0 / -1 = automatic); see p3m_sr_set_config."""
         _check(self._lib.p3m_sr_set_config(self._h, int(subtiles_per_dim), int(item_target),
                                            int(cluster_size), int(screen)))
+
+    def set_softening(self, eps=0.0):
+        """B-spline softening with eps_B = 2.8 eps for every following call
+        (0 = point particles); see p3m_sr_set_softening."""
+        _check(self._lib.p3m_sr_set_softening(self._h, float(eps)))
 
     def set_timing(self, enable=True):
         _check(self._lib.p3m_sr_set_timing(self._h, 1 if enable else 0))

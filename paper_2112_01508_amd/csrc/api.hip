@@ -82,6 +82,7 @@ struct p3m_sr_context {
     DevBuf key, rank, cells, sp, perm, sel, sp2, perm2, sel2, flags, actpos, ncl, clusters,
         itemcnt, items, bsum, counters, wa, scal, rp, rperm, rwa;
     int cfg_ns = 0, cfg_target = 0, cfg_csize = 0, cfg_screen = -1;
+    double eps = 0.0;   // Plummer-equivalent softening length (0: point particles)
     std::map<TuneKey, TuneVal> tuned;
     p3m_sr_stats stats{};
     hipStream_t last_stream = nullptr;
@@ -158,7 +159,7 @@ int pick_subtiles(int nt, int64_t n, int requested) {
     return ns;
 }
 
-Geom make_geom(double box, double x_s, double r_cut, int nt, int ns) {
+Geom make_geom(double box, double x_s, double r_cut, int nt, int ns, double eps_b) {
     Geom g{};
     g.box = box;
     g.inv_box = 1.0 / box;
@@ -185,6 +186,14 @@ Geom make_geom(double box, double x_s, double r_cut, int nt, int ns) {
     g.c3f = (float)g.c3;
     static_assert(P3M_H64_DEGREE + 1 <= (int)(sizeof(g.h64) / sizeof(double)), "H64 table");
     for (int k = 0; k <= P3M_H64_DEGREE; ++k) g.h64[k] = kH64[k];
+    if (eps_b > 0.0) {
+        g.eps_b = eps_b;
+        g.eps_b2 = eps_b * eps_b;
+        g.inv_eps_b = 1.0 / eps_b;
+        g.ks3 = 32.0 / (eps_b * eps_b * eps_b);
+        g.ks5 = g.ks3 / (eps_b * eps_b);
+        g.inv_eps_bf = (float)g.inv_eps_b;
+    }
     return g;
 }
 
@@ -213,6 +222,10 @@ constexpr int kDefaultCsize = 64;
 constexpr int kDefaultScreen = 0;
 
 bool valid_csize(int c) { return c == 8 || c == 16 || c == 32 || c == 64; }
+
+// B-spline softening length per Plummer-equivalent one (section 2.1.1, below
+// eq. bspline_force: eps_B = 2.8 eps).
+constexpr double kBsplinePerPlummer = 2.8;
 
 int run(p3m_sr_context *h, const Request &r) {
     hipStream_t s = r.stream;
@@ -244,7 +257,7 @@ int run(p3m_sr_context *h, const Request &r) {
     if (!valid_csize(csize)) csize = kDefaultCsize;
     if (screen < 0) screen = kDefaultScreen;
     if (r.backward) screen = 0;   // the adjoint streams suppliers directly
-    const Geom g = make_geom(r.box, r.x_s, r.r_cut, nt, ns);
+    const Geom g = make_geom(r.box, r.x_s, r.r_cut, nt, ns, kBsplinePerPlummer * h->eps);
     const size_t ncells = (size_t)g.nt3 * g.ns3;
 
     p3m_sr_stats st{};
@@ -255,6 +268,7 @@ int run(p3m_sr_context *h, const Request &r) {
     st.precision = r.precision;
     st.cluster_size = csize;
     st.screen = screen;
+    st.eps_b = kBsplinePerPlummer * h->eps;
     st.ms_build = st.ms_pairs = st.ms_total = -1.0f;
     h->last_stream = s;
     h->timed_last = false;
@@ -652,6 +666,15 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     // fastest unscreened layout of the forward trials
     h->tuned[TuneKey{n, nt, precision, 0}] = best_v;
     h->tuned[TuneKey{n, nt, precision, 1}] = best_direct_v;
+    return P3M_OK;
+}
+
+int p3m_sr_set_softening(p3m_sr_handle h, double eps) {
+    int rc;
+    if (!(eps >= 0.0) || !std::isfinite(eps))
+        return set_error(P3M_EINVAL, "eps must be finite and >= 0");
+    if ((rc = check_handle(h))) return rc;
+    h->eps = eps;
     return P3M_OK;
 }
 

@@ -82,11 +82,35 @@ __device__ inline double dist2(double dx, double dy, double dz) {
     return (xx + yy) + zz;
 }
 
+// ---- B-spline softening (section 2.1.1, eq. bspline_force) --------------------
+
+// For r < eps_b the pair factor g(u)/r^3 = r^-3 + c3 H(t) of the point-particle
+// force gains the softening bracket |r|_B^-3 - r^-3 of eq. p3m_gravity, so it
+// becomes c3 H(t) + |r|_B^-3.  With x = r / eps_b and ks3 = 32 / eps_b^3:
+//   x < 1/2:  |r|_B^-3 = ks3 (x^3 - 6/5 x^2 + 1/3)
+//   x >= 1/2: |r|_B^-3 = ks3 (-x^3/3 + 6/5 x^2 - 3/2 x + 2/3) - r^-3 / 15
+// (the x^-3 / 480 term of eq. bspline_force times ks3 is r^-3 / 15).
+__device__ inline double bspline_m3(double x, double ri3, const Geom &g) {
+    if (x < 0.5) return g.ks3 * fma(x * x, x - 1.2, 1.0 / 3.0);
+    return g.ks3 * fma(fma(fma(-1.0 / 3.0, x, 1.2), x, -1.5), x, 2.0 / 3.0) - ri3 * (1.0 / 15.0);
+}
+
+// -(d|r|_B^-3 / dr) / r, ks5 = 32 / eps_b^5:
+//   x < 1/2:  ks5 (12/5 - 3 x)
+//   x >= 1/2: ks5 (x - 12/5 + 3/2 eps_b / r) - r^-5 / 5
+__device__ inline double bspline_m3_c(double x, double ri, double ri5, const Geom &g) {
+    if (x < 0.5) return g.ks5 * (2.4 - 3.0 * x);
+    return g.ks5 * (x - 2.4 + 1.5 * g.eps_b * ri) - ri5 * 0.2;
+}
+
 // ---- per-pair bodies ---------------------------------------------------------
 
 // Forward, FP32 shape: g(u)/r^3 = r^-3 + H(t) / (2 x_s)^3 with t = u^2 (one
 // hardware rsqrt and one polynomial, no exponential).  UNIT: every mass is 1.
-template <bool UNIT>
+// SOFT: pairs inside the softening length take c3 H(t) + |r|_B^-3, with the
+// softening term in FP64 (it cancels to a few percent of its parts near
+// r = eps_b).
+template <bool UNIT, bool SOFT>
 struct FwdF32 {
     static constexpr bool kNeedW = !UNIT;
     double ax = 0.0, ay = 0.0, az = 0.0;
@@ -96,9 +120,16 @@ struct FwdF32 {
         const float r2f = (float)r2;
         const float ri = __builtin_amdgcn_rsqf(r2f);
         const float h = h_poly(fmaf(r2f, g.c2f, -P3M_HPOLY_T0));
-        const float sh = fmaf(g.c3f, h, ri * ri * ri);
-        const float s = UNIT ? sh : mu_f32(pj.w) * sh;
-        double sd = (double)s;
+        const float ri3 = ri * ri * ri;
+        double sd;
+        if (SOFT && r2 < g.eps_b2) {
+            const double x = (double)(r2f * ri * g.inv_eps_bf);
+            sd = (double)(g.c3f * h) + bspline_m3(x, (double)ri3, g);
+            if (!UNIT) sd *= (double)mu_f32(pj.w);
+        } else {
+            const float sh = fmaf(g.c3f, h, ri3);
+            sd = (double)(UNIT ? sh : mu_f32(pj.w) * sh);
+        }
         ax = fma(-sd, dx, ax);
         ay = fma(-sd, dy, ay);
         az = fma(-sd, dz, az);
@@ -107,7 +138,7 @@ struct FwdF32 {
 
 // Forward, FP64 shape: the same identity g(u)/r^3 = r^-3 + H(t) / (2 x_s)^3
 // with an FP64 rsqrt and a degree-17 polynomial (error 1.5e-15 in g).
-template <bool UNIT>
+template <bool UNIT, bool SOFT>
 struct FwdF64 {
     static constexpr bool kNeedW = !UNIT;
     double ax = 0.0, ay = 0.0, az = 0.0;
@@ -115,7 +146,10 @@ struct FwdF64 {
                                          const double4 &pj, int, const PairArgs &a) {
         const double ri = rsqrt(r2);
         const double h = h64(fma(r2, a.g.c2, -P3M_H64_T0), a.g.h64);
-        const double sh = fma(a.g.c3, h, ri * ri * ri);
+        const double ri3 = ri * ri * ri;
+        double sh;
+        if (SOFT && r2 < a.g.eps_b2) sh = fma(a.g.c3, h, bspline_m3(r2 * ri * a.g.inv_eps_b, ri3, a.g));
+        else sh = fma(a.g.c3, h, ri3);
         const double s = UNIT ? sh : pj.w * sh;
         ax -= s * dx;
         ay -= s * dy;
@@ -127,6 +161,9 @@ struct FwdF64 {
 // J = phi I - c r r^T with phi = g / r^3 = r^-3 + c3 H(t) and
 // c = -(dphi/dr)/r = 3 g / r^5 + exp(-u^2) / (2 sqrt(pi) x_s^3 r^2)
 //   = 3 r^-5 - 2 c2 c3 H'(t)   (t = r^2 c2).
+// Inside the softening length phi = c3 H(t) + |r|_B^-3 and
+// c = -2 c2 c3 H'(t) - (d|r|_B^-3/dr) / r.
+template <bool SOFT>
 struct BwdF64 {
     static constexpr bool kNeedW = true;
     double ax = 0.0, ay = 0.0, az = 0.0;
@@ -141,8 +178,15 @@ struct BwdF64 {
         const double ri2 = ri * ri;
         double dh;
         const double h = h64_d(fma(r2, a.g.c2, -P3M_H64_T0), a.g.h64, dh);
-        const double phi = fma(a.g.c3, h, ri2 * ri);
-        const double c = fma(3.0 * ri2 * ri2, ri, -2.0 * a.g.c2 * a.g.c3 * dh);
+        double phi, c;
+        if (SOFT && r2 < a.g.eps_b2) {
+            const double x = r2 * ri * a.g.inv_eps_b;
+            phi = fma(a.g.c3, h, bspline_m3(x, ri2 * ri, a.g));
+            c = fma(-2.0 * a.g.c2 * a.g.c3, dh, bspline_m3_c(x, ri, ri2 * ri2 * ri, a.g));
+        } else {
+            phi = fma(a.g.c3, h, ri2 * ri);
+            c = fma(3.0 * ri2 * ri2, ri, -2.0 * a.g.c2 * a.g.c3 * dh);
+        }
         double rv = dx * vx + dy * vy + dz * vz;
         ax -= phi * vx - c * rv * dx;
         ay -= phi * vy - c * rv * dy;
@@ -150,6 +194,10 @@ struct BwdF64 {
     }
 };
 
+// FP32 adjoint: phi and c from hardware exp2 and rsqrt with a polynomial for
+// erfcx(u) + 2u/sqrt(pi).  Inside the softening length phi - r^-3 would
+// cancel in FP32, so those pairs take the FP64 H form of BwdF64.
+template <bool SOFT>
 struct BwdF32 {
     static constexpr bool kNeedW = true;
     double ax = 0.0, ay = 0.0, az = 0.0;
@@ -162,6 +210,20 @@ struct BwdF32 {
         float vx = muj * wkx - muk * wj.x;
         float vy = muj * wky - muk * wj.y;
         float vz = muj * wkz - muk * wj.z;
+        if (SOFT && r2 < g.eps_b2) {
+            const double ri = rsqrt(r2);
+            const double ri2 = ri * ri;
+            const double x = r2 * ri * g.inv_eps_b;
+            double dh;
+            const double h = h64_d(fma(r2, g.c2, -P3M_H64_T0), g.h64, dh);
+            const double phi = fma(g.c3, h, bspline_m3(x, ri2 * ri, g));
+            const double c = fma(-2.0 * g.c2 * g.c3, dh, bspline_m3_c(x, ri, ri2 * ri2 * ri, g));
+            const double rv = dx * vx + dy * vy + dz * vz;
+            ax -= phi * vx - c * rv * dx;
+            ay -= phi * vy - c * rv * dy;
+            az -= phi * vz - c * rv * dz;
+            return;
+        }
         float r2f = (float)r2;
         float ri = __builtin_amdgcn_rsqf(r2f);
         float ri2 = ri * ri;
@@ -609,8 +671,8 @@ __device__ __forceinline__ void visit_item(Body &body, const Item &item, const C
 // The persistent pair kernel.  SG > 0 (forward modes only): suppliers are
 // screened against the cluster's box into LDS before the pair loop, with SG =
 // 64 / csize copies of each cluster per wave; SG = 0: suppliers stream
-// directly, with 64 / count copies.
-template <int MODE, bool UNIT, int SG>
+// directly, with 64 / count copies.  SOFT: B-spline softening inside eps_b.
+template <int MODE, bool UNIT, int SG, bool SOFT>
 __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
     constexpr bool SCREEN = SG > 0;
     __shared__ double4 lists[SCREEN ? kForceBlock / kWave : 1][SCREEN ? kListCap + kListSlack : 1];
@@ -641,21 +703,21 @@ __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
         c.zi = xp.z + far;
         double ax, ay, az;
         if constexpr (MODE == FWD_F32) {
-            FwdF32<UNIT> b;
+            FwdF32<UNIT, SOFT> b;
             visit_item<SG>(b, item, cl, c, a, wc, list);
             ax = b.ax; ay = b.ay; az = b.az;
         } else if constexpr (MODE == FWD_F64) {
-            FwdF64<UNIT> b;
+            FwdF64<UNIT, SOFT> b;
             visit_item<SG>(b, item, cl, c, a, wc, list);
             ax = b.ax; ay = b.ay; az = b.az;
         } else if constexpr (MODE == BWD_F64) {
-            BwdF64 b;
+            BwdF64<SOFT> b;
             const double4 w = a.rwa[cl.begin + il];
             b.wkx = w.x; b.wky = w.y; b.wkz = w.z; b.muk = xp.w;
             visit_item<0>(b, item, cl, c, a, wc, list);
             ax = b.ax; ay = b.ay; az = b.az;
         } else {
-            BwdF32 b;
+            BwdF32<SOFT> b;
             const float4 w = reinterpret_cast<const float4 *>(a.rwa)[cl.begin + il];
             b.wkx = w.x; b.wky = w.y; b.wkz = w.z; b.muk = mu_f32(xp.w);
             visit_item<0>(b, item, cl, c, a, wc, list);
@@ -694,21 +756,27 @@ __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
 template <int MODE, int SG>
 int blocks_per_cu_of() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs<MODE, false, SG>, kForceBlock,
-                                                     0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs<MODE, false, SG, false>,
+                                                     kForceBlock, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
+template <int MODE, bool UNIT, bool SOFT>
+void launch_fwd_soft(int sg, const PairArgs &a, dim3 gr, dim3 bl, hipStream_t s) {
+    switch (sg) {
+    case 1: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 1, SOFT>), gr, bl, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 2, SOFT>), gr, bl, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 4, SOFT>), gr, bl, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 8, SOFT>), gr, bl, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 0, SOFT>), gr, bl, 0, s, a); break;
+    }
+}
+
 template <int MODE, bool UNIT>
 void launch_fwd(int sg, const PairArgs &a, dim3 gr, dim3 bl, hipStream_t s) {
-    switch (sg) {
-    case 1: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 1>), gr, bl, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 2>), gr, bl, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 4>), gr, bl, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 8>), gr, bl, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 0>), gr, bl, 0, s, a); break;
-    }
+    if (a.g.eps_b > 0.0) launch_fwd_soft<MODE, UNIT, true>(sg, a, gr, bl, s);
+    else launch_fwd_soft<MODE, UNIT, false>(sg, a, gr, bl, s);
 }
 
 // screen groups: 64 / csize when screening (csize in {8, 16, 32, 64}), else 0
@@ -730,8 +798,14 @@ hipError_t launch_pairs(int mode, int screen, const PairArgs &a, int grid, hipSt
         if (a.unit_mass) launch_fwd<FWD_F64, true>(sg, a, gr, bl, s);
         else launch_fwd<FWD_F64, false>(sg, a, gr, bl, s);
         break;
-    case BWD_F32: hipLaunchKernelGGL((k_pairs<BWD_F32, false, 0>), gr, bl, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_pairs<BWD_F64, false, 0>), gr, bl, 0, s, a); break;
+    case BWD_F32:
+        if (a.g.eps_b > 0.0) hipLaunchKernelGGL((k_pairs<BWD_F32, false, 0, true>), gr, bl, 0, s, a);
+        else hipLaunchKernelGGL((k_pairs<BWD_F32, false, 0, false>), gr, bl, 0, s, a);
+        break;
+    default:
+        if (a.g.eps_b > 0.0) hipLaunchKernelGGL((k_pairs<BWD_F64, false, 0, true>), gr, bl, 0, s, a);
+        else hipLaunchKernelGGL((k_pairs<BWD_F64, false, 0, false>), gr, bl, 0, s, a);
+        break;
     }
     return hipGetLastError();
 }

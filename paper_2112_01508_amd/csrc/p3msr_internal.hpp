@@ -52,6 +52,11 @@ struct Geom {
     float c3f;         // 1 / (8 x_s^3): g(u) / r^3 = r^-3 + H(t) c3
     double c2, c3;     // FP64 copies of c2f and c3f
     double h64[18];    // FP64 H coefficients (kernel argument, so they sit in SGPRs)
+    double eps_b;      // B-spline softening length (0: point particles)
+    double eps_b2;     // eps_b^2: pairs with r^2 < eps_b2 take the softened form
+    double inv_eps_b;  // 1 / eps_b
+    double ks3, ks5;   // 32 / eps_b^3, 32 / eps_b^5
+    float inv_eps_bf;  // FP32 copy of inv_eps_b
 };
 
 struct Cluster {
