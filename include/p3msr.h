@@ -165,11 +165,11 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass,
  *                     sub-cells, so a cluster of consecutive receivers is
  *                     spatially compact; a wavefront carries 64 / cluster_size
  *                     copies of a cluster that walk different suppliers;
- *   screen            1: forward calls test each supplier of the surviving
- *                     subtiles against the cluster's bounding box before the
- *                     pair loop (the subtile-pair culling of section 2.1.3
+ *   screen            1: each supplier of the surviving subtiles is tested
+ *                     against the cluster's bounding box before the pair
+ *                     loop (the subtile-pair culling of section 2.1.3
  *                     carried down to single suppliers); 0: no screening;
- *                     -1: automatic.  The adjoint never screens.
+ *                     -1: automatic.
  * EINVAL outside those ranges.  Results do not depend on these settings
  * beyond FP64 summation order.
  */

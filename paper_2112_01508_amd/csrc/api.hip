@@ -256,7 +256,6 @@ int run(p3m_sr_context *h, const Request &r) {
     if (target <= 0) target = 1024;
     if (!valid_csize(csize)) csize = kDefaultCsize;
     if (screen < 0) screen = kDefaultScreen;
-    if (r.backward) screen = 0;   // the adjoint streams suppliers directly
     const Geom g = make_geom(r.box, r.x_s, r.r_cut, nt, ns, kBsplinePerPlummer * h->eps);
     const size_t ncells = (size_t)g.nt3 * g.ns3;
 
@@ -618,9 +617,8 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     hipEvent_t e0, e1;
     P3M_HIP(hipEventCreate(&e0));
     P3M_HIP(hipEventCreate(&e1));
-    float best = 1e30f, best_direct = 1e30f;
+    float best = 1e30f;
     TuneVal best_v{pick_subtiles(nt, n, 0), 1024, kDefaultCsize, kDefaultScreen};
-    TuneVal best_direct_v = best_v;   // fastest unscreened layout (the adjoint's)
     auto trial = [&](const TuneVal &v) -> int {
         r.force_ns = v.ns;
         r.force_target = v.target;
@@ -643,10 +641,6 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
             best = tot;
             best_v = v;
         }
-        if (v.screen == 0 && tot < best_direct) {
-            best_direct = tot;
-            best_direct_v = v;
-        }
         return P3M_OK;
     };
     for (int ns : ns_list) {
@@ -662,10 +656,9 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    // the adjoint streams suppliers directly (no screen): it takes the
-    // fastest unscreened layout of the forward trials
+    // the adjoint walks the same decomposition: it takes the forward winner
     h->tuned[TuneKey{n, nt, precision, 0}] = best_v;
-    h->tuned[TuneKey{n, nt, precision, 1}] = best_direct_v;
+    h->tuned[TuneKey{n, nt, precision, 1}] = best_v;
     return P3M_OK;
 }
 

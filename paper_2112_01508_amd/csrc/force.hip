@@ -113,7 +113,13 @@ __device__ inline double bspline_m3_c(double x, double ri, double ri5, const Geo
 template <bool UNIT, bool SOFT>
 struct FwdF32 {
     static constexpr bool kNeedW = !UNIT;
+    static constexpr bool kHasW = false;   // no per-supplier adjoint weight
+    using WT = float;
     double ax = 0.0, ay = 0.0, az = 0.0;
+    __device__ __forceinline__ void pair_w(double dx, double dy, double dz, double r2,
+                                           const double4 &pj, const WT &, const PairArgs &a) {
+        pair(dx, dy, dz, r2, pj, 0, a);
+    }
     __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
                                          const double4 &pj, int, const PairArgs &a) {
         const Geom &g = a.g;
@@ -141,7 +147,13 @@ struct FwdF32 {
 template <bool UNIT, bool SOFT>
 struct FwdF64 {
     static constexpr bool kNeedW = !UNIT;
+    static constexpr bool kHasW = false;   // no per-supplier adjoint weight
+    using WT = float;
     double ax = 0.0, ay = 0.0, az = 0.0;
+    __device__ __forceinline__ void pair_w(double dx, double dy, double dz, double r2,
+                                           const double4 &pj, const WT &, const PairArgs &a) {
+        pair(dx, dy, dz, r2, pj, 0, a);
+    }
     __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
                                          const double4 &pj, int, const PairArgs &a) {
         const double ri = rsqrt(r2);
@@ -166,11 +178,18 @@ struct FwdF64 {
 template <bool SOFT>
 struct BwdF64 {
     static constexpr bool kNeedW = true;
+    static constexpr bool kHasW = true;    // supplier weight w_j [j active]
+    using WT = double4;
     double ax = 0.0, ay = 0.0, az = 0.0;
     double wkx, wky, wkz, muk;
+    __device__ __forceinline__ static WT weight(const PairArgs &a, int j) { return a.wa[j]; }
     __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
                                          const double4 &pj, int j, const PairArgs &a) {
-        const double4 wj = a.wa[j];   // j may be wave-uniform or per lane
+        pair_w(dx, dy, dz, r2, pj, a.wa[j], a);   // j may be wave-uniform or per lane
+    }
+    __device__ __forceinline__ void pair_w(double dx, double dy, double dz, double r2,
+                                           const double4 &pj, const double4 &wj,
+                                           const PairArgs &a) {
         double vx = pj.w * wkx - muk * wj.x;
         double vy = pj.w * wky - muk * wj.y;
         double vz = pj.w * wkz - muk * wj.z;
@@ -200,12 +219,21 @@ struct BwdF64 {
 template <bool SOFT>
 struct BwdF32 {
     static constexpr bool kNeedW = true;
+    static constexpr bool kHasW = true;    // supplier weight w_j [j active], FP32
+    using WT = float4;
     double ax = 0.0, ay = 0.0, az = 0.0;
     float wkx, wky, wkz, muk;
+    __device__ __forceinline__ static WT weight(const PairArgs &a, int j) {
+        return reinterpret_cast<const float4 *>(a.wa)[j];
+    }
     __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
                                          const double4 &pj, int j, const PairArgs &a) {
+        pair_w(dx, dy, dz, r2, pj, weight(a, j), a);
+    }
+    __device__ __forceinline__ void pair_w(double dx, double dy, double dz, double r2,
+                                           const double4 &pj, const float4 &wj,
+                                           const PairArgs &a) {
         const Geom &g = a.g;
-        const float4 wj = reinterpret_cast<const float4 *>(a.wa)[j];
         const float muj = mu_f32(pj.w);
         float vx = muj * wkx - muk * wj.x;
         float vy = muj * wky - muk * wj.y;
@@ -358,18 +386,47 @@ __device__ __forceinline__ void list_write(double4 *p, const double4 &v) {
     }
 }
 
+// One receiver lane against one listed supplier that carries its adjoint
+// weight (the weight is unused by the forward bodies).
+template <bool SHIFT, class Body>
+__device__ __forceinline__ void test_pair_w(Body &body, double xi, double yi, double zi,
+                                            const double4 &pj, const typename Body::WT &wj,
+                                            double shx, double shy, double shz,
+                                            const PairArgs &a, int &n_ok) {
+    double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
+    if (SHIFT) {
+        dx -= shx;
+        dy -= shy;
+        dz -= shz;
+    }
+    const double r2 = dist2(dx, dy, dz);
+    if ((r2 < a.g.rc2) & (r2 > 0.0)) {
+        ++n_ok;   // per-lane count of accepted pairs
+        body.pair_w(dx, dy, dz, r2, pj, wj, a);
+    }
+}
+
+// wp: this lane's view of the list's weights (adjoint bodies only).
 template <int G, bool SHIFT, class Body>
-__device__ __forceinline__ void list_loop(Body &body, const double4 *p, int n_list, double xi,
+__device__ __forceinline__ void list_loop(Body &body, const double4 *p,
+                                          const typename Body::WT *wp, int n_list, double xi,
                                           double yi, double zi, double shx, double shy,
                                           double shz, const PairArgs &a, int &n_ok) {
     constexpr bool W = Body::kNeedW;
+    using WT = typename Body::WT;
     double4 A = list_read<W>(p);
+    WT wA{};
+    if constexpr (Body::kHasW) wA = wp[0];
     for (int k = 0; k < n_list; k += 2 * G) {
         const double4 *q = p + k;
         const double4 B = list_read<W>(q + G);
-        test_pair<SHIFT>(body, xi, yi, zi, A, 0, true, shx, shy, shz, a, n_ok);
+        WT wB{};
+        if constexpr (Body::kHasW) wB = wp[k + G];
+        test_pair_w<SHIFT>(body, xi, yi, zi, A, wA, shx, shy, shz, a, n_ok);
         A = list_read<W>(q + 2 * G);
-        if (k + G < n_list) test_pair<SHIFT>(body, xi, yi, zi, B, 0, true, shx, shy, shz, a, n_ok);
+        if constexpr (Body::kHasW) wA = wp[k + 2 * G];
+        if (k + G < n_list)
+            test_pair_w<SHIFT>(body, xi, yi, zi, B, wB, shx, shy, shz, a, n_ok);
     }
 }
 
@@ -432,7 +489,7 @@ struct DirectVisit {
 // The list goes to the pair loop when it is nearly full, when the next tile
 // has another periodic image, and at the end of the item.  G = 64 / csize
 // copies of the cluster share the wave.
-template <int G, class Body>
+template <int G, int CAP, class Body>
 struct ScreenVisit {
     static constexpr bool W = Body::kNeedW;
     Body &body;
@@ -440,6 +497,7 @@ struct ScreenVisit {
     const PairArgs &a;
     WaveCounts &wc;
     double4 *list;
+    typename Body::WT *wlist;   // adjoint: the listed suppliers' weights (else unused)
     int n_list = 0;
     int code = -1;   // periodic image of the records in the list and the open chunk
     double shx = 0.0, shy = 0.0, shz = 0.0;
@@ -456,10 +514,12 @@ struct ScreenVisit {
         wc.cand += (unsigned long long)n_list * (unsigned long long)c.cnt;
         wc.steps += (unsigned long long)((n_list + G - 1) / G);
         const double4 *p = list + c.rgrp;
+        const typename Body::WT *wp = wlist + c.rgrp;
         if (code != 13)
-            list_loop<G, true>(body, p, n_list, c.xi, c.yi, c.zi, shx, shy, shz, a, wc.n_ok);
+            list_loop<G, true>(body, p, wp, n_list, c.xi, c.yi, c.zi, shx, shy, shz, a, wc.n_ok);
         else
-            list_loop<G, false>(body, p, n_list, c.xi, c.yi, c.zi, 0.0, 0.0, 0.0, a, wc.n_ok);
+            list_loop<G, false>(body, p, wp, n_list, c.xi, c.yi, c.zi, 0.0, 0.0, 0.0, a,
+                                wc.n_ok);
         wave_lds_sync();
         n_list = 0;
     }
@@ -487,10 +547,15 @@ struct ScreenVisit {
         const unsigned long long m = ballot64(keep) & tail;
         const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                   __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-        if (keep) list_write<W>(list + n_list + off, p);
+        if (keep) {
+            list_write<W>(list + n_list + off, p);
+            // the adjoint's supplier weight (the padded weight array covers
+            // the reads of lanes past `fill`)
+            if constexpr (Body::kHasW) wlist[n_list + off] = Body::weight(a, jj + c.lane);
+        }
         n_list += __builtin_popcountll(m);
         fill = 0;
-        if (n_list > kListCap - kWave) flush();   // keeps n_list <= kListCap
+        if (n_list > CAP - kWave) flush();   // keeps n_list <= CAP
     }
     __device__ __forceinline__ void tile(int img, bool, double x, double y, double z) {
         if (img != code) {
@@ -655,18 +720,23 @@ __device__ inline int next_item(const PairArgs &a, int lane, ItemCursor &q) {
     return -1;
 }
 
-template <int SG, class Body>
+template <int SG, int CAP, class Body>
 __device__ __forceinline__ void visit_item(Body &body, const Item &item, const Cluster &cl,
                                            const ItemCtx &c, const PairArgs &a, WaveCounts &wc,
-                                           double4 *list) {
+                                           double4 *list, void *wlist) {
     if constexpr (SG > 0) {
-        ScreenVisit<SG, Body> v{body, c, a, wc, list};
+        ScreenVisit<SG, CAP, Body> v{body, c, a, wc, list, (typename Body::WT *)wlist};
         walk_item(v, item, cl, a, c.lane);
     } else {
         DirectVisit<Body> v{body, c, a, wc};
         walk_item(v, item, cl, a, c.lane);
     }
 }
+
+// Per-supplier adjoint weight kept beside a screened list entry.
+template <int MODE> struct ModeWeight { using T = float; };
+template <> struct ModeWeight<BWD_F64> { using T = double4; };
+template <> struct ModeWeight<BWD_F32> { using T = float4; };
 
 // The persistent pair kernel.  SG > 0 (forward modes only): suppliers are
 // screened against the cluster's box into LDS before the pair loop, with SG =
@@ -675,9 +745,17 @@ __device__ __forceinline__ void visit_item(Body &body, const Item &item, const C
 template <int MODE, bool UNIT, int SG, bool SOFT>
 __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
     constexpr bool SCREEN = SG > 0;
-    __shared__ double4 lists[SCREEN ? kForceBlock / kWave : 1][SCREEN ? kListCap + kListSlack : 1];
+    constexpr bool BWD = MODE == BWD_F32 || MODE == BWD_F64;
+    // the adjoint's list entries also carry the supplier's weight: a
+    // shorter list keeps the LDS per block at or below 40 KB
+    constexpr int CAP = BWD ? kListCapAdjoint : kListCap;
+    constexpr int NW = kForceBlock / kWave;
+    using WTk = typename ModeWeight<MODE>::T;
+    __shared__ double4 lists[SCREEN ? NW : 1][SCREEN ? CAP + kListSlack : 1];
+    __shared__ WTk wlists[SCREEN && BWD ? NW : 1][SCREEN && BWD ? CAP + kListSlack : 1];
     const int lane = threadIdx.x & (kWave - 1);
     double4 *list = lists[SCREEN ? threadIdx.x / kWave : 0];
+    void *wlist = wlists[SCREEN && BWD ? threadIdx.x / kWave : 0];
     ItemCursor cursor;
     WaveCounts wc;
     for (int it = next_item(a, lane, cursor); it >= 0; it = next_item(a, lane, cursor)) {
@@ -704,23 +782,23 @@ __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
         double ax, ay, az;
         if constexpr (MODE == FWD_F32) {
             FwdF32<UNIT, SOFT> b;
-            visit_item<SG>(b, item, cl, c, a, wc, list);
+            visit_item<SG, CAP>(b, item, cl, c, a, wc, list, wlist);
             ax = b.ax; ay = b.ay; az = b.az;
         } else if constexpr (MODE == FWD_F64) {
             FwdF64<UNIT, SOFT> b;
-            visit_item<SG>(b, item, cl, c, a, wc, list);
+            visit_item<SG, CAP>(b, item, cl, c, a, wc, list, wlist);
             ax = b.ax; ay = b.ay; az = b.az;
         } else if constexpr (MODE == BWD_F64) {
             BwdF64<SOFT> b;
             const double4 w = a.rwa[cl.begin + il];
             b.wkx = w.x; b.wky = w.y; b.wkz = w.z; b.muk = xp.w;
-            visit_item<0>(b, item, cl, c, a, wc, list);
+            visit_item<SG, CAP>(b, item, cl, c, a, wc, list, wlist);
             ax = b.ax; ay = b.ay; az = b.az;
         } else {
             BwdF32<SOFT> b;
             const float4 w = reinterpret_cast<const float4 *>(a.rwa)[cl.begin + il];
             b.wkx = w.x; b.wky = w.y; b.wkz = w.z; b.muk = mu_f32(xp.w);
-            visit_item<0>(b, item, cl, c, a, wc, list);
+            visit_item<SG, CAP>(b, item, cl, c, a, wc, list, wlist);
             ax = b.ax; ay = b.ay; az = b.az;
         }
         if (c.G > 1) {
@@ -798,26 +876,20 @@ hipError_t launch_pairs(int mode, int screen, const PairArgs &a, int grid, hipSt
         if (a.unit_mass) launch_fwd<FWD_F64, true>(sg, a, gr, bl, s);
         else launch_fwd<FWD_F64, false>(sg, a, gr, bl, s);
         break;
-    case BWD_F32:
-        if (a.g.eps_b > 0.0) hipLaunchKernelGGL((k_pairs<BWD_F32, false, 0, true>), gr, bl, 0, s, a);
-        else hipLaunchKernelGGL((k_pairs<BWD_F32, false, 0, false>), gr, bl, 0, s, a);
-        break;
-    default:
-        if (a.g.eps_b > 0.0) hipLaunchKernelGGL((k_pairs<BWD_F64, false, 0, true>), gr, bl, 0, s, a);
-        else hipLaunchKernelGGL((k_pairs<BWD_F64, false, 0, false>), gr, bl, 0, s, a);
-        break;
+    case BWD_F32: launch_fwd<BWD_F32, false>(sg, a, gr, bl, s); break;
+    default: launch_fwd<BWD_F64, false>(sg, a, gr, bl, s); break;
     }
     return hipGetLastError();
 }
 
 int pairs_blocks_per_cu(int mode, int screen) {
-    // every screened variant has the same LDS footprint; use G = 8's count
-    const bool sc = screen != 0 && (mode == FWD_F32 || mode == FWD_F64);
+    // every screened variant of a mode has the same LDS footprint; use G = 8's count
+    const bool sc = screen != 0;
     switch (mode) {
     case FWD_F32: return sc ? blocks_per_cu_of<FWD_F32, 8>() : blocks_per_cu_of<FWD_F32, 0>();
     case FWD_F64: return sc ? blocks_per_cu_of<FWD_F64, 8>() : blocks_per_cu_of<FWD_F64, 0>();
-    case BWD_F32: return blocks_per_cu_of<BWD_F32, 0>();
-    default: return blocks_per_cu_of<BWD_F64, 0>();
+    case BWD_F32: return sc ? blocks_per_cu_of<BWD_F32, 8>() : blocks_per_cu_of<BWD_F32, 0>();
+    default: return sc ? blocks_per_cu_of<BWD_F64, 8>() : blocks_per_cu_of<BWD_F64, 0>();
     }
 }
 

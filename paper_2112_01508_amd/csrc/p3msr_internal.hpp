@@ -31,6 +31,7 @@ constexpr int kFineSide = 8;                // fine order: 8x8x8 sub-cells per s
 constexpr int kFineBins = kFineSide * kFineSide * kFineSide;
 constexpr int kFineMin = 8;                 // subtiles with at most this many keep their order
 constexpr int kListCap = 224;               // screened supplier records per wave (LDS)
+constexpr int kListCapAdjoint = 128;        // the same for the adjoint (entries carry weights)
 constexpr int kListSlack = 32;              // records past the cap for look-ahead reads (3*8 used)
 
 // Geometry of one call.  Tiles are cubes of side box/nt >= r_cut; each tile
@@ -153,8 +154,8 @@ struct PairArgs {
     int csize;               // cluster size (receivers per cluster, 8..64)
     Geom g;
 };
-// screen != 0: forward modes test every supplier against the cluster's box
-// first and stream the survivors from LDS
+// screen != 0: every supplier is tested against the cluster's box first and
+// the survivors (with the adjoint's weights) stream from LDS
 hipError_t launch_pairs(int mode, int screen, const PairArgs &a, int grid, hipStream_t s);
 int pairs_blocks_per_cu(int mode, int screen);
 

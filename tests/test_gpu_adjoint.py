@@ -46,26 +46,27 @@ def test_vjp_matches_oracle(env, prec, tol, frac):
         assert np.all(g[zero] == 0)
 
 
-@pytest.mark.parametrize("csize", [8, 16, 32])
+@pytest.mark.parametrize("csize,screen", [(8, 1), (16, 1), (32, 1), (64, 1), (16, 0), (32, 0)])
 @pytest.mark.parametrize("prec, tol", [("fp64", 1e-12), ("fp32", 1e-5)])
-def test_vjp_small_clusters(env, prec, tol, csize):
-    """The adjoint on small clusters (several copies of a cluster per wave)
-    matches the oracle's VJP like the default layout does."""
+def test_vjp_small_clusters(env, prec, tol, csize, screen):
+    """The adjoint on small clusters (several copies of a cluster per wave),
+    with and without the per-supplier screen (the listed suppliers carry
+    their weights), matches the oracle's VJP like the default layout does."""
     torch, p3, ctx = env
-    print("vjp clustered n_side=24 csize", csize, prec, flush=True)
+    print("vjp clustered n_side=24 csize", csize, "screen", screen, prec, flush=True)
     wl = make_workload("diff64", n_side=24)
     rng = np.random.default_rng(12)
     mass = rng.uniform(0.5, 2.0, wl.n)
     active = (rng.random(wl.n) < 0.5).astype(np.uint8)
     w = rng.standard_normal((wl.n, 3))
     ref = oracle.vjp(wl.pos, mass, active, w, 1.0, wl.x_s, wl.r_cut, method="tiled")
-    ctx.set_config(cluster_size=csize, screen=1)   # the adjoint ignores screening
+    ctx.set_config(cluster_size=csize, screen=screen)
     try:
         g = gpu_vjp(env, wl.pos, mass, active, w, 1.0, wl.x_s, wl.r_cut, prec)
         st = ctx.stats()
     finally:
         ctx.set_config()
-    assert st["cluster_size"] == csize and st["screen"] == 0
+    assert st["cluster_size"] == csize and st["screen"] == screen
     rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
     row = np.max(np.linalg.norm(g - ref, axis=1)) / np.max(np.linalg.norm(ref, axis=1))
     assert rel <= tol and row <= tol, (rel, row)
