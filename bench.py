@@ -110,7 +110,9 @@ def adjoint_leg(torch, ctx, pos, mass, wl, steps, warmup):
         out[prec] = {"ms_per_call": wall * 1e3, "pair_kernel_ms": st["ms_pairs"],
                      "interactions": st["interactions"],
                      "value": st["interactions"] / wall,
-                     "achieved_tflops": 60 * st["interactions"] / (st["ms_pairs"] * 1e-3) / 1e12}
+                     "achieved_tflops": 60 * st["interactions"] / (st["ms_pairs"] * 1e-3) / 1e12,
+                     "layout": {k: st[k] for k in ("subtiles_per_dim", "item_target",
+                                                   "cluster_size", "screen")}}
         log("adjoint", prec, "%.3f ms" % (wall * 1e3))
     return out
 
