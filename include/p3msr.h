@@ -85,6 +85,22 @@ typedef struct {
     double eps_b;            /* B-spline softening length of the call (0: none) */
 } p3m_sr_stats;
 
+/* Timings of the most recent p3m_lr_force call (when timing is on, else -1). */
+typedef struct {
+    int64_t n;               /* particles */
+    int32_t n_grid;          /* PM grid points per dimension */
+    int32_t pad;
+    float ms_sort;           /* counting sort of the particles by CIC node, kernel tables */
+    float ms_deposit;        /* grid clear + CIC deposit */
+    float ms_fft_x_fwd;      /* real-to-half-spectrum pass along x */
+    float ms_fft_y_fwd;      /* forward pass along y */
+    float ms_fft_z_conv;     /* forward z, kernel multiply, inverse z (one pass) */
+    float ms_fft_y_inv;      /* inverse pass along y */
+    float ms_fft_x_inv;      /* half-spectrum-to-real pass along x */
+    float ms_readout;        /* 4-point difference + CIC readout */
+    float ms_total;          /* whole call (GPU side) */
+} p3m_lr_stats;
+
 /* Create a context on HIP device `device`.  *h receives the handle. */
 int p3m_sr_create(p3m_sr_handle *h, int device);
 
@@ -196,6 +212,37 @@ int p3m_sr_set_timing(p3m_sr_handle h, int enable);
 
 /* Counters of the most recent call on this handle (synchronises its stream). */
 int p3m_sr_get_stats(p3m_sr_handle h, p3m_sr_stats *out);
+
+/*
+ * Long-range (PM) acceleration: the upper half of eq. p3m_gravity (section
+ * 2.1.3), i.e. the PM method of eq. pm_method with the Poisson kernel
+ * replaced by the long-range kernel exp(-x_s^2 k^2) / k^2 of
+ * eq. ewald_potential:
+ *   rho_m   = sum_j mu_j W(x_m - x_j)            CIC (eq. W_CIC), nodes at
+ *                                                 x_m = h (m + 1/2), h = box/n_grid
+ *   phi     = F^-1 [ exp(-x_s^2 k^2) / k^2 * prod_d sinc(h k_d / 2)^-4 * F rho ],
+ *             the k = 0 mode zeroed, F^-1 normalised (eq. weight_fourier:
+ *             two CIC deconvolutions)
+ *   a_i     = 4 pi / h^4 * sum_m W(x_i - x_m) D4 phi_m
+ *             (eq. symmetric_diff_4 along each axis, per grid unit).
+ * Every particle deposits; rows of non-receivers (active[i] == 0) are set
+ * to 0.  a_i + the short-range acceleration of p3m_sr_force with the same
+ * x_s is the P3M acceleration of eq. p3m_gravity (without softening).
+ *   n_grid  grid points per dimension: a power of two, 16..1024 (the paper
+ *           uses n_grid = 2 cbrt(N) with x_s = 1.25 box / n_grid).
+ * All arithmetic is FP64.  The workspace holds 12 n_grid^3 + 16 (n_grid/2+1)
+ * n_grid^2 + 56 n bytes (grids, node histogram, particles sorted by node).
+ * The deposit adds with FP64 atomics, so results can differ between runs
+ * in the last bits.  Errors: EINVAL for n < 0, box or x_s not positive and
+ * finite, n_grid outside the supported set, NULL pos/acc_out with n > 0, or
+ * pointers not 8-byte aligned; EUNSUPPORTED for n > 2^31 - 16; ENOMEM; EHIP.
+ */
+int p3m_lr_force(p3m_sr_handle h, const double *pos, const double *mass,
+                 const uint8_t *active, int64_t n, double box, int n_grid, double x_s,
+                 double *acc_out, void *stream);
+
+/* Timings of the most recent p3m_lr_force call (synchronises its stream). */
+int p3m_lr_get_stats(p3m_sr_handle h, p3m_lr_stats *out);
 
 #ifdef __cplusplus
 }

@@ -83,12 +83,11 @@ def lr_green(n_grid, box, x_s):
     deconvolutions)."""
     hv = np.fft.fftfreq(n_grid, d=1.0 / n_grid)          # signed integers
     k1 = 2.0 * math.pi * hv / box
-    kx, ky, kz = np.meshgrid(k1, k1, k1, indexing="ij")
+    kx, ky, kz = k1[:, None, None], k1[None, :, None], k1[None, None, :]
     k2 = kx * kx + ky * ky + kz * kz
     # sinc(h k / 2) with h k / 2 = pi hv / n; np.sinc(t) = sin(pi t) / (pi t)
     s1 = np.sinc(hv / n_grid)
-    sx, sy, sz = np.meshgrid(s1, s1, s1, indexing="ij")
-    w2 = (sx * sy * sz) ** 4
+    w2 = (s1[:, None, None] * s1[None, :, None] * s1[None, None, :]) ** 4
     g = np.zeros_like(k2)
     nz = k2 > 0
     g[nz] = np.exp(-x_s * x_s * k2[nz]) / k2[nz] / w2[nz]
@@ -181,6 +180,21 @@ def ewald_long_range(pos, mass, box, x_s, recv=None):
     mu = np.ones(n) if mass is None else np.asarray(mass, dtype=np.float64)
     recv = np.arange(n) if recv is None else np.asarray(recv)
     return _reciprocal(pos, mu, box, x_s, _kvectors(box, x_s=x_s), recv)
+
+
+def long_range_pair(sep, mu, box, x_s):
+    """Continuum long-range acceleration of a particle at separation sep =
+    x_i - x_j from a single supplier mu_j, for |sep| much smaller than the
+    box: the Gaussian-smoothed Newtonian force -mu (1 - g(u)) sep / r^3
+    (erf(r / 2 x_s) / r is the long-range potential of eq. ewald_potential,
+    u = r / (2 x_s), g as in the short-range kernel) plus the first-order
+    pull of the periodic images of a cubic lattice, +mu (4 pi / 3) sep / L^3;
+    the next image term is O(r^3 / L^5), about 8 (r / L)^5 relative."""
+    sep = np.asarray(sep, dtype=np.float64)
+    r = float(np.linalg.norm(sep))
+    u = r / (2.0 * x_s)
+    g = math.erfc(u) + 2.0 / math.sqrt(math.pi) * u * math.exp(-u * u)
+    return -mu * ((1.0 - g) / r ** 3 - 4.0 * math.pi / (3.0 * box ** 3)) * sep
 
 
 def ewald_force(pos, mass, box, recv=None):

@@ -55,6 +55,17 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class LrStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_grid", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("ms_sort", ctypes.c_float), ("ms_deposit", ctypes.c_float), ("ms_fft_x_fwd", ctypes.c_float),
+                ("ms_fft_y_fwd", ctypes.c_float), ("ms_fft_z_conv", ctypes.c_float),
+                ("ms_fft_y_inv", ctypes.c_float), ("ms_fft_x_inv", ctypes.c_float),
+                ("ms_readout", ctypes.c_float), ("ms_total", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 _lib_lock = threading.Lock()
 _P = ctypes.c_void_p
@@ -75,6 +86,8 @@ EXPORTS = {
     "p3m_sr_set_timing": ([_P, _I], _I),
     "p3m_sr_set_softening": ([_P, ctypes.c_double], _I),
     "p3m_sr_get_stats": ([_P, ctypes.POINTER(Stats)], _I),
+    "p3m_lr_force": ([_P, _P, _P, _P, _I64, _D, _I, _D, _P, _P], _I),
+    "p3m_lr_get_stats": ([_P, ctypes.POINTER(LrStats)], _I),
 }
 
 
@@ -217,6 +230,20 @@ class Context:
                                               self._p(out), _stream_ptr(self.device)))
         return out
 
+    def force_long_range(self, pos, mass=None, active=None, *, box, n_grid, x_s, out=None):
+        """Long-range (PM) acceleration (n, 3) FP64; see p3m_lr_force."""
+        pos, mass, active, n = self._inputs(pos, mass, active, "active")
+        out = self._out(out, n)
+        _check(self._lib.p3m_lr_force(self._h, self._p(pos), self._p(mass), self._p(active), n,
+                                      float(box), int(n_grid), float(x_s), self._p(out),
+                                      _stream_ptr(self.device)))
+        return out
+
+    def lr_stats(self) -> dict:
+        s = LrStats()
+        _check(self._lib.p3m_lr_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
     def autotune(self, pos, mass=None, active=None, *, box, x_s, r_cut, precision="fp32",
                  level=1, out=None):
         """Measure-and-keep tuning of the decomposition for these inputs;
@@ -297,5 +324,12 @@ def sr_force_batched(pos, mass, rung, min_rung, *, box=1.0, x_s, r_cut, precisio
                              precision=precision)
 
 
-__all__ = ["Context", "P3MError", "Stats", "default_context", "load_library", "sr_force",
+def lr_force(pos, mass=None, active=None, *, box=1.0, n_grid, x_s,
+             context: Context | None = None):
+    """Long-range (PM) P3M acceleration (n, 3) FP64 of the active particles."""
+    ctx = context or default_context(pos.device)
+    return ctx.force_long_range(pos, mass, active, box=box, n_grid=n_grid, x_s=x_s)
+
+
+__all__ = ["Context", "P3MError", "Stats", "LrStats", "lr_force", "default_context", "load_library", "sr_force",
            "sr_force_batched", "LIB_PATH", "P3M_FP32", "P3M_FP64", "EXPORTS"]

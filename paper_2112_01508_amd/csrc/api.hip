@@ -89,6 +89,12 @@ struct p3m_sr_context {
     bool timing = false;
     bool timed_last = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // start, pairs start/end, end
+    // long-range PM workspace and timing
+    DevBuf pm_real, pm_spec, pm_tab, pm_key, pm_rank, pm_cnt, pm_rec, pm_nkey, pm_perm, pm_recv;
+    p3m_lr_stats lr_stats{};
+    bool lr_timed = false;
+    hipStream_t lr_stream = nullptr;
+    hipEvent_t lr_ev[9] = {};   // start, sort, deposit, x, y, z, y inverse, x inverse, readout
 };
 
 namespace {
@@ -460,10 +466,14 @@ int p3m_sr_destroy(p3m_sr_handle h) {
                       &h->sel,     &h->sp2,      &h->perm2,  &h->sel2,  &h->flags,
                       &h->actpos,  &h->ncl,      &h->clusters, &h->itemcnt, &h->items,
                       &h->bsum,    &h->counters, &h->wa,     &h->scal,
-                      &h->rp,      &h->rperm,    &h->rwa};
+                      &h->rp,      &h->rperm,    &h->rwa,
+                      &h->pm_real, &h->pm_spec,  &h->pm_tab, &h->pm_key,  &h->pm_rank,
+                      &h->pm_cnt,  &h->pm_rec,   &h->pm_nkey, &h->pm_perm, &h->pm_recv};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : h->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->lr_ev)
         if (e) (void)hipEventDestroy(e);
     delete h;
     return P3M_OK;
@@ -702,6 +712,105 @@ int p3m_sr_get_stats(p3m_sr_handle h, p3m_sr_stats *out) {
         st.ms_build = a;
         st.ms_pairs = b;
         st.ms_total = t;
+    }
+    *out = st;
+    return P3M_OK;
+}
+
+int p3m_lr_force(p3m_sr_handle h, const double *pos, const double *mass, const uint8_t *active,
+                 int64_t n, double box, int n_grid, double x_s, double *acc_out, void *stream) {
+    int rc;
+    if (n < 0) return set_error(P3M_EINVAL, "n must be >= 0");
+    if (!(box > 0.0) || !std::isfinite(box)) return set_error(P3M_EINVAL, "box must be > 0");
+    if (!(x_s > 0.0) || !std::isfinite(x_s)) return set_error(P3M_EINVAL, "x_s must be > 0");
+    if (n_grid < 16 || n_grid > 1024 || (n_grid & (n_grid - 1)) != 0)
+        return set_error(P3M_EINVAL, "n_grid must be a power of two in [16, 1024], got %d",
+                         n_grid);
+    if (n > 0 && (!pos || !acc_out)) return set_error(P3M_EINVAL, "pos and acc_out are required");
+    if (!aligned8(pos) || !aligned8(acc_out) || !aligned8(mass))
+        return set_error(P3M_EINVAL, "pos, mass and acc_out must be 8-byte aligned");
+    if ((rc = check_handle(h))) return rc;
+    if (n > (int64_t)0x7ffffff0)
+        return set_error(P3M_EUNSUPPORTED, "more than 2^31 - 16 particles");
+    if ((rc = set_device(h))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int np = (int)n;
+    const size_t g = (size_t)n_grid;
+    const size_t nh = g / 2 + 1;
+    if ((rc = ensure(h, h->pm_real, g * g * g * sizeof(double), s))) return rc;
+    if ((rc = ensure(h, h->pm_spec, nh * g * g * 2 * sizeof(double), s))) return rc;
+    if ((rc = ensure(h, h->pm_tab, (g / 2) * 2 * sizeof(double) + 2 * g * sizeof(double), s)))
+        return rc;
+    const size_t cells = g * g * g;
+    const size_t np1 = (size_t)np + 1;
+    if ((rc = ensure(h, h->pm_cnt, (cells + 1) * sizeof(int), s))) return rc;
+    if ((rc = ensure(h, h->bsum, sizeof(int) * scan_block_sums_needed(cells), s))) return rc;
+    if ((rc = ensure(h, h->pm_key, np1 * sizeof(int), s))) return rc;
+    if ((rc = ensure(h, h->pm_rank, np1 * sizeof(int), s))) return rc;
+    if ((rc = ensure(h, h->pm_rec, np1 * sizeof(double4), s))) return rc;
+    if ((rc = ensure(h, h->pm_nkey, np1 * sizeof(int), s))) return rc;
+    if ((rc = ensure(h, h->pm_perm, np1 * sizeof(int), s))) return rc;
+    if ((rc = ensure(h, h->pm_recv, np1, s))) return rc;
+    h->last_stream = s;
+    double2 *tw = (double2 *)h->pm_tab.p;
+    double *w1 = (double *)(tw + g / 2);
+    double *k2 = w1 + g;
+    const double hcell = box / (double)n_grid;
+    const bool timing = h->timing;
+    if (timing) {
+        for (hipEvent_t &e : h->lr_ev)
+            if (!e) P3M_HIP(hipEventCreate(&e));
+        P3M_HIP(hipEventRecord(h->lr_ev[0], s));
+    }
+    double4 *rec = (double4 *)h->pm_rec.p;
+    int *nkey = (int *)h->pm_nkey.p, *perm = (int *)h->pm_perm.p;
+    uint8_t *recv = (uint8_t *)h->pm_recv.p;
+    P3M_HIP(launch_pm_tables(n_grid, box, x_s, tw, w1, k2, s));
+    P3M_HIP(launch_pm_sort(pos, mass, active, np, n_grid, box, hcell, (int *)h->pm_key.p,
+                           (int *)h->pm_rank.p, (int *)h->pm_cnt.p, (int *)h->bsum.p, rec, nkey,
+                           perm, recv, s));
+    if (timing) P3M_HIP(hipEventRecord(h->lr_ev[1], s));
+    P3M_HIP(launch_pm_deposit(rec, nkey, np, (double *)h->pm_real.p, n_grid, s));
+    if (timing) P3M_HIP(hipEventRecord(h->lr_ev[2], s));
+    PmArgs a{};
+    a.n = n_grid;
+    a.real = (double *)h->pm_real.p;
+    a.spec = (double2 *)h->pm_spec.p;
+    a.tw = tw;
+    a.w1 = w1;
+    a.k2 = k2;
+    a.scale = 4.0 * M_PI / (hcell * hcell * hcell * hcell) / ((double)g * (double)g * (double)g);
+    P3M_HIP(launch_pm_fft_chain(a, s, timing ? h->lr_ev + 3 : nullptr));
+    if (timing) P3M_HIP(hipEventRecord(h->lr_ev[7], s));
+    P3M_HIP(launch_pm_readout(rec, nkey, perm, recv, np, (const double *)h->pm_real.p, n_grid,
+                              acc_out, s));
+    if (timing) P3M_HIP(hipEventRecord(h->lr_ev[8], s));
+    h->lr_stats = p3m_lr_stats{};
+    h->lr_stats.n = n;
+    h->lr_stats.n_grid = n_grid;
+    h->lr_timed = timing;
+    h->lr_stream = s;
+    return P3M_OK;
+}
+
+int p3m_lr_get_stats(p3m_sr_handle h, p3m_lr_stats *out) {
+    int rc;
+    if ((rc = check_handle(h))) return rc;
+    if (!out) return set_error(P3M_EINVAL, "NULL stats pointer");
+    if ((rc = set_device(h))) return rc;
+    p3m_lr_stats st = h->lr_stats;
+    float *ms[9] = {nullptr,          &st.ms_sort,       &st.ms_deposit,
+                    &st.ms_fft_x_fwd, &st.ms_fft_y_fwd,  &st.ms_fft_z_conv,
+                    &st.ms_fft_y_inv, &st.ms_fft_x_inv,  &st.ms_readout};
+    for (int k = 1; k < 9; ++k) *ms[k] = -1.0f;
+    st.ms_total = -1.0f;
+    if (h->lr_timed) {
+        P3M_HIP(hipEventSynchronize(h->lr_ev[8]));
+        for (int k = 1; k < 9; ++k)
+            P3M_HIP(hipEventElapsedTime(ms[k], h->lr_ev[k - 1], h->lr_ev[k]));
+        P3M_HIP(hipEventElapsedTime(&st.ms_total, h->lr_ev[0], h->lr_ev[8]));
+    } else if (h->lr_stream || st.n > 0) {
+        P3M_HIP(hipStreamSynchronize(h->lr_stream));
     }
     *out = st;
     return P3M_OK;

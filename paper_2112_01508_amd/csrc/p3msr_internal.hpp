@@ -157,6 +157,35 @@ struct PairArgs {
 // screen != 0: every supplier is tested against the cluster's box first and
 // the survivors (with the adjoint's weights) stream from LDS
 hipError_t launch_pairs(int mode, int screen, const PairArgs &a, int grid, hipStream_t s);
+
+// Long-range PM (pm.hip).  real: n^3 FP64 (rho, then phi), x fastest;
+// spec: (n/2 + 1) n^2 complex FP64, kx fastest; tw: n/2 twiddles; w1, k2:
+// per-axis kernel tables of n values; scale = 4 pi / h^4 / n^3.
+struct PmArgs {
+    int n;
+    double *real;
+    double2 *spec;
+    const double2 *tw;
+    const double *w1, *k2;
+    double scale;
+};
+hipError_t launch_pm_tables(int n, double box, double x_s, double2 *tw, double *w1, double *k2,
+                            hipStream_t s);
+// sort: key/rank n_part ints, count n^3 + 1 ints (scanned in place into the
+// first sorted index of each node), bsum scan block sums;
+// rec (CIC fractions, mu), nkey, perm, recv n_part entries in node order
+hipError_t launch_pm_sort(const double *pos, const double *mass, const uint8_t *active,
+                          int n_part, int n, double box, double h, int *key, int *rank,
+                          int *count, int *bsum, double4 *rec, int *nkey, int *perm,
+                          uint8_t *recv, hipStream_t s);
+hipError_t launch_pm_deposit(const double4 *rec, const int *nkey, int n_part, double *rho, int n,
+                             hipStream_t s);
+// ev (optional): 4 events recorded after the x, y and z passes and the y
+// inverse pass
+hipError_t launch_pm_fft_chain(const PmArgs &a, hipStream_t s, hipEvent_t *ev);
+hipError_t launch_pm_readout(const double4 *rec, const int *nkey, const int *perm,
+                             const uint8_t *recv, int n_part, const double *phi, int n,
+                             double *acc, hipStream_t s);
 int pairs_blocks_per_cu(int mode, int screen);
 
 }  // namespace p3m

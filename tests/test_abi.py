@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "p3msr.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(p3m_sr_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(p3m_(?:sr|lr)_\w+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -29,7 +29,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ["p3m_sr_create", "p3m_sr_destroy", "p3m_sr_force", "p3m_sr_force_backward",
                  "p3m_sr_force_batched", "p3m_sr_autotune", "p3m_sr_get_stats",
-                 "p3m_sr_last_error"]:
+                 "p3m_sr_last_error", "p3m_lr_force", "p3m_lr_get_stats"]:
         assert must in names
 
 
@@ -87,3 +87,25 @@ def test_batched_and_config_checks(lib):
 
 def test_n_too_large_is_unsupported(lib):
     assert _force(lib, n=1 << 31) == -4
+
+
+@pytest.mark.parametrize("kw, msg", [
+    (dict(n=-1), "n must be"),
+    (dict(box=0.0), "box"),
+    (dict(x_s=0.0), "x_s"),
+    (dict(n_grid=48), "power of two"),
+    (dict(n_grid=8), "power of two"),
+    (dict(n_grid=2048), "power of two"),
+    (dict(pos=None), "required"),
+    (dict(out=None), "required"),
+    (dict(out=ctypes.c_void_p(20)), "aligned"),
+    (dict(), "NULL handle"),
+])
+def test_long_range_invalid_arguments_are_rejected(lib, kw, msg):
+    args = dict(h=None, pos=ctypes.c_void_p(8), mass=None, active=None, n=10, box=1.0,
+                n_grid=64, x_s=1.25 / 64, out=ctypes.c_void_p(8), stream=None)
+    args.update(kw)
+    rc = lib.p3m_lr_force(args["h"], args["pos"], args["mass"], args["active"], args["n"],
+                          args["box"], args["n_grid"], args["x_s"], args["out"], args["stream"])
+    assert rc == -1
+    assert msg in lib.p3m_sr_last_error().decode()

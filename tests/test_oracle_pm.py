@@ -150,7 +150,7 @@ def test_pm_matches_continuum_long_range():
 @pytest.mark.parametrize("r", [0.01, 0.002])
 def test_ewald_small_separation(r):
     # periodic images of a cubic lattice add -(4 pi / 3) r / L^3 to Newton at
-    # first order; the next term is O(r^5 / L^7)
+    # first order; the next term is O(r^3 / L^5)
     d = np.array([0.48, -0.6, 0.64])
     d /= np.linalg.norm(d)
     pos = np.array([[0.3, 0.4, 0.5], [0.3, 0.4, 0.5]])
@@ -186,3 +186,19 @@ def test_p3m_total_matches_ewald():
     ref = pm.ewald_force(pos, mass, BOX, recv=recv)
     err = np.linalg.norm(a_lr + a_sr - ref, axis=1) / np.linalg.norm(ref, axis=1)
     assert np.sqrt(np.mean(err ** 2)) <= 1e-2 and err.max() <= 3e-2, (err.mean(), err.max())
+
+
+@pytest.mark.parametrize("n_grid, r_cells", [(64, 3.0), (128, 8.0)])
+def test_long_range_pair_closed_form(n_grid, r_cells):
+    """The closed-form continuum long-range pair force (smoothed Newton plus
+    the cubic-lattice image term) against the reciprocal Ewald sum at the
+    same split scale: they agree to the next image term, about
+    8 (r / L)^5 relative (3e-6 at r = 0.047 L, 8e-6 at 0.0625 L)."""
+    h = BOX / n_grid
+    x_s = 1.25 * h
+    d = np.array([0.36, 0.48, -0.8])
+    pos = np.array([[0.2, 0.7, 0.4], [0.2, 0.7, 0.4]])
+    pos[1] -= r_cells * h * d
+    ref = pm.ewald_long_range(pos, None, BOX, x_s, recv=[0])[0]
+    got = pm.long_range_pair(pos[0] - pos[1], 1.0, BOX, x_s)
+    assert np.linalg.norm(got - ref) <= 2e-5 * np.linalg.norm(ref)
