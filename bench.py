@@ -48,8 +48,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="adjoint,batched,softened",
-                    help="extra measured legs beside the forward force: adjoint, batched")
+    ap.add_argument("--legs", default="adjoint,batched,softened,long_range",
+                    help="extra measured legs beside the forward force: adjoint, batched, "
+                         "softened, long_range")
     ap.add_argument("--batched-workload", default="clustered256")
     return ap.parse_args()
 
@@ -136,6 +137,66 @@ def softened_leg(torch, ctx, pos, mass, wl, steps, warmup):
     finally:
         ctx.set_softening(0.0)
     return out
+
+
+def long_range_bytes(n_grid, n_part):
+    """Algorithmic HBM bytes of each long-range stage: every grid read or
+    written once per pass (real grid 8 B per node, half spectrum 16 B per
+    complex value), particles read and written once per stage that uses
+    them."""
+    cells = n_grid ** 3
+    half = (n_grid // 2 + 1) * n_grid * n_grid * 16
+    return {
+        # positions and masses in, node keys, ranks, histogram; sorted records out
+        "sort": n_part * (24 + 8 + 4 + 4) + 2 * 4 * cells + n_part * (32 + 4 + 4 + 1),
+        "deposit": 8 * cells + n_part * (32 + 4) + 8 * cells,   # clear, records, grid
+        "fft_x_fwd": 8 * cells + half,
+        "fft_y_fwd": 2 * half,
+        "fft_z_conv": 2 * half,
+        "fft_y_inv": 2 * half,
+        "fft_x_inv": half + 8 * cells,
+        "readout": 8 * cells + n_part * (32 + 4 + 4 + 1 + 24),
+    }
+
+
+def long_range_leg(torch, ctx, pos, mass, wl, steps, warmup, cpu=True):
+    """The long-range PM half of the P3M force (p3m_lr_force) on the main
+    workload's grid, with per-stage HIP-event times and the HBM roofline of
+    the FFT passes; the CPU oracle (numpy FFT) of the same call beside it."""
+    kw = dict(box=wl.box, n_grid=wl.n_pm, x_s=wl.x_s)
+    out = torch.empty((wl.n, 3), dtype=torch.float64, device=pos.device)
+    wall = time_calls(torch, lambda: ctx.force_long_range(pos, mass, None, out=out, **kw),
+                      steps, warmup)
+    ctx.set_timing(True)
+    rows = []
+    for _ in range(steps):
+        ctx.force_long_range(pos, mass, None, out=out, **kw)
+        rows.append(ctx.lr_stats())
+    ctx.set_timing(False)
+    stages = ("sort", "deposit", "fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv",
+              "readout")
+    ms = {k: sum(r["ms_" + k] for r in rows) / len(rows) for k in stages}
+    nbytes = long_range_bytes(wl.n_pm, wl.n)
+    fft = [k for k in stages if k.startswith("fft")]
+    fft_ms = sum(ms[k] for k in fft)
+    fft_gbs = sum(nbytes[k] for k in fft) / (fft_ms * 1e-3) / 1e9
+    res = {"workload": "%s: N=%d, PM grid %d^3, x_s=1.25 cells, CIC, 2 deconvolutions, D4"
+                       % (wl.name, wl.n, wl.n_pm),
+           "ms_per_call": wall * 1e3,
+           "stage_ms": ms,
+           "stage_gbs": {k: nbytes[k] / (ms[k] * 1e-3) / 1e9 for k in stages},
+           "fft_roofline": {"bound": "hbm", "achieved": fft_gbs, "peak": 8000.0, "unit": "GB/s",
+                            "frac": fft_gbs / 8000.0, "bytes": sum(nbytes[k] for k in fft)}}
+    log("long range %.3f ms per call, FFT passes %.3f ms at %.0f GB/s"
+        % (wall * 1e3, fft_ms, fft_gbs))
+    if cpu:
+        from oracle import pm_oracle
+        t0 = time.perf_counter()
+        pm_oracle.pm_force(wl.pos, None if mass is None else wl.mass, wl.box, wl.n_pm, wl.x_s)
+        dt = time.perf_counter() - t0
+        res["cpu_oracle"] = {"ms_per_call": dt * 1e3, "cores": 1, "kind": "oracle",
+                             "sample": "the whole call (numpy FFT, one thread)"}
+    return res
 
 
 def batched_leg(torch, p3, name, steps, warmup, layouts=None):
@@ -297,6 +358,11 @@ def main():
         line["adjoint"] = adjoint_leg(torch, ctx, pos, mass, wl, args.steps, args.warmup)
     if "softened" in legs:
         line["softened"] = softened_leg(torch, ctx, pos, mass, wl, args.steps, args.warmup)
+    if "long_range" in legs:
+        line["long_range"] = long_range_leg(torch, ctx, pos, mass, wl, args.steps, args.warmup,
+                                            cpu=not args.no_cpu_baseline)
+        line["long_range"]["p3m_step_ms_fp32"] = (line["ms_per_step"]
+                                                  + line["long_range"]["ms_per_call"])
     if "batched" in legs:
         layouts = {p: tuple(results[p]["stats"][k] for k in
                             ("subtiles_per_dim", "item_target", "cluster_size", "screen"))
