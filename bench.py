@@ -48,9 +48,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="adjoint,batched,softened,long_range",
+    ap.add_argument("--legs", default="adjoint,batched,softened,long_range,kdk",
                     help="extra measured legs beside the forward force: adjoint, batched, "
-                         "softened, long_range")
+                         "softened, long_range, kdk")
     ap.add_argument("--batched-workload", default="clustered256")
     return ap.parse_args()
 
@@ -196,6 +196,51 @@ def long_range_leg(torch, ctx, pos, mass, wl, steps, warmup, cpu=True):
         dt = time.perf_counter() - t0
         res["cpu_oracle"] = {"ms_per_call": dt * 1e3, "cores": 1, "kind": "oracle",
                              "sample": "the whole call (numpy FFT, one thread)"}
+    return res
+
+
+def kdk_leg(torch, ctx, pos, mass, wl, repeats=2):
+    """One synchronised period (one global step) of the rung-hierarchical KDK
+    scheme (p3m_kdk_step) on the main workload from rest: FP32 short range
+    with B-spline softening eps = 0.03 L / cbrt(N), PM long range, eta =
+    0.025, at most 8 rungs.  dt puts the particle with the median short-range
+    acceleration on the boundary of rung 0 (eq. rung), so the halo cores fill
+    the upper rungs."""
+    eta = 0.025
+    eps = 0.03 / round(wl.n ** (1.0 / 3.0))
+    kw = dict(box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut)
+    ctx.set_softening(eps)
+    try:
+        acc = ctx.force(pos, mass, None, precision="fp32", **kw)
+    finally:
+        ctx.set_softening(0.0)
+    amag = torch.linalg.norm(acc, dim=1)
+    dt = math.sqrt(2.0 * eta * eps / float(amag.median()))
+    z = dt * torch.sqrt(amag / (2.0 * eta * eps))
+    start = torch.clamp(torch.ceil(torch.log2(torch.clamp(z, min=1e-300))), 0, 7).to(torch.int64)
+    res = {"dt": dt, "eps": eps, "eta": eta,
+           "start_rungs": torch.bincount(start, minlength=8).tolist()}
+    times = []
+    for _ in range(repeats):
+        p = pos.clone()
+        v = torch.zeros_like(pos)
+        r = torch.zeros(wl.n, dtype=torch.uint8, device=pos.device)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.kdk_step(p, v, mass, r, n_grid=wl.n_pm, dt=dt, n_steps=1, eta=eta, eps=eps,
+                     precision="fp32", **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    st = ctx.kdk_stats()
+    wall = min(times)
+    res.update({"ms_per_period": wall * 1e3, "highest_rung": st["highest_rung"],
+                "substeps": st["substeps"], "sr_calls": st["sr_calls"],
+                "lr_calls": st["lr_calls"], "interactions": st["interactions"],
+                "interactions_per_s": st["interactions"] / wall,
+                "end_rungs": torch.bincount(r.to(torch.int64), minlength=8).tolist(),
+                "ms_per_substep": wall * 1e3 / st["substeps"]})
+    log("kdk period %.1f ms, %d sub-steps, %d short-range calls, %.3g interactions"
+        % (wall * 1e3, st["substeps"], st["sr_calls"], st["interactions"]))
     return res
 
 
@@ -363,6 +408,8 @@ def main():
                                             cpu=not args.no_cpu_baseline)
         line["long_range"]["p3m_step_ms_fp32"] = (line["ms_per_step"]
                                                   + line["long_range"]["ms_per_call"])
+    if "kdk" in legs:
+        line["kdk"] = kdk_leg(torch, ctx, pos, mass, wl)
     if "batched" in legs:
         layouts = {p: tuple(results[p]["stats"][k] for k in
                             ("subtiles_per_dim", "item_target", "cluster_size", "screen"))

@@ -101,6 +101,21 @@ typedef struct {
     float ms_total;          /* whole call (GPU side) */
 } p3m_lr_stats;
 
+/* Counters of the most recent p3m_kdk_step call. */
+typedef struct {
+    int64_t n;               /* particles */
+    int32_t highest_rung;    /* L: highest rung of the period (drift sub-step dt / 2^L) */
+    int32_t substeps;        /* drift sub-steps: n_steps 2^L */
+    int32_t sr_calls;        /* short-range force evaluations (the start + sub-steps with kicks) */
+    int32_t lr_calls;        /* long-range force evaluations (rung-0 kicks) */
+    float ms_total;          /* whole call (GPU side), when timing is on, else -1 */
+    int32_t pad;
+    int64_t interactions;    /* accepted pairs summed over the period's short-range calls */
+} p3m_kdk_stats;
+
+/* p3m_kdk_step flags */
+enum { P3M_KDK_FIXED_RUNGS = 1 };
+
 /* Create a context on HIP device `device`.  *h receives the handle. */
 int p3m_sr_create(p3m_sr_handle *h, int device);
 
@@ -243,6 +258,47 @@ int p3m_lr_force(p3m_sr_handle h, const double *pos, const double *mass,
 
 /* Timings of the most recent p3m_lr_force call (synchronises its stream). */
 int p3m_lr_get_stats(p3m_sr_handle h, p3m_lr_stats *out);
+
+/*
+ * Rung-hierarchical kick-drift-kick step (section 2.2.2, "Individual time
+ * steps", the time-stepping figure and eq. rung) in a static periodic box:
+ * drift x += v tau, kick v += a t_kick, with a from p3m_sr_force (B-spline
+ * softening eps) and, when n_grid > 0, from p3m_lr_force.
+ *   pos, vel  n x 3 FP64, in/out: a synchronised state, advanced by
+ *             n_steps steps of dt and synchronised again (the paper's period
+ *             of steps between synchronisations).  Positions stay in [0, box).
+ *   rung      n uint8, out: eq. rung from the final short-range
+ *             accelerations, rung = max(0, ceil(log2(dt sqrt(|a| /
+ *             (2 eta eps))))) capped at max_rung (the next period's rungs).
+ *             With flags & P3M_KDK_FIXED_RUNGS it is an input instead and
+ *             stays unchanged: every particle keeps its rung.
+ * The period starts from eq. rung on the short-range accelerations at the
+ * start (or the fixed rungs); L is the highest rung and positions drift in
+ * dt / 2^L sub-steps.  Rung l kicks every dt / 2^l with the short-range
+ * force, its particles as receivers and all particles as suppliers; a kick
+ * brings the particle's momentum half a step of its rung ahead (the first
+ * is the half kick from the start, the last ends at the period's end).
+ * After each kick the rung follows eq. rung by at most one step, downwards
+ * only where the lower rung kicks next (the next kick after a jump is then
+ * half or three quarters of the usual one).  The long-range force kicks
+ * every particle whenever rung 0 kicks.
+ *   n_grid    0 (short range only) or the PM grid of p3m_lr_force.
+ *   eta, eps  eq. rung's accuracy parameter (the paper: 0.025) and the
+ *             Plummer-equivalent softening length (also the softening of the
+ *             short-range force; eps > 0 unless rungs are fixed).
+ *   max_rung  0..7 (the paper's default maximum of 8 rungs).
+ * Synchronises with the host once per sub-step.  Errors: those of
+ * p3m_sr_force, plus EINVAL for dt <= 0, n_steps outside [1, 64], max_rung
+ * outside [0, 7], unknown flags, eps < 0, eps or eta not positive without
+ * fixed rungs, fixed rungs above max_rung, NULL vel or rung.
+ */
+int p3m_kdk_step(p3m_sr_handle h, double *pos, double *vel, const double *mass, uint8_t *rung,
+                 int64_t n, double box, double x_s, double r_cut, int n_grid, double dt,
+                 int n_steps, double eta, double eps, int max_rung, int flags, int precision,
+                 void *stream);
+
+/* Counters of the most recent p3m_kdk_step call. */
+int p3m_kdk_get_stats(p3m_sr_handle h, p3m_kdk_stats *out);
 
 #ifdef __cplusplus
 }

@@ -66,6 +66,18 @@ class LrStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class KdkStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("highest_rung", ctypes.c_int32),
+                ("substeps", ctypes.c_int32), ("sr_calls", ctypes.c_int32),
+                ("lr_calls", ctypes.c_int32), ("ms_total", ctypes.c_float),
+                ("pad", ctypes.c_int32), ("interactions", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+P3M_KDK_FIXED_RUNGS = 1
+
 _lib = None
 _lib_lock = threading.Lock()
 _P = ctypes.c_void_p
@@ -88,6 +100,9 @@ EXPORTS = {
     "p3m_sr_get_stats": ([_P, ctypes.POINTER(Stats)], _I),
     "p3m_lr_force": ([_P, _P, _P, _P, _I64, _D, _I, _D, _P, _P], _I),
     "p3m_lr_get_stats": ([_P, ctypes.POINTER(LrStats)], _I),
+    "p3m_kdk_step": ([_P, _P, _P, _P, _P, _I64, _D, _D, _D, _I, _D, _I, _D, _D, _I, _I, _I, _P],
+                     _I),
+    "p3m_kdk_get_stats": ([_P, ctypes.POINTER(KdkStats)], _I),
 }
 
 
@@ -239,6 +254,30 @@ class Context:
                                       _stream_ptr(self.device)))
         return out
 
+    def kdk_step(self, pos, vel, mass, rung, *, box, x_s, r_cut, n_grid, dt, n_steps=1,
+                 eta=0.025, eps=0.0, max_rung=7, fixed_rungs=False, precision="fp64"):
+        """Advance pos, vel (n x 3 FP64, in place) by n_steps steps of dt with
+        the rung-hierarchical KDK scheme; rung (n uint8) receives eq. rung at
+        the end (or is the fixed input with fixed_rungs).  See p3m_kdk_step."""
+        pos, mass, rung, n = self._inputs(pos, mass, rung, "rung")
+        vel = _dev_ptr(vel, torch.float64, (3,), "vel", self.device)
+        if vel.shape[0] != n:
+            raise ValueError("vel must have n rows")
+        if rung is None:
+            raise ValueError("rung (n uint8) is required")
+        _check(self._lib.p3m_kdk_step(self._h, self._p(pos), self._p(vel), self._p(mass),
+                                      self._p(rung), n, float(box), float(x_s), float(r_cut),
+                                      int(n_grid), float(dt), int(n_steps), float(eta),
+                                      float(eps), int(max_rung),
+                                      P3M_KDK_FIXED_RUNGS if fixed_rungs else 0,
+                                      _prec(precision), _stream_ptr(self.device)))
+        return pos, vel, rung
+
+    def kdk_stats(self) -> dict:
+        s = KdkStats()
+        _check(self._lib.p3m_kdk_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
     def lr_stats(self) -> dict:
         s = LrStats()
         _check(self._lib.p3m_lr_get_stats(self._h, ctypes.byref(s)))
@@ -331,5 +370,6 @@ def lr_force(pos, mass=None, active=None, *, box=1.0, n_grid, x_s,
     return ctx.force_long_range(pos, mass, active, box=box, n_grid=n_grid, x_s=x_s)
 
 
-__all__ = ["Context", "P3MError", "Stats", "LrStats", "lr_force", "default_context", "load_library", "sr_force",
+__all__ = ["Context", "P3MError", "Stats", "LrStats", "KdkStats", "lr_force",
+           "P3M_KDK_FIXED_RUNGS", "default_context", "load_library", "sr_force",
            "sr_force_batched", "LIB_PATH", "P3M_FP32", "P3M_FP64", "EXPORTS"]

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libp3msr.so")
-SOURCES = ["api.hip", "sort.hip", "force.hip", "pm.hip"]
+SOURCES = ["api.hip", "sort.hip", "force.hip", "pm.hip", "kdk.hip"]
 ARCH = os.environ.get("P3MSR_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

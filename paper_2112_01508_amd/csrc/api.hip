@@ -95,6 +95,9 @@ struct p3m_sr_context {
     bool lr_timed = false;
     hipStream_t lr_stream = nullptr;
     hipEvent_t lr_ev[9] = {};   // start, sort, deposit, x, y, z, y inverse, x inverse, readout
+    // KDK step workspace
+    DevBuf kdk_acc, kdk_lr, kdk_tq, kdk_tnext, kdk_due, kdk_scal;
+    p3m_kdk_stats kdk_stats{};
 };
 
 namespace {
@@ -432,6 +435,69 @@ int set_device(p3m_sr_handle h) {
     return P3M_OK;
 }
 
+// The long-range call after its arguments were checked (also used by the
+// KDK step).
+int lr_run(p3m_sr_context *h, const double *pos, const double *mass, const uint8_t *active,
+           int np, double box, int n_grid, double x_s, double *acc_out, hipStream_t s) {
+    int rc;
+    const size_t g = (size_t)n_grid;
+    const size_t nh = g / 2 + 1;
+    if ((rc = ensure(h, h->pm_real, g * g * g * sizeof(double), s))) return rc;
+    if ((rc = ensure(h, h->pm_spec, nh * g * g * 2 * sizeof(double), s))) return rc;
+    if ((rc = ensure(h, h->pm_tab, (g / 2) * 2 * sizeof(double) + 2 * g * sizeof(double), s)))
+        return rc;
+    const size_t cells = g * g * g;
+    const size_t np1 = (size_t)np + 1;
+    if ((rc = ensure(h, h->pm_cnt, (cells + 1) * sizeof(int), s))) return rc;
+    if ((rc = ensure(h, h->bsum, sizeof(int) * scan_block_sums_needed(cells), s))) return rc;
+    if ((rc = ensure(h, h->pm_key, np1 * sizeof(int), s))) return rc;
+    if ((rc = ensure(h, h->pm_rank, np1 * sizeof(int), s))) return rc;
+    if ((rc = ensure(h, h->pm_rec, np1 * sizeof(double4), s))) return rc;
+    if ((rc = ensure(h, h->pm_nkey, np1 * sizeof(int), s))) return rc;
+    if ((rc = ensure(h, h->pm_perm, np1 * sizeof(int), s))) return rc;
+    if ((rc = ensure(h, h->pm_recv, np1, s))) return rc;
+    h->last_stream = s;
+    double2 *tw = (double2 *)h->pm_tab.p;
+    double *w1 = (double *)(tw + g / 2);
+    double *k2 = w1 + g;
+    const double hcell = box / (double)n_grid;
+    const bool timing = h->timing;
+    if (timing) {
+        for (hipEvent_t &e : h->lr_ev)
+            if (!e) P3M_HIP(hipEventCreate(&e));
+        P3M_HIP(hipEventRecord(h->lr_ev[0], s));
+    }
+    double4 *rec = (double4 *)h->pm_rec.p;
+    int *nkey = (int *)h->pm_nkey.p, *perm = (int *)h->pm_perm.p;
+    uint8_t *recv = (uint8_t *)h->pm_recv.p;
+    P3M_HIP(launch_pm_tables(n_grid, box, x_s, tw, w1, k2, s));
+    P3M_HIP(launch_pm_sort(pos, mass, active, np, n_grid, box, hcell, (int *)h->pm_key.p,
+                           (int *)h->pm_rank.p, (int *)h->pm_cnt.p, (int *)h->bsum.p, rec, nkey,
+                           perm, recv, s));
+    if (timing) P3M_HIP(hipEventRecord(h->lr_ev[1], s));
+    P3M_HIP(launch_pm_deposit(rec, nkey, np, (double *)h->pm_real.p, n_grid, s));
+    if (timing) P3M_HIP(hipEventRecord(h->lr_ev[2], s));
+    PmArgs a{};
+    a.n = n_grid;
+    a.real = (double *)h->pm_real.p;
+    a.spec = (double2 *)h->pm_spec.p;
+    a.tw = tw;
+    a.w1 = w1;
+    a.k2 = k2;
+    a.scale = 4.0 * M_PI / (hcell * hcell * hcell * hcell) / ((double)g * (double)g * (double)g);
+    P3M_HIP(launch_pm_fft_chain(a, s, timing ? h->lr_ev + 3 : nullptr));
+    if (timing) P3M_HIP(hipEventRecord(h->lr_ev[7], s));
+    P3M_HIP(launch_pm_readout(rec, nkey, perm, recv, np, (const double *)h->pm_real.p, n_grid,
+                              acc_out, s));
+    if (timing) P3M_HIP(hipEventRecord(h->lr_ev[8], s));
+    h->lr_stats = p3m_lr_stats{};
+    h->lr_stats.n = np;
+    h->lr_stats.n_grid = n_grid;
+    h->lr_timed = timing;
+    h->lr_stream = s;
+    return P3M_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -468,7 +534,9 @@ int p3m_sr_destroy(p3m_sr_handle h) {
                       &h->bsum,    &h->counters, &h->wa,     &h->scal,
                       &h->rp,      &h->rperm,    &h->rwa,
                       &h->pm_real, &h->pm_spec,  &h->pm_tab, &h->pm_key,  &h->pm_rank,
-                      &h->pm_cnt,  &h->pm_rec,   &h->pm_nkey, &h->pm_perm, &h->pm_recv};
+                      &h->pm_cnt,  &h->pm_rec,   &h->pm_nkey, &h->pm_perm, &h->pm_recv,
+                      &h->kdk_acc, &h->kdk_lr,   &h->kdk_tq,  &h->kdk_tnext, &h->kdk_due,
+                      &h->kdk_scal};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : h->ev)
@@ -733,64 +801,8 @@ int p3m_lr_force(p3m_sr_handle h, const double *pos, const double *mass, const u
     if (n > (int64_t)0x7ffffff0)
         return set_error(P3M_EUNSUPPORTED, "more than 2^31 - 16 particles");
     if ((rc = set_device(h))) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    const int np = (int)n;
-    const size_t g = (size_t)n_grid;
-    const size_t nh = g / 2 + 1;
-    if ((rc = ensure(h, h->pm_real, g * g * g * sizeof(double), s))) return rc;
-    if ((rc = ensure(h, h->pm_spec, nh * g * g * 2 * sizeof(double), s))) return rc;
-    if ((rc = ensure(h, h->pm_tab, (g / 2) * 2 * sizeof(double) + 2 * g * sizeof(double), s)))
-        return rc;
-    const size_t cells = g * g * g;
-    const size_t np1 = (size_t)np + 1;
-    if ((rc = ensure(h, h->pm_cnt, (cells + 1) * sizeof(int), s))) return rc;
-    if ((rc = ensure(h, h->bsum, sizeof(int) * scan_block_sums_needed(cells), s))) return rc;
-    if ((rc = ensure(h, h->pm_key, np1 * sizeof(int), s))) return rc;
-    if ((rc = ensure(h, h->pm_rank, np1 * sizeof(int), s))) return rc;
-    if ((rc = ensure(h, h->pm_rec, np1 * sizeof(double4), s))) return rc;
-    if ((rc = ensure(h, h->pm_nkey, np1 * sizeof(int), s))) return rc;
-    if ((rc = ensure(h, h->pm_perm, np1 * sizeof(int), s))) return rc;
-    if ((rc = ensure(h, h->pm_recv, np1, s))) return rc;
-    h->last_stream = s;
-    double2 *tw = (double2 *)h->pm_tab.p;
-    double *w1 = (double *)(tw + g / 2);
-    double *k2 = w1 + g;
-    const double hcell = box / (double)n_grid;
-    const bool timing = h->timing;
-    if (timing) {
-        for (hipEvent_t &e : h->lr_ev)
-            if (!e) P3M_HIP(hipEventCreate(&e));
-        P3M_HIP(hipEventRecord(h->lr_ev[0], s));
-    }
-    double4 *rec = (double4 *)h->pm_rec.p;
-    int *nkey = (int *)h->pm_nkey.p, *perm = (int *)h->pm_perm.p;
-    uint8_t *recv = (uint8_t *)h->pm_recv.p;
-    P3M_HIP(launch_pm_tables(n_grid, box, x_s, tw, w1, k2, s));
-    P3M_HIP(launch_pm_sort(pos, mass, active, np, n_grid, box, hcell, (int *)h->pm_key.p,
-                           (int *)h->pm_rank.p, (int *)h->pm_cnt.p, (int *)h->bsum.p, rec, nkey,
-                           perm, recv, s));
-    if (timing) P3M_HIP(hipEventRecord(h->lr_ev[1], s));
-    P3M_HIP(launch_pm_deposit(rec, nkey, np, (double *)h->pm_real.p, n_grid, s));
-    if (timing) P3M_HIP(hipEventRecord(h->lr_ev[2], s));
-    PmArgs a{};
-    a.n = n_grid;
-    a.real = (double *)h->pm_real.p;
-    a.spec = (double2 *)h->pm_spec.p;
-    a.tw = tw;
-    a.w1 = w1;
-    a.k2 = k2;
-    a.scale = 4.0 * M_PI / (hcell * hcell * hcell * hcell) / ((double)g * (double)g * (double)g);
-    P3M_HIP(launch_pm_fft_chain(a, s, timing ? h->lr_ev + 3 : nullptr));
-    if (timing) P3M_HIP(hipEventRecord(h->lr_ev[7], s));
-    P3M_HIP(launch_pm_readout(rec, nkey, perm, recv, np, (const double *)h->pm_real.p, n_grid,
-                              acc_out, s));
-    if (timing) P3M_HIP(hipEventRecord(h->lr_ev[8], s));
-    h->lr_stats = p3m_lr_stats{};
-    h->lr_stats.n = n;
-    h->lr_stats.n_grid = n_grid;
-    h->lr_timed = timing;
-    h->lr_stream = s;
-    return P3M_OK;
+    return lr_run(h, pos, mass, active, (int)n, box, n_grid, x_s, acc_out,
+                  (hipStream_t)stream);
 }
 
 int p3m_lr_get_stats(p3m_sr_handle h, p3m_lr_stats *out) {
@@ -813,6 +825,159 @@ int p3m_lr_get_stats(p3m_sr_handle h, p3m_lr_stats *out) {
         P3M_HIP(hipStreamSynchronize(h->lr_stream));
     }
     *out = st;
+    return P3M_OK;
+}
+
+int p3m_kdk_step(p3m_sr_handle h, double *pos, double *vel, const double *mass, uint8_t *rung,
+                 int64_t n, double box, double x_s, double r_cut, int n_grid, double dt,
+                 int n_steps, double eta, double eps, int max_rung, int flags, int precision,
+                 void *stream) {
+    int rc;
+    if ((rc = check_geometry(n, box, x_s, r_cut))) return rc;
+    if (precision != P3M_FP32 && precision != P3M_FP64)
+        return set_error(P3M_EINVAL, "precision must be P3M_FP64 or P3M_FP32");
+    if (n_grid != 0 && (n_grid < 16 || n_grid > 1024 || (n_grid & (n_grid - 1)) != 0))
+        return set_error(P3M_EINVAL, "n_grid must be 0 or a power of two in [16, 1024], got %d",
+                         n_grid);
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(P3M_EINVAL, "dt must be > 0");
+    if (n_steps < 1 || n_steps > 64) return set_error(P3M_EINVAL, "n_steps must be in [1, 64]");
+    if (max_rung < 0 || max_rung > 7) return set_error(P3M_EINVAL, "max_rung must be in [0, 7]");
+    if (flags & ~P3M_KDK_FIXED_RUNGS) return set_error(P3M_EINVAL, "unknown flags 0x%x", flags);
+    const bool fixed = (flags & P3M_KDK_FIXED_RUNGS) != 0;
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return set_error(P3M_EINVAL, "eps must be >= 0");
+    if (!fixed && !(eps > 0.0 && eta > 0.0 && std::isfinite(eta)))
+        return set_error(P3M_EINVAL, "eq. rung needs eta > 0 and eps > 0 (or fixed rungs)");
+    if (n > 0 && (!pos || !vel || !rung))
+        return set_error(P3M_EINVAL, "pos, vel and rung are required");
+    if (!aligned8(pos) || !aligned8(vel) || !aligned8(mass))
+        return set_error(P3M_EINVAL, "pos, vel and mass must be 8-byte aligned");
+    if ((rc = check_handle(h))) return rc;
+    if (n > (int64_t)0x7ffffff0)
+        return set_error(P3M_EUNSUPPORTED, "more than 2^31 - 16 particles");
+    if ((rc = set_device(h))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int np = (int)n;
+    const size_t np1 = (size_t)np + 1;
+    if ((rc = ensure(h, h->kdk_acc, np1 * 3 * sizeof(double), s))) return rc;
+    if (n_grid && (rc = ensure(h, h->kdk_lr, np1 * 3 * sizeof(double), s))) return rc;
+    if ((rc = ensure(h, h->kdk_tq, np1 * sizeof(int), s))) return rc;
+    if ((rc = ensure(h, h->kdk_tnext, np1 * sizeof(int), s))) return rc;
+    if ((rc = ensure(h, h->kdk_due, np1, s))) return rc;
+    if ((rc = ensure(h, h->kdk_scal, 8 * sizeof(int), s))) return rc;
+    double *acc = (double *)h->kdk_acc.p, *acc_lr = (double *)h->kdk_lr.p;
+    int *t_q = (int *)h->kdk_tq.p, *t_next = (int *)h->kdk_tnext.p;
+    int *scal = (int *)h->kdk_scal.p;   // [0] highest rung, [1] due count, [2..3] pairs
+    unsigned long long *pairs = (unsigned long long *)(scal + 2);
+    uint8_t *due = (uint8_t *)h->kdk_due.p;
+
+    // the call's softening is eps for both the forces and eq. rung
+    struct EpsGuard {
+        p3m_sr_context *h;
+        double saved;
+        ~EpsGuard() { h->eps = saved; }
+    } guard{h, h->eps};
+    h->eps = eps;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->timing) {
+        P3M_HIP(hipEventCreate(&e0));
+        P3M_HIP(hipEventCreate(&e1));
+        P3M_HIP(hipEventRecord(e0, s));
+    }
+
+    Request r{};
+    r.pos = pos;
+    r.mass = mass;
+    r.sel = nullptr;
+    r.sel_kind = SEL_ALL;
+    r.n_sub = 1;
+    r.n = n;
+    r.box = box;
+    r.x_s = x_s;
+    r.r_cut = r_cut;
+    r.precision = precision;
+    r.out = acc;
+    r.stream = s;
+    int sr_calls = 0, lr_calls = 0;
+    // short-range accelerations at the synchronised start: eq. rung's "fake"
+    // kick and the half kicks
+    P3M_HIP(launch_fill_i32(scal, 0, 8, s));
+    if ((rc = run(h, r))) return rc;
+    ++sr_calls;
+    if (np > 0) P3M_HIP(launch_kdk_accum((const Counters *)h->counters.p, pairs, s));
+    KdkArgs k{};
+    k.dt = dt;
+    k.two_eta_eps = 2.0 * eta * eps;
+    k.max_rung = max_rung;
+    k.fixed = fixed ? 1 : 0;
+    P3M_HIP(launch_kdk_assign(acc, np, k, rung, scal, s));
+    int L = 0;
+    P3M_HIP(hipMemcpyAsync(&L, scal, sizeof(int), hipMemcpyDeviceToHost, s));
+    P3M_HIP(hipStreamSynchronize(s));
+    if (L > max_rung)
+        return set_error(P3M_EINVAL, "input rung %d exceeds max_rung %d", L, max_rung);
+    k.L = L;
+    const double tau = dt / (double)(1 << L);
+    k.half_tau = 0.5 * tau;
+    k.period = n_steps * (1 << (L + 1));
+    const int span0 = 1 << (L + 1);
+    P3M_HIP(launch_kdk_first(vel, acc, np, k, rung, t_q, t_next, s));
+    int t_lr = 0;
+    if (n_grid) {
+        if ((rc = lr_run(h, pos, mass, nullptr, np, box, n_grid, x_s, acc_lr, s))) return rc;
+        ++lr_calls;
+        const int target = span0 / 2;
+        P3M_HIP(launch_kdk_lr_kick(vel, acc_lr, np, (double)(target - t_lr) * k.half_tau, s));
+        t_lr = target;
+    }
+    for (int t = 2; t <= k.period; t += 2) {
+        P3M_HIP(launch_kdk_drift(pos, vel, np, tau, box, s));
+        P3M_HIP(launch_fill_i32(scal + 1, 0, 1, s));
+        P3M_HIP(launch_kdk_due(t_next, np, t, due, scal + 1, s));
+        int n_due = 0;
+        P3M_HIP(hipMemcpyAsync(&n_due, scal + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+        P3M_HIP(hipStreamSynchronize(s));
+        if (n_due > 0) {
+            r.sel = due;
+            r.sel_kind = SEL_MASK;
+            if ((rc = run(h, r))) return rc;
+            ++sr_calls;
+            P3M_HIP(launch_kdk_accum((const Counters *)h->counters.p, pairs, s));
+            P3M_HIP(launch_kdk_kick(vel, acc, due, np, t, k, rung, t_q, t_next, s));
+        }
+        if (n_grid && t % span0 == 0) {
+            if ((rc = lr_run(h, pos, mass, nullptr, np, box, n_grid, x_s, acc_lr, s))) return rc;
+            ++lr_calls;
+            const int target = t == k.period ? k.period : t + span0 / 2;
+            P3M_HIP(launch_kdk_lr_kick(vel, acc_lr, np, (double)(target - t_lr) * k.half_tau, s));
+            t_lr = target;
+        }
+    }
+    h->kdk_stats = p3m_kdk_stats{};
+    h->kdk_stats.n = n;
+    h->kdk_stats.highest_rung = L;
+    h->kdk_stats.substeps = k.period / 2;
+    h->kdk_stats.sr_calls = sr_calls;
+    h->kdk_stats.lr_calls = lr_calls;
+    h->kdk_stats.ms_total = -1.0f;
+    unsigned long long total = 0;
+    P3M_HIP(hipMemcpyAsync(&total, pairs, sizeof(total), hipMemcpyDeviceToHost, s));
+    P3M_HIP(hipStreamSynchronize(s));
+    h->kdk_stats.interactions = (int64_t)total;
+    if (e0) {
+        P3M_HIP(hipEventRecord(e1, s));
+        P3M_HIP(hipEventSynchronize(e1));
+        P3M_HIP(hipEventElapsedTime(&h->kdk_stats.ms_total, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    return P3M_OK;
+}
+
+int p3m_kdk_get_stats(p3m_sr_handle h, p3m_kdk_stats *out) {
+    int rc;
+    if ((rc = check_handle(h))) return rc;
+    if (!out) return set_error(P3M_EINVAL, "NULL stats pointer");
+    *out = h->kdk_stats;
     return P3M_OK;
 }
 

@@ -188,4 +188,28 @@ hipError_t launch_pm_readout(const double4 *rec, const int *nkey, const int *per
                              double *acc, hipStream_t s);
 int pairs_blocks_per_cu(int mode, int screen);
 
+// KDK step (kdk.hip).  Times in units of tau / 2, tau = dt / 2^L.
+struct KdkArgs {
+    double dt;
+    double two_eta_eps;   // 2 eta eps of eq. rung
+    double half_tau;
+    int L;                // highest rung of the period
+    int period;           // n_steps 2^(L+1)
+    int max_rung;
+    int fixed;            // 1: rungs are inputs and never change
+};
+hipError_t launch_kdk_assign(const double *acc, int n, const KdkArgs &k, uint8_t *rung,
+                             int *max_rung, hipStream_t s);
+hipError_t launch_kdk_first(double *vel, const double *acc, int n, const KdkArgs &k,
+                            const uint8_t *rung, int *t_q, int *t_next, hipStream_t s);
+hipError_t launch_kdk_drift(double *pos, const double *vel, int n, double tau, double box,
+                            hipStream_t s);
+hipError_t launch_kdk_due(const int *t_next, int n, int t, uint8_t *due, int *n_due,
+                          hipStream_t s);
+hipError_t launch_kdk_kick(double *vel, const double *acc, const uint8_t *due, int n, int t,
+                           const KdkArgs &k, uint8_t *rung, int *t_q, int *t_next,
+                           hipStream_t s);
+hipError_t launch_kdk_lr_kick(double *vel, const double *acc, int n, double dk, hipStream_t s);
+hipError_t launch_kdk_accum(const Counters *c, unsigned long long *total, hipStream_t s);
+
 }  // namespace p3m

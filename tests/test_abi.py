@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "p3msr.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(p3m_(?:sr|lr)_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(p3m_(?:sr|lr|kdk)_\w+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -29,7 +29,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ["p3m_sr_create", "p3m_sr_destroy", "p3m_sr_force", "p3m_sr_force_backward",
                  "p3m_sr_force_batched", "p3m_sr_autotune", "p3m_sr_get_stats",
-                 "p3m_sr_last_error", "p3m_lr_force", "p3m_lr_get_stats"]:
+                 "p3m_sr_last_error", "p3m_lr_force", "p3m_lr_get_stats", "p3m_kdk_step",
+                 "p3m_kdk_get_stats"]:
         assert must in names
 
 
@@ -107,5 +108,34 @@ def test_long_range_invalid_arguments_are_rejected(lib, kw, msg):
     args.update(kw)
     rc = lib.p3m_lr_force(args["h"], args["pos"], args["mass"], args["active"], args["n"],
                           args["box"], args["n_grid"], args["x_s"], args["out"], args["stream"])
+    assert rc == -1
+    assert msg in lib.p3m_sr_last_error().decode()
+
+
+@pytest.mark.parametrize("kw, msg", [
+    (dict(n=-1), "n must be"),
+    (dict(r_cut=0.6), "box/2"),
+    (dict(prec=5), "precision"),
+    (dict(n_grid=48), "n_grid"),
+    (dict(dt=0.0), "dt"),
+    (dict(n_steps=0), "n_steps"),
+    (dict(n_steps=65), "n_steps"),
+    (dict(max_rung=8), "max_rung"),
+    (dict(flags=2), "flags"),
+    (dict(eps=-1.0), "eps"),
+    (dict(eps=0.0), "eq. rung"),
+    (dict(eta=0.0), "eq. rung"),
+    (dict(vel=None), "required"),
+    (dict(rung=None), "required"),
+    (dict(vel=ctypes.c_void_p(12)), "aligned"),
+    (dict(), "NULL handle"),
+])
+def test_kdk_invalid_arguments_are_rejected(lib, kw, msg):
+    args = dict(h=None, pos=ctypes.c_void_p(8), vel=ctypes.c_void_p(8), mass=None,
+                rung=ctypes.c_void_p(8), n=10, box=1.0, x_s=0.01, r_cut=0.045, n_grid=64,
+                dt=0.01, n_steps=1, eta=0.025, eps=1e-3, max_rung=7, flags=0, prec=0,
+                stream=None)
+    args.update(kw)
+    rc = lib.p3m_kdk_step(*args.values())
     assert rc == -1
     assert msg in lib.p3m_sr_last_error().decode()
