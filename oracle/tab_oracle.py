@@ -1,0 +1,81 @@
+"""Plain oracle of the tabulated short-range kernel shape.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+benchmark's CPU legs are the only callers.  The GPU library never imports
+this module and this module never imports the GPU library.
+
+The paper tabulates the bracket of eq. p3m_gravity in a 1D table indexed by
+r^2 between 0 and x_r^2 and reads it by nearest grid point (section 2.1.3,
+"Other optimisations"; 2^12 entries by default), noting that a smaller table
+with linear interpolation would also do.  Without softening the bracket
+g(u)/r^3 diverges at r = 0, so the table here holds its smooth part:
+
+    g(u) / r^3 = r^-3 + H(t) / (2 x_s)^3,   t = u^2,   H(t) = (g(u) - 1) / u^3,
+
+and r^-3 is computed exactly.  Bin k covers r^2 in [k, k + 1) rc2 / n.
+NGP takes H at the bin centre; linear interpolation takes H at the bin's two
+ends.  The bin index is computed in FP32 from the FP32 r^2 and the FP32
+entries-per-r^2 factor, so that both sides of a comparison pick the same
+bin; the rest is FP64.  H comes from erfc and exp (math module), with the
+Maclaurin series of g - 1 for u < 0.05 where g - 1 cancels.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+NGP, LINEAR = 1, 2
+
+
+def h_exact(t):
+    """H(t) = (g(u) - 1) / u^3 with u = sqrt(t), g(u) = erfc(u) + 2u exp(-u^2)/sqrt(pi)."""
+    u = math.sqrt(t)
+    if u < 0.05:
+        # g - 1 = (2/sqrt(pi)) (-2/3 u^3 + 2/5 u^5 - 1/7 u^7 + 1/27 u^9 - ...)
+        s = -2.0 / 3.0 + t * (2.0 / 5.0 + t * (-1.0 / 7.0 + t * (1.0 / 27.0)))
+        return 2.0 / math.sqrt(math.pi) * s
+    g = math.erfc(u) + 2.0 / math.sqrt(math.pi) * u * math.exp(-u * u)
+    return (g - 1.0) / (u * u * u)
+
+
+def table(kind, n, rc2, c2):
+    """The table as float32: NGP n values, linear n (value, next - value) pairs."""
+    if kind == NGP:
+        return np.array([h_exact((k + 0.5) * rc2 / n * c2) for k in range(n)], dtype=np.float32)
+    nodes = [h_exact(k * rc2 / n * c2) for k in range(n + 1)]
+    out = np.empty((n, 2), dtype=np.float32)
+    for k in range(n):
+        out[k, 0] = nodes[k]
+        out[k, 1] = nodes[k + 1] - nodes[k]
+    return out
+
+
+def force(pos, mass, box, x_s, r_cut, recv, kind, n):
+    """Short-range acceleration of the receivers `recv` with the tabulated
+    shape, brute force over all suppliers (minimum image, r < r_cut, r > 0)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    m = pos.shape[0]
+    mu = np.ones(m) if mass is None else np.asarray(mass, dtype=np.float64)
+    rc2 = r_cut * r_cut
+    c2 = 1.0 / (4.0 * x_s * x_s)
+    c3 = 1.0 / (8.0 * x_s ** 3)
+    tab = table(kind, n, rc2, c2)
+    scale = np.float32(n / rc2)
+    out = np.zeros((len(recv), 3))
+    for a, i in enumerate(recv):
+        d = pos[i] - pos
+        d -= box * np.rint(d / box)
+        r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        sel = (r2 < rc2) & (r2 > 0.0)
+        r2s, ds, mus = r2[sel], d[sel], mu[sel]
+        x = r2s.astype(np.float32) * scale               # FP32, as the bin index
+        k = np.minimum(x.astype(np.int64), n - 1)
+        if kind == NGP:
+            h = tab[k].astype(np.float64)
+        else:
+            f = (x - k.astype(np.float32)).astype(np.float64)
+            h = tab[k, 0].astype(np.float64) + tab[k, 1].astype(np.float64) * f
+        s = mus * (1.0 / (r2s * np.sqrt(r2s)) + c3 * h)
+        out[a] = -(s[:, None] * ds).sum(axis=0)
+    return out
