@@ -48,9 +48,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="adjoint,batched,softened,long_range,kdk",
+    ap.add_argument("--legs", default="adjoint,batched,softened,long_range,kdk,shapes",
                     help="extra measured legs beside the forward force: adjoint, batched, "
-                         "softened, long_range, kdk")
+                         "softened, long_range, kdk, shapes")
     ap.add_argument("--batched-workload", default="clustered256")
     return ap.parse_args()
 
@@ -197,6 +197,27 @@ def long_range_leg(torch, ctx, pos, mass, wl, steps, warmup, cpu=True):
         res["cpu_oracle"] = {"ms_per_call": dt * 1e3, "cores": 1, "kind": "oracle",
                              "sample": "the whole call (numpy FFT, one thread)"}
     return res
+
+
+def shapes_leg(torch, ctx, pos, mass, wl, steps, warmup):
+    """The tabulated FP32 kernel shapes (the paper's 2^12-entry NGP table on
+    r^2 and a 1024-entry linearly interpolated one) against the polynomial,
+    on the main workload with the layout the FP32 autotuner chose; their
+    force errors are filled in from the CPU oracle sample afterwards."""
+    out = {}
+    for kind, size in (("poly", 0), ("table_ngp", 4096), ("table_linear", 1024)):
+        ctx.set_shape(kind, size)
+        try:
+            acc, wall, st, pairs_ms, _ = time_steps(torch, ctx, pos, mass, wl, "fp32",
+                                                    max(2, steps // 2), warmup)
+        finally:
+            ctx.set_shape("poly")
+        key = kind if not size else "%s_%d" % (kind, size)
+        out[key] = {"ms_per_step": wall * 1e3, "pair_kernel_ms": pairs_ms,
+                    "achieved_tflops": FLOPS_PER_INTERACTION * st["interactions"]
+                    / (pairs_ms * 1e-3) / 1e12, "_acc": acc.cpu().numpy()}
+        log("shape", key, "pairs %.3f ms" % pairs_ms)
+    return out
 
 
 def kdk_leg(torch, ctx, pos, mass, wl, repeats=2):
@@ -408,6 +429,8 @@ def main():
                                             cpu=not args.no_cpu_baseline)
         line["long_range"]["p3m_step_ms_fp32"] = (line["ms_per_step"]
                                                   + line["long_range"]["ms_per_call"])
+    if "shapes" in legs:
+        line["shapes"] = shapes_leg(torch, ctx, pos, mass, wl, args.steps, args.warmup)
     if "kdk" in legs:
         line["kdk"] = kdk_leg(torch, ctx, pos, mass, wl)
     if "batched" in legs:
@@ -441,6 +464,11 @@ def main():
             errs[prec] = oracle.errors(r["out"][idx], ref, absum)
         line["force_error"] = {p: {"e_l2": e["e_l2"], "e_max_cond": e["e_max_cond"],
                                    "p999": e["p999"]} for p, e in errs.items()}
+        for key, rec in line.get("shapes", {}).items():
+            e = oracle.errors(rec["_acc"][idx], ref, absum)
+            rec["force_error"] = {"e_l2": e["e_l2"], "e_max_cond": e["e_max_cond"]}
+    for rec in line.get("shapes", {}).values():
+        rec.pop("_acc", None)
     print(json.dumps(line), flush=True)
 
 

@@ -36,7 +36,9 @@
  * Geometry requirements (EINVAL otherwise): box > 0, x_s > 0, r_cut > 0,
  * r_cut < box / 2 (a single nearest image, as eq. p3m_gravity assumes), and
  * floor(box / r_cut) >= 3 tiles per dimension (section 2.1.3: at least three
- * tiles across the box so that no tile pair is visited twice).
+ * tiles across the box so that no tile pair is visited twice).  r_cut may
+ * not exceed 4.5 x_s, the paper's default (EUNSUPPORTED): the kernel-shape
+ * fits cover u = r / (2 x_s) <= 2.25.
  */
 #ifndef P3MSR_H
 #define P3MSR_H
@@ -53,6 +55,13 @@ typedef enum {
     P3M_FP64 = 0, /* all pair arithmetic in FP64 */
     P3M_FP32 = 1  /* FP64 separation, cut-off test and accumulation; FP32 kernel shape */
 } p3m_precision;
+
+/* FP32 forward kernel shape (p3m_sr_set_shape) */
+typedef enum {
+    P3M_SHAPE_POLY = 0,       /* hardware rsqrt + degree-9 polynomial, error 1.9e-7 in g */
+    P3M_SHAPE_TAB_NGP = 1,    /* the paper's table on r^2, nearest grid point */
+    P3M_SHAPE_TAB_LINEAR = 2  /* the same table, linear interpolation */
+} p3m_shape;
 
 enum {
     P3M_OK = 0,
@@ -80,7 +89,7 @@ typedef struct {
     float ms_total;          /* whole call (GPU side), when timing is on, else -1 */
     int32_t cluster_size;    /* receivers per cluster: 8, 16, 32 or 64 */
     int32_t screen;          /* 1: suppliers screened against each cluster's box */
-    int32_t pad;
+    int32_t shape;           /* p3m_shape of the FP32 forward kernel shape used */
     int64_t screened;        /* supplier records tested by the screen (0 without it) */
     double eps_b;            /* B-spline softening length of the call (0: none) */
 } p3m_sr_stats;
@@ -206,6 +215,24 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass,
  */
 int p3m_sr_set_config(p3m_sr_handle h, int subtiles_per_dim, int item_target,
                       int cluster_size, int screen);
+
+/*
+ * Kernel-shape knob for FP32 forward calls without softening (force and
+ * batched; FP64, adjoint and softened calls always evaluate the polynomial):
+ * g(u)/r^3 = r^-3 + H(u^2) / (2 x_s)^3, with r^-3 from a hardware rsqrt and
+ * the smooth H either from the degree-9 polynomial (P3M_SHAPE_POLY, the
+ * default) or looked up in a table over r^2 in [0, r_cut^2) as section 2.1.3
+ * ("Other optimisations") does for its whole bracket: P3M_SHAPE_TAB_NGP takes
+ * the value at the centre of the r^2 bin (the paper's choice, 2^12 entries by
+ * default), P3M_SHAPE_TAB_LINEAR interpolates linearly between the bin's
+ * ends (the paper's smaller-table alternative).  The table is filled from an
+ * FP64 evaluation of H at each call and held in LDS by every pair-kernel
+ * block.  table_size: a power of two in [64, 4096] (NGP) or [64, 2048]
+ * (linear), 0 for the largest.  Accuracy: see the measured errors with each
+ * choice; the NGP table's error grows like 1 / table_size, the linear one's
+ * like 1 / table_size^2.  EINVAL for an unknown kind or table size.
+ */
+int p3m_sr_set_shape(p3m_sr_handle h, int kind, int table_size);
 
 /*
  * Softening (section 2.1.1 and the softening bracket of eq. p3m_gravity):

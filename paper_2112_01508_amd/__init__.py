@@ -48,7 +48,7 @@ class Stats(ctypes.Structure):
                 ("item_target", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("ms_build", ctypes.c_float), ("ms_pairs", ctypes.c_float),
                 ("ms_total", ctypes.c_float), ("cluster_size", ctypes.c_int32),
-                ("screen", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("screen", ctypes.c_int32), ("shape", ctypes.c_int32),
                 ("screened", ctypes.c_int64), ("eps_b", ctypes.c_double)]
 
     def as_dict(self):
@@ -97,6 +97,7 @@ EXPORTS = {
     "p3m_sr_set_config": ([_P, _I, _I, _I, _I], _I),
     "p3m_sr_set_timing": ([_P, _I], _I),
     "p3m_sr_set_softening": ([_P, ctypes.c_double], _I),
+    "p3m_sr_set_shape": ([_P, _I, _I], _I),
     "p3m_sr_get_stats": ([_P, ctypes.POINTER(Stats)], _I),
     "p3m_lr_force": ([_P, _P, _P, _P, _I64, _D, _I, _D, _P, _P], _I),
     "p3m_lr_get_stats": ([_P, ctypes.POINTER(LrStats)], _I),
@@ -298,6 +299,15 @@ class Context:
         """Fix the decomposition (0 / -1 = automatic); see p3m_sr_set_config."""
         _check(self._lib.p3m_sr_set_config(self._h, int(subtiles_per_dim), int(item_target),
                                            int(cluster_size), int(screen)))
+
+    SHAPES = {"poly": 0, "table_ngp": 1, "table_linear": 2}
+
+    def set_shape(self, kind="poly", table_size=0):
+        """FP32 forward kernel shape: "poly" (default), "table_ngp" or
+        "table_linear" with table_size entries (0 = largest); see
+        p3m_sr_set_shape."""
+        k = self.SHAPES[kind] if isinstance(kind, str) else int(kind)
+        _check(self._lib.p3m_sr_set_shape(self._h, k, int(table_size)))
 
     def set_softening(self, eps=0.0):
         """B-spline softening with eps_B = 2.8 eps for every following call

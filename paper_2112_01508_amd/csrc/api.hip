@@ -78,10 +78,12 @@ struct TuneVal {
 struct p3m_sr_context {
     int device = 0;
     int n_cu = 0;
-    int blocks_per_cu[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    int blocks_per_cu[4][2][2] = {};   // [mode][screen][tabulated shape]
     DevBuf key, rank, cells, sp, perm, sel, sp2, perm2, sel2, flags, actpos, ncl, clusters,
         itemcnt, items, bsum, counters, wa, scal, rp, rperm, rwa;
     int cfg_ns = 0, cfg_target = 0, cfg_csize = 0, cfg_screen = -1;
+    int cfg_shape = SHAPE_POLY, cfg_tab_n = 0;   // FP32 forward shape (p3m_sr_set_shape)
+    DevBuf htab;
     double eps = 0.0;   // Plummer-equivalent softening length (0: point particles)
     std::map<TuneKey, TuneVal> tuned;
     p3m_sr_stats stats{};
@@ -144,6 +146,10 @@ int check_geometry(int64_t n, double box, double x_s, double r_cut) {
         return set_error(P3M_EINVAL, "r_cut must be < box/2 for a single nearest image");
     if (std::floor(box / r_cut) < 3.0)
         return set_error(P3M_EINVAL, "need at least 3 tiles of side >= r_cut per dimension");
+    // the kernel-shape fits cover u = r / (2 x_s) <= 2.25, the paper's r_cut = 4.5 x_s
+    if (r_cut > 4.5 * x_s * (1.0 + 1e-12))
+        return set_error(P3M_EUNSUPPORTED, "r_cut = %g x_s exceeds the supported 4.5 x_s",
+                         r_cut / x_s);
     return P3M_OK;
 }
 
@@ -405,15 +411,26 @@ int run(p3m_sr_context *h, const Request &r) {
     a.unit_mass = r.mass ? 0 : 1;
     a.csize = csize;
     a.g = g;
-    int &bpc = h->blocks_per_cu[mode][screen];
-    if (bpc == 0) bpc = pairs_blocks_per_cu(mode, screen);
+    // tabulated FP32 shape (point particles, forward only)
+    const int shape = (fp32 && !r.backward && g.eps_b == 0.0) ? h->cfg_shape : SHAPE_POLY;
+    if (shape != SHAPE_POLY) {
+        const int tab_n = h->cfg_tab_n;
+        if ((rc = ensure(h, h->htab, kTabFloats * sizeof(float), s))) return rc;
+        P3M_HIP(launch_build_htab(shape, tab_n, g, (float *)h->htab.p, s));
+        a.htab = (const float *)h->htab.p;
+        a.tab_n = tab_n;
+        a.tab_scale = (float)((double)tab_n / g.rc2);
+    }
+    st.shape = shape;
+    int &bpc = h->blocks_per_cu[mode][screen][shape != SHAPE_POLY ? 1 : 0];
+    if (bpc == 0) bpc = pairs_blocks_per_cu(mode, screen, shape);
     long long waves_wanted = (n_items + 0ll);
     long long grid = std::min<long long>((waves_wanted + 3) / 4, (long long)h->n_cu * bpc);
     if (grid < 1) grid = 1;
     // items per queue atomic: about 32 claims per wave, at most 8 items each
     a.batch = (int)std::max<long long>(1, std::min<long long>(8, n_items / (grid * 4 * 32)));
     if (h->timing) P3M_HIP(hipEventRecord(h->ev[1], s));
-    P3M_HIP(launch_pairs(mode, screen, a, (int)grid, s));
+    P3M_HIP(launch_pairs(mode, screen, shape, a, (int)grid, s));
     if (h->timing) {
         P3M_HIP(hipEventRecord(h->ev[2], s));
         h->timed_last = true;
@@ -536,7 +553,7 @@ int p3m_sr_destroy(p3m_sr_handle h) {
                       &h->pm_real, &h->pm_spec,  &h->pm_tab, &h->pm_key,  &h->pm_rank,
                       &h->pm_cnt,  &h->pm_rec,   &h->pm_nkey, &h->pm_perm, &h->pm_recv,
                       &h->kdk_acc, &h->kdk_lr,   &h->kdk_tq,  &h->kdk_tnext, &h->kdk_due,
-                      &h->kdk_scal};
+                      &h->kdk_scal, &h->htab};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : h->ev)
@@ -737,6 +754,21 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     // the adjoint walks the same decomposition: it takes the forward winner
     h->tuned[TuneKey{n, nt, precision, 0}] = best_v;
     h->tuned[TuneKey{n, nt, precision, 1}] = best_v;
+    return P3M_OK;
+}
+
+int p3m_sr_set_shape(p3m_sr_handle h, int kind, int table_size) {
+    int rc;
+    if (kind != P3M_SHAPE_POLY && kind != P3M_SHAPE_TAB_NGP && kind != P3M_SHAPE_TAB_LINEAR)
+        return set_error(P3M_EINVAL, "unknown shape kind %d", kind);
+    const int max_n = kind == P3M_SHAPE_TAB_LINEAR ? kTabFloats / 2 : kTabFloats;
+    if (table_size == 0) table_size = kind == P3M_SHAPE_POLY ? 0 : max_n;
+    if (kind != P3M_SHAPE_POLY &&
+        (table_size < 64 || table_size > max_n || (table_size & (table_size - 1)) != 0))
+        return set_error(P3M_EINVAL, "table_size must be a power of two in [64, %d]", max_n);
+    if ((rc = check_handle(h))) return rc;
+    h->cfg_shape = kind;
+    h->cfg_tab_n = kind == P3M_SHAPE_POLY ? 0 : table_size;
     return P3M_OK;
 }
 

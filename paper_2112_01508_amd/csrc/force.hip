@@ -110,12 +110,20 @@ __device__ inline double bspline_m3_c(double x, double ri, double ri5, const Geo
 // SOFT: pairs inside the softening length take c3 H(t) + |r|_B^-3, with the
 // softening term in FP64 (it cancels to a few percent of its parts near
 // r = eps_b).
-template <bool UNIT, bool SOFT>
+//
+// TAB (point particles only): H is looked up instead of evaluated, in a table
+// over r^2 in [0, r_cut^2) held in LDS - the paper's 1D table indexed by r^2
+// (section 2.1.3, "Other optimisations"), here of the smooth part only, since
+// the r^-3 part diverges at r = 0 and costs one rsqrt.  SHAPE_TAB_NGP: the
+// value of the bin (nearest grid point); SHAPE_TAB_LINEAR: linear
+// interpolation between the bin's nodes.
+template <bool UNIT, bool SOFT, int TAB = SHAPE_POLY>
 struct FwdF32 {
     static constexpr bool kNeedW = !UNIT;
     static constexpr bool kHasW = false;   // no per-supplier adjoint weight
     using WT = float;
     double ax = 0.0, ay = 0.0, az = 0.0;
+    const float *tab = nullptr;            // the LDS copy of the table (TAB != 0)
     __device__ __forceinline__ void pair_w(double dx, double dy, double dz, double r2,
                                            const double4 &pj, const WT &, const PairArgs &a) {
         pair(dx, dy, dz, r2, pj, 0, a);
@@ -125,7 +133,18 @@ struct FwdF32 {
         const Geom &g = a.g;
         const float r2f = (float)r2;
         const float ri = __builtin_amdgcn_rsqf(r2f);
-        const float h = h_poly(fmaf(r2f, g.c2f, -P3M_HPOLY_T0));
+        float h;
+        if constexpr (TAB == SHAPE_TAB_NGP) {
+            const int k = min((int)(r2f * a.tab_scale), a.tab_n - 1);
+            h = tab[k];
+        } else if constexpr (TAB == SHAPE_TAB_LINEAR) {
+            const float x = r2f * a.tab_scale;
+            const int k = min((int)x, a.tab_n - 1);
+            const float2 e = reinterpret_cast<const float2 *>(tab)[k];
+            h = fmaf(e.y, x - (float)k, e.x);
+        } else {
+            h = h_poly(fmaf(r2f, g.c2f, -P3M_HPOLY_T0));
+        }
         const float ri3 = ri * ri * ri;
         double sd;
         if (SOFT && r2 < g.eps_b2) {
@@ -742,7 +761,7 @@ template <> struct ModeWeight<BWD_F32> { using T = float4; };
 // screened against the cluster's box into LDS before the pair loop, with SG =
 // 64 / csize copies of each cluster per wave; SG = 0: suppliers stream
 // directly, with 64 / count copies.  SOFT: B-spline softening inside eps_b.
-template <int MODE, bool UNIT, int SG, bool SOFT>
+template <int MODE, bool UNIT, int SG, bool SOFT, int TAB = SHAPE_POLY>
 __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
     constexpr bool SCREEN = SG > 0;
     constexpr bool BWD = MODE == BWD_F32 || MODE == BWD_F64;
@@ -753,6 +772,12 @@ __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
     using WTk = typename ModeWeight<MODE>::T;
     __shared__ double4 lists[SCREEN ? NW : 1][SCREEN ? CAP + kListSlack : 1];
     __shared__ WTk wlists[SCREEN && BWD ? NW : 1][SCREEN && BWD ? CAP + kListSlack : 1];
+    __shared__ float tabs[TAB != SHAPE_POLY ? kTabFloats : 1];
+    if constexpr (TAB != SHAPE_POLY) {
+        const int nf = TAB == SHAPE_TAB_LINEAR ? 2 * a.tab_n : a.tab_n;
+        for (int k = threadIdx.x; k < nf; k += blockDim.x) tabs[k] = a.htab[k];
+        __syncthreads();
+    }
     const int lane = threadIdx.x & (kWave - 1);
     double4 *list = lists[SCREEN ? threadIdx.x / kWave : 0];
     void *wlist = wlists[SCREEN && BWD ? threadIdx.x / kWave : 0];
@@ -781,7 +806,8 @@ __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
         c.zi = xp.z + far;
         double ax, ay, az;
         if constexpr (MODE == FWD_F32) {
-            FwdF32<UNIT, SOFT> b;
+            FwdF32<UNIT, SOFT, TAB> b;
+            b.tab = tabs;
             visit_item<SG, CAP>(b, item, cl, c, a, wc, list, wlist);
             ax = b.ax; ay = b.ay; az = b.az;
         } else if constexpr (MODE == FWD_F64) {
@@ -831,23 +857,23 @@ __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
     }
 }
 
-template <int MODE, int SG>
+template <int MODE, int SG, int TAB = SHAPE_POLY>
 int blocks_per_cu_of() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs<MODE, false, SG, false>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs<MODE, false, SG, false, TAB>,
                                                      kForceBlock, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-template <int MODE, bool UNIT, bool SOFT>
+template <int MODE, bool UNIT, bool SOFT, int TAB = SHAPE_POLY>
 void launch_fwd_soft(int sg, const PairArgs &a, dim3 gr, dim3 bl, hipStream_t s) {
     switch (sg) {
-    case 1: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 1, SOFT>), gr, bl, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 2, SOFT>), gr, bl, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 4, SOFT>), gr, bl, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 8, SOFT>), gr, bl, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 0, SOFT>), gr, bl, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 1, SOFT, TAB>), gr, bl, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 2, SOFT, TAB>), gr, bl, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 4, SOFT, TAB>), gr, bl, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 8, SOFT, TAB>), gr, bl, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 0, SOFT, TAB>), gr, bl, 0, s, a); break;
     }
 }
 
@@ -857,20 +883,59 @@ void launch_fwd(int sg, const PairArgs &a, dim3 gr, dim3 bl, hipStream_t s) {
     else launch_fwd_soft<MODE, UNIT, false>(sg, a, gr, bl, s);
 }
 
+// FP32 forward without softening, tabulated shape
+template <bool UNIT>
+void launch_fwd_tab(int tab, int sg, const PairArgs &a, dim3 gr, dim3 bl, hipStream_t s) {
+    if (tab == SHAPE_TAB_NGP) launch_fwd_soft<FWD_F32, UNIT, false, SHAPE_TAB_NGP>(sg, a, gr, bl, s);
+    else launch_fwd_soft<FWD_F32, UNIT, false, SHAPE_TAB_LINEAR>(sg, a, gr, bl, s);
+}
+
 // screen groups: 64 / csize when screening (csize in {8, 16, 32, 64}), else 0
 inline int screen_groups(int screen, int csize) { return screen ? kWave / csize : 0; }
 
+// H at t = u^2 in FP64 from the degree-17 interpolant (error 1.5e-15 in g).
+__global__ void k_build_htab(int kind, int n, Geom g, float *tab) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    if (kind == SHAPE_TAB_NGP) {
+        const double r2 = ((double)k + 0.5) * g.rc2 / (double)n;
+        tab[k] = (float)h64(r2 * g.c2 - P3M_H64_T0, g.h64);
+    } else {
+        const double h0 = h64((double)k * g.rc2 / (double)n * g.c2 - P3M_H64_T0, g.h64);
+        const double h1 = h64((double)(k + 1) * g.rc2 / (double)n * g.c2 - P3M_H64_T0, g.h64);
+        tab[2 * k] = (float)h0;
+        tab[2 * k + 1] = (float)(h1 - h0);
+    }
+}
+
 }  // namespace
 
-hipError_t launch_pairs(int mode, int screen, const PairArgs &a, int grid, hipStream_t s) {
+hipError_t launch_build_htab(int kind, int n, const Geom &g, float *tab, hipStream_t s) {
+    k_build_htab<<<(n + 255) / 256, 256, 0, s>>>(kind, n, g, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs(int mode, int screen, int tab, const PairArgs &a, int grid,
+                        hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;
     if (a.csize != 8 && a.csize != 16 && a.csize != 32 && a.csize != 64) return hipErrorInvalidValue;
     dim3 gr((unsigned)grid), bl(kForceBlock);
     const int sg = screen_groups(screen, a.csize);
+    const bool tabulated = mode == FWD_F32 && tab != SHAPE_POLY && a.g.eps_b == 0.0;
+    if (tabulated) {
+        const int nf = tab == SHAPE_TAB_LINEAR ? 2 * a.tab_n : a.tab_n;
+        if (!a.htab || a.tab_n < 1 || nf > kTabFloats) return hipErrorInvalidValue;
+    }
     switch (mode) {
     case FWD_F32:
-        if (a.unit_mass) launch_fwd<FWD_F32, true>(sg, a, gr, bl, s);
-        else launch_fwd<FWD_F32, false>(sg, a, gr, bl, s);
+        if (tabulated) {
+            if (a.unit_mass) launch_fwd_tab<true>(tab, sg, a, gr, bl, s);
+            else launch_fwd_tab<false>(tab, sg, a, gr, bl, s);
+        } else if (a.unit_mass) {
+            launch_fwd<FWD_F32, true>(sg, a, gr, bl, s);
+        } else {
+            launch_fwd<FWD_F32, false>(sg, a, gr, bl, s);
+        }
         break;
     case FWD_F64:
         if (a.unit_mass) launch_fwd<FWD_F64, true>(sg, a, gr, bl, s);
@@ -882,11 +947,15 @@ hipError_t launch_pairs(int mode, int screen, const PairArgs &a, int grid, hipSt
     return hipGetLastError();
 }
 
-int pairs_blocks_per_cu(int mode, int screen) {
+int pairs_blocks_per_cu(int mode, int screen, int tab) {
     // every screened variant of a mode has the same LDS footprint; use G = 8's count
     const bool sc = screen != 0;
     switch (mode) {
-    case FWD_F32: return sc ? blocks_per_cu_of<FWD_F32, 8>() : blocks_per_cu_of<FWD_F32, 0>();
+    case FWD_F32:
+        if (tab != SHAPE_POLY)   // the two table kinds take the same LDS
+            return sc ? blocks_per_cu_of<FWD_F32, 8, SHAPE_TAB_NGP>()
+                      : blocks_per_cu_of<FWD_F32, 0, SHAPE_TAB_NGP>();
+        return sc ? blocks_per_cu_of<FWD_F32, 8>() : blocks_per_cu_of<FWD_F32, 0>();
     case FWD_F64: return sc ? blocks_per_cu_of<FWD_F64, 8>() : blocks_per_cu_of<FWD_F64, 0>();
     case BWD_F32: return sc ? blocks_per_cu_of<BWD_F32, 8>() : blocks_per_cu_of<BWD_F32, 0>();
     default: return sc ? blocks_per_cu_of<BWD_F64, 8>() : blocks_per_cu_of<BWD_F64, 0>();

@@ -152,11 +152,24 @@ struct PairArgs {
     int batch;               // items a wave claims per queue atomic (>= 1)
     int unit_mass;           // no mass array: every mu_j is 1 (forward kernels specialise)
     int csize;               // cluster size (receivers per cluster, 8..64)
+    // tabulated FP32 forward shape (kernel kind 1 or 2, see force.hip)
+    const float *htab;       // NGP: tab_n values; linear: tab_n (value, slope) pairs
+    float tab_scale;         // table entries per unit of r^2: tab_n / r_cut^2
+    int tab_n;
     Geom g;
 };
+
+constexpr int kTabFloats = 4096;   // LDS floats a table may take (16 KB)
+enum ShapeKind { SHAPE_POLY = 0, SHAPE_TAB_NGP = 1, SHAPE_TAB_LINEAR = 2 };
+// Fills the table of H(t) (g(u) / r^3 = r^-3 + H(t) / (2 x_s)^3, t = u^2) on
+// r^2 in [0, rc2): NGP holds H at the n bin centres, linear the value at the
+// n + 1 nodes as (value, next - value) pairs.
+hipError_t launch_build_htab(int kind, int n, const Geom &g, float *tab, hipStream_t s);
 // screen != 0: every supplier is tested against the cluster's box first and
 // the survivors (with the adjoint's weights) stream from LDS
-hipError_t launch_pairs(int mode, int screen, const PairArgs &a, int grid, hipStream_t s);
+// tab: ShapeKind of the FP32 forward shape (the other modes ignore it)
+hipError_t launch_pairs(int mode, int screen, int tab, const PairArgs &a, int grid,
+                        hipStream_t s);
 
 // Long-range PM (pm.hip).  real: n^3 FP64 (rho, then phi), x fastest;
 // spec: (n/2 + 1) n^2 complex FP64, kx fastest; tw: n/2 twiddles; w1, k2:
@@ -186,7 +199,7 @@ hipError_t launch_pm_fft_chain(const PmArgs &a, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_pm_readout(const double4 *rec, const int *nkey, const int *perm,
                              const uint8_t *recv, int n_part, const double *phi, int n,
                              double *acc, hipStream_t s);
-int pairs_blocks_per_cu(int mode, int screen);
+int pairs_blocks_per_cu(int mode, int screen, int tab);
 
 // KDK step (kdk.hip).  Times in units of tau / 2, tau = dt / 2^L.
 struct KdkArgs {

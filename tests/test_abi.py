@@ -139,3 +139,18 @@ def test_kdk_invalid_arguments_are_rejected(lib, kw, msg):
     rc = lib.p3m_kdk_step(*args.values())
     assert rc == -1
     assert msg in lib.p3m_sr_last_error().decode()
+
+
+def test_r_cut_beyond_fitted_range_is_unsupported(lib):
+    rc = _force(lib, x_s=0.005, r_cut=0.045)            # 9 x_s
+    assert rc == -4
+    assert "4.5 x_s" in lib.p3m_sr_last_error().decode()
+
+
+@pytest.mark.parametrize("kind, size, msg", [(3, 0, "unknown shape"), (1, 100, "power of two"),
+                                             (1, 8192, "power of two"), (2, 4096, "power of two"),
+                                             (2, 32, "power of two"), (0, 0, "NULL handle"),
+                                             (1, 0, "NULL handle")])
+def test_shape_arguments(lib, kind, size, msg):
+    assert lib.p3m_sr_set_shape(None, kind, size) == -1
+    assert msg in lib.p3m_sr_last_error().decode()
