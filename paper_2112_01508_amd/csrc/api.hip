@@ -458,7 +458,7 @@ int lr_run(p3m_sr_context *h, const double *pos, const double *mass, const uint8
            int np, double box, int n_grid, double x_s, double *acc_out, hipStream_t s) {
     int rc;
     const size_t g = (size_t)n_grid;
-    const size_t nh = g / 2 + 1;
+    const size_t nh = ((g / 2 + 1) + 7) & ~(size_t)7;   // padded half-spectrum row
     if ((rc = ensure(h, h->pm_real, g * g * g * sizeof(double), s))) return rc;
     if ((rc = ensure(h, h->pm_spec, nh * g * g * 2 * sizeof(double), s))) return rc;
     if ((rc = ensure(h, h->pm_tab, (g / 2) * 2 * sizeof(double) + 2 * g * sizeof(double), s)))

@@ -172,7 +172,8 @@ hipError_t launch_pairs(int mode, int screen, int tab, const PairArgs &a, int gr
                         hipStream_t s);
 
 // Long-range PM (pm.hip).  real: n^3 FP64 (rho, then phi), x fastest;
-// spec: (n/2 + 1) n^2 complex FP64, kx fastest; tw: n/2 twiddles; w1, k2:
+// spec: n^2 rows of n/2 + 1 complex FP64 (kx fastest) at a stride rounded up
+// to 8; tw: n/2 twiddles; w1, k2:
 // per-axis kernel tables of n values; scale = 4 pi / h^4 / n^3.
 struct PmArgs {
     int n;

@@ -26,7 +26,8 @@
 //
 // Layouts in HBM: real grids (rho, then phi in the same buffer) are n^3 FP64
 // with x fastest, index (z n + y) n + x.  The half-spectrum grid holds
-// nh = n/2 + 1 complex FP64 values per (y, z) line, index (z n + y) nh + kx.
+// nh = n/2 + 1 complex FP64 values per (y, z) line at a row stride rs of nh
+// rounded up to 8, index (z n + y) rs + kx.
 #include <hip/hip_runtime.h>
 
 #include "p3msr_internal.hpp"
@@ -35,7 +36,10 @@ namespace p3m {
 namespace {
 
 constexpr int kFftThreads = 256;
-constexpr int kFftTile = 4096;   // complex values per workgroup tile (64 KB of LDS)
+#ifndef P3M_FFT_TILE
+#define P3M_FFT_TILE 2048
+#endif
+constexpr int kFftTile = P3M_FFT_TILE;   // complex values per workgroup tile (16 B each)
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -177,8 +181,14 @@ __global__ void k_pm_tables(int n, double box, double x_s, double2 *tw, double *
 // the sum and difference to 2j - k and 2j - k + Ns, so the result comes out in
 // natural order without a bit reversal.  lane_j: consecutive threads take
 // consecutive j (line-major tiles) or consecutive lines (interleaved tiles).
+// Copies the n/2 twiddles into LDS (the caller synchronises before use).
+template <int N>
+__device__ __forceinline__ void stage_twiddles(double2 *tws, const double2 *__restrict__ tw) {
+    for (int k = threadIdx.x; k < N / 2; k += kFftThreads) tws[k] = tw[k];
+}
+
 template <int N, int LINES, int IS, int LS, bool LANE_J, bool INV>
-__device__ __forceinline__ void lds_fft(double2 *buf, const double2 *__restrict__ tw) {
+__device__ __forceinline__ void lds_fft(double2 *buf, const double2 *tw) {
     constexpr int NB = LINES * (N / 2);
     constexpr int PER = (NB + kFftThreads - 1) / kFftThreads;
     const int t = threadIdx.x;
@@ -217,6 +227,14 @@ __device__ __forceinline__ void lds_fft(double2 *buf, const double2 *__restrict_
     }
 }
 
+// Half-spectrum rows hold NH = N/2 + 1 values, stored with a stride rounded
+// up to 8 complex values (128 B) so that column tiles start on cache lines.
+template <int N>
+struct Row {
+    static constexpr int kNH = N / 2 + 1;
+    static constexpr int kStride = (kNH + 7) & ~7;
+};
+
 template <int N>
 struct XTile {
     static constexpr int kLines = (kFftTile / N) < (N * N / 2) ? (kFftTile / N) : (N * N / 2);
@@ -232,6 +250,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x_fwd(const double *__restr
     constexpr int P = XTile<N>::kLines;     // complex lines per tile
     constexpr int NH = N / 2 + 1;
     __shared__ double2 buf[P * N];
+    __shared__ double2 tws[N / 2];
+    stage_twiddles<N>(tws, tw);
     const size_t line0 = (size_t)blockIdx.x * 2 * P;   // first real line of the tile
     const double *src = rho + line0 * N;
     double *bufd = reinterpret_cast<double *>(buf);
@@ -240,8 +260,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x_fwd(const double *__restr
         bufd[2 * ((r >> 1) * N + i) + (r & 1)] = src[e];
     }
     __syncthreads();
-    lds_fft<N, P, 1, N, true, false>(buf, tw);
-    double2 *dst = spec + line0 * NH;
+    lds_fft<N, P, 1, N, true, false>(buf, tws);
+    double2 *dst = spec + line0 * Row<N>::kStride;
     for (int e = threadIdx.x; e < 2 * P * NH; e += kFftThreads) {
         const int r = e / NH, k = e % NH;
         const int p = r >> 1;
@@ -251,7 +271,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x_fwd(const double *__restr
         double2 v;
         if ((r & 1) == 0) v = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
         else v = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
-        dst[e] = v;
+        dst[(size_t)r * Row<N>::kStride + k] = v;
     }
 }
 
@@ -265,18 +285,20 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x_inv(const double2 *__rest
     constexpr int P = XTile<N>::kLines;
     constexpr int NH = N / 2 + 1;
     __shared__ double2 buf[P * N];
+    __shared__ double2 tws[N / 2];
+    stage_twiddles<N>(tws, tw);
     const size_t line0 = (size_t)blockIdx.x * 2 * P;
-    const double2 *src = spec + line0 * NH;
+    const double2 *src = spec + line0 * Row<N>::kStride;
     for (int e = threadIdx.x; e < P * N; e += kFftThreads) {
         const int p = e / N, k = e % N;
         const bool lo = k <= N / 2;
         const int kk = lo ? k : N - k;
-        const double2 a = src[(2 * p) * NH + kk];
-        const double2 b = src[(2 * p + 1) * NH + kk];
+        const double2 a = src[(size_t)(2 * p) * Row<N>::kStride + kk];
+        const double2 b = src[(size_t)(2 * p + 1) * Row<N>::kStride + kk];
         buf[e] = lo ? make_double2(a.x - b.y, a.y + b.x) : make_double2(a.x + b.y, b.x - a.y);
     }
     __syncthreads();
-    lds_fft<N, P, 1, N, true, true>(buf, tw);
+    lds_fft<N, P, 1, N, true, true>(buf, tws);
     double *dst = phi + line0 * N;
     const double *bufd = reinterpret_cast<const double *>(buf);
     for (int e = threadIdx.x; e < 2 * P * N; e += kFftThreads) {
@@ -287,12 +309,15 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x_inv(const double2 *__rest
 
 template <int N>
 struct STile {
-    static constexpr int kCols = (kFftTile / N) < 16 ? (kFftTile / N) : 16;
+    // 4..16 adjacent columns: rows are read at least 64 B at a time
+    static constexpr int kRaw = kFftTile / N;
+    static constexpr int kCols = kRaw < 4 ? 4 : (kRaw > 16 ? 16 : kRaw);
 };
 
 // Strided passes over tiles of C adjacent kx columns.  AXIS 1 (y): blockIdx.y
-// is z, elements step by NH.  AXIS 2 (z): blockIdx.y is y, elements step by
-// N * NH.  CONV: forward FFT, multiply by the kernel, inverse FFT.
+// is z, elements step by the row stride.  AXIS 2 (z): blockIdx.y is y,
+// elements step by N row strides.  CONV: forward FFT, multiply by the kernel,
+// inverse FFT.
 template <int N, int AXIS, int MODE>   // MODE 0 forward, 1 inverse, 2 convolve
 __global__ __launch_bounds__(kFftThreads) void k_fft_strided(double2 *__restrict__ spec,
                                                              const double2 *__restrict__ tw,
@@ -302,10 +327,13 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_strided(double2 *__restrict
     constexpr int C = STile<N>::kCols;
     constexpr int NH = N / 2 + 1;
     __shared__ double2 buf[C * N];
+    __shared__ double2 tws[N / 2];
+    stage_twiddles<N>(tws, tw);
     const int kx0 = blockIdx.x * C;
     const int other = blockIdx.y;   // z for the y pass, y for the z pass
-    const size_t base = AXIS == 1 ? (size_t)other * N * NH + kx0 : (size_t)other * NH + kx0;
-    const size_t step = AXIS == 1 ? (size_t)NH : (size_t)N * NH;
+    constexpr size_t RS = Row<N>::kStride;
+    const size_t base = AXIS == 1 ? (size_t)other * N * RS + kx0 : (size_t)other * RS + kx0;
+    const size_t step = AXIS == 1 ? RS : (size_t)N * RS;
     const int ncol = NH - kx0 < C ? NH - kx0 : C;
     for (int e = threadIdx.x; e < C * N; e += kFftThreads) {
         const int c = e % C, i = e / C;
@@ -313,9 +341,9 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_strided(double2 *__restrict
     }
     __syncthreads();
     if (MODE == 1) {
-        lds_fft<N, C, C, 1, false, true>(buf, tw);
+        lds_fft<N, C, C, 1, false, true>(buf, tws);
     } else {
-        lds_fft<N, C, C, 1, false, false>(buf, tw);
+        lds_fft<N, C, C, 1, false, false>(buf, tws);
     }
     if (MODE == 2) {
         // element (c, kz) of column kx = kx0 + c on the line ky = other
@@ -330,7 +358,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_strided(double2 *__restrict
             }
         }
         __syncthreads();
-        lds_fft<N, C, C, 1, false, true>(buf, tw);
+        lds_fft<N, C, C, 1, false, true>(buf, tws);
     }
     for (int e = threadIdx.x; e < C * N; e += kFftThreads) {
         const int c = e % C, i = e / C;
