@@ -48,6 +48,7 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 // Wrap one coordinate into [0, box) as the oracle does (remainder, then a
 // result that rounded up to box itself becomes box - box = 0).
 __device__ __forceinline__ double wrap_coord(double x, double box) {
+    if (x >= 0.0 && x < box) return x;   // the usual case: already in the box
     double r = fmod(x, box);
     if (r < 0.0) r += box;
     if (r >= box) r -= box;

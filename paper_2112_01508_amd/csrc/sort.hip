@@ -20,6 +20,15 @@ namespace {
 __global__ void k_fill_i32(int *p, int v, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
+    if (((uintptr_t)p & 15) == 0) {
+        // 16-byte stores for the bulk, then the tail
+        int4 *p4 = reinterpret_cast<int4 *>(p);
+        const size_t n4 = n / 4;
+        const int4 v4 = make_int4(v, v, v, v);
+        for (size_t j = i; j < n4; j += stride) p4[j] = v4;
+        for (size_t j = 4 * n4 + i; j < n; j += stride) p[j] = v;
+        return;
+    }
     for (; i < n; i += stride) p[i] = v;
 }
 
@@ -86,14 +95,16 @@ __device__ inline int block_exclusive_scan(int v, int *lds, int *total) {
     return base + x - v;
 }
 
+// Tiles of kScanTile values; a block's threads load them striped (value
+// k * kScanBlock + t), so every wave load is coalesced.
 __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const int *__restrict__ in, size_t n,
                                                             int *__restrict__ bsum) {
     __shared__ int lds[kScanBlock / kWave];
-    size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanPerThread;
+    const size_t base = (size_t)blockIdx.x * kScanTile + threadIdx.x;
     int s = 0;
 #pragma unroll
     for (int k = 0; k < kScanPerThread; ++k) {
-        size_t i = base + k;
+        const size_t i = base + (size_t)k * kScanBlock;
         if (i < n) s += in[i];
     }
     int total;
@@ -119,25 +130,45 @@ __global__ __launch_bounds__(1024) void k_scan_top(int *__restrict__ bsum, int n
     }
 }
 
+// Down-sweep: the tile is loaded striped into LDS, each thread scans its
+// kScanPerThread consecutive values there (a pad word per 16 keeps the
+// per-thread reads free of bank conflicts), and the result is stored striped.
+// in and out may be the same array.
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 4); }
+
 __global__ __launch_bounds__(kScanBlock) void k_scan_down(const int *in, int *out, size_t n,
                                                           const int *__restrict__ bsum) {
     __shared__ int lds[kScanBlock / kWave];
-    size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanPerThread;
+    __shared__ int tile[kScanTile + kScanTile / 16];
+    const size_t base = (size_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        const int e = k * kScanBlock + threadIdx.x;
+        const size_t i = base + e;
+        tile[scan_pad(e)] = i < n ? in[i] : 0;
+    }
+    __syncthreads();
+    const int first = threadIdx.x * kScanPerThread;
     int v[kScanPerThread];
     int s = 0;
 #pragma unroll
     for (int k = 0; k < kScanPerThread; ++k) {
-        size_t i = base + k;
-        v[k] = i < n ? in[i] : 0;
+        v[k] = tile[scan_pad(first + k)];
         s += v[k];
     }
     int total;
     int run = block_exclusive_scan(s, lds, &total) + bsum[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < kScanPerThread; ++k) {
-        size_t i = base + k;
-        if (i < n) out[i] = run;
+        tile[scan_pad(first + k)] = run;
         run += v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        const int e = k * kScanBlock + threadIdx.x;
+        const size_t i = base + e;
+        if (i < n) out[i] = tile[scan_pad(e)];
     }
 }
 
