@@ -91,6 +91,7 @@ struct p3m_sr_context {
     bool timing = false;
     bool timed_last = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // start, pairs start/end, end
+    int *host_tot = nullptr;   // pinned: receivers, clusters, items of the current call
     // long-range PM workspace and timing
     DevBuf pm_real, pm_spec, pm_tab, pm_key, pm_rank, pm_cnt, pm_rec, pm_nkey, pm_perm, pm_recv;
     p3m_lr_stats lr_stats{};
@@ -334,7 +335,7 @@ int run(p3m_sr_context *h, const Request &r) {
     Cluster *clusters = (Cluster *)h->clusters.p;
     int *itemcnt = (int *)h->itemcnt.p, *bsum = (int *)h->bsum.p;
     Counters *counters = (Counters *)h->counters.p;
-    int *scal = (int *)h->scal.p;   // [0] cells total, [1] flags total, [2] clusters, [3] items
+    int *scal = (int *)h->scal.p;   // [16 ..] the XCD work queues
 
     // ---- sort ----
     P3M_HIP(launch_fill_i32(cells, 0, ncells + 1, s));
@@ -369,13 +370,9 @@ int run(p3m_sr_context *h, const Request &r) {
     P3M_HIP(launch_item_count(clusters, ncl + ncl_len, (int)cl_bound, cells, g, target, itemcnt,
                               s));
     P3M_HIP(launch_scan(itemcnt, itemcnt, cl_bound, bsum, s));
-    P3M_HIP(hipMemcpyAsync(scal + 0, flags + nflags, sizeof(int), hipMemcpyDeviceToDevice, s));
-    P3M_HIP(hipMemcpyAsync(scal + 1, ncl + ncl_len, sizeof(int), hipMemcpyDeviceToDevice, s));
-    P3M_HIP(hipMemcpyAsync(scal + 2, itemcnt + cl_bound, sizeof(int), hipMemcpyDeviceToDevice, s));
-    int host_scal[3] = {0, 0, 0};
-    P3M_HIP(hipMemcpyAsync(host_scal, scal, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    P3M_HIP(launch_totals(flags + nflags, ncl + ncl_len, itemcnt + cl_bound, h->host_tot, s));
     P3M_HIP(hipStreamSynchronize(s));
-    const int n_recv = host_scal[0], n_clusters = host_scal[1], n_items = host_scal[2];
+    const int n_recv = h->host_tot[0], n_clusters = h->host_tot[1], n_items = h->host_tot[2];
     st.receivers = n_recv;
     st.clusters = n_clusters;
     st.items = n_items;
@@ -533,6 +530,15 @@ int p3m_sr_create(p3m_sr_handle *out, int device) {
     P3M_HIP(hipSetDevice(device));
     p3m_sr_context *h = new p3m_sr_context();
     h->device = device;
+    // fine-grained (coherent) pinned memory: the kernel's stores reach the
+    // host without a cache flush, and are read after the stream synchronises
+    if (hipHostMalloc((void **)&h->host_tot, 4 * sizeof(int),
+                      hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        return set_error(P3M_ENOMEM, "pinned host scalars could not be allocated");
+    }
     if (hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, device) !=
             hipSuccess ||
         h->n_cu <= 0)
@@ -560,6 +566,7 @@ int p3m_sr_destroy(p3m_sr_handle h) {
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : h->lr_ev)
         if (e) (void)hipEventDestroy(e);
+    if (h->host_tot) (void)hipHostFree(h->host_tot);
     delete h;
     return P3M_OK;
 }

@@ -112,6 +112,9 @@ hipError_t launch_fine_order(const double4 *sp, const int *perm, const uint8_t *
 hipError_t launch_flags(const uint8_t *sel_s, int n, int n_sub, int kind,
                         const uint8_t *thr_host, int *flags, hipStream_t s);
 hipError_t launch_compact(const int *scan, int n, int n_sub, int *act_pos, hipStream_t s);
+// *a, *b, *c -> host_out[0..2] (pinned host memory)
+hipError_t launch_totals(const int *a, const int *b, const int *c, int *host_out,
+                         hipStream_t s);
 hipError_t launch_cluster_count(const int *cell_start, const int *scan, int n, int n_sub,
                                 const Geom &g, int csize, int *ncl, hipStream_t s);
 hipError_t launch_cluster_write(const int *cell_start, const int *scan, const int *cl_off,

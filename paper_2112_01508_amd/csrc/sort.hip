@@ -568,6 +568,22 @@ hipError_t launch_flags(const uint8_t *sel_s, int n, int n_sub, int kind, const 
     return hipGetLastError();
 }
 
+// Three device counts into host-visible (pinned) memory: one launch instead
+// of a copy per value; read after the stream has been synchronised.
+__global__ void k_totals(const int *a, const int *b, const int *c, int *out) {
+    if (threadIdx.x == 0) {
+        out[0] = *a;
+        out[1] = *b;
+        out[2] = *c;
+    }
+}
+
+hipError_t launch_totals(const int *a, const int *b, const int *c, int *host_out,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_totals, dim3(1), dim3(64), 0, s, a, b, c, host_out);
+    return hipGetLastError();
+}
+
 hipError_t launch_compact(const int *scan, int n, int n_sub, int *act_pos, hipStream_t s) {
     size_t total = (size_t)n * n_sub;
     if (total == 0) return hipSuccess;
