@@ -18,6 +18,7 @@ import argparse
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -81,7 +82,7 @@ def time_steps(torch, ctx, pos, mass, wl, prec, steps, warmup):
         build_ms.append(st["ms_build"])
     ctx.set_timing(False)
     st = ctx.stats()
-    return out, wall, st, sum(pairs_ms) / len(pairs_ms), sum(build_ms) / len(build_ms)
+    return out, wall, st, statistics.median(pairs_ms), statistics.median(build_ms)
 
 
 def time_calls(torch, fn, steps, warmup):
@@ -303,10 +304,10 @@ def batched_leg(torch, p3, name, steps, warmup, layouts=None):
     return res
 
 
-def profiled_traffic(name, st):
-    """HBM bytes per launch of the pair kernel from the committed rocprofv3
-    counter runs (profiles/traffic.json), or None when the kernel sources or
-    the decomposition differ from the ones the counters were taken with."""
+def profiled_record(name, st):
+    """The committed rocprofv3 counter record of the pair kernel
+    (profiles/traffic.json), or None when the kernel sources or the
+    decomposition differ from the ones the counters were taken with."""
     import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[name]
@@ -319,7 +320,7 @@ def profiled_traffic(name, st):
     keys = ("subtiles_per_dim", "item_target", "cluster_size", "screen")
     if h.hexdigest() != rec.get("kernel_sources_sha256") or any(rec.get(k) != st[k] for k in keys):
         return None
-    return rec["traffic_bytes"]
+    return rec
 
 
 def copy_probe():
@@ -404,12 +405,21 @@ def main():
                    "cluster_size": r32["stats"]["cluster_size"],
                    "screen": r32["stats"]["screen"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": profiled_traffic("k_pairs_fwd_fp32_%s" % args.workload,
-                                                 r32["stats"])},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
         "pair_kernel_ms": r32["pairs_ms"],
         "build_ms": r32["build_ms"],
     }
+    prof = profiled_record("k_pairs_fwd_fp32_%s" % args.workload, r32["stats"])
+    if prof:
+        line["roofline"]["traffic"] = prof["traffic_bytes"]
+        if "counter_fp32_tflops" in prof:
+            # SQ_INSTS_VALU_FLOPS_FP32/_FP64 x 64 lanes over the traced kernel time;
+            # masked lanes count as well
+            line["roofline"]["counter"] = {
+                "fp32_tflops": prof["counter_fp32_tflops"],
+                "fp64_tflops": prof["counter_fp64_tflops"],
+                "fp32_frac": prof["counter_fp32_tflops"] / PEAK_FP32_TFLOPS,
+                "includes_masked_lanes": True}
     if "fp64" in results:
         r64 = results["fp64"]
         a64 = FLOPS_PER_INTERACTION * r64["stats"]["interactions"] / (r64["pairs_ms"] * 1e-3) / 1e12
@@ -458,7 +468,15 @@ def main():
             "value": float(cnt.sum()) / dt, "unit": "interactions/s", "cores": oracle.threads(),
             "kind": "oracle",
             "sample": "FP64 brute force over all N suppliers for %d seeded receivers "
-                      "(%d interactions, %.1f s)" % (idx.size, int(cnt.sum()), dt)}
+                      "(%d interactions, %.1f s)" % (idx.size, int(cnt.sum()), dt),
+            "pair_tests_per_s": float(idx.size) * wl.n / dt}
+        # the oracle's cell-list walk on the same receivers: the fair CPU rate
+        t0 = time.perf_counter()
+        _, cnt_t, _, _ = oracle.force(wl.pos, wl.mass, wl.box, wl.x_s, wl.r_cut, recv=idx,
+                                      method="tiled")
+        dt_t = time.perf_counter() - t0
+        line["cpu_baseline"]["tiled"] = {"value": float(cnt_t.sum()) / dt_t,
+                                         "unit": "interactions/s", "seconds": dt_t}
         errs = {}
         for prec, r in results.items():
             errs[prec] = oracle.errors(r["out"][idx], ref, absum)
