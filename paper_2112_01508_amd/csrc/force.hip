@@ -51,6 +51,17 @@ __device__ inline float h_poly(float v) {
 
 // FP64 H and, optionally, dH/dv from one Horner pass; the coefficients come
 // from the kernel arguments (SGPRs) so each step is one v_fma_f64.
+// 1/sqrt(x) in FP64 for a positive normal x (the pair loop's 0 < r^2 < r_cut^2):
+// the hardware estimate y0 and one step of the series
+// (1 - e)^(-1/2) = 1 + e/2 + 3 e^2 / 8 + ...,  e = 1 - x y0^2,
+// which triples the estimate's correct bits.  Zero, infinite and subnormal
+// inputs need no handling here.
+__device__ __forceinline__ double rsqrt_pos(double x) {
+    const double y0 = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y0, y0, 1.0);
+    return fma(y0 * e, fma(e, 0.375, 0.5), y0);
+}
+
 __device__ inline double h64(double v, const double *c) {
     double h = c[P3M_H64_DEGREE];
 #pragma unroll
@@ -175,7 +186,7 @@ struct FwdF64 {
     }
     __device__ __forceinline__ void pair(double dx, double dy, double dz, double r2,
                                          const double4 &pj, int, const PairArgs &a) {
-        const double ri = rsqrt(r2);
+        const double ri = rsqrt_pos(r2);
         const double h = h64(fma(r2, a.g.c2, -P3M_H64_T0), a.g.h64);
         const double ri3 = ri * ri * ri;
         double sh;
@@ -212,7 +223,7 @@ struct BwdF64 {
         double vx = pj.w * wkx - muk * wj.x;
         double vy = pj.w * wky - muk * wj.y;
         double vz = pj.w * wkz - muk * wj.z;
-        const double ri = rsqrt(r2);
+        const double ri = rsqrt_pos(r2);
         const double ri2 = ri * ri;
         double dh;
         const double h = h64_d(fma(r2, a.g.c2, -P3M_H64_T0), a.g.h64, dh);
@@ -258,7 +269,7 @@ struct BwdF32 {
         float vy = muj * wky - muk * wj.y;
         float vz = muj * wkz - muk * wj.z;
         if (SOFT && r2 < g.eps_b2) {
-            const double ri = rsqrt(r2);
+            const double ri = rsqrt_pos(r2);
             const double ri2 = ri * ri;
             const double x = r2 * ri * g.inv_eps_b;
             double dh;
