@@ -350,7 +350,9 @@ int run(p3m_sr_context *h, const Request &r) {
         double4 *sp_f = (double4 *)h->sp2.p;
         int *perm_f = (int *)h->perm2.p;
         uint8_t *sel_f = (uint8_t *)h->sel2.p;
-        P3M_HIP(launch_fine_order(sp, perm, sel_s, cells, g, key, rank, sp_f, perm_f, sel_f, s));
+        // a subtile no larger than one cluster gains nothing from the reorder
+        P3M_HIP(launch_fine_order(sp, perm, sel_s, cells, g, key, rank, sp_f, perm_f, sel_f,
+                                  csize, s));
         sp = sp_f;
         perm = perm_f;
         sel_s = sel_f;

@@ -108,7 +108,8 @@ hipError_t launch_scatter(const double *pos, const double *mass, const uint8_t *
 // sub-cell (sp/perm/sel -> sp2/perm2/sel2; fkey/frank: n ints of scratch)
 hipError_t launch_fine_order(const double4 *sp, const int *perm, const uint8_t *sel,
                              const int *cell_start, const Geom &g, int *fkey, int *frank,
-                             double4 *sp2, int *perm2, uint8_t *sel2, hipStream_t s);
+                             double4 *sp2, int *perm2, uint8_t *sel2, int csize,
+                             hipStream_t s);
 hipError_t launch_flags(const uint8_t *sel_s, int n, int n_sub, int kind,
                         const uint8_t *thr_host, int *flags, hipStream_t s);
 hipError_t launch_compact(const int *scan, int n, int n_sub, int *act_pos, hipStream_t s);

@@ -240,14 +240,15 @@ __global__ __launch_bounds__(kWave) void k_fine_order(const double4 *__restrict_
                                                       int *__restrict__ frank,
                                                       double4 *__restrict__ sp2,
                                                       int *__restrict__ perm2,
-                                                      uint8_t *__restrict__ sel2) {
+                                                      uint8_t *__restrict__ sel2,
+                                                      int keep_max) {
     __shared__ int hist[kFineBins];
     const int lane = threadIdx.x;
     for (long long tile = blockIdx.x; tile < g.nt3; tile += gridDim.x) {
         const int *c = cs + tile * g.ns3;
         for (int s = 0; s < g.ns3; ++s) {
             const int a0 = c[s], a1 = c[s + 1];
-            if (a1 - a0 <= kFineMin) {
+            if (a1 - a0 <= keep_max) {
                 for (int i = a0 + lane; i < a1; i += kWave) {
                     sp2[i] = sp[i];
                     perm2[i] = perm[i];
@@ -549,10 +550,12 @@ hipError_t launch_scatter(const double *pos, const double *mass, const uint8_t *
 
 hipError_t launch_fine_order(const double4 *sp, const int *perm, const uint8_t *sel,
                              const int *cell_start, const Geom &g, int *fkey, int *frank,
-                             double4 *sp2, int *perm2, uint8_t *sel2, hipStream_t s) {
+                             double4 *sp2, int *perm2, uint8_t *sel2, int csize,
+                             hipStream_t s) {
     long long grid = std::min<long long>(g.nt3, 1ll << 20);
     hipLaunchKernelGGL(k_fine_order, dim3((unsigned)grid), dim3(kWave), 0, s, sp, perm, sel,
-                       cell_start, g, fkey, frank, sp2, perm2, sel2);
+                       cell_start, g, fkey, frank, sp2, perm2, sel2,
+                       csize > kFineMin ? csize : kFineMin);
     return hipGetLastError();
 }
 
