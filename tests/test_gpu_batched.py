@@ -78,8 +78,9 @@ def clustered256():
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_batched_clustered256_full(env, clustered256, prec):
     """Full-size N=256^3 clustered set, 8 nested rung subsets in one launch:
-    256 receivers per rung (stratified, seeded) checked in every subset they
-    belong to against brute force over all N suppliers."""
+    2048 receivers per rung (stratified, seeded; 16384 in all) checked in
+    every subset they belong to against the oracle's cell-list sum over all
+    N suppliers (pinned against its brute force)."""
     torch, p3, ctx = env
     wl = clustered256
     thr = list(range(8))
@@ -89,8 +90,9 @@ def test_batched_clustered256_full(env, clustered256, prec):
     st = ctx.stats()
     print(prec, st, flush=True)
     assert st["receivers"] == sum(int((wl.rung >= k).sum()) for k in thr)
-    idx = stratified_by_rung(wl.rung, 256, wl.config_id)
-    ref, cnt, absum, _ = oracle.force(wl.pos, wl.mass, 1.0, wl.x_s, wl.r_cut, recv=idx)
+    idx = stratified_by_rung(wl.rung, 2048, wl.config_id)
+    ref, cnt, absum, _ = oracle.force(wl.pos, wl.mass, 1.0, wl.x_s, wl.r_cut, recv=idx,
+                                      method="tiled")
     for k in thr:
         sel = wl.rung[idx] >= k
         got = out[k][torch.from_numpy(idx[sel]).to(out.device)].cpu().numpy()
