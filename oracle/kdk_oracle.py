@@ -15,7 +15,7 @@ q / m is the velocity v):
   * At the start every particle gets a rung from eq. rung,
         rung = max(0, ceil(log2(dt sqrt(|a| / (2 eta eps))))),
     capped at max_rung, where |a| is its short-range acceleration at the
-    start (the "fake" kick whose momentum update is not applied).  L is the
+    start (a force evaluation whose momentum update is not applied).  L is the
     highest rung; positions drift in sub-steps tau = dt / 2^L.
   * Rung l kicks every dt / 2^l.  A kick at time t with the particle on
     rung l brings its momentum from wherever it is to t + dt / 2^(l+1)

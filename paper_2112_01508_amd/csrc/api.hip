@@ -939,8 +939,8 @@ int p3m_kdk_step(p3m_sr_handle h, double *pos, double *vel, const double *mass, 
     r.out = acc;
     r.stream = s;
     int sr_calls = 0, lr_calls = 0;
-    // short-range accelerations at the synchronised start: eq. rung's "fake"
-    // kick and the half kicks
+    // short-range accelerations at the synchronised start: they set the rungs
+    // (eq. rung, no momentum update) and drive the half kicks
     P3M_HIP(launch_fill_i32(scal, 0, 8, s));
     if ((rc = run(h, r))) return rc;
     ++sr_calls;

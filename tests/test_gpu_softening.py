@@ -1,7 +1,7 @@
 """B-spline softened short-range force on the GPU (section 2.1.1,
 eq. bspline_force; the softening bracket of eq. p3m_gravity) against the
 FP64 oracle, through the C ABI.  The softening length is eps = 0.03 L/cbrt(N)
-(a few percent of the mean inter-particle distance), eps_B = 2.8 eps; the
+(a small fraction of the mean inter-particle distance), eps_B = 2.8 eps; the
 clustered sets put many pairs inside eps_B in their halo cores."""
 import numpy as np
 import pytest
