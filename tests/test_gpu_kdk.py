@@ -127,3 +127,26 @@ def test_kdk_fixed_rungs_reversible(env):
     x2, v2, _, _ = gpu_run(env, x1, -v1, mass, 2e-3, 2, eps, rung=rung, fixed=True)
     assert np.max(np.abs(periodic_diff(x2, pos))) <= 1e-11
     assert np.max(np.abs(-v2 - vel)) <= 1e-9 * np.max(np.abs(v1 - vel))
+
+
+def test_kdk_empty(env):
+    torch, p3, ctx = env
+    z = torch.zeros((0, 3), dtype=torch.float64, device="cuda:0")
+    r = torch.zeros(0, dtype=torch.uint8, device="cuda:0")
+    ctx.kdk_step(z, z.clone(), None, r, box=1.0, x_s=X_S, r_cut=R_CUT, n_grid=N_GRID, dt=1e-3,
+                 eps=1e-3)
+    st = ctx.kdk_stats()
+    assert st["n"] == 0 and st["interactions"] == 0
+
+
+@pytest.mark.parametrize("n_grid", [0, N_GRID])
+def test_kdk_free_particle_drifts(env, n_grid):
+    """One particle feels no force (no pair; the PM self-force of CIC with an
+    antisymmetric difference vanishes), so it coasts: x = x0 + v T, wrapped."""
+    pos = np.array([[0.97, 0.5, 0.02]])
+    vel = np.array([[0.5, -0.25, -0.75]])
+    xg, vg, rg, st = gpu_run(env, pos, vel, np.ones(1), 0.01, 3, 1e-3, n_grid=n_grid)
+    assert st["highest_rung"] == 0 and st["substeps"] == 3
+    want = (pos + 3 * 0.01 * vel) % 1.0
+    assert np.max(np.abs(periodic_diff(xg, want))) <= 1e-12
+    assert np.max(np.abs(vg - vel)) <= 1e-9
