@@ -200,6 +200,28 @@ def long_range_leg(torch, ctx, pos, mass, wl, steps, warmup, cpu=True):
     return res
 
 
+def p3m_leg(torch, ctx, pos, mass, wl, steps, warmup):
+    """The whole P3M acceleration in one call (p3m_force: FP32 short range
+    and PM overlapped on two streams) against the two halves called one
+    after the other on one stream."""
+    kw = dict(box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut)
+    out = torch.empty((wl.n, 3), dtype=torch.float64, device=pos.device)
+    lro = torch.empty_like(out)
+
+    def seq():
+        ctx.force(pos, mass, None, precision="fp32", out=out, **kw)
+        ctx.force_long_range(pos, mass, None, box=wl.box, n_grid=wl.n_pm, x_s=wl.x_s, out=lro)
+
+    both = time_calls(torch, lambda: ctx.force_total(pos, mass, None, n_grid=wl.n_pm,
+                                                     precision="fp32", out=out, **kw),
+                      steps, warmup)
+    one_by_one = time_calls(torch, seq, steps, warmup)
+    log("p3m force %.3f ms overlapped, %.3f ms one after the other"
+        % (both * 1e3, one_by_one * 1e3))
+    return {"ms_per_call": both * 1e3, "ms_sequential": one_by_one * 1e3,
+            "interactions_per_s": ctx.stats()["interactions"] / both}
+
+
 def shapes_leg(torch, ctx, pos, mass, wl, steps, warmup):
     """The tabulated FP32 kernel shapes (the paper's 2^12-entry NGP table on
     r^2 and a 1024-entry linearly interpolated one) against the polynomial,
@@ -439,6 +461,8 @@ def main():
                                             cpu=not args.no_cpu_baseline)
         line["long_range"]["p3m_step_ms_fp32"] = (line["ms_per_step"]
                                                   + line["long_range"]["ms_per_call"])
+        line["long_range"]["p3m_force"] = p3m_leg(torch, ctx, pos, mass, wl, args.steps,
+                                                  args.warmup)
     if "shapes" in legs:
         line["shapes"] = shapes_leg(torch, ctx, pos, mass, wl, args.steps, args.warmup)
     if "kdk" in legs:

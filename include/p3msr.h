@@ -287,6 +287,29 @@ int p3m_lr_force(p3m_sr_handle h, const double *pos, const double *mass,
 int p3m_lr_get_stats(p3m_sr_handle h, p3m_lr_stats *out);
 
 /*
+ * The whole P3M acceleration of eq. p3m_gravity (section 2.1.3): the
+ * short-range sum of p3m_sr_force plus the long-range PM term of
+ * p3m_lr_force, with the same x_s, written to acc_out (n x 3 FP64).  The
+ * two halves are independent until the final sum, so the long range runs on
+ * an auxiliary stream of the handle (default priority, created on the first
+ * call) that waits for the work queued on `stream` before the call, while
+ * the short range runs on `stream`; `stream` then waits for the long range
+ * and adds it.  On return every piece of the call is ordered before later
+ * work on `stream`, as for the other entry points.  Arguments, layouts,
+ * softening, shape and precision of the short range are those of
+ * p3m_sr_force; n_grid, the long range's workspace and its FP64 arithmetic
+ * those of p3m_lr_force; the workspace adds n x 3 doubles for the long-range
+ * half.  Rows of non-receivers (active[i] == 0) are 0.  p3m_sr_get_stats
+ * and p3m_lr_get_stats report the two halves.  Calls on one handle must not
+ * overlap (the auxiliary stream and the workspace are per handle).
+ * Errors: those of p3m_sr_force and p3m_lr_force; on an error of the short
+ * range, `stream` still waits for the queued long range.
+ */
+int p3m_force(p3m_sr_handle h, const double *pos, const double *mass, const uint8_t *active,
+              int64_t n, double box, double x_s, double r_cut, int n_grid, int precision,
+              double *acc_out, void *stream);
+
+/*
  * Rung-hierarchical kick-drift-kick step (section 2.2.2, "Individual time
  * steps", the time-stepping figure and eq. rung) in a static periodic box:
  * drift x += v tau, kick v += a t_kick, with a from p3m_sr_force (B-spline

@@ -101,6 +101,7 @@ EXPORTS = {
     "p3m_sr_get_stats": ([_P, ctypes.POINTER(Stats)], _I),
     "p3m_lr_force": ([_P, _P, _P, _P, _I64, _D, _I, _D, _P, _P], _I),
     "p3m_lr_get_stats": ([_P, ctypes.POINTER(LrStats)], _I),
+    "p3m_force": ([_P, _P, _P, _P, _I64, _D, _D, _D, _I, _I, _P, _P], _I),
     "p3m_kdk_step": ([_P, _P, _P, _P, _P, _I64, _D, _D, _D, _I, _D, _I, _D, _D, _I, _I, _I, _P],
                      _I),
     "p3m_kdk_get_stats": ([_P, ctypes.POINTER(KdkStats)], _I),
@@ -255,6 +256,17 @@ class Context:
                                       _stream_ptr(self.device)))
         return out
 
+    def force_total(self, pos, mass=None, active=None, *, box, x_s, r_cut, n_grid,
+                    precision="fp32", out=None):
+        """Short- plus long-range P3M acceleration (n, 3) FP64, the two halves
+        overlapped on two streams; see p3m_force."""
+        pos, mass, active, n = self._inputs(pos, mass, active, "active")
+        out = self._out(out, n)
+        _check(self._lib.p3m_force(self._h, self._p(pos), self._p(mass), self._p(active), n,
+                                   float(box), float(x_s), float(r_cut), int(n_grid),
+                                   _prec(precision), self._p(out), _stream_ptr(self.device)))
+        return out
+
     def kdk_step(self, pos, vel, mass, rung, *, box, x_s, r_cut, n_grid, dt, n_steps=1,
                  eta=0.025, eps=0.0, max_rung=7, fixed_rungs=False, precision="fp64"):
         """Advance pos, vel (n x 3 FP64, in place) by n_steps steps of dt with
@@ -380,6 +392,14 @@ def lr_force(pos, mass=None, active=None, *, box=1.0, n_grid, x_s,
     return ctx.force_long_range(pos, mass, active, box=box, n_grid=n_grid, x_s=x_s)
 
 
-__all__ = ["Context", "P3MError", "Stats", "LrStats", "KdkStats", "lr_force",
+def p3m_force(pos, mass=None, active=None, *, box=1.0, x_s, r_cut, n_grid, precision="fp32",
+              context: Context | None = None):
+    """The whole P3M acceleration (n, 3) FP64 (short range + PM) of the active particles."""
+    ctx = context or default_context(pos.device)
+    return ctx.force_total(pos, mass, active, box=box, x_s=x_s, r_cut=r_cut, n_grid=n_grid,
+                           precision=precision)
+
+
+__all__ = ["Context", "P3MError", "Stats", "LrStats", "KdkStats", "lr_force", "p3m_force",
            "P3M_KDK_FIXED_RUNGS", "default_context", "load_library", "sr_force",
            "sr_force_batched", "LIB_PATH", "P3M_FP32", "P3M_FP64", "EXPORTS"]

@@ -93,7 +93,11 @@ struct p3m_sr_context {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // start, pairs start/end, end
     int *host_tot = nullptr;   // pinned: receivers, clusters, items of the current call
     // long-range PM workspace and timing
-    DevBuf pm_real, pm_spec, pm_tab, pm_key, pm_rank, pm_cnt, pm_rec, pm_nkey, pm_perm, pm_recv;
+    DevBuf pm_real, pm_spec, pm_tab, pm_key, pm_rank, pm_cnt, pm_rec, pm_nkey, pm_perm, pm_recv,
+        pm_bsum, p3m_lr;
+    // p3m_force: the long-range half runs on this stream beside the short range
+    hipStream_t aux = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     p3m_lr_stats lr_stats{};
     bool lr_timed = false;
     hipStream_t lr_stream = nullptr;
@@ -465,7 +469,7 @@ int lr_run(p3m_sr_context *h, const double *pos, const double *mass, const uint8
     const size_t cells = g * g * g;
     const size_t np1 = (size_t)np + 1;
     if ((rc = ensure(h, h->pm_cnt, (cells + 1) * sizeof(int), s))) return rc;
-    if ((rc = ensure(h, h->bsum, sizeof(int) * scan_block_sums_needed(cells), s))) return rc;
+    if ((rc = ensure(h, h->pm_bsum, sizeof(int) * scan_block_sums_needed(cells), s))) return rc;
     if ((rc = ensure(h, h->pm_key, np1 * sizeof(int), s))) return rc;
     if ((rc = ensure(h, h->pm_rank, np1 * sizeof(int), s))) return rc;
     if ((rc = ensure(h, h->pm_rec, np1 * sizeof(double4), s))) return rc;
@@ -488,7 +492,7 @@ int lr_run(p3m_sr_context *h, const double *pos, const double *mass, const uint8
     uint8_t *recv = (uint8_t *)h->pm_recv.p;
     P3M_HIP(launch_pm_tables(n_grid, box, x_s, tw, w1, k2, s));
     P3M_HIP(launch_pm_sort(pos, mass, active, np, n_grid, box, hcell, (int *)h->pm_key.p,
-                           (int *)h->pm_rank.p, (int *)h->pm_cnt.p, (int *)h->bsum.p, rec, nkey,
+                           (int *)h->pm_rank.p, (int *)h->pm_cnt.p, (int *)h->pm_bsum.p, rec, nkey,
                            perm, recv, s));
     if (timing) P3M_HIP(hipEventRecord(h->lr_ev[1], s));
     P3M_HIP(launch_pm_deposit(rec, nkey, np, (double *)h->pm_real.p, n_grid, s));
@@ -561,7 +565,7 @@ int p3m_sr_destroy(p3m_sr_handle h) {
                       &h->pm_real, &h->pm_spec,  &h->pm_tab, &h->pm_key,  &h->pm_rank,
                       &h->pm_cnt,  &h->pm_rec,   &h->pm_nkey, &h->pm_perm, &h->pm_recv,
                       &h->kdk_acc, &h->kdk_lr,   &h->kdk_tq,  &h->kdk_tnext, &h->kdk_due,
-                      &h->kdk_scal, &h->htab};
+                      &h->kdk_scal, &h->htab,   &h->pm_bsum, &h->p3m_lr};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : h->ev)
@@ -569,6 +573,9 @@ int p3m_sr_destroy(p3m_sr_handle h) {
     for (hipEvent_t e : h->lr_ev)
         if (e) (void)hipEventDestroy(e);
     if (h->host_tot) (void)hipHostFree(h->host_tot);
+    if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+    if (h->join_ev) (void)hipEventDestroy(h->join_ev);
+    if (h->aux) (void)hipStreamDestroy(h->aux);
     delete h;
     return P3M_OK;
 }
@@ -967,7 +974,7 @@ int p3m_kdk_step(p3m_sr_handle h, double *pos, double *vel, const double *mass, 
         if ((rc = lr_run(h, pos, mass, nullptr, np, box, n_grid, x_s, acc_lr, s))) return rc;
         ++lr_calls;
         const int target = span0 / 2;
-        P3M_HIP(launch_kdk_lr_kick(vel, acc_lr, np, (double)(target - t_lr) * k.half_tau, s));
+        P3M_HIP(launch_axpy3(vel, acc_lr, np, (double)(target - t_lr) * k.half_tau, s));
         t_lr = target;
     }
     for (int t = 2; t <= k.period; t += 2) {
@@ -989,7 +996,7 @@ int p3m_kdk_step(p3m_sr_handle h, double *pos, double *vel, const double *mass, 
             if ((rc = lr_run(h, pos, mass, nullptr, np, box, n_grid, x_s, acc_lr, s))) return rc;
             ++lr_calls;
             const int target = t == k.period ? k.period : t + span0 / 2;
-            P3M_HIP(launch_kdk_lr_kick(vel, acc_lr, np, (double)(target - t_lr) * k.half_tau, s));
+            P3M_HIP(launch_axpy3(vel, acc_lr, np, (double)(target - t_lr) * k.half_tau, s));
             t_lr = target;
         }
     }
@@ -1011,6 +1018,61 @@ int p3m_kdk_step(p3m_sr_handle h, double *pos, double *vel, const double *mass, 
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }
+    return P3M_OK;
+}
+
+int p3m_force(p3m_sr_handle h, const double *pos, const double *mass, const uint8_t *active,
+              int64_t n, double box, double x_s, double r_cut, int n_grid, int precision,
+              double *acc_out, void *stream) {
+    int rc;
+    if ((rc = check_geometry(n, box, x_s, r_cut))) return rc;
+    if (precision != P3M_FP32 && precision != P3M_FP64)
+        return set_error(P3M_EINVAL, "precision must be P3M_FP64 or P3M_FP32");
+    if (n_grid < 16 || n_grid > 1024 || (n_grid & (n_grid - 1)) != 0)
+        return set_error(P3M_EINVAL, "n_grid must be a power of two in [16, 1024], got %d",
+                         n_grid);
+    if (n > 0 && (!pos || !acc_out)) return set_error(P3M_EINVAL, "pos and acc_out are required");
+    if (!aligned8(pos) || !aligned8(acc_out) || !aligned8(mass))
+        return set_error(P3M_EINVAL, "pos, mass and acc_out must be 8-byte aligned");
+    if ((rc = check_handle(h))) return rc;
+    if (n > (int64_t)0x7ffffff0)
+        return set_error(P3M_EUNSUPPORTED, "more than 2^31 - 16 particles");
+    if ((rc = set_device(h))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int np = (int)n;
+    if (!h->aux) {
+        P3M_HIP(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+        P3M_HIP(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
+        P3M_HIP(hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming));
+    }
+    if ((rc = ensure(h, h->p3m_lr, ((size_t)np + 1) * 3 * sizeof(double), s))) return rc;
+    // the long range waits for the caller's earlier work, then runs on the
+    // auxiliary stream while the short range runs on the caller's
+    P3M_HIP(hipEventRecord(h->fork_ev, s));
+    P3M_HIP(hipStreamWaitEvent(h->aux, h->fork_ev, 0));
+    if ((rc = lr_run(h, pos, mass, active, np, box, n_grid, x_s, (double *)h->p3m_lr.p,
+                     h->aux)))
+        return rc;
+    P3M_HIP(hipEventRecord(h->join_ev, h->aux));
+    Request r{};
+    r.pos = pos;
+    r.mass = mass;
+    r.sel = active;
+    r.sel_kind = active ? SEL_MASK : SEL_ALL;
+    r.n_sub = 1;
+    r.n = n;
+    r.box = box;
+    r.x_s = x_s;
+    r.r_cut = r_cut;
+    r.precision = precision;
+    r.out = acc_out;
+    r.stream = s;
+    rc = run(h, r);
+    // join before returning, also when the short range failed
+    P3M_HIP(hipStreamWaitEvent(s, h->join_ev, 0));
+    if (rc) return rc;
+    P3M_HIP(launch_axpy3(acc_out, (const double *)h->p3m_lr.p, np, 1.0, s));
+    h->last_stream = s;
     return P3M_OK;
 }
 

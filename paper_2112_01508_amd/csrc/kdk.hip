@@ -119,8 +119,9 @@ __global__ void k_kdk_kick(double *__restrict__ vel, const double *__restrict__ 
     t_next[i] = (t / sp + 1) * sp;
 }
 
-__global__ void k_kdk_lr_kick(double *__restrict__ vel, const double *__restrict__ acc, size_t n3,
-                              double dk) {
+// y += a x over n x 3 values (long-range kicks; summing the two force halves)
+__global__ void k_axpy3(double *__restrict__ vel, const double *__restrict__ acc, size_t n3,
+                        double dk) {
     const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n3) return;
     vel[j] = vel[j] + acc[j] * dk;
@@ -171,9 +172,9 @@ hipError_t launch_kdk_kick(double *vel, const double *acc, const uint8_t *due, i
     return hipGetLastError();
 }
 
-hipError_t launch_kdk_lr_kick(double *vel, const double *acc, int n, double dk, hipStream_t s) {
+hipError_t launch_axpy3(double *vel, const double *acc, int n, double dk, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    k_kdk_lr_kick<<<blocks(3 * (size_t)n), 256, 0, s>>>(vel, acc, 3 * (size_t)n, dk);
+    k_axpy3<<<blocks(3 * (size_t)n), 256, 0, s>>>(vel, acc, 3 * (size_t)n, dk);
     return hipGetLastError();
 }
 

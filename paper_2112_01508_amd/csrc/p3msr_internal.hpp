@@ -227,7 +227,8 @@ hipError_t launch_kdk_due(const int *t_next, int n, int t, uint8_t *due, int *n_
 hipError_t launch_kdk_kick(double *vel, const double *acc, const uint8_t *due, int n, int t,
                            const KdkArgs &k, uint8_t *rung, int *t_q, int *t_next,
                            hipStream_t s);
-hipError_t launch_kdk_lr_kick(double *vel, const double *acc, int n, double dk, hipStream_t s);
+// vel += dk acc over n x 3 values
+hipError_t launch_axpy3(double *vel, const double *acc, int n, double dk, hipStream_t s);
 hipError_t launch_kdk_accum(const Counters *c, unsigned long long *total, hipStream_t s);
 
 }  // namespace p3m

@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "p3msr.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(p3m_(?:sr|lr|kdk)_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(p3m_(?:(?:sr|lr|kdk)_\w+|force))\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -30,7 +30,7 @@ def test_header_declares_the_boundary():
     for must in ["p3m_sr_create", "p3m_sr_destroy", "p3m_sr_force", "p3m_sr_force_backward",
                  "p3m_sr_force_batched", "p3m_sr_autotune", "p3m_sr_get_stats",
                  "p3m_sr_last_error", "p3m_lr_force", "p3m_lr_get_stats", "p3m_kdk_step",
-                 "p3m_kdk_get_stats"]:
+                 "p3m_kdk_get_stats", "p3m_force"]:
         assert must in names
 
 
@@ -138,6 +138,26 @@ def test_kdk_invalid_arguments_are_rejected(lib, kw, msg):
     args.update(kw)
     rc = lib.p3m_kdk_step(*args.values())
     assert rc == -1
+    assert msg in lib.p3m_sr_last_error().decode()
+
+
+@pytest.mark.parametrize("kw, msg", [
+    (dict(n=-1), "n must be"),
+    (dict(r_cut=0.6), "box/2"),
+    (dict(x_s=0.005), "4.5 x_s"),
+    (dict(prec=5), "precision"),
+    (dict(n_grid=48), "n_grid"),
+    (dict(n_grid=2048), "n_grid"),
+    (dict(pos=None), "required"),
+    (dict(out=ctypes.c_void_p(20)), "aligned"),
+    (dict(), "NULL handle"),
+])
+def test_p3m_force_invalid_arguments_are_rejected(lib, kw, msg):
+    args = dict(h=None, pos=ctypes.c_void_p(8), mass=None, active=None, n=10, box=1.0,
+                x_s=0.01, r_cut=0.045, n_grid=64, prec=1, out=ctypes.c_void_p(8), stream=None)
+    args.update(kw)
+    rc = lib.p3m_force(*args.values())
+    assert rc == (-4 if "4.5" in msg else -1)
     assert msg in lib.p3m_sr_last_error().decode()
 
 
