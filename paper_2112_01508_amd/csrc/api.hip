@@ -80,7 +80,7 @@ struct p3m_sr_context {
     int n_cu = 0;
     int blocks_per_cu[4][2][2] = {};   // [mode][screen][tabulated shape]
     DevBuf key, rank, cells, sp, perm, sel, sp2, perm2, sel2, flags, actpos, ncl, clusters,
-        itemcnt, items, bsum, counters, wa, scal, rp, rperm, rwa;
+        itemcnt, items, bsum, counters, wa, scal, rp, rperm, rwa, fbig;
     int cfg_ns = 0, cfg_target = 0, cfg_csize = 0, cfg_screen = -1;
     int cfg_shape = SHAPE_POLY, cfg_tab_n = 0;   // FP32 forward shape (p3m_sr_set_shape)
     DevBuf htab;
@@ -91,6 +91,7 @@ struct p3m_sr_context {
     bool timing = false;
     bool timed_last = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // start, pairs start/end, end
+    hipEvent_t tot_ev = nullptr;   // after the totals of a call reach host memory
     int *host_tot = nullptr;   // pinned: receivers, clusters, items of the current call
     // long-range PM workspace and timing
     DevBuf pm_real, pm_spec, pm_tab, pm_key, pm_rank, pm_cnt, pm_rec, pm_nkey, pm_perm, pm_recv,
@@ -308,10 +309,14 @@ int run(p3m_sr_context *h, const Request &r) {
     const size_t ncl_len = (size_t)n_sub * g.nt3;
     const size_t cl_bound = ncl_len + (nflags + csize - 1) / csize;
     const size_t scan_max = std::max(std::max(ncells, nflags), std::max(ncl_len, cl_bound));
+    // one subset with every particle a receiver: receivers are the sorted
+    // particles themselves, no flags, scan or compaction
+    const bool all_recv = n_sub == 1 && (r.backward || r.sel_kind == SEL_ALL);
     int rc;
     if ((rc = ensure(h, h->key, sizeof(int) * n, s))) return rc;
     if ((rc = ensure(h, h->rank, sizeof(int) * n, s))) return rc;
     if ((rc = ensure(h, h->cells, sizeof(int) * (ncells + 1), s))) return rc;
+    if ((rc = ensure(h, h->fbig, sizeof(int) * (2 + (size_t)n / kFineBig), s))) return rc;
     if ((rc = ensure(h, h->sp, sizeof(double4) * ((size_t)n + kSupplierPad), s))) return rc;
     if ((rc = ensure(h, h->perm, sizeof(int) * n, s))) return rc;
     if ((rc = ensure(h, h->sel, (size_t)n, s))) return rc;
@@ -342,8 +347,20 @@ int run(p3m_sr_context *h, const Request &r) {
     int *scal = (int *)h->scal.p;   // [16 ..] the XCD work queues
 
     // ---- sort ----
-    P3M_HIP(launch_fill_i32(cells, 0, ncells + 1, s));
-    P3M_HIP(launch_fill_i32((int *)counters, 0, sizeof(Counters) / sizeof(int), s));
+    int *fbig = (int *)h->fbig.p;
+    int *queue = scal + 16;
+    double4 *sp_f = (double4 *)h->sp2.p;   // the sorted particles after the fine order
+    {
+        // every small initialisation of the call in one launch
+        FillSet f{};
+        f.add(cells, ncells + 1, 0);
+        f.add((int *)counters, sizeof(Counters) / sizeof(int), 0);
+        f.add(fbig, 1, 0);
+        f.add(queue, kXcds, 0);
+        f.add((int *)(sp_f + n), kSupplierPad * sizeof(double4) / sizeof(int), 0);
+        if (all_recv) f.add(flags + nflags, 1, n);   // the receiver total
+        P3M_HIP(launch_fill_multi(f, s));
+    }
     P3M_HIP(launch_keys(r.pos, n, g, key, rank, cells, s));
     P3M_HIP(launch_scan(cells, cells, ncells, bsum, s));
     const uint8_t *sel_src = (r.sel_kind == SEL_ALL && !r.backward) ? nullptr : r.sel;
@@ -351,33 +368,54 @@ int run(p3m_sr_context *h, const Request &r) {
                            sel_s, s));
     // fine order inside dense subtiles (key/rank are free again as scratch)
     {
-        double4 *sp_f = (double4 *)h->sp2.p;
         int *perm_f = (int *)h->perm2.p;
         uint8_t *sel_f = (uint8_t *)h->sel2.p;
         // a subtile no larger than one cluster gains nothing from the reorder
         P3M_HIP(launch_fine_order(sp, perm, sel_s, cells, g, key, rank, sp_f, perm_f, sel_f,
-                                  csize, s));
+                                  csize, n, fbig, s));
         sp = sp_f;
         perm = perm_f;
         sel_s = sel_f;
     }
-    P3M_HIP(launch_fill_i32((int *)(sp + n), 0, kSupplierPad * sizeof(double4) / sizeof(int), s));
 
     // ---- receivers -> clusters -> items ----
     // the adjoint needs every particle as a receiver (its output rows are
     // the particles near any active one); activity enters through wa
     const int kind = r.backward ? SEL_ALL : r.sel_kind;
-    P3M_HIP(launch_flags(sel_s, n, n_sub, kind, r.thr, flags, s));
-    P3M_HIP(launch_scan(flags, flags, nflags, bsum, s));
-    P3M_HIP(launch_compact(flags, n, n_sub, actpos, s));
-    P3M_HIP(launch_cluster_count(cells, flags, n, n_sub, g, csize, ncl, s));
+    const int *recv_scan = flags, *recv_pos = actpos;
+    if (all_recv) {
+        recv_scan = recv_pos = nullptr;
+    } else {
+        P3M_HIP(launch_flags(sel_s, n, n_sub, kind, r.thr, flags, s));
+        P3M_HIP(launch_scan(flags, flags, nflags, bsum, s));
+        P3M_HIP(launch_compact(flags, n, n_sub, actpos, s));
+    }
+    P3M_HIP(launch_cluster_count(cells, recv_scan, n, n_sub, g, csize, ncl, s));
     P3M_HIP(launch_scan(ncl, ncl, ncl_len, bsum, s));
-    P3M_HIP(launch_cluster_write(cells, flags, ncl, n, n_sub, g, csize, clusters, s));
+    P3M_HIP(launch_cluster_write(cells, recv_scan, ncl, n, n_sub, g, csize, clusters, s));
     P3M_HIP(launch_item_count(clusters, ncl + ncl_len, (int)cl_bound, cells, g, target, itemcnt,
                               s));
     P3M_HIP(launch_scan(itemcnt, itemcnt, cl_bound, bsum, s));
     P3M_HIP(launch_totals(flags + nflags, ncl + ncl_len, itemcnt + cl_bound, h->host_tot, s));
-    P3M_HIP(hipStreamSynchronize(s));
+    if (!h->tot_ev) P3M_HIP(hipEventCreateWithFlags(&h->tot_ev, hipEventDisableTiming));
+    P3M_HIP(hipEventRecord(h->tot_ev, s));
+
+    // work that needs no totals runs while the host waits for them
+    double4 *wa = r.backward ? (double4 *)h->wa.p : nullptr;
+    if (r.backward) P3M_HIP(launch_gather_weights(r.grad_acc, sel_s, perm, n, fp32, wa, s));
+    // with every particle a receiver the receivers are sp / perm / wa as they are
+    double4 *rp = all_recv ? nullptr : (double4 *)h->rp.p;
+    P3M_HIP(launch_cluster_finish(clusters, ncl + ncl_len, cl_bound, csize, recv_pos, sp, perm, wa,
+                                  rp, (int *)h->rperm.p,
+                                  r.backward ? (double4 *)h->rwa.p : nullptr, s));
+    P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, s));
+    // tabulated FP32 shape (point particles, forward only)
+    const int shape = (fp32 && !r.backward && g.eps_b == 0.0) ? h->cfg_shape : SHAPE_POLY;
+    if (shape != SHAPE_POLY) {
+        if ((rc = ensure(h, h->htab, kTabFloats * sizeof(float), s))) return rc;
+        P3M_HIP(launch_build_htab(shape, h->cfg_tab_n, g, (float *)h->htab.p, s));
+    }
+    P3M_HIP(hipEventSynchronize(h->tot_ev));
     const int n_recv = h->host_tot[0], n_clusters = h->host_tot[1], n_items = h->host_tot[2];
     st.receivers = n_recv;
     st.clusters = n_clusters;
@@ -387,26 +425,18 @@ int run(p3m_sr_context *h, const Request &r) {
         return rc;
     Item *items = (Item *)h->items.p;
     P3M_HIP(launch_item_write(clusters, n_clusters, cells, g, target, itemcnt, items, s));
-    double4 *wa = r.backward ? (double4 *)h->wa.p : nullptr;
-    if (r.backward) P3M_HIP(launch_gather_weights(r.grad_acc, sel_s, perm, n, fp32, wa, s));
-    P3M_HIP(launch_cluster_finish(clusters, n_clusters, actpos, sp, perm, wa, (double4 *)h->rp.p,
-                                  (int *)h->rperm.p, r.backward ? (double4 *)h->rwa.p : nullptr,
-                                  s));
-    int *queue = scal + 16;
-    P3M_HIP(launch_fill_i32(queue, 0, kXcds, s));
 
     // ---- pairs ----
-    P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, s));
     PairArgs a{};
     a.sp = sp;
-    a.rp = (const double4 *)h->rp.p;
-    a.rwa = (const double4 *)h->rwa.p;
+    a.rp = all_recv ? sp : (const double4 *)h->rp.p;
+    a.rwa = all_recv ? wa : (const double4 *)h->rwa.p;
     a.cell_start = cells;
     a.clusters = clusters;
     a.items = items;
     a.wa = wa;
     a.queue = queue;
-    a.rperm = (const int *)h->rperm.p;
+    a.rperm = all_recv ? perm : (const int *)h->rperm.p;
     a.out = r.out;
     a.out_stride = 3ll * n;
     a.counters = counters;
@@ -414,15 +444,10 @@ int run(p3m_sr_context *h, const Request &r) {
     a.unit_mass = r.mass ? 0 : 1;
     a.csize = csize;
     a.g = g;
-    // tabulated FP32 shape (point particles, forward only)
-    const int shape = (fp32 && !r.backward && g.eps_b == 0.0) ? h->cfg_shape : SHAPE_POLY;
     if (shape != SHAPE_POLY) {
-        const int tab_n = h->cfg_tab_n;
-        if ((rc = ensure(h, h->htab, kTabFloats * sizeof(float), s))) return rc;
-        P3M_HIP(launch_build_htab(shape, tab_n, g, (float *)h->htab.p, s));
         a.htab = (const float *)h->htab.p;
-        a.tab_n = tab_n;
-        a.tab_scale = (float)((double)tab_n / g.rc2);
+        a.tab_n = h->cfg_tab_n;
+        a.tab_scale = (float)((double)h->cfg_tab_n / g.rc2);
     }
     st.shape = shape;
     int &bpc = h->blocks_per_cu[mode][screen][shape != SHAPE_POLY ? 1 : 0];
@@ -561,7 +586,7 @@ int p3m_sr_destroy(p3m_sr_handle h) {
                       &h->sel,     &h->sp2,      &h->perm2,  &h->sel2,  &h->flags,
                       &h->actpos,  &h->ncl,      &h->clusters, &h->itemcnt, &h->items,
                       &h->bsum,    &h->counters, &h->wa,     &h->scal,
-                      &h->rp,      &h->rperm,    &h->rwa,
+                      &h->rp,      &h->rperm,    &h->rwa,    &h->fbig,
                       &h->pm_real, &h->pm_spec,  &h->pm_tab, &h->pm_key,  &h->pm_rank,
                       &h->pm_cnt,  &h->pm_rec,   &h->pm_nkey, &h->pm_perm, &h->pm_recv,
                       &h->kdk_acc, &h->kdk_lr,   &h->kdk_tq,  &h->kdk_tnext, &h->kdk_due,
@@ -570,6 +595,7 @@ int p3m_sr_destroy(p3m_sr_handle h) {
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : h->ev)
         if (e) (void)hipEventDestroy(e);
+    if (h->tot_ev) (void)hipEventDestroy(h->tot_ev);
     for (hipEvent_t e : h->lr_ev)
         if (e) (void)hipEventDestroy(e);
     if (h->host_tot) (void)hipHostFree(h->host_tot);

@@ -30,6 +30,9 @@ constexpr int kSupplierPad = 128;           // zeroed records after the sorted p
 constexpr int kFineSide = 8;                // fine order: 8x8x8 sub-cells per subtile
 constexpr int kFineBins = kFineSide * kFineSide * kFineSide;
 constexpr int kFineMin = 8;                 // subtiles with at most this many keep their order
+constexpr int kFineBig = 1024;              // larger subtiles are ordered by a whole block
+constexpr int kFineWaves = 4;               // tiles (one per wave) per fine-order block
+constexpr int kFinishWaves = 4;             // clusters (one per wave) per finishing block
 constexpr int kListCap = 224;               // screened supplier records per wave (LDS)
 constexpr int kListCapAdjoint = 128;        // the same for the adjoint (entries carry weights)
 constexpr int kListSlack = 32;              // records past the cap for look-ahead reads (3*8 used)
@@ -94,6 +97,7 @@ enum SelKind { SEL_ALL = 0, SEL_MASK = 1, SEL_RUNG = 2 };
 // sort.hip
 hipError_t launch_fill_i32(int *p, int v, size_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
+// cell key and rank inside the cell of every particle (cell_count zeroed)
 hipError_t launch_keys(const double *pos, int n, const Geom &g, int *key, int *rank,
                        int *cell_count, hipStream_t s);
 size_t scan_block_sums_needed(size_t n);
@@ -105,17 +109,20 @@ hipError_t launch_scatter(const double *pos, const double *mass, const uint8_t *
                           const int *cell_start, int fp32, double4 *sp, int *perm,
                           uint8_t *sel_s, hipStream_t s);
 // reorder the particles of every subtile by the Morton index of their fine
-// sub-cell (sp/perm/sel -> sp2/perm2/sel2; fkey/frank: n ints of scratch)
+// sub-cell (sp/perm/sel -> sp2/perm2/sel2; fkey/frank: n ints of scratch;
+// big_list: 1 + n / kFineBig ints, big_list[0] zeroed before the call)
 hipError_t launch_fine_order(const double4 *sp, const int *perm, const uint8_t *sel,
                              const int *cell_start, const Geom &g, int *fkey, int *frank,
-                             double4 *sp2, int *perm2, uint8_t *sel2, int csize,
-                             hipStream_t s);
+                             double4 *sp2, int *perm2, uint8_t *sel2, int csize, int n,
+                             int *big_list, hipStream_t s);
 hipError_t launch_flags(const uint8_t *sel_s, int n, int n_sub, int kind,
                         const uint8_t *thr_host, int *flags, hipStream_t s);
 hipError_t launch_compact(const int *scan, int n, int n_sub, int *act_pos, hipStream_t s);
 // *a, *b, *c -> host_out[0..2] (pinned host memory)
 hipError_t launch_totals(const int *a, const int *b, const int *c, int *host_out,
                          hipStream_t s);
+// scan == nullptr (one subset, every particle a receiver): receivers are the
+// sorted particles themselves
 hipError_t launch_cluster_count(const int *cell_start, const int *scan, int n, int n_sub,
                                 const Geom &g, int csize, int *ncl, hipStream_t s);
 hipError_t launch_cluster_write(const int *cell_start, const int *scan, const int *cl_off,
@@ -129,11 +136,28 @@ hipError_t launch_item_write(const Cluster *clusters, int n_clusters, const int 
                              hipStream_t s);
 hipError_t launch_gather_weights(const double *grad_acc, const uint8_t *sel_s, const int *perm,
                                  int n, int fp32, double4 *wa, hipStream_t s);
-// per cluster: receivers copied to rp / rperm / rwa (indexed like act_pos) and
-// the bounding box filled in
-hipError_t launch_cluster_finish(Cluster *clusters, int n_clusters, const int *act_pos,
-                                 const double4 *sp, const int *perm, const double4 *wa,
-                                 double4 *rp, int *rperm, double4 *rwa, hipStream_t s);
+// per cluster: receivers copied to rp / rperm / rwa (indexed like act_pos;
+// rp == nullptr: no copy, act_pos == nullptr as scan == nullptr above) and the
+// bounding box filled in; *n_clusters_dev clusters, at most `bound`
+hipError_t launch_cluster_finish(Cluster *clusters, const int *n_clusters_dev, size_t bound,
+                                 int csize, const int *act_pos, const double4 *sp,
+                                 const int *perm, const double4 *wa, double4 *rp, int *rperm,
+                                 double4 *rwa, hipStream_t s);
+// up to kFillMax int regions set to their values in one launch
+constexpr int kFillMax = 8;
+struct FillSet {
+    int *p[kFillMax];
+    size_t n[kFillMax];
+    int v[kFillMax];
+    int count;
+    void add(int *ptr, size_t len, int val) {
+        p[count] = ptr;
+        n[count] = len;
+        v[count] = val;
+        ++count;
+    }
+};
+hipError_t launch_fill_multi(const FillSet &f, hipStream_t s);
 
 // force.hip
 enum PairMode { FWD_F32 = 0, FWD_F64 = 1, BWD_F32 = 2, BWD_F64 = 3 };

@@ -58,16 +58,45 @@ __device__ inline int key_of(int cx, int cy, int cz, const Geom &g) {
     return tile * g.ns3 + (sx * g.ns + sy) * g.ns + sz;
 }
 
+// Cell key and rank inside the cell.  Lanes of a wave that share a cell
+// take one atomic for the group (a dense cell's particles often sit in the
+// same wave): the first lane of each group adds the group's size, and each
+// member's rank is the returned base plus its place in the group.  Device-
+// scope atomics are performed at the memory side, so their count, not
+// contention, sets this kernel's time.
 __global__ void k_keys(const double *__restrict__ pos, int n, Geom g, int *__restrict__ key,
                        int *__restrict__ rank, int *__restrict__ cell_count) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double wx = wrap_coord(pos[3 * (size_t)i], g);
-    double wy = wrap_coord(pos[3 * (size_t)i + 1], g);
-    double wz = wrap_coord(pos[3 * (size_t)i + 2], g);
-    int k = key_of(cell_of(wx, g), cell_of(wy, g), cell_of(wz, g), g);
-    key[i] = k;
-    rank[i] = atomicAdd(&cell_count[k], 1);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool live = i < n;
+    int k = -1;
+    if (live) {
+        const double wx = wrap_coord(pos[3 * (size_t)i], g);
+        const double wy = wrap_coord(pos[3 * (size_t)i + 1], g);
+        const double wz = wrap_coord(pos[3 * (size_t)i + 2], g);
+        k = key_of(cell_of(wx, g), cell_of(wy, g), cell_of(wz, g), g);
+        key[i] = k;
+    }
+    // group the live lanes by key: my_lead = first lane of my group, my_off =
+    // my place in it, lead lanes also hold the group size
+    unsigned long long todo = __ballot(live);
+    int my_lead = 0, my_off = 0, size = 0;
+    while (todo) {
+        const int lead = __ffsll((long long)todo) - 1;
+        const int kl = __shfl(k, lead, kWave);
+        const unsigned long long grp = __ballot(k == kl) & todo;
+        if ((grp >> lane) & 1ull) {
+            my_lead = lead;
+            my_off = __builtin_amdgcn_mbcnt_hi((unsigned)(grp >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((unsigned)grp, 0u));
+        }
+        if (lane == lead) size = __popcll(grp);
+        todo &= ~grp;
+    }
+    int base = 0;
+    if (live && lane == my_lead) base = atomicAdd(&cell_count[k], size);
+    base = __shfl(base, my_lead, kWave);
+    if (live) rank[i] = base + my_off;
 }
 
 // ---- exclusive scan (reduce / top / down-sweep) -----------------------------
@@ -226,25 +255,25 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// One wave per tile.  Inside every subtile holding more than kFineMin
-// particles the particles are reordered by fine_key (a counting sort over
-// kFineBins bins in LDS); smaller subtiles are copied as they are.  Reads
-// sp/perm/sel and writes sp2/perm2/sel2; fkey/frank are scratch indexed by
-// sorted position.  Consecutive receivers then lie close together, so small
-// clusters have small bounding boxes.
-__global__ __launch_bounds__(kWave) void k_fine_order(const double4 *__restrict__ sp,
-                                                      const int *__restrict__ perm,
-                                                      const uint8_t *__restrict__ sel,
-                                                      const int *__restrict__ cs, Geom g,
-                                                      int *__restrict__ fkey,
-                                                      int *__restrict__ frank,
-                                                      double4 *__restrict__ sp2,
-                                                      int *__restrict__ perm2,
-                                                      uint8_t *__restrict__ sel2,
-                                                      int keep_max) {
-    __shared__ int hist[kFineBins];
-    const int lane = threadIdx.x;
-    for (long long tile = blockIdx.x; tile < g.nt3; tile += gridDim.x) {
+// Fine order, small and medium subtiles: one wave per tile, kFineWaves
+// tiles per block.  Inside every subtile holding more than keep_max and at
+// most kFineBig particles the particles are reordered by fine_key (a
+// counting sort over kFineBins bins in LDS); smaller subtiles are copied as
+// they are; larger ones are appended to big_list (big_list[0] counts them)
+// for k_fine_order_big.  Reads sp/perm/sel and writes sp2/perm2/sel2;
+// fkey/frank are scratch indexed by sorted position.  Consecutive receivers
+// then lie close together, so small clusters have small bounding boxes.
+__global__ __launch_bounds__(kFineWaves * kWave) void k_fine_order(
+    const double4 *__restrict__ sp, const int *__restrict__ perm, const uint8_t *__restrict__ sel,
+    const int *__restrict__ cs, Geom g, int *__restrict__ fkey, int *__restrict__ frank,
+    double4 *__restrict__ sp2, int *__restrict__ perm2, uint8_t *__restrict__ sel2, int keep_max,
+    int *__restrict__ big_list) {
+    __shared__ int hists[kFineWaves][kFineBins];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    int *hist = hists[w];
+    for (long long tile = (long long)blockIdx.x * kFineWaves + w; tile < g.nt3;
+         tile += (long long)gridDim.x * kFineWaves) {
         const int *c = cs + tile * g.ns3;
         for (int s = 0; s < g.ns3; ++s) {
             const int a0 = c[s], a1 = c[s + 1];
@@ -254,6 +283,10 @@ __global__ __launch_bounds__(kWave) void k_fine_order(const double4 *__restrict_
                     perm2[i] = perm[i];
                     sel2[i] = sel[i];
                 }
+                continue;
+            }
+            if (a1 - a0 > kFineBig) {
+                if (lane == 0) big_list[1 + atomicAdd(big_list, 1)] = (int)(tile * g.ns3 + s);
                 continue;
             }
             for (int b = lane; b < kFineBins; b += kWave) hist[b] = 0;
@@ -295,6 +328,44 @@ __global__ __launch_bounds__(kWave) void k_fine_order(const double4 *__restrict_
     }
 }
 
+// Fine order of the subtiles holding more than kFineBig particles (listed
+// by k_fine_order): one block of kFineBins threads per subtile, the same
+// counting sort with one bin per thread in the scan.  A single wave would
+// take the densest halo cores alone, long after the rest of the grid.
+__global__ __launch_bounds__(kFineBins) void k_fine_order_big(
+    const double4 *__restrict__ sp, const int *__restrict__ perm, const uint8_t *__restrict__ sel,
+    const int *__restrict__ cs, Geom g, int *__restrict__ fkey, int *__restrict__ frank,
+    double4 *__restrict__ sp2, int *__restrict__ perm2, uint8_t *__restrict__ sel2,
+    const int *__restrict__ big_list) {
+    __shared__ int hist[kFineBins];
+    __shared__ int lds[kFineBins / kWave];
+    const int t = threadIdx.x;
+    const int n_big = big_list[0];
+    for (int j = blockIdx.x; j < n_big; j += gridDim.x) {
+        const int cell = big_list[1 + j];
+        const int a0 = cs[cell], a1 = cs[cell + 1];
+        hist[t] = 0;
+        __syncthreads();
+        for (int i = a0 + t; i < a1; i += kFineBins) {
+            const int k = fine_key(sp[i], g);
+            fkey[i] = k;
+            frank[i] = atomicAdd(&hist[k], 1);
+        }
+        __syncthreads();
+        int total;
+        const int ex = block_exclusive_scan(hist[t], lds, &total);
+        hist[t] = ex;   // every thread has read its own bin in the call above
+        __syncthreads();
+        for (int i = a0 + t; i < a1; i += kFineBins) {
+            const int dst = a0 + hist[fkey[i]] + frank[i];
+            sp2[dst] = sp[i];
+            perm2[dst] = perm[i];
+            sel2[dst] = sel[i];
+        }
+        __syncthreads();
+    }
+}
+
 // ---- receiver selection and compaction ---------------------------------------
 
 struct Thresholds { uint8_t t[64]; };
@@ -331,8 +402,10 @@ __global__ void k_cluster_count(const int *__restrict__ cs, const int *__restric
     int k = idx / g.nt3;
     int t = idx - k * g.nt3;
     size_t off = (size_t)k * n;
-    int a0 = scan[off + cs[(size_t)t * g.ns3]];
-    int a1 = scan[off + cs[(size_t)(t + 1) * g.ns3]];
+    // scan == nullptr: every particle is a receiver (one subset)
+    const int b0 = cs[(size_t)t * g.ns3], b1 = cs[(size_t)(t + 1) * g.ns3];
+    int a0 = scan ? scan[off + b0] : b0;
+    int a1 = scan ? scan[off + b1] : b1;
     ncl[idx] = (a1 - a0 + csize - 1) / csize;
 }
 
@@ -344,8 +417,9 @@ __global__ void k_cluster_write(const int *__restrict__ cs, const int *__restric
     int k = idx / g.nt3;
     int t = idx - k * g.nt3;
     size_t off = (size_t)k * n;
-    int a0 = scan[off + cs[(size_t)t * g.ns3]];
-    int a1 = scan[off + cs[(size_t)(t + 1) * g.ns3]];
+    const int b0 = cs[(size_t)t * g.ns3], b1 = cs[(size_t)(t + 1) * g.ns3];
+    int a0 = scan ? scan[off + b0] : b0;
+    int a1 = scan ? scan[off + b1] : b1;
     int o = cl_off[idx];
     for (int b = a0; b < a1; b += csize) {
         Cluster c{};
@@ -454,35 +528,65 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
-// One wave per cluster: gather the receivers into contiguous arrays and
-// compute their bounding box (lanes past count repeat receiver 0).
-__global__ __launch_bounds__(kWave) void k_cluster_finish(Cluster *__restrict__ clusters,
-                                                          const int *__restrict__ act_pos,
-                                                          const double4 *__restrict__ sp,
-                                                          const int *__restrict__ perm,
-                                                          const double4 *__restrict__ wa,
-                                                          double4 *__restrict__ rp,
-                                                          int *__restrict__ rperm,
-                                                          double4 *__restrict__ rwa) {
-    const int c = blockIdx.x;
-    const int lane = threadIdx.x;
-    Cluster cl = clusters[c];
-    const bool live = lane < cl.count;
-    const int a = cl.begin + (live ? lane : 0);
-    const int p = act_pos[a];
-    const double4 x = sp[p];
-    if (live) {
-        rp[a] = x;
-        rperm[a] = perm[p];
-        if (rwa) rwa[a] = wa[p];
+// Receivers of each cluster gathered into contiguous arrays (rp / rperm /
+// rwa, skipped when rp == nullptr: the receivers are then the sorted
+// particles themselves, act_pos == nullptr) and the cluster's bounding box.
+// One lane group of csize lanes per cluster, 64 / csize clusters per wave,
+// kFinishWaves waves per block; lanes past a cluster's count repeat its
+// first receiver.  The cluster count is read on the device, so the launch
+// can be sized by an upper bound before the count reaches the host.
+__global__ __launch_bounds__(kFinishWaves * kWave) void k_cluster_finish(
+    Cluster *__restrict__ clusters, const int *__restrict__ n_clusters_dev, int csize,
+    const int *__restrict__ act_pos, const double4 *__restrict__ sp, const int *__restrict__ perm,
+    const double4 *__restrict__ wa, double4 *__restrict__ rp, int *__restrict__ rperm,
+    double4 *__restrict__ rwa) {
+    const int n_clusters = *n_clusters_dev;
+    const int per_wave = kWave / csize;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = blockIdx.x * kFinishWaves + (int)(threadIdx.x / kWave);
+    if (wave * per_wave >= n_clusters) return;   // whole waves leave together
+    const int c = wave * per_wave + lane / csize;
+    const int li = lane & (csize - 1);
+    const bool have = c < n_clusters;
+    Cluster cl{};
+    double4 x = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (have) {
+        cl = clusters[c];
+        const bool live = li < cl.count;
+        const int a = cl.begin + (live ? li : 0);
+        const int p = act_pos ? act_pos[a] : a;
+        x = sp[p];
+        if (live && rp) {
+            rp[a] = x;
+            rperm[a] = perm[p];
+            if (rwa) rwa[a] = wa[p];
+        }
     }
-    const double lx = wave_min(x.x), ly = wave_min(x.y), lz = wave_min(x.z);
-    const double hx = wave_max(x.x), hy = wave_max(x.y), hz = wave_max(x.z);
-    if (lane == 0) {
+    // min / max over each aligned group of csize lanes
+    double lx = x.x, ly = x.y, lz = x.z, hx = x.x, hy = x.y, hz = x.z;
+    for (int off = csize >> 1; off > 0; off >>= 1) {
+        lx = fmin(lx, __shfl_xor(lx, off, kWave));
+        ly = fmin(ly, __shfl_xor(ly, off, kWave));
+        lz = fmin(lz, __shfl_xor(lz, off, kWave));
+        hx = fmax(hx, __shfl_xor(hx, off, kWave));
+        hy = fmax(hy, __shfl_xor(hy, off, kWave));
+        hz = fmax(hz, __shfl_xor(hz, off, kWave));
+    }
+    if (have && li == 0) {
         cl.lo[0] = lx; cl.lo[1] = ly; cl.lo[2] = lz;
         cl.hi[0] = hx; cl.hi[1] = hy; cl.hi[2] = hz;
         clusters[c] = cl;
     }
+}
+
+// Several int fills in one launch: region blockIdx.y, grid-stride over it.
+__global__ void k_fill_multi(FillSet f) {
+    const int r = blockIdx.y;
+    int *__restrict__ p = f.p[r];
+    const size_t n = f.n[r];
+    const int v = f.v[r];
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
 inline unsigned grid_for(size_t n, int block) {
@@ -492,12 +596,25 @@ inline unsigned grid_for(size_t n, int block) {
 
 }  // namespace
 
-hipError_t launch_cluster_finish(Cluster *clusters, int n_clusters, const int *act_pos,
-                                 const double4 *sp, const int *perm, const double4 *wa,
-                                 double4 *rp, int *rperm, double4 *rwa, hipStream_t s) {
-    if (n_clusters <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cluster_finish, dim3((unsigned)n_clusters), dim3(kWave), 0, s, clusters,
-                       act_pos, sp, perm, wa, rp, rperm, rwa);
+hipError_t launch_cluster_finish(Cluster *clusters, const int *n_clusters_dev, size_t bound,
+                                 int csize, const int *act_pos, const double4 *sp,
+                                 const int *perm, const double4 *wa, double4 *rp, int *rperm,
+                                 double4 *rwa, hipStream_t s) {
+    if (bound == 0) return hipSuccess;
+    const size_t per_block = (size_t)kFinishWaves * (kWave / csize);
+    hipLaunchKernelGGL(k_cluster_finish, dim3(grid_for(bound, (int)per_block)),
+                       dim3(kFinishWaves * kWave), 0, s, clusters, n_clusters_dev, csize, act_pos,
+                       sp, perm, wa, rp, rperm, rwa);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_multi(const FillSet &f, hipStream_t s) {
+    size_t most = 0;
+    for (int r = 0; r < f.count; ++r) most = std::max(most, f.n[r]);
+    if (most == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_multi,
+                       dim3((unsigned)std::min<size_t>(grid_for(most, 256), 4096), f.count),
+                       dim3(256), 0, s, f);
     return hipGetLastError();
 }
 
@@ -550,12 +667,17 @@ hipError_t launch_scatter(const double *pos, const double *mass, const uint8_t *
 
 hipError_t launch_fine_order(const double4 *sp, const int *perm, const uint8_t *sel,
                              const int *cell_start, const Geom &g, int *fkey, int *frank,
-                             double4 *sp2, int *perm2, uint8_t *sel2, int csize,
-                             hipStream_t s) {
-    long long grid = std::min<long long>(g.nt3, 1ll << 20);
-    hipLaunchKernelGGL(k_fine_order, dim3((unsigned)grid), dim3(kWave), 0, s, sp, perm, sel,
-                       cell_start, g, fkey, frank, sp2, perm2, sel2,
-                       csize > kFineMin ? csize : kFineMin);
+                             double4 *sp2, int *perm2, uint8_t *sel2, int csize, int n,
+                             int *big_list, hipStream_t s) {
+    // big_list[0] was zeroed on the stream; it holds at most n / kFineBig ids
+    long long grid = std::min<long long>((g.nt3 + kFineWaves - 1) / kFineWaves, 1ll << 20);
+    hipLaunchKernelGGL(k_fine_order, dim3((unsigned)grid), dim3(kFineWaves * kWave), 0, s, sp,
+                       perm, sel, cell_start, g, fkey, frank, sp2, perm2, sel2,
+                       csize > kFineMin ? csize : kFineMin, big_list);
+    const int big_grid = std::min(n / kFineBig, 256);
+    if (big_grid > 0)
+        hipLaunchKernelGGL(k_fine_order_big, dim3((unsigned)big_grid), dim3(kFineBins), 0, s, sp,
+                           perm, sel, cell_start, g, fkey, frank, sp2, perm2, sel2, big_list);
     return hipGetLastError();
 }
 
