@@ -66,7 +66,9 @@ __device__ __forceinline__ int cic_node(double x, double box, double h, int n, d
 // Counting sort of the particles by their lower CIC node (key (z n + y) n + x):
 // rank inside the node from an atomic counter, then a scatter to
 // start[key] + rank.  The sorted record holds the CIC fractions and mu, so the
-// deposit and the readout need neither the positions nor a division.
+// deposit and the readout need neither the positions nor a division.  (Nodes
+// are too fine for lanes of a wave to share one often: grouping the lanes by
+// node before the atomic, as the cell count does, made this kernel slower.)
 __global__ void k_pm_keys(const double *__restrict__ pos, int n_part, int n, double box, double h,
                           int *__restrict__ key, int *__restrict__ rank,
                           int *__restrict__ count) {

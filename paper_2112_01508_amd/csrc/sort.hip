@@ -58,16 +58,11 @@ __device__ inline int key_of(int cx, int cy, int cz, const Geom &g) {
     return tile * g.ns3 + (sx * g.ns + sy) * g.ns + sz;
 }
 
-// Cell key and rank inside the cell.  Lanes of a wave that share a cell
-// take one atomic for the group (a dense cell's particles often sit in the
-// same wave): the first lane of each group adds the group's size, and each
-// member's rank is the returned base plus its place in the group.  Device-
-// scope atomics are performed at the memory side, so their count, not
-// contention, sets this kernel's time.
+// Cell key and rank inside the cell, one atomic per distinct cell of a wave
+// (a dense cell's particles often share a wave; see wave_grouped_rank).
 __global__ void k_keys(const double *__restrict__ pos, int n, Geom g, int *__restrict__ key,
                        int *__restrict__ rank, int *__restrict__ cell_count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & (kWave - 1);
     const bool live = i < n;
     int k = -1;
     if (live) {
@@ -77,26 +72,8 @@ __global__ void k_keys(const double *__restrict__ pos, int n, Geom g, int *__res
         k = key_of(cell_of(wx, g), cell_of(wy, g), cell_of(wz, g), g);
         key[i] = k;
     }
-    // group the live lanes by key: my_lead = first lane of my group, my_off =
-    // my place in it, lead lanes also hold the group size
-    unsigned long long todo = __ballot(live);
-    int my_lead = 0, my_off = 0, size = 0;
-    while (todo) {
-        const int lead = __ffsll((long long)todo) - 1;
-        const int kl = __shfl(k, lead, kWave);
-        const unsigned long long grp = __ballot(k == kl) & todo;
-        if ((grp >> lane) & 1ull) {
-            my_lead = lead;
-            my_off = __builtin_amdgcn_mbcnt_hi((unsigned)(grp >> 32),
-                                               __builtin_amdgcn_mbcnt_lo((unsigned)grp, 0u));
-        }
-        if (lane == lead) size = __popcll(grp);
-        todo &= ~grp;
-    }
-    int base = 0;
-    if (live && lane == my_lead) base = atomicAdd(&cell_count[k], size);
-    base = __shfl(base, my_lead, kWave);
-    if (live) rank[i] = base + my_off;
+    const int rk = wave_grouped_rank(cell_count, k, live);
+    if (live) rank[i] = rk;
 }
 
 // ---- exclusive scan (reduce / top / down-sweep) -----------------------------
