@@ -520,7 +520,8 @@ int lr_run(p3m_sr_context *h, const double *pos, const double *mass, const uint8
                            (int *)h->pm_rank.p, (int *)h->pm_cnt.p, (int *)h->pm_bsum.p, rec, nkey,
                            perm, recv, s));
     if (timing) P3M_HIP(hipEventRecord(h->lr_ev[1], s));
-    P3M_HIP(launch_pm_deposit(rec, nkey, np, (double *)h->pm_real.p, n_grid, s));
+    P3M_HIP(launch_pm_deposit(rec, nkey, (const int *)h->pm_cnt.p, np, (double *)h->pm_real.p,
+                              n_grid, s));
     if (timing) P3M_HIP(hipEventRecord(h->lr_ev[2], s));
     PmArgs a{};
     a.n = n_grid;

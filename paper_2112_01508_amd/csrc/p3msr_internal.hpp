@@ -250,8 +250,10 @@ hipError_t launch_pm_sort(const double *pos, const double *mass, const uint8_t *
                           int n_part, int n, double box, double h, int *key, int *rank,
                           int *count, int *bsum, double4 *rec, int *nkey, int *perm,
                           uint8_t *recv, hipStream_t s);
-hipError_t launch_pm_deposit(const double4 *rec, const int *nkey, int n_part, double *rho, int n,
-                             hipStream_t s);
+// rho (n^3, fully written) from the node-sorted records; start: the node
+// starts of the sort (n^3 + 1 entries)
+hipError_t launch_pm_deposit(const double4 *rec, const int *nkey, const int *start, int n_part,
+                             double *rho, int n, hipStream_t s);
 // ev (optional): 4 events recorded after the x, y and z passes and the y
 // inverse pass
 hipError_t launch_pm_fft_chain(const PmArgs &a, hipStream_t s, hipEvent_t *ev);

@@ -104,34 +104,144 @@ __global__ void k_pm_scatter(const double *__restrict__ pos, const double *__res
     recv[dst] = active ? (uint8_t)(active[i] != 0) : (uint8_t)1;
 }
 
-// CIC deposit of node-sorted particles.  Lanes of a wavefront that share a
-// node hold consecutive records; a segmented suffix sum over the wave (six
-// shuffle steps) leaves each run's total with its first lane, which alone
-// issues the 8 FP64 atomics.  In dense halos this replaces up to 64
-// serialised atomics on one address by one.  (A per-node gather without
-// atomics was slower: one thread per node loops over all particles of the
-// 8 nodes below it, and halo cores hold hundreds per node.)
+// CIC deposit, split by how many particles a source node holds (a node's
+// particles are the sorted records start[k] .. start[k+1] - 1).
+//
+// Sparse source nodes (at most kDenseNode particles) are deposited brick by
+// brick: one block owns B^3 grid nodes (B = 16, or 8 on a 16^3 grid), lists
+// the particles of the sparse nodes among the (B+1)^3 source nodes that
+// reach them (offsets
+// 0 or -1 per axis), adds their weights into the brick in LDS and stores the
+// brick, so this part needs neither global atomics nor a cleared grid.  In
+// the uniform background most nodes hold 0 or 1 particle, where 8 global
+// atomics per particle dominated the deposit; a one-thread-per-node gather
+// cost as much (16 scattered start[] loads per node).
+//
+// Dense source nodes: the particles' 8 weights go through global atomics
+// after a segmented suffix sum over the wave (lanes that share a node hold
+// consecutive records; six shuffle steps leave each run's total with its
+// first lane, which alone issues the 8 FP64 atomics).  In halo cores this
+// replaces up to 64 serialised atomics on one address by one.  The bricks
+// run first; the atomics add on top of them.
+constexpr int kDenseNode = 8;
+
+// kBrick^3 nodes per block of kBrickThreads threads; kBrick <= n / 2 keeps the
+// (kBrick + 1) source nodes per axis distinct.
+template <int kBrick, int kBrickThreads>
+__global__ __launch_bounds__(kBrickThreads) void k_pm_deposit_brick(
+    const double4 *__restrict__ rec, const int *__restrict__ nkey, const int *__restrict__ start,
+    int n, int lg, double *__restrict__ rho) {
+    constexpr int kBrickSrc = (kBrick + 1) * (kBrick + 1) * (kBrick + 1);
+    constexpr int kBrickPer = (kBrickSrc + kBrickThreads - 1) / kBrickThreads;
+    __shared__ double acc[kBrick * kBrick * kBrick];
+    __shared__ int src_a[kBrickSrc];          // first record of each listed source node
+    __shared__ int pre[kBrickSrc + 1];        // exclusive prefix of their sparse counts
+    __shared__ int wsum[kBrickThreads / kWave];
+    const int t = threadIdx.x;
+    const int lane = t & (kWave - 1), wave = t / kWave;
+    const int msk = n - 1;
+    const int nb = n / kBrick;
+    const int b = blockIdx.x;
+    const int x0 = (b % nb) * kBrick, y0 = ((b / nb) % nb) * kBrick, z0 = (b / (nb * nb)) * kBrick;
+    for (int j = t; j < kBrick * kBrick * kBrick; j += kBrickThreads) acc[j] = 0.0;
+    // source node j = (sz * 9 + sy) * 9 + sx covers (x0 - 1 + sx, y0 - 1 + sy, z0 - 1 + sz)
+    int len[kBrickPer];
+    int mine = 0;
+#pragma unroll
+    for (int q = 0; q < kBrickPer; ++q) {
+        const int j = t * kBrickPer + q;
+        len[q] = 0;
+        if (j < kBrickSrc) {
+            const int sx = j % (kBrick + 1), sy = (j / (kBrick + 1)) % (kBrick + 1),
+                      sz = j / ((kBrick + 1) * (kBrick + 1));
+            const size_t g = ((size_t)((z0 - 1 + sz) & msk) * n + ((y0 - 1 + sy) & msk)) * n +
+                             ((x0 - 1 + sx) & msk);
+            const int a0 = start[g], a1 = start[g + 1];
+            src_a[j] = a0;
+            len[q] = a1 - a0 <= kDenseNode ? a1 - a0 : 0;
+        }
+        mine += len[q];
+    }
+    // block exclusive scan of the per-thread totals
+    int incl = mine;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int y = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += y;
+    }
+    if (lane == kWave - 1) wsum[wave] = incl;
+    __syncthreads();
+    int base = incl - mine, total = 0;
+    for (int w = 0; w < kBrickThreads / kWave; ++w) {
+        if (w < wave) base += wsum[w];
+        total += wsum[w];
+    }
+#pragma unroll
+    for (int q = 0; q < kBrickPer; ++q) {
+        const int j = t * kBrickPer + q;
+        if (j < kBrickSrc) pre[j] = base;
+        base += len[q];
+    }
+    if (t == 0) pre[kBrickSrc] = total;
+    __syncthreads();
+    for (int i = t; i < total; i += kBrickThreads) {
+        // the listed node holding entry i: the last j with pre[j] <= i
+        int lo = 0, hi = kBrickSrc;   // pre[lo] <= i < pre[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        const int q = src_a[lo] + (i - pre[lo]);
+        const double4 r = rec[q];
+        const int k = nkey[q];
+        const int x = k & msk, y = (k >> lg) & msk, z = k >> (2 * lg);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int cx = (c >> 2) & 1, cy = (c >> 1) & 1, cz = c & 1;
+            const int tx = (x + cx - x0) & msk, ty = (y + cy - y0) & msk, tz = (z + cz - z0) & msk;
+            if (tx < kBrick && ty < kBrick && tz < kBrick) {
+                const double wx = cx ? r.x : 1.0 - r.x;
+                const double wy = cy ? r.y : 1.0 - r.y;
+                const double wz = cz ? r.z : 1.0 - r.z;
+                atomicAdd(&acc[(tz * kBrick + ty) * kBrick + tx], r.w * wx * wy * wz);
+            }
+        }
+    }
+    __syncthreads();
+    for (int j = t; j < kBrick * kBrick * kBrick; j += kBrickThreads) {
+        const int tx = j % kBrick, ty = (j / kBrick) % kBrick, tz = j / (kBrick * kBrick);
+        rho[((size_t)(z0 + tz) * n + (y0 + ty)) * n + (x0 + tx)] = acc[j];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_pm_deposit(const double4 *__restrict__ rec,
-                                                    const int *__restrict__ nkey, int n_part,
+                                                    const int *__restrict__ nkey,
+                                                    const int *__restrict__ start, int n_part,
                                                     double *__restrict__ rho, int n) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
-    int key = -1 - lane;   // idle lanes: keys no other lane holds
+    int key = -1 - lane;   // idle and sparse lanes: keys no other lane holds
+    bool dense = false;
     double v[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] = 0.0;
     if (p < n_part) {
-        const double4 r = rec[p];
-        key = nkey[p];
+        const int k = nkey[p];
+        dense = start[k + 1] - start[k] > kDenseNode;
+        if (dense) {
+            const double4 r = rec[p];
+            key = k;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const double wx = (c & 4) ? r.x : 1.0 - r.x;
-            const double wy = (c & 2) ? r.y : 1.0 - r.y;
-            const double wz = (c & 1) ? r.z : 1.0 - r.z;
-            v[c] = r.w * wx * wy * wz;
+            for (int c = 0; c < 8; ++c) {
+                const double wx = (c & 4) ? r.x : 1.0 - r.x;
+                const double wy = (c & 2) ? r.y : 1.0 - r.y;
+                const double wz = (c & 1) ? r.z : 1.0 - r.z;
+                v[c] = r.w * wx * wy * wz;
+            }
         }
-    } else {
-#pragma unroll
-        for (int c = 0; c < 8; ++c) v[c] = 0.0;
     }
+    // no dense particle in this wave: nothing to add
+    if (!__ballot(dense)) return;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
         const int k2 = __shfl_down(key, off, kWave);
@@ -143,7 +253,7 @@ __global__ __launch_bounds__(256) void k_pm_deposit(const double4 *__restrict__ 
         }
     }
     const int prev = __shfl_up(key, 1, kWave);
-    if (p >= n_part || (lane > 0 && prev == key)) return;
+    if (!dense || (lane > 0 && prev == key)) return;
     const int m = n - 1;
     const int ix = key & m, iy = (key / n) & m, iz = key / (n * n);
 #pragma unroll
@@ -378,6 +488,9 @@ __device__ __forceinline__ double d4_at(const double *v) {
     return (v[0] - 8.0 * v[1] + 8.0 * v[3] - v[4]) / 12.0;
 }
 
+// (Staging phi per brick in LDS and reading the stencils from there was
+// slower: 241 us with 16^3 bricks and 275 us with 8^3 against 216 us for
+// this per-particle gather on clustered128's 256^3 grid.)
 __global__ void k_pm_readout(const double4 *__restrict__ rec, const int *__restrict__ nkey,
                              const int *__restrict__ perm, const uint8_t *__restrict__ recv,
                              int n_part, const double *__restrict__ phi, int n,
@@ -479,12 +592,23 @@ hipError_t launch_pm_sort(const double *pos, const double *mass, const uint8_t *
     return hipGetLastError();
 }
 
-hipError_t launch_pm_deposit(const double4 *rec, const int *nkey, int n_part, double *rho, int n,
-                             hipStream_t s) {
+hipError_t launch_pm_deposit(const double4 *rec, const int *nkey, const int *start, int n_part,
+                             double *rho, int n, hipStream_t s) {
+    int lg = 0;
+    while ((1 << lg) < n) ++lg;
+    if (n >= 32) {
+        const size_t nb = (size_t)n / 16;
+        k_pm_deposit_brick<16, 1024><<<(unsigned)(nb * nb * nb), 1024, 0, s>>>(rec, nkey, start,
+                                                                              n, lg, rho);
+    } else {
+        const size_t nb = (size_t)n / 8;
+        k_pm_deposit_brick<8, 256><<<(unsigned)(nb * nb * nb), 256, 0, s>>>(rec, nkey, start, n,
+                                                                           lg, rho);
+    }
     hipError_t e;
-    if ((e = launch_fill_f64(rho, 0.0, (size_t)n * n * n, s)) != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (n_part == 0) return hipSuccess;
-    k_pm_deposit<<<(unsigned)((n_part + 255) / 256), 256, 0, s>>>(rec, nkey, n_part, rho, n);
+    k_pm_deposit<<<(unsigned)((n_part + 255) / 256), 256, 0, s>>>(rec, nkey, start, n_part, rho, n);
     return hipGetLastError();
 }
 

@@ -225,3 +225,35 @@ def test_repeat_calls_stable(env):
     a1, s1 = run_force(env, wl.pos, wl.mass, None, 1.0, wl.x_s, wl.r_cut, "fp32")
     assert s0["interactions"] == s1["interactions"]
     assert np.max(np.abs(a0 - a1)) <= 1e-12 * np.max(np.abs(a0))
+
+
+@pytest.mark.parametrize("csize,screen", [(32, 1), (8, 1), (64, 0)])
+@pytest.mark.parametrize("masked", [False, True])
+def test_dense_subtiles(env, csize, screen, masked):
+    """Subtiles far above 1024 particles (the block-wide fine order), whole
+    waves of particles in one cell (grouped cell counts), sparse cells around
+    them, with and without an active mask (the flag scan and compaction, or
+    the receivers taken in place)."""
+    print("dense subtiles csize=%d screen=%d masked=%d" % (csize, screen, masked), flush=True)
+    rng = np.random.default_rng(77)
+    n = 9000
+    pos = rng.random((n, 3))
+    pos[:3000] = 0.31 + 0.004 * rng.random((3000, 3))          # one dense subtile
+    pos[3000:5000] = 0.72 + 0.01 * rng.standard_normal((2000, 3))
+    pos %= 1.0
+    mass = rng.uniform(0.5, 2.0, n)
+    active = (rng.random(n) < 0.6).astype(np.uint8) if masked else None
+    x_s, r_cut = 1.25 / 32, 4.5 * 1.25 / 32
+    recv = np.concatenate([np.arange(0, 3000, 7), np.arange(3000, n, 11)])
+    if masked:
+        recv = recv[active[recv] != 0]
+    ref, cnt, absum = oracle.force(pos, mass, 1.0, x_s, r_cut, recv=recv)[:3]
+    for prec in ("fp64", "fp32"):
+        acc, st = run_force(env, pos, mass, active, 1.0, x_s, r_cut, prec, subtiles_per_dim=1,
+                            cluster_size=csize, screen=screen)
+        e = oracle.errors(acc[recv], ref, absum)
+        assert e["e_l2"] <= TOL[prec] and e["e_max_cond"] <= TOL[prec], (prec, e)
+        if masked:
+            assert np.all(acc[active == 0] == 0)
+        else:
+            assert st["receivers"] == n
