@@ -100,7 +100,7 @@ typedef struct {
     int32_t n_grid;          /* PM grid points per dimension */
     int32_t pad;
     float ms_sort;           /* counting sort of the particles by CIC node, kernel tables */
-    float ms_deposit;        /* grid clear + CIC deposit */
+    float ms_deposit;        /* CIC deposit (sparse nodes per brick, dense nodes by atomics) */
     float ms_fft_x_fwd;      /* real-to-half-spectrum pass along x */
     float ms_fft_y_fwd;      /* forward pass along y */
     float ms_fft_z_conv;     /* forward z, kernel multiply, inverse z (one pass) */
@@ -274,8 +274,9 @@ int p3m_sr_get_stats(p3m_sr_handle h, p3m_sr_stats *out);
  *           uses n_grid = 2 cbrt(N) with x_s = 1.25 box / n_grid).
  * All arithmetic is FP64.  The workspace holds 12 n_grid^3 + 16 (n_grid/2+1)
  * n_grid^2 + 56 n bytes (grids, node histogram, particles sorted by node).
- * The deposit adds with FP64 atomics, so results can differ between runs
- * in the last bits.  Errors: EINVAL for n < 0, box or x_s not positive and
+ * The deposit adds with FP64 atomics (in LDS for nodes holding at most 8
+ * particles, in HBM for denser ones), so results can differ between runs in
+ * the last bits.  Errors: EINVAL for n < 0, box or x_s not positive and
  * finite, n_grid outside the supported set, NULL pos/acc_out with n > 0, or
  * pointers not 8-byte aligned; EUNSUPPORTED for n > 2^31 - 16; ENOMEM; EHIP.
  */
