@@ -1077,10 +1077,13 @@ int p3m_force(p3m_sr_handle h, const double *pos, const double *mass, const uint
     // auxiliary stream while the short range runs on the caller's
     P3M_HIP(hipEventRecord(h->fork_ev, s));
     P3M_HIP(hipStreamWaitEvent(h->aux, h->fork_ev, 0));
-    if ((rc = lr_run(h, pos, mass, active, np, box, n_grid, x_s, (double *)h->p3m_lr.p,
-                     h->aux)))
-        return rc;
+    rc = lr_run(h, pos, mass, active, np, box, n_grid, x_s, (double *)h->p3m_lr.p, h->aux);
     P3M_HIP(hipEventRecord(h->join_ev, h->aux));
+    if (rc) {
+        // whatever the long range queued still finishes before later work on `stream`
+        P3M_HIP(hipStreamWaitEvent(s, h->join_ev, 0));
+        return rc;
+    }
     Request r{};
     r.pos = pos;
     r.mass = mass;
