@@ -165,15 +165,15 @@ def test_clustered128_sampled(env, prec, csize, screen):
     assert 1.0e9 < st["interactions"] < 2.5e9
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_clustered128_65536_receivers(env, prec):
-    """Full-size N=128^3 clustered set in the bench's layout (ns 1, items of
-    4096, 32-receiver clusters, screened): 65536 seeded receivers against
-    the cell-list oracle over all N, with their exact pair counts."""
-    print("clustered128 N=128^3, 65536 receivers", prec, flush=True)
+@pytest.mark.parametrize("prec,csize", [("fp32", 32), ("fp64", 32), ("fp64", 16)])
+def test_clustered128_65536_receivers(env, prec, csize):
+    """Full-size N=128^3 clustered set in the bench's layouts (ns 1, items of
+    4096, screened, 32-receiver clusters for FP32 and 16 for FP64): 65536
+    seeded receivers against the cell-list oracle over all N."""
+    print("clustered128 N=128^3, 65536 receivers", prec, csize, flush=True)
     wl = make_workload("clustered128", with_rungs=False)
     acc, st = run_force(env, wl.pos, None, None, 1.0, wl.x_s, wl.r_cut, prec,
-                        subtiles_per_dim=1, item_target=4096, cluster_size=32, screen=1)
+                        subtiles_per_dim=1, item_target=4096, cluster_size=csize, screen=1)
     idx = sample_indices(wl.n, 65536, wl.config_id, salt=1)
     ref, cnt, absum, _ = oracle.force(wl.pos, None, 1.0, wl.x_s, wl.r_cut, recv=idx,
                                       method="tiled")
