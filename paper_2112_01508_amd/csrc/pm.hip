@@ -288,56 +288,94 @@ __global__ void k_pm_tables(int n, double box, double x_s, double2 *tw, double *
     }
 }
 
-// Radix-2 Stockham FFT of `lines` lines of length N held in LDS.  Element
-// (l, i) sits at i * IS + l * LS.  Each stage reads x[j] and x[j + N/2],
-// multiplies the second by exp(-+2 pi i k / (2 Ns)) (k = j mod Ns) and writes
-// the sum and difference to 2j - k and 2j - k + Ns, so the result comes out in
-// natural order without a bit reversal.  lane_j: consecutive threads take
-// consecutive j (line-major tiles) or consecutive lines (interleaved tiles).
 // Copies the n/2 twiddles into LDS (the caller synchronises before use).
 template <int N>
 __device__ __forceinline__ void stage_twiddles(double2 *tws, const double2 *__restrict__ tw) {
     for (int k = threadIdx.x; k < N / 2; k += kFftThreads) tws[k] = tw[k];
 }
 
-template <int N, int LINES, int IS, int LS, bool LANE_J, bool INV>
-__device__ __forceinline__ void lds_fft(double2 *buf, const double2 *tw) {
-    constexpr int NB = LINES * (N / 2);
+// Twiddle exp(-2 pi i m / N) for 0 <= m < N from the half table tw[m < N/2].
+template <int N>
+__device__ __forceinline__ double2 twiddle(const double2 *tw, int m) {
+    if (m < N / 2) return tw[m];
+    const double2 w = tw[m - N / 2];
+    return make_double2(-w.x, -w.y);
+}
+
+// One radix-R Stockham stage (R = 2 or 4) at span Ns: butterfly j reads
+// x_q = x[j + q N/R], multiplies x_q by w^(q k) with w = exp(-+2 pi i /
+// (R Ns)) and k = j mod Ns, takes the R-point DFT and writes output q to
+// (j - k) R + k + q Ns.
+template <int N, int LINES, int IS, int LS, bool LANE_J, bool INV, int R>
+__device__ __forceinline__ void fft_stage(double2 *buf, const double2 *tw, int Ns) {
+    constexpr int NB = LINES * (N / R);
     constexpr int PER = (NB + kFftThreads - 1) / kFftThreads;
     const int t = threadIdx.x;
-#pragma unroll 1
-    for (int Ns = 1; Ns < N; Ns *= 2) {
-        double2 a[PER], b[PER];
-        int dst[PER];
-        const int tw_step = N / (2 * Ns);
+    const int step = N / (R * Ns);   // twiddle table stride per unit of q k
+    double2 y[PER][R];
+    int dst[PER];
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int bi = t + u * kFftThreads;
-            if (NB % kFftThreads == 0 || bi < NB) {
-                const int j = LANE_J ? bi % (N / 2) : bi / LINES;
-                const int l = LANE_J ? bi / (N / 2) : bi % LINES;
-                const int k = j & (Ns - 1);
-                const double2 x0 = buf[j * IS + l * LS];
-                double2 x1 = buf[(j + N / 2) * IS + l * LS];
-                double2 w = tw[k * tw_step];
-                if (INV) w.y = -w.y;
-                x1 = cmul(x1, w);
-                a[u] = make_double2(x0.x + x1.x, x0.y + x1.y);
-                b[u] = make_double2(x0.x - x1.x, x0.y - x1.y);
-                dst[u] = (2 * j - k) * IS + l * LS;
-            }
-        }
-        __syncthreads();
+    for (int u = 0; u < PER; ++u) {
+        const int bi = t + u * kFftThreads;
+        if (NB % kFftThreads == 0 || bi < NB) {
+            const int j = LANE_J ? bi % (N / R) : bi / LINES;
+            const int l = LANE_J ? bi / (N / R) : bi % LINES;
+            const int k = j & (Ns - 1);
+            double2 x[R];
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int bi = t + u * kFftThreads;
-            if (NB % kFftThreads == 0 || bi < NB) {
-                buf[dst[u]] = a[u];
-                buf[dst[u] + Ns * IS] = b[u];
+            for (int q = 0; q < R; ++q) {
+                x[q] = buf[(j + q * (N / R)) * IS + l * LS];
+                if (q > 0) {
+                    double2 w = twiddle<N>(tw, q * k * step);
+                    if (INV) w.y = -w.y;
+                    x[q] = cmul(x[q], w);
+                }
             }
+            if constexpr (R == 2) {
+                y[u][0] = make_double2(x[0].x + x[1].x, x[0].y + x[1].y);
+                y[u][1] = make_double2(x[0].x - x[1].x, x[0].y - x[1].y);
+            } else {
+                const double2 a0 = make_double2(x[0].x + x[2].x, x[0].y + x[2].y);
+                const double2 a1 = make_double2(x[0].x - x[2].x, x[0].y - x[2].y);
+                const double2 a2 = make_double2(x[1].x + x[3].x, x[1].y + x[3].y);
+                const double2 d = make_double2(x[1].x - x[3].x, x[1].y - x[3].y);
+                // a3 = d * (-i) forward, d * (+i) inverse
+                const double2 a3 = INV ? make_double2(-d.y, d.x) : make_double2(d.y, -d.x);
+                y[u][0] = make_double2(a0.x + a2.x, a0.y + a2.y);
+                y[u][1] = make_double2(a1.x + a3.x, a1.y + a3.y);
+                y[u][2] = make_double2(a0.x - a2.x, a0.y - a2.y);
+                y[u][3] = make_double2(a1.x - a3.x, a1.y - a3.y);
+            }
+            dst[u] = ((j - k) * R + k) * IS + l * LS;
         }
-        __syncthreads();
     }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int bi = t + u * kFftThreads;
+        if (NB % kFftThreads == 0 || bi < NB) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[dst[u] + q * Ns * IS] = y[u][q];
+        }
+    }
+    __syncthreads();
+}
+
+// FFT of `lines` lines of length N held in LDS.  Element (l, i) sits at
+// i * IS + l * LS.  Mixed-radix Stockham: radix-4 stages, after one radix-2
+// stage when log2 N is odd; the result comes out in natural order without a
+// bit reversal.  lane_j: consecutive threads take consecutive j (line-major
+// tiles) or consecutive lines (interleaved tiles).
+template <int N, int LINES, int IS, int LS, bool LANE_J, bool INV>
+__device__ __forceinline__ void lds_fft(double2 *buf, const double2 *tw) {
+    constexpr int LOG = __builtin_ctz(N);
+    int Ns = 1;
+    if constexpr (LOG % 2 == 1) {
+        fft_stage<N, LINES, IS, LS, LANE_J, INV, 2>(buf, tw, 1);
+        Ns = 2;
+    }
+#pragma unroll 1
+    for (; Ns < N; Ns *= 4) fft_stage<N, LINES, IS, LS, LANE_J, INV, 4>(buf, tw, Ns);
 }
 
 // Half-spectrum rows hold NH = N/2 + 1 values, stored with a stride rounded
