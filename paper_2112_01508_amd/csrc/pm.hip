@@ -83,6 +83,8 @@ __global__ void k_pm_keys(const double *__restrict__ pos, int n_part, int n, dou
     rank[i] = atomicAdd(&count[k], 1);
 }
 
+// (Writing only the sorted index here and building the records in sorted
+// order with gathered reads took as long: 0.026 + 0.083 ms against 0.114.)
 __global__ void k_pm_scatter(const double *__restrict__ pos, const double *__restrict__ mass,
                              const uint8_t *__restrict__ active, int n_part, int n, double box,
                              double h, const int *__restrict__ key, const int *__restrict__ rank,
@@ -413,16 +415,15 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x_fwd(const double *__restr
     __syncthreads();
     lds_fft<N, P, 1, N, true, false>(buf, tws);
     double2 *dst = spec + line0 * Row<N>::kStride;
-    for (int e = threadIdx.x; e < 2 * P * NH; e += kFftThreads) {
-        const int r = e / NH, k = e % NH;
-        const int p = r >> 1;
+    // both half spectra of a line pair from one read of Z_k and Z_{N-k}
+    for (int e = threadIdx.x; e < P * NH; e += kFftThreads) {
+        const int p = e / NH, k = e % NH;
         const double2 z = buf[p * N + k];
-        const double2 zc = buf[p * N + ((N - k) & (N - 1))];
-        // zc enters conjugated
-        double2 v;
-        if ((r & 1) == 0) v = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
-        else v = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
-        dst[(size_t)r * Row<N>::kStride + k] = v;
+        const double2 zc = buf[p * N + ((N - k) & (N - 1))];   // enters conjugated
+        dst[(size_t)(2 * p) * Row<N>::kStride + k] =
+            make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+        dst[(size_t)(2 * p + 1) * Row<N>::kStride + k] =
+            make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
     }
 }
 
