@@ -186,7 +186,9 @@ int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
  * faster).  Times p3m_sr_force on these inputs for candidate subtile counts
  * per dimension crossed with cluster layouts (cluster size, screening) and,
  * at level >= 2, work-item sizes around the winner; stores the fastest in the
- * handle; later calls on the same particle count and geometry use it.
+ * handle (a candidate replaces an earlier one only when more than 3 % faster,
+ * so near-ties do not flip with timing noise); later calls on the same
+ * particle count and geometry use it.
  * acc_scratch is an n x 3 FP64 device buffer the trials write into.
  * level: 1 = subtiles only, 2 = subtiles and item size.  Synchronises.
  */
