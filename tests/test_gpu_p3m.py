@@ -144,3 +144,26 @@ def test_p3m_force_stats_cover_both_halves(env):
         ctx.set_timing(False)
     assert sr["n"] == 20000 and sr["interactions"] > 0 and sr["ms_pairs"] >= 0
     assert lr["n"] == 20000 and lr["n_grid"] == 64 and lr["ms_total"] >= 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_p3m_force_softened(env, precision):
+    """B-spline softening (eps_B = 2.8 eps) applies to the short-range half
+    of the whole force; the long-range half is unsoftened."""
+    torch, p3, ctx = env
+    n, n_grid = 6000, 32
+    pos, mass, active = random_particles(n, seed=4242, active_frac=0.7)
+    pos[:1500] = (0.6 + 0.01 * np.random.default_rng(1).standard_normal((1500, 3))) % 1.0
+    x_s, r_cut = scales(n_grid)
+    eps = 0.03 / 18.0
+    sr = oracle.force_full(pos, mass, 1.0, x_s, r_cut, active=active, eps=eps)[0]
+    lr = pm.pm_force(pos, mass, 1.0, n_grid, x_s, active=active)
+    ctx.set_softening(eps)
+    try:
+        got = total(env, pos, mass, active, n_grid, precision)
+    finally:
+        ctx.set_softening(0.0)
+    ref = sr + lr
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print("softened p3m", precision, "max err / max |a| = %.3e" % err, flush=True)
+    assert err <= (TOL_FP64 if precision == "fp64" else 1e-5)
