@@ -58,8 +58,20 @@ def _load():
     lib.p3o_fd_grad.argtypes = [_I64, _P, _P, _P, _P, _D, _D, _D, _D, _D, ctypes.c_int, _I64,
                                 _P, _P, _P]
     lib.p3o_fd_grad.restype = None
+    lib.p3o_sq_dist.argtypes = [_I64, _P, _P]
+    lib.p3o_sq_dist.restype = None
     _lib = lib
     return lib
+
+
+def sq_dist(d):
+    """r^2 = fma(dz, dz, fma(dy, dy, dx * dx)) for the rows of d (m x 3): the
+    rounding every cut-off decision uses (numpy has no fused multiply-add)."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    out = np.empty(d.shape[0])
+    if d.shape[0]:
+        _load().p3o_sq_dist(d.shape[0], _ptr(d), _ptr(out))
+    return out
 
 
 # B-spline softening length from the Plummer-equivalent softening length

@@ -24,7 +24,8 @@
  * where mu_j = G m_j and r_ij = x_i - x_j is taken to the nearest periodic
  * image (the single image n' of eq. p3m_gravity; minimum image per
  * component).  The sum is strict, |r| < r_cut, and a candidate is rejected
- * when r^2 >= r_cut^2 (section 2.1.3, "Other optimisations").  The bracket of
+ * when r^2 >= r_cut^2 (section 2.1.3, "Other optimisations"), with r^2 =
+ * fma(dz, dz, fma(dy, dy, dx * dx)).  The bracket of
  * eq. p3m_gravity, r^-3 erfc(u) + r^-2 exp(-u^2) / (sqrt(pi) x_s), equals
  * g(u) / r^3 because r / (sqrt(pi) x_s) = 2u / sqrt(pi).
  *
@@ -112,6 +113,20 @@ static double pair_phi(double r, double r2, double x_s, double eps_b) {
 }
 
 /* Nearest periodic image of a coordinate difference. */
+/* r^2 = fma(dz, dz, fma(dy, dy, dx * dx)): the squared distance of the
+ * cut-off test, r^2 < r_cut^2 (section 2.1.3, "Other optimisations"), with
+ * its rounding fixed (the paper leaves it open) so that every implementation
+ * takes the same accept / reject decision near r_cut. */
+static inline double sq_dist(double dx, double dy, double dz) {
+    return fma(dz, dz, fma(dy, dy, dx * dx));
+}
+
+/* The same squared distance for n rows (dx, dy, dz) of d, for the numpy
+ * oracles that take a cut-off decision. */
+void p3o_sq_dist(int64_t n, const double *d, double *out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = sq_dist(d[3 * i], d[3 * i + 1], d[3 * i + 2]);
+}
+
 static inline double min_image(double d, double box) {
     return d - box * rint(d / box);
 }
@@ -145,7 +160,7 @@ void p3o_force(int64_t n, const double *pos, const double *mass, double box, dou
             double dx = min_image(xi - pos[3 * j], box);
             double dy = min_image(yi - pos[3 * j + 1], box);
             double dz = min_image(zi - pos[3 * j + 2], box);
-            double r2 = dx * dx + dy * dy + dz * dz;
+            double r2 = sq_dist(dx, dy, dz);
             if (r2 >= rc2 || r2 == 0.0) continue;
             double r = sqrt(r2);
             double mu = mass ? mass[j] : 1.0;
@@ -240,7 +255,7 @@ int p3o_force_tiled(int64_t n, const double *pos, const double *mass, double box
                 double dx = min_image(xi - pos[3 * j], box);
                 double dy = min_image(yi - pos[3 * j + 1], box);
                 double dz = min_image(zi - pos[3 * j + 2], box);
-                double r2 = dx * dx + dy * dy + dz * dz;
+                double r2 = sq_dist(dx, dy, dz);
                 if (r2 >= rc2 || r2 == 0.0) continue;
                 double r = sqrt(r2);
                 double mu = mass ? mass[j] : 1.0;
@@ -294,7 +309,7 @@ int p3o_cell_census(int64_t n, const double *pos, double box, double r_cut,
                     double dx = min_image(xi - pos[3 * j], box);
                     double dy = min_image(yi - pos[3 * j + 1], box);
                     double dz = min_image(zi - pos[3 * j + 2], box);
-                    double r2 = dx * dx + dy * dy + dz * dz;
+                    double r2 = sq_dist(dx, dy, dz);
                     lc[kind]++;
                     if (r2 < rc2 && r2 > 0.0) la[kind]++;
                 }
@@ -361,7 +376,7 @@ void p3o_vjp(int64_t n, const double *pos, const double *mass, const uint8_t *ac
             double dx = min_image(pos[3 * k] - pos[3 * j], box);
             double dy = min_image(pos[3 * k + 1] - pos[3 * j + 1], box);
             double dz = min_image(pos[3 * k + 2] - pos[3 * j + 2], box);
-            double r2 = dx * dx + dy * dy + dz * dz;
+            double r2 = sq_dist(dx, dy, dz);
             if (r2 >= rc2 || r2 == 0.0) continue;
             double muj = mass ? mass[j] : 1.0;
             double vx = 0, vy = 0, vz = 0;
@@ -407,7 +422,7 @@ int p3o_vjp_tiled(int64_t n, const double *pos, const double *mass, const uint8_
                 double dx = min_image(xk - pos[3 * j], box);
                 double dy = min_image(yk - pos[3 * j + 1], box);
                 double dz = min_image(zk - pos[3 * j + 2], box);
-                double r2 = dx * dx + dy * dy + dz * dz;
+                double r2 = sq_dist(dx, dy, dz);
                 if (r2 >= rc2 || r2 == 0.0) continue;
                 double muj = mass ? mass[j] : 1.0;
                 double vx = 0, vy = 0, vz = 0;
@@ -458,7 +473,7 @@ static double local_loss(int64_t n, const double *pos, const double *mass, const
         double dx = min_image(y[0] - pos[3 * j], box);
         double dy = min_image(y[1] - pos[3 * j + 1], box);
         double dz = min_image(y[2] - pos[3 * j + 2], box);
-        double r2 = dx * dx + dy * dy + dz * dz;
+        double r2 = sq_dist(dx, dy, dz);
         int in1 = (r2 < rc2 && r2 > 0.0);
         if (in0 != in1 && flip) *flip = 1;
         int use = mode == 0 ? in0 : in1;

@@ -25,6 +25,8 @@ import math
 
 import numpy as np
 
+from . import sq_dist
+
 NGP, LINEAR = 1, 2
 
 
@@ -66,7 +68,7 @@ def force(pos, mass, box, x_s, r_cut, recv, kind, n):
     for a, i in enumerate(recv):
         d = pos[i] - pos
         d -= box * np.rint(d / box)
-        r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        r2 = sq_dist(d)                       # the cut-off test's rounding
         sel = (r2 < rc2) & (r2 > 0.0)
         r2s, ds, mus = r2[sel], d[sel], mu[sel]
         x = r2s.astype(np.float32) * scale               # FP32, as the bin index

@@ -83,14 +83,12 @@ __device__ inline float mu_f32(double w) {
     return __uint_as_float((unsigned int)(unsigned long long)__double_as_longlong(w));
 }
 
-// Squared distance in the order of a plain evaluation: ((dx*dx + dy*dy) + dz*dz),
-// every product and sum rounded (no fused multiply-add).
+// Squared distance of the cut-off test, rounded as fma(dz, dz, fma(dy, dy,
+// dx * dx)): three instructions instead of five, and the rounding every
+// implementation of the test uses, so accept / reject decisions near r_cut
+// are the same everywhere.
 __device__ inline double dist2(double dx, double dy, double dz) {
-#pragma clang fp contract(off)
-    double xx = dx * dx;
-    double yy = dy * dy;
-    double zz = dz * dz;
-    return (xx + yy) + zz;
+    return fma(dz, dz, fma(dy, dy, dx * dx));
 }
 
 // ---- B-spline softening (section 2.1.1, eq. bspline_force) --------------------

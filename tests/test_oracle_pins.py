@@ -194,9 +194,11 @@ def test_translation_permutation_axis_reflection():
     assert np.array_equal(c_p, cnt[perm])
     assert oracle.errors(a_p, a[perm], absum[perm])["e_max_cond"] <= 1e-15
 
+    # r^2 = fma(dz, dz, fma(dy, dy, dx dx)) rounds differently once the axes
+    # are permuted: agreement to rounding, not to the bit
     axes = [2, 0, 1]
     a_ax, _, _, _ = oracle.force(pos[:, axes], mass, 1.0, x_s, r_cut)
-    assert oracle.errors(a_ax, a[:, axes], absum)["e_max_cond"] <= 1e-15
+    assert oracle.errors(a_ax, a[:, axes], absum)["e_max_cond"] <= 1e-14
 
     refl = pos.copy()
     refl[:, 1] = -refl[:, 1]
