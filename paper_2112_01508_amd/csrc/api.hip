@@ -78,7 +78,9 @@ struct TuneVal {
 struct p3m_sr_context {
     int device = 0;
     int n_cu = 0;
-    int blocks_per_cu[4][2][2] = {};   // [mode][screen][tabulated shape]
+    // resident pair-kernel blocks per CU, per variant: mode, screen, cluster size,
+    // shape, unit mass, softening
+    int blocks_per_cu[4 * 2 * 4 * 3 * 4] = {};
     DevBuf key, rank, cells, sp, perm, sel, sp2, perm2, sel2, flags, actpos, ncl, clusters,
         itemcnt, items, bsum, counters, wa, scal, rp, rperm, rwa, fbig;
     int cfg_ns = 0, cfg_target = 0, cfg_csize = 0, cfg_screen = -1;
@@ -450,8 +452,11 @@ int run(p3m_sr_context *h, const Request &r) {
         a.tab_scale = (float)((double)h->cfg_tab_n / g.rc2);
     }
     st.shape = shape;
-    int &bpc = h->blocks_per_cu[mode][screen][shape != SHAPE_POLY ? 1 : 0];
-    if (bpc == 0) bpc = pairs_blocks_per_cu(mode, screen, shape);
+    const int unit = r.mass ? 0 : 1, soft = g.eps_b > 0.0 ? 1 : 0;
+    const int cs_idx = csize == 8 ? 0 : csize == 16 ? 1 : csize == 32 ? 2 : 3;
+    const int slot = (((mode * 2 + (screen ? 1 : 0)) * 4 + cs_idx) * 3 + shape) * 4 + unit * 2 + soft;
+    int &bpc = h->blocks_per_cu[slot];
+    if (bpc == 0) bpc = pairs_blocks_per_cu(mode, screen, shape, csize, unit, soft);
     long long waves_wanted = (n_items + 0ll);
     long long grid = std::min<long long>((waves_wanted + 3) / 4, (long long)h->n_cu * bpc);
     if (grid < 1) grid = 1;

@@ -770,13 +770,29 @@ template <> struct ModeWeight<BWD_F32> { using T = float4; };
 // screened against the cluster's box into LDS before the pair loop, with SG =
 // 64 / csize copies of each cluster per wave; SG = 0: suppliers stream
 // directly, with 64 / count copies.  SOFT: B-spline softening inside eps_b.
+// Six waves per SIMD for the FP32 forward kernel with unit masses, no
+// softening and the polynomial shape: it is limited by issue latency more
+// than by VALU throughput and runs 4 % faster at six waves (80 VGPRs, five
+// registers spilled outside the pair loop, 26 KB of list LDS per block) than
+// at five.  The other variants spill more there (or are held to fewer waves
+// by the table in LDS); they keep the compiler's choice, and the FP64 ones
+// measured slower at six.
+template <int MODE, bool UNIT, bool SOFT, int TAB>
+struct PairsSix {
+    static constexpr bool v = MODE == FWD_F32 && UNIT && !SOFT && TAB == SHAPE_POLY;
+};
+
 template <int MODE, bool UNIT, int SG, bool SOFT, int TAB = SHAPE_POLY>
-__global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
+__global__ __launch_bounds__(kForceBlock)
+__attribute__((amdgpu_waves_per_eu(PairsSix<MODE, UNIT, SOFT, TAB>::v ? 6 : 1)))
+void k_pairs(PairArgs a) {
     constexpr bool SCREEN = SG > 0;
     constexpr bool BWD = MODE == BWD_F32 || MODE == BWD_F64;
     // the adjoint's list entries also carry the supplier's weight: a
-    // shorter list keeps the LDS per block at or below 40 KB
-    constexpr int CAP = BWD ? kListCapAdjoint : kListCap;
+    // shorter list keeps the LDS per block at or below 40 KB; the six-wave
+    // variant's list fits six blocks per CU
+    constexpr int CAP = BWD ? kListCapAdjoint
+                            : (PairsSix<MODE, UNIT, SOFT, TAB>::v ? kListCapF32 : kListCap);
     constexpr int NW = kForceBlock / kWave;
     using WTk = typename ModeWeight<MODE>::T;
     __shared__ double4 lists[SCREEN ? NW : 1][SCREEN ? CAP + kListSlack : 1];
@@ -866,37 +882,23 @@ __global__ __launch_bounds__(kForceBlock) void k_pairs(PairArgs a) {
     }
 }
 
-template <int MODE, int SG, int TAB = SHAPE_POLY>
-int blocks_per_cu_of() {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs<MODE, false, SG, false, TAB>,
-                                                     kForceBlock, 0) != hipSuccess)
-        return 1;
-    return nb > 0 ? nb : 1;
-}
+// The pair-kernel variant for a layout: all share the signature void(PairArgs).
+using PairsFn = void (*)(PairArgs);
 
 template <int MODE, bool UNIT, bool SOFT, int TAB = SHAPE_POLY>
-void launch_fwd_soft(int sg, const PairArgs &a, dim3 gr, dim3 bl, hipStream_t s) {
+PairsFn pairs_fn_sg(int sg) {
     switch (sg) {
-    case 1: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 1, SOFT, TAB>), gr, bl, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 2, SOFT, TAB>), gr, bl, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 4, SOFT, TAB>), gr, bl, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 8, SOFT, TAB>), gr, bl, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_pairs<MODE, UNIT, 0, SOFT, TAB>), gr, bl, 0, s, a); break;
+    case 1: return k_pairs<MODE, UNIT, 1, SOFT, TAB>;
+    case 2: return k_pairs<MODE, UNIT, 2, SOFT, TAB>;
+    case 4: return k_pairs<MODE, UNIT, 4, SOFT, TAB>;
+    case 8: return k_pairs<MODE, UNIT, 8, SOFT, TAB>;
+    default: return k_pairs<MODE, UNIT, 0, SOFT, TAB>;
     }
 }
 
 template <int MODE, bool UNIT>
-void launch_fwd(int sg, const PairArgs &a, dim3 gr, dim3 bl, hipStream_t s) {
-    if (a.g.eps_b > 0.0) launch_fwd_soft<MODE, UNIT, true>(sg, a, gr, bl, s);
-    else launch_fwd_soft<MODE, UNIT, false>(sg, a, gr, bl, s);
-}
-
-// FP32 forward without softening, tabulated shape
-template <bool UNIT>
-void launch_fwd_tab(int tab, int sg, const PairArgs &a, dim3 gr, dim3 bl, hipStream_t s) {
-    if (tab == SHAPE_TAB_NGP) launch_fwd_soft<FWD_F32, UNIT, false, SHAPE_TAB_NGP>(sg, a, gr, bl, s);
-    else launch_fwd_soft<FWD_F32, UNIT, false, SHAPE_TAB_LINEAR>(sg, a, gr, bl, s);
+PairsFn pairs_fn_soft(int sg, bool soft) {
+    return soft ? pairs_fn_sg<MODE, UNIT, true>(sg) : pairs_fn_sg<MODE, UNIT, false>(sg);
 }
 
 // screen groups: 64 / csize when screening (csize in {8, 16, 32, 64}), else 0
@@ -924,51 +926,62 @@ hipError_t launch_build_htab(int kind, int n, const Geom &g, float *tab, hipStre
     return hipGetLastError();
 }
 
+// The kernel that launch_pairs runs for this call (nullptr: invalid layout).
+// The FP32 forward with the tabulated shape exists without softening only.
+static PairsFn pairs_kernel(int mode, int screen, int tab, int csize, bool unit, bool soft) {
+    if (csize != 8 && csize != 16 && csize != 32 && csize != 64) return nullptr;
+    const int sg = screen_groups(screen, csize);
+    switch (mode) {
+    case FWD_F32:
+        if (tab != SHAPE_POLY && !soft) {
+            if (tab == SHAPE_TAB_NGP)
+                return unit ? pairs_fn_sg<FWD_F32, true, false, SHAPE_TAB_NGP>(sg)
+                            : pairs_fn_sg<FWD_F32, false, false, SHAPE_TAB_NGP>(sg);
+            return unit ? pairs_fn_sg<FWD_F32, true, false, SHAPE_TAB_LINEAR>(sg)
+                        : pairs_fn_sg<FWD_F32, false, false, SHAPE_TAB_LINEAR>(sg);
+        }
+        return unit ? pairs_fn_soft<FWD_F32, true>(sg, soft) : pairs_fn_soft<FWD_F32, false>(sg, soft);
+    case FWD_F64:
+        return unit ? pairs_fn_soft<FWD_F64, true>(sg, soft) : pairs_fn_soft<FWD_F64, false>(sg, soft);
+    case BWD_F32: return pairs_fn_soft<BWD_F32, false>(sg, soft);
+    default: return pairs_fn_soft<BWD_F64, false>(sg, soft);
+    }
+}
+
 hipError_t launch_pairs(int mode, int screen, int tab, const PairArgs &a, int grid,
                         hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;
-    if (a.csize != 8 && a.csize != 16 && a.csize != 32 && a.csize != 64) return hipErrorInvalidValue;
-    dim3 gr((unsigned)grid), bl(kForceBlock);
-    const int sg = screen_groups(screen, a.csize);
-    const bool tabulated = mode == FWD_F32 && tab != SHAPE_POLY && a.g.eps_b == 0.0;
-    if (tabulated) {
+    const bool soft = a.g.eps_b > 0.0;
+    if (mode == FWD_F32 && tab != SHAPE_POLY && !soft) {
         const int nf = tab == SHAPE_TAB_LINEAR ? 2 * a.tab_n : a.tab_n;
         if (!a.htab || a.tab_n < 1 || nf > kTabFloats) return hipErrorInvalidValue;
     }
-    switch (mode) {
-    case FWD_F32:
-        if (tabulated) {
-            if (a.unit_mass) launch_fwd_tab<true>(tab, sg, a, gr, bl, s);
-            else launch_fwd_tab<false>(tab, sg, a, gr, bl, s);
-        } else if (a.unit_mass) {
-            launch_fwd<FWD_F32, true>(sg, a, gr, bl, s);
-        } else {
-            launch_fwd<FWD_F32, false>(sg, a, gr, bl, s);
-        }
-        break;
-    case FWD_F64:
-        if (a.unit_mass) launch_fwd<FWD_F64, true>(sg, a, gr, bl, s);
-        else launch_fwd<FWD_F64, false>(sg, a, gr, bl, s);
-        break;
-    case BWD_F32: launch_fwd<BWD_F32, false>(sg, a, gr, bl, s); break;
-    default: launch_fwd<BWD_F64, false>(sg, a, gr, bl, s); break;
-    }
+    const bool unit = a.unit_mass && (mode == FWD_F32 || mode == FWD_F64);
+    const PairsFn fn = pairs_kernel(mode, screen, tab, a.csize, unit, soft);
+    if (!fn) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kForceBlock), 0, s, a);
     return hipGetLastError();
 }
 
-int pairs_blocks_per_cu(int mode, int screen, int tab) {
-    // every screened variant of a mode has the same LDS footprint; use G = 8's count
-    const bool sc = screen != 0;
-    switch (mode) {
-    case FWD_F32:
-        if (tab != SHAPE_POLY)   // the two table kinds take the same LDS
-            return sc ? blocks_per_cu_of<FWD_F32, 8, SHAPE_TAB_NGP>()
-                      : blocks_per_cu_of<FWD_F32, 0, SHAPE_TAB_NGP>();
-        return sc ? blocks_per_cu_of<FWD_F32, 8>() : blocks_per_cu_of<FWD_F32, 0>();
-    case FWD_F64: return sc ? blocks_per_cu_of<FWD_F64, 8>() : blocks_per_cu_of<FWD_F64, 0>();
-    case BWD_F32: return sc ? blocks_per_cu_of<BWD_F32, 8>() : blocks_per_cu_of<BWD_F32, 0>();
-    default: return sc ? blocks_per_cu_of<BWD_F64, 8>() : blocks_per_cu_of<BWD_F64, 0>();
+// Blocks of the persistent grid per CU.  The six-wave FP32 variant is sized by
+// its own limit (6).  Every other variant is sized by what the mode's largest
+// screened variant (per-particle masses, 8-receiver clusters: the most
+// registers) leaves room for, as if it were launched: for FP64 that is 4 blocks,
+// against the 5 the unit-mass variant would fit, and 4 measured 2 % faster.
+int pairs_blocks_per_cu(int mode, int screen, int tab, int csize, int unit_mass, int soft) {
+    bool unit = unit_mass && (mode == FWD_F32 || mode == FWD_F64);
+    const bool six = mode == FWD_F32 && unit && !soft && tab == SHAPE_POLY;
+    if (!six) {
+        unit = false;
+        screen = screen ? 1 : 0;
+        if (screen) csize = 8;
+        soft = 0;
     }
+    const PairsFn fn = pairs_kernel(mode, screen, tab, csize, unit, soft != 0);
+    int nb = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kForceBlock, 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
 }
 
 }  // namespace p3m

@@ -34,6 +34,7 @@ constexpr int kFineBig = 1024;              // larger subtiles are ordered by a 
 constexpr int kFineWaves = 4;               // tiles (one per wave) per fine-order block
 constexpr int kFinishWaves = 4;             // clusters (one per wave) per finishing block
 constexpr int kListCap = 224;               // screened supplier records per wave (LDS)
+constexpr int kListCapF32 = 176;            // the same for the six-wave FP32 forward kernel
 constexpr int kListCapAdjoint = 128;        // the same for the adjoint (entries carry weights)
 constexpr int kListSlack = 32;              // records past the cap for look-ahead reads (3*8 used)
 
@@ -260,7 +261,8 @@ hipError_t launch_pm_fft_chain(const PmArgs &a, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_pm_readout(const double4 *rec, const int *nkey, const int *perm,
                              const uint8_t *recv, int n_part, const double *phi, int n,
                              double *acc, hipStream_t s);
-int pairs_blocks_per_cu(int mode, int screen, int tab);
+// pair-kernel workgroups resident per CU for the variant launch_pairs would run
+int pairs_blocks_per_cu(int mode, int screen, int tab, int csize, int unit_mass, int soft);
 
 // KDK step (kdk.hip).  Times in units of tau / 2, tau = dt / 2^L.
 struct KdkArgs {
