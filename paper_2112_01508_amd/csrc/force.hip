@@ -776,7 +776,8 @@ template <> struct ModeWeight<BWD_F32> { using T = float4; };
 // registers spilled outside the pair loop, 26 KB of list LDS per block) than
 // at five.  The other variants spill more there (or are held to fewer waves
 // by the table in LDS); they keep the compiler's choice, and the FP64 ones
-// measured slower at six.
+// measured slower at six.  Seven waves (72 VGPRs, 20 registers spilled) were
+// slower again: 2.79 against 2.68 ms.
 template <int MODE, bool UNIT, bool SOFT, int TAB>
 struct PairsSix {
     static constexpr bool v = MODE == FWD_F32 && UNIT && !SOFT && TAB == SHAPE_POLY;
