@@ -772,12 +772,14 @@ template <> struct ModeWeight<BWD_F32> { using T = float4; };
 // directly, with 64 / count copies.  SOFT: B-spline softening inside eps_b.
 // Six waves per SIMD for the FP32 forward kernel with unit masses, no
 // softening and the polynomial shape: it is limited by issue latency more
-// than by VALU throughput and runs 4 % faster at six waves (80 VGPRs, five
-// registers spilled outside the pair loop, 26 KB of list LDS per block) than
-// at five.  The other variants spill more there (or are held to fewer waves
-// by the table in LDS); they keep the compiler's choice, and the FP64 ones
-// measured slower at six.  Seven waves (72 VGPRs, 20 registers spilled) were
-// slower again: 2.79 against 2.68 ms.
+// than by VALU throughput and runs about 5 % faster at six waves (80 VGPRs,
+// 5 registers spilled outside the pair loop, 26 KB of list LDS per block)
+// than at five (2.78 -> 2.64 ms on N = 128^3 clustered).  With per-particle
+// masses (19 registers spilled) two runs gave -3 % and +0.7 %; the softened
+// kernel (103 VGPRs, four waves) gained nothing at five; the tabulated ones
+// are held to fewer waves by the table in LDS; the FP64 ones measured slower
+// at six.  Those keep the compiler's choice.  Seven waves (72 VGPRs, 20
+// registers spilled) were slower again: 2.79 against 2.68 ms.
 template <int MODE, bool UNIT, bool SOFT, int TAB>
 struct PairsSix {
     static constexpr bool v = MODE == FWD_F32 && UNIT && !SOFT && TAB == SHAPE_POLY;
@@ -964,19 +966,19 @@ hipError_t launch_pairs(int mode, int screen, int tab, const PairArgs &a, int gr
     return hipGetLastError();
 }
 
-// Blocks of the persistent grid per CU.  The six-wave FP32 variant is sized by
-// its own limit (6).  Every other variant is sized by what the mode's largest
-// screened variant (per-particle masses, 8-receiver clusters: the most
-// registers) leaves room for, as if it were launched: for FP64 that is 4 blocks,
-// against the 5 the unit-mass variant would fit, and 4 measured 2 % faster.
+// Blocks of the persistent grid per CU.  The six-wave FP32 variant is sized
+// by its own limit (6).  Every other variant is sized by what the largest
+// screened variant of its mode and softening (per-particle masses, 8-receiver
+// clusters: the most registers) leaves room for, as if it were launched: for
+// FP64 that is 4 blocks, against the 5 the unit-mass variant would fit, and 4
+// measured 2 % faster.
 int pairs_blocks_per_cu(int mode, int screen, int tab, int csize, int unit_mass, int soft) {
     bool unit = unit_mass && (mode == FWD_F32 || mode == FWD_F64);
-    const bool six = mode == FWD_F32 && unit && !soft && tab == SHAPE_POLY;
+    const bool six = mode == FWD_F32 && unit && tab == SHAPE_POLY && !soft;
     if (!six) {
         unit = false;
         screen = screen ? 1 : 0;
         if (screen) csize = 8;
-        soft = 0;
     }
     const PairsFn fn = pairs_kernel(mode, screen, tab, csize, unit, soft != 0);
     int nb = 0;
