@@ -96,13 +96,16 @@ def time_calls(torch, fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
-def adjoint_leg(torch, ctx, pos, mass, wl, steps, warmup):
-    """Vector-Jacobian product of the force (60 algorithmic flops per pair)."""
+def adjoint_leg(torch, ctx, pos, mass, wl, steps, warmup, tune=True):
+    """Vector-Jacobian product of the force (60 algorithmic flops per pair),
+    in the layout the autotuner picks for the adjoint itself."""
     gen = torch.Generator(device=pos.device).manual_seed(4003)
     w = torch.randn((wl.n, 3), dtype=torch.float64, device=pos.device, generator=gen)
     out = {}
     for prec in ("fp32", "fp64"):
         kw = dict(box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut, precision=prec)
+        if tune:
+            ctx.autotune(pos, mass, None, level=2, adjoint=True, **kw)
         wall = time_calls(torch, lambda: ctx.force_backward(pos, mass, None, w, **kw),
                           max(2, steps // 4), 1)
         ctx.set_timing(True)
@@ -453,7 +456,8 @@ def main():
 
     legs = [l for l in args.legs.split(",") if l]
     if "adjoint" in legs:
-        line["adjoint"] = adjoint_leg(torch, ctx, pos, mass, wl, args.steps, args.warmup)
+        line["adjoint"] = adjoint_leg(torch, ctx, pos, mass, wl, args.steps, args.warmup,
+                                      tune=not (args.no_autotune or fixed))
     if "softened" in legs:
         line["softened"] = softened_leg(torch, ctx, pos, mass, wl, args.steps, args.warmup)
     if "long_range" in legs:

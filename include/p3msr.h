@@ -191,7 +191,12 @@ int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
  * particle count and geometry use it.
  * acc_scratch is an n x 3 FP64 device buffer the trials write into.
  * level: 1 = subtiles only, 2 = subtiles and item size.  Synchronises.
+ * Without P3M_TUNE_ADJOINT the forward is tuned, and the adjoint
+ * (p3m_sr_force_backward) takes the same decomposition; with level |
+ * P3M_TUNE_ADJOINT the adjoint is timed instead (unit weights on every
+ * receiver, workspace of n x 3 doubles for them) and keeps its own winner.
  */
+#define P3M_TUNE_ADJOINT 4
 int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass,
                     const uint8_t *active, int64_t n, double box, double x_s, double r_cut,
                     int precision, int level, double *acc_scratch, void *stream);

@@ -77,6 +77,7 @@ class KdkStats(ctypes.Structure):
 
 
 P3M_KDK_FIXED_RUNGS = 1
+P3M_TUNE_ADJOINT = 4          # p3m_sr_autotune level flag: tune the adjoint
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -297,14 +298,16 @@ class Context:
         return s.as_dict()
 
     def autotune(self, pos, mass=None, active=None, *, box, x_s, r_cut, precision="fp32",
-                 level=1, out=None):
-        """Measure-and-keep tuning of the decomposition for these inputs;
-        `out` (n x 3 FP64 on the device) is optional scratch for the trials."""
+                 level=1, out=None, adjoint=False):
+        """Measure-and-keep tuning of the decomposition for these inputs (of
+        the adjoint instead of the forward with adjoint=True); `out` (n x 3
+        FP64 on the device) is optional scratch for the trials."""
         pos, mass, active, n = self._inputs(pos, mass, active, "active")
         scratch = self._out(out, n)
+        lvl = int(level) | (P3M_TUNE_ADJOINT if adjoint else 0)
         _check(self._lib.p3m_sr_autotune(self._h, self._p(pos), self._p(mass), self._p(active),
                                          n, float(box), float(x_s), float(r_cut),
-                                         _prec(precision), int(level), self._p(scratch),
+                                         _prec(precision), lvl, self._p(scratch),
                                          _stream_ptr(self.device)))
 
     def set_config(self, subtiles_per_dim=0, item_target=0, cluster_size=0, screen=-1):
@@ -401,5 +404,5 @@ def p3m_force(pos, mass=None, active=None, *, box=1.0, x_s, r_cut, n_grid, preci
 
 
 __all__ = ["Context", "P3MError", "Stats", "LrStats", "KdkStats", "lr_force", "p3m_force",
-           "P3M_KDK_FIXED_RUNGS", "default_context", "load_library", "sr_force",
+           "P3M_KDK_FIXED_RUNGS", "P3M_TUNE_ADJOINT", "default_context", "load_library", "sr_force",
            "sr_force_batched", "LIB_PATH", "P3M_FP32", "P3M_FP64", "EXPORTS"]

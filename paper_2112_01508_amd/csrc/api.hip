@@ -97,7 +97,7 @@ struct p3m_sr_context {
     int *host_tot = nullptr;   // pinned: receivers, clusters, items of the current call
     // long-range PM workspace and timing
     DevBuf pm_real, pm_spec, pm_tab, pm_key, pm_rank, pm_cnt, pm_rec, pm_nkey, pm_perm, pm_recv,
-        pm_bsum, p3m_lr;
+        pm_bsum, p3m_lr, tune_w;
     // p3m_force: the long-range half runs on this stream beside the short range
     hipStream_t aux = nullptr;
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
@@ -596,7 +596,7 @@ int p3m_sr_destroy(p3m_sr_handle h) {
                       &h->pm_real, &h->pm_spec,  &h->pm_tab, &h->pm_key,  &h->pm_rank,
                       &h->pm_cnt,  &h->pm_rec,   &h->pm_nkey, &h->pm_perm, &h->pm_recv,
                       &h->kdk_acc, &h->kdk_lr,   &h->kdk_tq,  &h->kdk_tnext, &h->kdk_due,
-                      &h->kdk_scal, &h->htab,   &h->pm_bsum, &h->p3m_lr};
+                      &h->kdk_scal, &h->htab,   &h->pm_bsum, &h->p3m_lr, &h->tune_w};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : h->ev)
@@ -732,7 +732,10 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     if ((rc = check_geometry(n, box, x_s, r_cut))) return rc;
     if (precision != P3M_FP32 && precision != P3M_FP64)
         return set_error(P3M_EINVAL, "precision must be P3M_FP64 or P3M_FP32");
-    if (level < 1 || level > 2) return set_error(P3M_EINVAL, "level must be 1 or 2");
+    const bool adjoint = (level & P3M_TUNE_ADJOINT) != 0;
+    level &= ~P3M_TUNE_ADJOINT;
+    if (level < 1 || level > 2)
+        return set_error(P3M_EINVAL, "level must be 1 or 2, optionally | P3M_TUNE_ADJOINT");
     if (n > 0 && (!pos || !acc_scratch))
         return set_error(P3M_EINVAL, "pos and acc_scratch are required");
     if ((rc = check_handle(h))) return rc;
@@ -751,6 +754,13 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     r.precision = precision;
     r.out = acc_scratch;
     r.stream = s;
+    if (adjoint) {
+        // the adjoint's trials take unit weights on every receiver as grad_acc
+        if ((rc = ensure(h, h->tune_w, ((size_t)n + 1) * 3 * sizeof(double), s))) return rc;
+        P3M_HIP(launch_fill_f64((double *)h->tune_w.p, 1.0, (size_t)n * 3, s));
+        r.backward = true;
+        r.grad_acc = (const double *)h->tune_w.p;
+    }
     const int nt = tiles_per_dim(box, r_cut);
     // level 1: subtiles x layout (cluster size, screening) x two item sizes;
     // level 2 also sweeps the item size around the level-1 winner
@@ -801,9 +811,13 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    // the adjoint walks the same decomposition: it takes the forward winner
-    h->tuned[TuneKey{n, nt, precision, 0}] = best_v;
-    h->tuned[TuneKey{n, nt, precision, 1}] = best_v;
+    if (adjoint) {
+        h->tuned[TuneKey{n, nt, precision, 1}] = best_v;
+    } else {
+        // until it is tuned on its own, the adjoint takes the forward's winner
+        h->tuned[TuneKey{n, nt, precision, 0}] = best_v;
+        h->tuned[TuneKey{n, nt, precision, 1}] = best_v;
+    }
     return P3M_OK;
 }
 

@@ -174,3 +174,11 @@ def test_r_cut_beyond_fitted_range_is_unsupported(lib):
 def test_shape_arguments(lib, kind, size, msg):
     assert lib.p3m_sr_set_shape(None, kind, size) == -1
     assert msg in lib.p3m_sr_last_error().decode()
+
+
+@pytest.mark.parametrize("level", [0, 3, 4, 8, 12, -1])
+def test_autotune_level_is_checked(lib, level):
+    rc = lib.p3m_sr_autotune(None, ctypes.c_void_p(8), None, None, 10, 1.0, 0.01, 0.045, 1,
+                             level, ctypes.c_void_p(8), None)
+    assert rc == -1
+    assert "level" in lib.p3m_sr_last_error().decode()
