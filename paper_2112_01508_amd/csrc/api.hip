@@ -366,12 +366,12 @@ int run(p3m_sr_context *h, const Request &r) {
     P3M_HIP(launch_keys(r.pos, n, g, key, rank, cells, s));
     P3M_HIP(launch_scan(cells, cells, ncells, bsum, s));
     const uint8_t *sel_src = (r.sel_kind == SEL_ALL && !r.backward) ? nullptr : r.sel;
-    P3M_HIP(launch_scatter(r.pos, r.mass, sel_src, n, g, key, rank, cells, fp32 ? 1 : 0, sp, perm,
-                           sel_s, s));
-    // fine order inside dense subtiles (key/rank are free again as scratch)
     {
         int *perm_f = (int *)h->perm2.p;
         uint8_t *sel_f = (uint8_t *)h->sel2.p;
+        P3M_HIP(launch_scatter(r.pos, r.mass, sel_src, n, g, key, rank, cells, fp32 ? 1 : 0,
+                               csize, sp, perm, sel_s, sp_f, perm_f, sel_f, s));
+        // fine order inside dense subtiles (key/rank are free again as scratch)
         // a subtile no larger than one cluster gains nothing from the reorder
         P3M_HIP(launch_fine_order(sp, perm, sel_s, cells, g, key, rank, sp_f, perm_f, sel_f,
                                   csize, n, fbig, s));

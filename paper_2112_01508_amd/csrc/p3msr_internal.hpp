@@ -135,10 +135,14 @@ size_t scan_block_sums_needed(size_t n);
 // exclusive scan of n int32 values; out has n+1 entries (out[n] = total).
 // in may equal out.
 hipError_t launch_scan(const int *in, int *out, size_t n, int *block_sums, hipStream_t s);
+// scatter into tile -> subtile order: particles of subtiles that the fine
+// order leaves as they are (at most max(csize, kFineMin)) go to sp2/perm2/sel2,
+// the others to sp/perm/sel_s for launch_fine_order
 hipError_t launch_scatter(const double *pos, const double *mass, const uint8_t *sel, int n,
                           const Geom &g, const int *key, const int *rank,
-                          const int *cell_start, int fp32, double4 *sp, int *perm,
-                          uint8_t *sel_s, hipStream_t s);
+                          const int *cell_start, int fp32, int csize, double4 *sp, int *perm,
+                          uint8_t *sel_s, double4 *sp2, int *perm2, uint8_t *sel2,
+                          hipStream_t s);
 // reorder the particles of every subtile by the Morton index of their fine
 // sub-cell (sp/perm/sel -> sp2/perm2/sel2; fkey/frank: n ints of scratch;
 // big_list: 1 + n / kFineBig ints, big_list[0] zeroed before the call)

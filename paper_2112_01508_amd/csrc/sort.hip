@@ -180,15 +180,25 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const int *in, int *ou
 
 // ---- scatter into tile -> subtile order --------------------------------------
 
+// Particles of subtiles with at most keep_max particles keep their scattered
+// order, so they go straight to the final arrays (sp_f, perm_f, sel_f); the
+// others go to the staging arrays that the fine-order pass reorders from.
 __global__ void k_scatter(const double *__restrict__ pos, const double *__restrict__ mass,
                           const uint8_t *__restrict__ sel, int n, Geom g,
                           const int *__restrict__ key, const int *__restrict__ rank,
-                          const int *__restrict__ cell_start, int fp32,
-                          double4 *__restrict__ sp, int *__restrict__ perm,
-                          uint8_t *__restrict__ sel_s) {
+                          const int *__restrict__ cell_start, int fp32, int keep_max,
+                          double4 *__restrict__ sp_s, int *__restrict__ perm_s,
+                          uint8_t *__restrict__ sel_st, double4 *__restrict__ sp_f,
+                          int *__restrict__ perm_f, uint8_t *__restrict__ sel_f) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int dst = cell_start[key[i]] + rank[i];
+    const int k = key[i];
+    const int c0 = cell_start[k];
+    int dst = c0 + rank[i];
+    const bool direct = cell_start[k + 1] - c0 <= keep_max;
+    double4 *__restrict__ sp = direct ? sp_f : sp_s;
+    int *__restrict__ perm = direct ? perm_f : perm_s;
+    uint8_t *__restrict__ sel_s = direct ? sel_f : sel_st;
     double4 v;
     v.x = wrap_coord(pos[3 * (size_t)i], g);
     v.y = wrap_coord(pos[3 * (size_t)i + 1], g);
@@ -232,12 +242,12 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Fine order, small and medium subtiles: one wave per tile, kFineWaves
-// tiles per block.  Inside every subtile holding more than keep_max and at
-// most kFineBig particles the particles are reordered by fine_key (a
-// counting sort over kFineBins bins in LDS); smaller subtiles are copied as
-// they are; larger ones are appended to big_list (big_list[0] counts them)
-// for k_fine_order_big.  Reads sp/perm/sel and writes sp2/perm2/sel2;
+// Fine order, medium subtiles: one wave per tile, kFineWaves tiles per
+// block.  Inside every subtile holding more than keep_max and at most
+// kFineBig particles the particles are reordered by fine_key (a counting sort
+// over kFineBins bins in LDS); smaller subtiles are already in place (the
+// scatter wrote them to sp2/perm2/sel2); larger ones are appended to big_list
+// (big_list[0] counts them) for k_fine_order_big.  Reads sp/perm/sel and writes sp2/perm2/sel2;
 // fkey/frank are scratch indexed by sorted position.  Consecutive receivers
 // then lie close together, so small clusters have small bounding boxes.
 __global__ __launch_bounds__(kFineWaves * kWave) void k_fine_order(
@@ -254,14 +264,7 @@ __global__ __launch_bounds__(kFineWaves * kWave) void k_fine_order(
         const int *c = cs + tile * g.ns3;
         for (int s = 0; s < g.ns3; ++s) {
             const int a0 = c[s], a1 = c[s + 1];
-            if (a1 - a0 <= keep_max) {
-                for (int i = a0 + lane; i < a1; i += kWave) {
-                    sp2[i] = sp[i];
-                    perm2[i] = perm[i];
-                    sel2[i] = sel[i];
-                }
-                continue;
-            }
+            if (a1 - a0 <= keep_max) continue;   // written in place by k_scatter
             if (a1 - a0 > kFineBig) {
                 if (lane == 0) big_list[1 + atomicAdd(big_list, 1)] = (int)(tile * g.ns3 + s);
                 continue;
@@ -635,10 +638,12 @@ hipError_t launch_scan(const int *in, int *out, size_t n, int *bsum, hipStream_t
 
 hipError_t launch_scatter(const double *pos, const double *mass, const uint8_t *sel, int n,
                           const Geom &g, const int *key, const int *rank, const int *cell_start,
-                          int fp32, double4 *sp, int *perm, uint8_t *sel_s, hipStream_t s) {
+                          int fp32, int csize, double4 *sp, int *perm, uint8_t *sel_s,
+                          double4 *sp2, int *perm2, uint8_t *sel2, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, pos, mass, sel, n, g,
-                       key, rank, cell_start, fp32, sp, perm, sel_s);
+                       key, rank, cell_start, fp32, csize > kFineMin ? csize : kFineMin, sp,
+                       perm, sel_s, sp2, perm2, sel2);
     return hipGetLastError();
 }
 
