@@ -35,6 +35,18 @@ namespace {
 
 __device__ inline unsigned long long ballot64(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// Number of lanes of the wave whose squared distance r2 passes the cut-off
+// test 0 < r2 < rc2.  The ballot of a single compare is that compare's own
+// lane mask, so with one ballot per compare the count is two scalar ANDs and
+// a population count on the scalar unit, and no vector instruction.  Called
+// in wave-uniform control flow only (all 64 lanes active), where the running
+// total stays wave-uniform.  The loops below sum these counts in 32 bits
+// (one scalar add per step) and add the sum to the wave's 64-bit total once
+// per supplier range or list.
+__device__ __forceinline__ unsigned count_pass(double r2, double rc2) {
+    return (unsigned)__builtin_popcountll(ballot64(r2 < rc2) & ballot64(r2 > 0.0));
+}
+
 __device__ inline float q_poly(float v) {
     float q = kGpoly[P3M_GPOLY_DEGREE];
 #pragma unroll
@@ -316,7 +328,8 @@ __device__ __forceinline__ double4 load_uniform(const double4 *base, int j) {
 template <bool SHIFT, class Body>
 __device__ __forceinline__ void test_pair(Body &body, double xi, double yi, double zi,
                                           const double4 &pj, int j, bool valid, double shx,
-                                          double shy, double shz, const PairArgs &a, int &n_ok) {
+                                          double shy, double shz, const PairArgs &a,
+                                          unsigned &n_ok) {
     double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
     if (SHIFT) {
         dx -= shx;
@@ -324,10 +337,8 @@ __device__ __forceinline__ void test_pair(Body &body, double xi, double yi, doub
         dz -= shz;
     }
     const double r2 = dist2(dx, dy, dz);
-    if (valid & (r2 < a.g.rc2) & (r2 > 0.0)) {
-        ++n_ok;   // per-lane count of accepted pairs
-        body.pair(dx, dy, dz, r2, pj, j, a);
-    }
+    n_ok += valid ? count_pass(r2, a.g.rc2) : 0u;
+    if (valid & (r2 < a.g.rc2) & (r2 > 0.0)) body.pair(dx, dy, dz, r2, pj, j, a);
 }
 
 // A full cluster (G = 1): every lane tests the same supplier, read through
@@ -336,18 +347,21 @@ __device__ __forceinline__ void test_pair(Body &body, double xi, double yi, doub
 template <bool SHIFT, class Body>
 __device__ __forceinline__ void range_loop_full(Body &body, double xi, double yi, double zi,
                                                 int j0, int j1, double shx, double shy,
-                                                double shz, const PairArgs &a, int &n_ok) {
+                                                double shz, const PairArgs &a,
+                                                unsigned long long &n_ok) {
     j0 = __builtin_amdgcn_readfirstlane(j0);
     j1 = __builtin_amdgcn_readfirstlane(j1);
     // the sorted array is padded by kSupplierPad records: the look-ahead
     // loads past j1 stay inside the allocation
     double4 A = load_uniform(a.sp, j0);
+    unsigned cnt = 0;
     for (int j = j0; j < j1; j += 2) {
         const double4 B = load_uniform(a.sp, j + 1);
-        test_pair<SHIFT>(body, xi, yi, zi, A, j, true, shx, shy, shz, a, n_ok);
+        test_pair<SHIFT>(body, xi, yi, zi, A, j, true, shx, shy, shz, a, cnt);
         A = load_uniform(a.sp, j + 2);
-        test_pair<SHIFT>(body, xi, yi, zi, B, j + 1, j + 1 < j1, shx, shy, shz, a, n_ok);
+        test_pair<SHIFT>(body, xi, yi, zi, B, j + 1, j + 1 < j1, shx, shy, shz, a, cnt);
     }
+    n_ok += cnt;
 }
 
 // The wave holds G copies ("groups") of the cluster's receivers; group g
@@ -356,7 +370,8 @@ __device__ __forceinline__ void range_loop_full(Body &body, double xi, double yi
 template <bool SHIFT, class Body>
 __device__ __forceinline__ void range_loop(Body &body, double xi, double yi, double zi, int j0,
                                            int j1, int grp, int G, double shx, double shy,
-                                           double shz, const PairArgs &a, int &n_ok) {
+                                           double shz, const PairArgs &a,
+                                           unsigned long long &n_ok) {
     if (G == 1) {
         range_loop_full<SHIFT>(body, xi, yi, zi, j0, j1, shx, shy, shz, a, n_ok);
         return;
@@ -369,6 +384,7 @@ __device__ __forceinline__ void range_loop(Body &body, double xi, double yi, dou
     // the allocation
     const double4 *__restrict__ base = a.sp + j0;
     double4 nxt = base[grp];
+    unsigned cnt = 0;
     for (int k = 0; k < len; k += G) {
         const double4 pj = nxt;
         nxt = base[k + G + grp];   // next step's supplier, loaded one step ahead
@@ -380,11 +396,11 @@ __device__ __forceinline__ void range_loop(Body &body, double xi, double yi, dou
             dz -= shz;
         }
         const double r2 = dist2(dx, dy, dz);
-        if (ok & (r2 < rc2) & (r2 > 0.0)) {
-            ++n_ok;   // per-lane count of accepted pairs
-            body.pair(dx, dy, dz, r2, pj, j0 + k + grp, a);
-        }
+        cnt += (unsigned)__builtin_popcountll(ballot64(ok) & ballot64(r2 < rc2) &
+                                              ballot64(r2 > 0.0));
+        if (ok & (r2 < rc2) & (r2 > 0.0)) body.pair(dx, dy, dz, r2, pj, j0 + k + grp, a);
     }
+    n_ok += cnt;
 }
 
 // Screened suppliers in LDS: group g takes list entries g, g + G, ...; all
@@ -420,7 +436,7 @@ template <bool SHIFT, class Body>
 __device__ __forceinline__ void test_pair_w(Body &body, double xi, double yi, double zi,
                                             const double4 &pj, const typename Body::WT &wj,
                                             double shx, double shy, double shz,
-                                            const PairArgs &a, int &n_ok) {
+                                            const PairArgs &a, unsigned &n_ok) {
     double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
     if (SHIFT) {
         dx -= shx;
@@ -428,10 +444,8 @@ __device__ __forceinline__ void test_pair_w(Body &body, double xi, double yi, do
         dz -= shz;
     }
     const double r2 = dist2(dx, dy, dz);
-    if ((r2 < a.g.rc2) & (r2 > 0.0)) {
-        ++n_ok;   // per-lane count of accepted pairs
-        body.pair_w(dx, dy, dz, r2, pj, wj, a);
-    }
+    n_ok += count_pass(r2, a.g.rc2);
+    if ((r2 < a.g.rc2) & (r2 > 0.0)) body.pair_w(dx, dy, dz, r2, pj, wj, a);
 }
 
 // wp: this lane's view of the list's weights (adjoint bodies only).
@@ -439,23 +453,26 @@ template <int G, bool SHIFT, class Body>
 __device__ __forceinline__ void list_loop(Body &body, const double4 *p,
                                           const typename Body::WT *wp, int n_list, double xi,
                                           double yi, double zi, double shx, double shy,
-                                          double shz, const PairArgs &a, int &n_ok) {
+                                          double shz, const PairArgs &a,
+                                          unsigned long long &n_ok) {
     constexpr bool W = Body::kNeedW;
     using WT = typename Body::WT;
     double4 A = list_read<W>(p);
     WT wA{};
     if constexpr (Body::kHasW) wA = wp[0];
+    unsigned cnt = 0;
     for (int k = 0; k < n_list; k += 2 * G) {
         const double4 *q = p + k;
         const double4 B = list_read<W>(q + G);
         WT wB{};
         if constexpr (Body::kHasW) wB = wp[k + G];
-        test_pair_w<SHIFT>(body, xi, yi, zi, A, wA, shx, shy, shz, a, n_ok);
+        test_pair_w<SHIFT>(body, xi, yi, zi, A, wA, shx, shy, shz, a, cnt);
         A = list_read<W>(q + 2 * G);
         if constexpr (Body::kHasW) wA = wp[k + 2 * G];
         if (k + G < n_list)
-            test_pair_w<SHIFT>(body, xi, yi, zi, B, wB, shx, shy, shz, a, n_ok);
+            test_pair_w<SHIFT>(body, xi, yi, zi, B, wB, shx, shy, shz, a, cnt);
     }
+    n_ok += cnt;
 }
 
 __device__ inline void wave_lds_sync() {
@@ -467,7 +484,7 @@ __device__ inline void wave_lds_sync() {
 // contended atomic per item would also delay the next item's loads (vector
 // memory operations retire in order).
 struct WaveCounts {
-    int n_ok = 0;                       // per lane: accepted pairs
+    unsigned long long n_ok = 0;        // accepted pairs of the wave (wave-uniform)
     unsigned long long cand = 0;        // receiver x supplier pairs handed to the pair loop
     unsigned long long steps = 0;       // wave steps of the pair loop
     unsigned long long screened = 0;    // supplier records tested against the cluster box
@@ -875,8 +892,7 @@ void k_pairs(PairArgs a) {
             }
         }
     }
-    unsigned long long tot = (unsigned long long)wc.n_ok;
-    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, kWave);
+    const unsigned long long tot = wc.n_ok;
     if (lane == 0 && a.counters) {
         atomicAdd(&a.counters->interactions, tot);
         atomicAdd(&a.counters->candidates, wc.cand);
