@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from gpu_common import TOL, gpu_or_skip, to_dev
-from workloads import make_workload, random_particles, sample_indices
+from workloads import lattice_sites, make_workload, random_particles, sample_indices
 
 pytestmark = pytest.mark.gpu
 
@@ -215,6 +215,28 @@ def test_edge_cases(env):
     with pytest.raises(p3.P3MError) as ei:
         ctx.force(to_dev(torch, pos), None, None, box=1.0, x_s=0.1, r_cut=0.4)
     assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("csize,screen", [(32, 1), (8, 1), (64, 0)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_lattice_pairs_on_the_cutoff(env, prec, csize, screen):
+    """Sites of a 64^3 lattice, r_cut = 4 spacings: hundreds of pairs exactly
+    at r_cut (rejected), coincident distinct particles (no contribution) and
+    coordinates of exactly 1.0 (the same point as 0.0).  Separations are exact,
+    so the accepted-pair count must match the oracle's exactly."""
+    print("lattice", prec, csize, screen, flush=True)
+    n_side, k = 64, 4
+    pos, _ = lattice_sites(n_side, 6000, 300, 60, seed=11)
+    rng = np.random.default_rng(12)
+    mass = rng.uniform(0.5, 2.0, pos.shape[0])
+    active = (rng.random(pos.shape[0]) < 0.6).astype(np.uint8)
+    r_cut = k / n_side
+    x_s = r_cut / 4.5
+    ref, cnt, absum = oracle.force_full(pos, mass, 1.0, x_s, r_cut, active=active,
+                                        method="brute")
+    acc, st = run_force(env, pos, mass, active, 1.0, x_s, r_cut, prec, cluster_size=csize,
+                        screen=screen)
+    check(acc, st, ref, cnt, absum, prec, active)
 
 
 def test_repeat_calls_stable(env):

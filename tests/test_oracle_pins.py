@@ -19,7 +19,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import make_workload, random_particles
+from workloads import lattice_sites, make_workload, random_particles
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 mp.mp.dps = 40
@@ -120,6 +120,36 @@ def test_coincident_pair_contributes_nothing():
     acc, cnt, _, _ = oracle.force(pos, None, 1.0, 0.01, 0.045)
     assert cnt.tolist() == [1, 1, 2]
     assert np.all(np.isfinite(acc))
+
+
+def lattice_counts(ijk, n_side, r_cut_sites):
+    """Accepted partners per particle by integer arithmetic: the minimum-image
+    site difference (each component reduced to [-n_side/2, n_side/2)),
+    0 < d^2 < r_cut^2, all in lattice units."""
+    d = ijk[:, None, :] - ijk[None, :, :]
+    d = (d + n_side // 2) % n_side - n_side // 2
+    d2 = (d * d).sum(axis=2)
+    return ((d2 > 0) & (d2 < r_cut_sites ** 2)).sum(axis=1)
+
+
+def test_lattice_counts_are_integer_exact():
+    """Sites of a 64^3 lattice with r_cut = 4 spacings: many pairs lie exactly
+    on the cut-off (strict <, section 2.1.3), duplicated sites are coincident
+    distinct particles (no contribution), and a coordinate of exactly 1.0 is
+    the same point as 0.0 (nearest image).  The oracle's accepted-pair counts
+    must equal the integer count, and every pair's separation is exact."""
+    n_side, k = 64, 4
+    pos, ijk = lattice_sites(n_side, 3000, 200, 40, seed=7)
+    r_cut = k / n_side
+    x_s = r_cut / 4.5
+    want = lattice_counts(ijk, n_side, k)
+    d = ijk[:, None, :] - ijk[None, :, :]
+    d = (d + n_side // 2) % n_side - n_side // 2
+    assert ((d * d).sum(axis=2) == k * k).sum() > 100     # pairs exactly at r_cut exist
+    for method in ("brute", "tiled"):
+        acc, cnt, _ = oracle.force_full(pos, None, 1.0, x_s, r_cut, method=method)
+        assert np.array_equal(cnt, want), method
+        assert np.all(np.isfinite(acc))
 
 
 def test_minimum_image_across_boundary():

@@ -74,5 +74,29 @@ def random_particles(n: int, seed: int, box: float = 1.0, mass_range=(0.5, 2.0),
     return pos, mass, active
 
 
+def lattice_sites(n_side: int, n_sites: int, n_dup: int, n_edge: int, seed: int):
+    """Particles on sites of an n_side^3 lattice in the unit box (n_side a
+    power of two, so every coordinate and every separation is exact in
+    FP64), for tests whose pair distances fall exactly on a cut-off.
+
+    n_sites distinct random sites, then n_dup copies of some of them
+    (coincident distinct particles) and n_edge copies with one coordinate
+    moved from 0 to exactly 1.0 (the same point of the periodic box).
+    Returns (pos, ijk): positions (N, 3) and the integer site indices, with
+    1.0 given as index n_side."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    flat = rng.choice(n_side ** 3, size=n_sites, replace=False)
+    ijk = np.stack([flat // (n_side * n_side), (flat // n_side) % n_side, flat % n_side], axis=1)
+    dup = ijk[rng.integers(0, n_sites, n_dup)]
+    zero = np.flatnonzero((ijk == 0).any(axis=1))
+    edge = ijk[rng.choice(zero, size=min(n_edge, zero.size), replace=False)].copy()
+    for row in edge:
+        row[rng.choice(np.flatnonzero(row == 0))] = n_side
+    ijk = np.concatenate([ijk, dup, edge]).astype(np.int64)
+    perm = rng.permutation(ijk.shape[0])
+    ijk = ijk[perm]
+    return ijk.astype(np.float64) / n_side, ijk
+
+
 __all__ = ["CONFIGS", "make_workload", "random_particles", "Workload", "sample_indices",
-           "stratified_by_rung", "wrap_unit", "p3m_scales"]
+           "stratified_by_rung", "wrap_unit", "p3m_scales", "lattice_sites"]
