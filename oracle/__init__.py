@@ -194,17 +194,26 @@ def errors(a, ref, absum):
 
     e_l2       = ||a - ref||_2 / ||ref||_2 over all components;
     e_max_cond = max_i |a_i - ref_i| / absum_i, the error relative to the
-                 sum of pair-force magnitudes (immune to cancellation);
-    p999       = 99.9th percentile of |a_i - ref_i| / |ref_i|.
+                 sum of pair-force magnitudes (immune to cancellation).  A row
+                 with absum_i = 0 has no accepted pair, so its exact value is
+                 0: any nonzero |a_i - ref_i| there makes e_max_cond infinite;
+    p999       = 99.9th percentile of |a_i - ref_i| / |ref_i| over the rows
+                 with ref_i != 0 (numpy's linear interpolation between ranks);
+    max_abs    = max_i |a_i - ref_i|.
     """
     a = np.asarray(a, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
+    absum = np.asarray(absum, dtype=np.float64)
+    assert a.shape == ref.shape and a.ndim == 2 and absum.shape == (a.shape[0],)
     d = np.linalg.norm(a - ref, axis=1)
     nr = np.linalg.norm(ref, axis=1)
     den = np.linalg.norm(ref)
     e_l2 = float(np.linalg.norm(a - ref) / den) if den > 0 else float(np.linalg.norm(a - ref))
     ok = absum > 0
-    e_cond = float(np.max(d[ok] / absum[ok])) if ok.any() else float(np.max(d, initial=0.0))
+    if np.any(d[~ok] != 0.0):
+        e_cond = float("inf")
+    else:
+        e_cond = float(np.max(d[ok] / absum[ok])) if ok.any() else 0.0
     nz = nr > 0
     p999 = float(np.percentile(d[nz] / nr[nz], 99.9)) if nz.any() else 0.0
     return dict(e_l2=e_l2, e_max_cond=e_cond, p999=p999, max_abs=float(np.max(d, initial=0.0)))

@@ -468,7 +468,7 @@ static double local_loss(int64_t n, const double *pos, const double *mass, const
         double dx0 = min_image(pos[3 * k] - pos[3 * j], box);
         double dy0 = min_image(pos[3 * k + 1] - pos[3 * j + 1], box);
         double dz0 = min_image(pos[3 * k + 2] - pos[3 * j + 2], box);
-        double r20 = dx0 * dx0 + dy0 * dy0 + dz0 * dz0;
+        double r20 = sq_dist(dx0, dy0, dz0);
         int in0 = (r20 < rc2 && r20 > 0.0);
         double dx = min_image(y[0] - pos[3 * j], box);
         double dy = min_image(y[1] - pos[3 * j + 1], box);

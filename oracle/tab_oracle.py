@@ -12,12 +12,21 @@ g(u)/r^3 diverges at r = 0, so the table here holds its smooth part:
 
     g(u) / r^3 = r^-3 + H(t) / (2 x_s)^3,   t = u^2,   H(t) = (g(u) - 1) / u^3,
 
-and r^-3 is computed exactly.  Bin k covers r^2 in [k, k + 1) rc2 / n.
-NGP takes H at the bin centre; linear interpolation takes H at the bin's two
-ends.  The bin index is computed in FP32 from the FP32 r^2 and the FP32
-entries-per-r^2 factor, so that both sides of a comparison pick the same
-bin; the rest is FP64.  H comes from erfc and exp (math module), with the
-Maclaurin series of g - 1 for u < 0.05 where g - 1 cancels.
+and r^-3 is computed exactly.  Written from that definition, in FP64:
+
+  - the table has n bins on r^2 in [0, r_cut^2); bin k covers
+    [k, k + 1) r_cut^2 / n;
+  - NGP reads H at the centre of the pair's bin;
+  - linear interpolation reads H at the bin's two ends and interpolates at
+    the pair's own position x = r^2 n / r_cut^2 inside it (FP64).
+
+The one rule shared with the GPU is which bin a pair falls in: the paper
+gives no rounding for the index, and a nearest-grid-point table is
+discontinuous at bin edges, so both sides take k = floor(fl32(fl32(r^2) *
+fl32(n / r_cut^2))) (capped at n - 1).  Linear interpolation is continuous,
+so there the choice only matters at the level of FP64 rounding.  H comes
+from erfc and exp (math module), with the Maclaurin series of g - 1 for
+u < 0.05 where g - 1 cancels.
 """
 from __future__ import annotations
 
@@ -41,16 +50,29 @@ def h_exact(t):
     return (g - 1.0) / (u * u * u)
 
 
-def table(kind, n, rc2, c2):
-    """The table as float32: NGP n values, linear n (value, next - value) pairs."""
+def bin_index(r2, n, rc2):
+    """The pair's bin: floor(fl32(fl32(r^2) * fl32(n / rc2))), at most n - 1."""
+    x = np.asarray(r2, dtype=np.float64).astype(np.float32) * np.float32(n / rc2)
+    return np.minimum(x.astype(np.int64), n - 1)
+
+
+def nodes(kind, n, rc2, c2):
+    """FP64 values of H the table is made of: NGP the n bin centres, linear
+    the n + 1 bin ends."""
     if kind == NGP:
-        return np.array([h_exact((k + 0.5) * rc2 / n * c2) for k in range(n)], dtype=np.float32)
-    nodes = [h_exact(k * rc2 / n * c2) for k in range(n + 1)]
-    out = np.empty((n, 2), dtype=np.float32)
-    for k in range(n):
-        out[k, 0] = nodes[k]
-        out[k, 1] = nodes[k + 1] - nodes[k]
-    return out
+        return np.array([h_exact((k + 0.5) * rc2 / n * c2) for k in range(n)])
+    return np.array([h_exact(k * rc2 / n * c2) for k in range(n + 1)])
+
+
+def shape_h(r2, kind, n, rc2, c2, node_values=None):
+    """Tabulated H for squared distances r2 (FP64 everywhere but the bin)."""
+    r2 = np.asarray(r2, dtype=np.float64)
+    v = nodes(kind, n, rc2, c2) if node_values is None else node_values
+    k = bin_index(r2, n, rc2)
+    if kind == NGP:
+        return v[k]
+    f = r2 * (n / rc2) - k
+    return v[k] + (v[k + 1] - v[k]) * f
 
 
 def force(pos, mass, box, x_s, r_cut, recv, kind, n):
@@ -62,8 +84,7 @@ def force(pos, mass, box, x_s, r_cut, recv, kind, n):
     rc2 = r_cut * r_cut
     c2 = 1.0 / (4.0 * x_s * x_s)
     c3 = 1.0 / (8.0 * x_s ** 3)
-    tab = table(kind, n, rc2, c2)
-    scale = np.float32(n / rc2)
+    v = nodes(kind, n, rc2, c2)
     out = np.zeros((len(recv), 3))
     for a, i in enumerate(recv):
         d = pos[i] - pos
@@ -71,13 +92,7 @@ def force(pos, mass, box, x_s, r_cut, recv, kind, n):
         r2 = sq_dist(d)                       # the cut-off test's rounding
         sel = (r2 < rc2) & (r2 > 0.0)
         r2s, ds, mus = r2[sel], d[sel], mu[sel]
-        x = r2s.astype(np.float32) * scale               # FP32, as the bin index
-        k = np.minimum(x.astype(np.int64), n - 1)
-        if kind == NGP:
-            h = tab[k].astype(np.float64)
-        else:
-            f = (x - k.astype(np.float32)).astype(np.float64)
-            h = tab[k, 0].astype(np.float64) + tab[k, 1].astype(np.float64) * f
+        h = shape_h(r2s, kind, n, rc2, c2, v)
         s = mus * (1.0 / (r2s * np.sqrt(r2s)) + c3 * h)
         out[a] = -(s[:, None] * ds).sum(axis=0)
     return out

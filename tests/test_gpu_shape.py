@@ -1,7 +1,8 @@
 """Tabulated FP32 kernel shape on the GPU (p3m_sr_set_shape; section 2.1.3,
-"Other optimisations") against the tabulated-shape oracle (the same table
-and bin choice, FP64 elsewhere) and, for the stated accuracy, against the
-exact FP64 oracle, through the C ABI."""
+"Other optimisations") against the tabulated-shape oracle (the table from
+its definition in FP64, only the bin choice shared) and, for the stated
+accuracy, against the exact FP64 oracle, through the C ABI."""
+
 import numpy as np
 import pytest
 
@@ -104,3 +105,48 @@ def test_shape_clustered128_sampled(env, kind):
     e_t = oracle.errors(acc[idx], ref_t, absum)
     print(e_t, oracle.errors(acc[idx], ref, absum), flush=True)
     assert e_t["e_max_cond"] <= 2e-6
+
+
+def isolated_pairs(n_per_dim, r_cut, bins, seed):
+    """Pairs of particles far apart from every other pair (centres on a grid
+    of spacing 1 / n_per_dim >= 3 r_cut), pair k at squared separation
+    (k + f_k) r_cut^2 / bins with f_k in (0.02, 0.98) and a random direction:
+    every particle's force is its one pair's, and the pairs cover every bin."""
+    rng = np.random.default_rng(seed)
+    s = 1.0 / n_per_dim
+    assert s >= 3.0 * r_cut and n_per_dim ** 3 >= bins
+    g = (np.arange(n_per_dim) + 0.5) * s
+    c = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    c = c + rng.uniform(-0.05, 0.05, c.shape) * s
+    m = c.shape[0]
+    k = np.arange(m) % bins
+    r = np.sqrt((k + rng.uniform(0.02, 0.98, m)) * r_cut * r_cut / bins)
+    u = rng.standard_normal((m, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    return np.concatenate([c, c + r[:, None] * u])
+
+
+@pytest.mark.parametrize("kind, size", [("table_ngp", 4096), ("table_ngp", 1024),
+                                        ("table_linear", 2048), ("table_linear", 256)])
+def test_shape_table_per_bin(env, kind, size):
+    """The kernel's FP32 table agrees with the table's definition (H at FP64
+    nodes) to FP32 rounding in every bin: on isolated pairs each particle's
+    force is one pair's factor r^-3 + H / (2 x_s)^3 times the separation, and
+    it must match the oracle's within 2^-20 of the factor's scale r^-3 +
+    |H| / (2 x_s)^3 (a bin off by one misses by about 1e-3 of that scale)."""
+    x_s = 0.004
+    r_cut = 4.5 * x_s
+    pos = isolated_pairs(16, r_cut, size, seed=size + 3)
+    n = pos.shape[0]
+    acc, st = gpu_force(env, pos, None, None, x_s, r_cut, kind, size)
+    assert st["interactions"] == n
+    ref = tb.force(pos, None, 1.0, x_s, r_cut, np.arange(n), KINDS[kind], size)
+    half = n // 2
+    d = pos[:half] - pos[half:]
+    r2 = (d * d).sum(axis=1)
+    c3 = 1.0 / (8.0 * x_s ** 3)
+    h = np.array([abs(tb.h_exact(t)) for t in r2 / (4.0 * x_s * x_s)])
+    scale = np.tile((r2 ** -1.5 + c3 * h) * np.sqrt(r2), 2)
+    err = np.linalg.norm(acc - ref, axis=1) / scale
+    print(kind, size, "max err / scale %.3e" % err.max(), flush=True)
+    assert err.max() <= 2.0 ** -20

@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import make_workload, random_particles
+from workloads import lattice_sites, make_workload, random_particles
 
 mp.mp.dps = 40
 
@@ -141,3 +141,64 @@ def test_vjp_inactive_particles_only_supply():
     w = np.ones((200, 3))
     g = oracle.vjp(pos, mass, np.zeros(200, np.uint8), w, 1.0, 0.04, 0.18)
     assert np.all(g == 0)
+
+
+def test_fd_fixed_on_lattice_sites_with_pairs_on_cutoff():
+    """Sites of a 64^3 lattice with r_cut = 4 spacings: hundreds of pairs lie
+    exactly on r_cut (excluded: the sum is strict), duplicated sites are
+    coincident particles (no contribution).  The frozen pair set of the
+    finite differences and the analytic VJP must make the same decisions, so
+    they agree to the differences' truncation error on every sample."""
+    n_side, k = 64, 4
+    pos, ijk = lattice_sites(n_side, 3000, 200, 40, seed=9)
+    r_cut = k / n_side
+    x_s = r_cut / 4.5
+    d = ijk[:, None, :] - ijk[None, :, :]
+    d = (d + n_side // 2) % n_side - n_side // 2
+    on_cut = ((d * d).sum(axis=2) == k * k).any(axis=1)
+    assert on_cut.sum() > 100
+    w = np.random.default_rng(10).standard_normal((pos.shape[0], 3))
+    kidx = np.flatnonzero(on_cut)[:60]
+    g = oracle.vjp(pos, None, None, w, 1.0, x_s, r_cut, kidx=kidx)
+    fd, _ = oracle.fd_grad(pos, None, None, w, 1.0, x_s, r_cut, kidx, h=1e-7, mode="fixed")
+    nz = np.linalg.norm(fd, axis=1) > 0
+    assert np.all(g[~nz] == 0)
+    rel = np.linalg.norm(g[nz] - fd[nz], axis=1) / np.linalg.norm(fd[nz], axis=1)
+    assert np.max(rel) <= 1e-6
+
+
+def _pair_split_by_rounding(r_cut, seed):
+    """Two particles whose separation d has fma(dz, dz, fma(dy, dy, dx dx))
+    below r_cut^2 while the unfused ((dx dx + dy dy) + dz dz) is not (or the
+    reverse): the pair's membership depends on the rounding of r^2."""
+    rng = np.random.default_rng(seed)
+    rc2 = r_cut * r_cut
+    for _ in range(200000):
+        u = rng.standard_normal(3)
+        u /= np.linalg.norm(u)
+        x0 = rng.uniform(0.3, 0.7, 3)
+        x1 = x0 - u * r_cut
+        dd = x0 - x1
+        fused = oracle.sq_dist(dd[None, :])[0]
+        plain = (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2]
+        if (fused < rc2) != (plain < rc2):
+            return np.stack([x0, x1]), fused < rc2
+    raise AssertionError("no pair found")
+
+
+def test_fd_fixed_pair_set_uses_the_cutoff_rounding():
+    """The frozen pair set of the finite differences is decided with the same
+    r^2 rounding as the force and the VJP (the fused form), so a pair whose
+    membership depends on that rounding is in both sets or in neither."""
+    x_s = 0.01
+    r_cut = 4.5 * x_s
+    pos, inside = _pair_split_by_rounding(r_cut, seed=3)
+    w = np.array([[0.3, -1.0, 0.7], [0.5, 0.2, -0.4]])
+    g = oracle.vjp(pos, None, None, w, 1.0, x_s, r_cut, kidx=[0, 1])
+    fd, _ = oracle.fd_grad(pos, None, None, w, 1.0, x_s, r_cut, [0, 1], h=1e-7, mode="fixed")
+    if inside:
+        assert np.all(np.linalg.norm(g, axis=1) > 0)
+        rel = np.linalg.norm(g - fd, axis=1) / np.linalg.norm(g, axis=1)
+        assert np.max(rel) <= 1e-6
+    else:
+        assert np.all(g == 0) and np.all(fd == 0)
