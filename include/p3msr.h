@@ -53,7 +53,12 @@ typedef struct p3m_sr_context *p3m_sr_handle;
 
 typedef enum {
     P3M_FP64 = 0, /* all pair arithmetic in FP64 */
-    P3M_FP32 = 1  /* FP64 separation, cut-off test and accumulation; FP32 kernel shape */
+    P3M_FP32 = 1  /* FP32 kernel shape, FP64 accumulation.  The separation, r^2 and the
+                     cut-off test are FP64, except with layout screen = 2 on all-active
+                     forward calls (p3m_sr_set_config): FP32 on cluster-relative
+                     coordinates, redone in FP64 where FP32 could decide a pair
+                     differently or lose accuracy, so the accepted pairs are the FP64
+                     ones */
 } p3m_precision;
 
 /* FP32 forward kernel shape (p3m_sr_set_shape) */
@@ -92,6 +97,7 @@ typedef struct {
     int32_t shape;           /* p3m_shape of the FP32 forward kernel shape used */
     int64_t screened;        /* supplier records tested by the screen (0 without it) */
     double eps_b;            /* B-spline softening length of the call (0: none) */
+    int64_t fp64_steps;      /* screen 2: wavefront steps that redid a pair in FP64 */
 } p3m_sr_stats;
 
 /* Timings of the most recent p3m_lr_force call (when timing is on, else -1). */
@@ -184,7 +190,8 @@ int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
  * Measure-and-keep autotuning (the paper's automatic subtile refinement,
  * section 2.1.3 "Subtiles": try a finer subdivision, time it, keep it if
  * faster).  Times p3m_sr_force on these inputs for candidate subtile counts
- * per dimension crossed with cluster layouts (cluster size, screening) and,
+ * per dimension crossed with cluster layouts (cluster size, screening, and
+ * for all-active FP32 forward calls the mutual layout screen = 2) and,
  * at level >= 2, work-item sizes around the winner; stores the fastest in the
  * handle (a candidate replaces an earlier one only when more than 3 % faster,
  * so near-ties do not flip with timing noise); later calls on the same
@@ -216,9 +223,19 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass,
  *                     against the cluster's bounding box before the pair
  *                     loop (the subtile-pair culling of section 2.1.3
  *                     carried down to single suppliers); 0: no screening;
- *                     -1: automatic.
+ *                     2: screened, and for all-active P3M_FP32 forward calls
+ *                     (no softening, polynomial shape, n <= 2^27) each pair
+ *                     is evaluated once for both partners (Newton's third
+ *                     law, as the paper's tile pairing in section 2.1.3,
+ *                     "Tiles"): clusters visit the upper half of their tile
+ *                     stencil, the pair arithmetic is FP32 on coordinates
+ *                     relative to the cluster's centre and the reactions are
+ *                     added to the partners' FP64 sums; cluster_size must be
+ *                     16, 32 or 64 (0 keeps the automatic choice); other calls
+ *                     take layout 1; -1: automatic.
  * EINVAL outside those ranges.  Results do not depend on these settings
- * beyond FP64 summation order.
+ * beyond FP64 summation order and, with screen 2, the FP32 rounding of the
+ * separation (within the FP32 path's accuracy).
  */
 int p3m_sr_set_config(p3m_sr_handle h, int subtiles_per_dim, int item_target,
                       int cluster_size, int screen);

@@ -81,8 +81,9 @@ struct p3m_sr_context {
     // resident pair-kernel blocks per CU, per variant: mode, screen, cluster size,
     // shape, unit mass, softening
     int blocks_per_cu[4 * 2 * 4 * 3 * 4] = {};
+    int mutual_blocks_per_cu[4 * 2] = {};   // by cluster size and unit mass
     DevBuf key, rank, cells, sp, perm, sel, sp2, perm2, sel2, flags, actpos, ncl, clusters,
-        itemcnt, items, bsum, counters, wa, scal, rp, rperm, rwa, fbig;
+        itemcnt, items, bsum, counters, wa, scal, rp, rperm, rwa, fbig, msum;
     int cfg_ns = 0, cfg_target = 0, cfg_csize = 0, cfg_screen = -1;
     int cfg_shape = SHAPE_POLY, cfg_tab_n = 0;   // FP32 forward shape (p3m_sr_set_shape)
     DevBuf htab;
@@ -243,6 +244,9 @@ struct Request {
 // Default layout before tuning: full 64-receiver clusters without screening.
 constexpr int kDefaultCsize = 64;
 constexpr int kDefaultScreen = 0;
+// screen == kScreenMutual: all-active FP32 forward calls evaluate each pair
+// once for both partners (other calls screen)
+constexpr int kScreenMutual = 2;
 
 bool valid_csize(int c) { return c == 8 || c == 16 || c == 32 || c == 64; }
 
@@ -281,6 +285,19 @@ int run(p3m_sr_context *h, const Request &r) {
     if (screen < 0) screen = kDefaultScreen;
     const Geom g = make_geom(r.box, r.x_s, r.r_cut, nt, ns, kBsplinePerPlummer * h->eps);
     const size_t ncells = (size_t)g.nt3 * g.ns3;
+    // one subset with every particle a receiver: receivers are the sorted
+    // particles themselves, no flags, scan or compaction
+    const bool all_recv = n_sub == 1 && (r.backward || r.sel_kind == SEL_ALL);
+    // tabulated FP32 shape (point particles, forward only)
+    const int shape = (fp32 && !r.backward && g.eps_b == 0.0) ? h->cfg_shape : SHAPE_POLY;
+    // each pair once for both partners: all-active FP32 forward calls with
+    // the polynomial shape, no softening, clusters of 16, 32 or 64 and fewer
+    // than 2^27 particles (the list entries hold the sorted index in 27 bits);
+    // other calls with this layout take the screened kernel
+    const bool mutual = screen == kScreenMutual && fp32 && !r.backward && all_recv &&
+                        shape == SHAPE_POLY && g.eps_b == 0.0 && csize >= 16 &&
+                        r.n <= (int64_t)(1u << 27);
+    if (screen == kScreenMutual && !mutual) screen = 1;
 
     p3m_sr_stats st{};
     st.n = r.n;
@@ -289,7 +306,7 @@ int run(p3m_sr_context *h, const Request &r) {
     st.item_target = target;
     st.precision = r.precision;
     st.cluster_size = csize;
-    st.screen = screen;
+    st.screen = mutual ? kScreenMutual : screen;
     st.eps_b = kBsplinePerPlummer * h->eps;
     st.ms_build = st.ms_pairs = st.ms_total = -1.0f;
     h->last_stream = s;
@@ -311,9 +328,6 @@ int run(p3m_sr_context *h, const Request &r) {
     const size_t ncl_len = (size_t)n_sub * g.nt3;
     const size_t cl_bound = ncl_len + (nflags + csize - 1) / csize;
     const size_t scan_max = std::max(std::max(ncells, nflags), std::max(ncl_len, cl_bound));
-    // one subset with every particle a receiver: receivers are the sorted
-    // particles themselves, no flags, scan or compaction
-    const bool all_recv = n_sub == 1 && (r.backward || r.sel_kind == SEL_ALL);
     int rc;
     if ((rc = ensure(h, h->key, sizeof(int) * n, s))) return rc;
     if ((rc = ensure(h, h->rank, sizeof(int) * n, s))) return rc;
@@ -337,6 +351,7 @@ int run(p3m_sr_context *h, const Request &r) {
     if ((rc = ensure(h, h->rperm, sizeof(int) * (nflags + 1), s))) return rc;
     if (r.backward && (rc = ensure(h, h->rwa, sizeof(double4) * (nflags + 1), s))) return rc;
     if (r.backward && (rc = ensure(h, h->wa, sizeof(double4) * ((size_t)n + kSupplierPad), s))) return rc;
+    if (mutual && (rc = ensure(h, h->msum, sizeof(double) * 3 * (size_t)n, s))) return rc;
 
     int *key = (int *)h->key.p, *rank = (int *)h->rank.p, *cells = (int *)h->cells.p;
     double4 *sp = (double4 *)h->sp.p;
@@ -395,8 +410,8 @@ int run(p3m_sr_context *h, const Request &r) {
     P3M_HIP(launch_cluster_count(cells, recv_scan, n, n_sub, g, csize, ncl, s));
     P3M_HIP(launch_scan(ncl, ncl, ncl_len, bsum, s));
     P3M_HIP(launch_cluster_write(cells, recv_scan, ncl, n, n_sub, g, csize, clusters, s));
-    P3M_HIP(launch_item_count(clusters, ncl + ncl_len, (int)cl_bound, cells, g, target, itemcnt,
-                              s));
+    P3M_HIP(launch_item_count(clusters, ncl + ncl_len, (int)cl_bound, cells, g, target,
+                              mutual ? 1 : 0, itemcnt, s));
     P3M_HIP(launch_scan(itemcnt, itemcnt, cl_bound, bsum, s));
     P3M_HIP(launch_totals(flags + nflags, ncl + ncl_len, itemcnt + cl_bound, h->host_tot, s));
     if (!h->tot_ev) P3M_HIP(hipEventCreateWithFlags(&h->tot_ev, hipEventDisableTiming));
@@ -410,9 +425,9 @@ int run(p3m_sr_context *h, const Request &r) {
     P3M_HIP(launch_cluster_finish(clusters, ncl + ncl_len, cl_bound, csize, recv_pos, sp, perm, wa,
                                   rp, (int *)h->rperm.p,
                                   r.backward ? (double4 *)h->rwa.p : nullptr, s));
-    P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, s));
-    // tabulated FP32 shape (point particles, forward only)
-    const int shape = (fp32 && !r.backward && g.eps_b == 0.0) ? h->cfg_shape : SHAPE_POLY;
+    // the mutual kernel adds into its sorted-order sums, then writes acc_out
+    if (mutual) P3M_HIP(launch_fill_f64((double *)h->msum.p, 0.0, 3 * (size_t)n, s));
+    else P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, s));
     if (shape != SHAPE_POLY) {
         if ((rc = ensure(h, h->htab, kTabFloats * sizeof(float), s))) return rc;
         P3M_HIP(launch_build_htab(shape, h->cfg_tab_n, g, (float *)h->htab.p, s));
@@ -426,7 +441,8 @@ int run(p3m_sr_context *h, const Request &r) {
     if ((rc = ensure(h, h->items, sizeof(Item) * (size_t)(n_items > 0 ? n_items : 1), s)))
         return rc;
     Item *items = (Item *)h->items.p;
-    P3M_HIP(launch_item_write(clusters, n_clusters, cells, g, target, itemcnt, items, s));
+    P3M_HIP(launch_item_write(clusters, n_clusters, cells, g, target, mutual ? 1 : 0, itemcnt,
+                              items, s));
 
     // ---- pairs ----
     PairArgs a{};
@@ -454,16 +470,31 @@ int run(p3m_sr_context *h, const Request &r) {
     st.shape = shape;
     const int unit = r.mass ? 0 : 1, soft = g.eps_b > 0.0 ? 1 : 0;
     const int cs_idx = csize == 8 ? 0 : csize == 16 ? 1 : csize == 32 ? 2 : 3;
-    const int slot = (((mode * 2 + (screen ? 1 : 0)) * 4 + cs_idx) * 3 + shape) * 4 + unit * 2 + soft;
-    int &bpc = h->blocks_per_cu[slot];
-    if (bpc == 0) bpc = pairs_blocks_per_cu(mode, screen, shape, csize, unit, soft);
+    int bpc;
+    if (mutual) {
+        int &slot_m = h->mutual_blocks_per_cu[cs_idx * 2 + unit];
+        if (slot_m == 0) slot_m = mutual_blocks_per_cu(csize, unit);
+        bpc = slot_m;
+        a.out = (double *)h->msum.p;
+        a.out_stride = n;
+        a.rc2_lo = (float)(g.rc2 * (1.0 - std::ldexp(1.0, -17)));
+        a.rc2_hi = (float)(g.rc2 * (1.0 + std::ldexp(1.0, -17)));
+    } else {
+        const int slot =
+            (((mode * 2 + (screen ? 1 : 0)) * 4 + cs_idx) * 3 + shape) * 4 + unit * 2 + soft;
+        int &slot_b = h->blocks_per_cu[slot];
+        if (slot_b == 0) slot_b = pairs_blocks_per_cu(mode, screen, shape, csize, unit, soft);
+        bpc = slot_b;
+    }
     long long waves_wanted = (n_items + 0ll);
     long long grid = std::min<long long>((waves_wanted + 3) / 4, (long long)h->n_cu * bpc);
     if (grid < 1) grid = 1;
     // items per queue atomic: about 32 claims per wave, at most 8 items each
     a.batch = (int)std::max<long long>(1, std::min<long long>(8, n_items / (grid * 4 * 32)));
     if (h->timing) P3M_HIP(hipEventRecord(h->ev[1], s));
-    P3M_HIP(launch_pairs(mode, screen, shape, a, (int)grid, s));
+    if (mutual) P3M_HIP(launch_pairs_mutual(a, (int)grid, s));
+    else P3M_HIP(launch_pairs(mode, screen, shape, a, (int)grid, s));
+    if (mutual) P3M_HIP(launch_mutual_out((const double *)h->msum.p, perm, n, r.out, s));
     if (h->timing) {
         P3M_HIP(hipEventRecord(h->ev[2], s));
         h->timed_last = true;
@@ -596,7 +627,8 @@ int p3m_sr_destroy(p3m_sr_handle h) {
                       &h->pm_real, &h->pm_spec,  &h->pm_tab, &h->pm_key,  &h->pm_rank,
                       &h->pm_cnt,  &h->pm_rec,   &h->pm_nkey, &h->pm_perm, &h->pm_recv,
                       &h->kdk_acc, &h->kdk_lr,   &h->kdk_tq,  &h->kdk_tnext, &h->kdk_due,
-                      &h->kdk_scal, &h->htab,   &h->pm_bsum, &h->p3m_lr, &h->tune_w};
+                      &h->kdk_scal, &h->htab,   &h->pm_bsum, &h->p3m_lr, &h->tune_w,
+                      &h->msum};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : h->ev)
@@ -716,7 +748,9 @@ int p3m_sr_set_config(p3m_sr_handle h, int subtiles_per_dim, int item_target, in
         return set_error(P3M_EINVAL, "item_target must be 0 or in 64..2^20");
     if (cluster_size != 0 && !valid_csize(cluster_size))
         return set_error(P3M_EINVAL, "cluster_size must be 0, 8, 16, 32 or 64");
-    if (screen < -1 || screen > 1) return set_error(P3M_EINVAL, "screen must be -1, 0 or 1");
+    if (screen < -1 || screen > 2) return set_error(P3M_EINVAL, "screen must be -1, 0, 1 or 2");
+    if (screen == kScreenMutual && cluster_size != 0 && cluster_size < 16)
+        return set_error(P3M_EINVAL, "screen 2 needs cluster_size 16, 32 or 64");
     if ((rc = check_handle(h))) return rc;
     h->cfg_ns = subtiles_per_dim;
     h->cfg_target = item_target;
@@ -765,8 +799,12 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     // level 1: subtiles x layout (cluster size, screening) x two item sizes;
     // level 2 also sweeps the item size around the level-1 winner
     std::vector<int> ns_list = {1, 2, 3, 4};
-    const std::pair<int, int> layouts[] = {{64, 0}, {64, 1}, {32, 1}, {16, 1}, {8, 1}, {16, 0},
-                                           {8, 0}};
+    std::vector<std::pair<int, int>> layouts = {{64, 0}, {64, 1}, {32, 1}, {16, 1}, {8, 1},
+                                                {16, 0}, {8, 0}};
+    // all-active FP32 forward calls can evaluate each pair once for both partners
+    if (!adjoint && !active && precision == P3M_FP32 && h->eps == 0.0 &&
+        h->cfg_shape == SHAPE_POLY)
+        for (int c : {32, 64, 16}) layouts.push_back({c, kScreenMutual});
     hipEvent_t e0, e1;
     P3M_HIP(hipEventCreate(&e0));
     P3M_HIP(hipEventCreate(&e1));
@@ -866,6 +904,7 @@ int p3m_sr_get_stats(p3m_sr_handle h, p3m_sr_stats *out) {
         st.candidates = (int64_t)c.candidates;
         st.steps = (int64_t)c.steps;
         st.screened = (int64_t)c.screened;
+        st.fp64_steps = (int64_t)c.rare;
     }
     if (h->timed_last) {
         float a = 0, b = 0, t = 0;

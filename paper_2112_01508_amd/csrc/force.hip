@@ -511,7 +511,7 @@ struct DirectVisit {
     WaveCounts &wc;
     bool shifted = false;
     double shx = 0.0, shy = 0.0, shz = 0.0;
-    __device__ __forceinline__ void tile(int, bool sh, double x, double y, double z) {
+    __device__ __forceinline__ void tile(int, int, bool sh, double x, double y, double z) {
         shifted = sh;
         shx = x;
         shy = y;
@@ -606,7 +606,7 @@ struct ScreenVisit {
         fill = 0;
         if (n_list > CAP - kWave) flush();   // keeps n_list <= CAP
     }
-    __device__ __forceinline__ void tile(int img, bool, double x, double y, double z) {
+    __device__ __forceinline__ void tile(int, int img, bool, double x, double y, double z) {
         if (img != code) {
             screen_chunk();
             flush();
@@ -710,7 +710,7 @@ __device__ __forceinline__ void walk_item(Visit &v, const Item &item, const Clus
             const int ix = nx < 0 ? -1 : (nx >= g.nt ? 1 : 0);
             const int iy = ny < 0 ? -1 : (ny >= g.nt ? 1 : 0);
             const int iz = nz < 0 ? -1 : (nz >= g.nt ? 1 : 0);
-            v.tile((ix + 1) * 9 + (iy + 1) * 3 + (iz + 1), (ix | iy | iz) != 0, ix * g.box,
+            v.tile(t, (ix + 1) * 9 + (iy + 1) * 3 + (iz + 1), (ix | iy | iz) != 0, ix * g.box,
                    iy * g.box, iz * g.box);
             while (m) {
                 const int ra = __builtin_ctzll(m);
@@ -885,7 +885,7 @@ void k_pairs(PairArgs a) {
         // cluster's only one, else added (FP64 atomics) into the zeroed output
         if (c.grp == 0) {
             double *o = a.out + (long long)cl.subset * a.out_stride + 3ll * a.rperm[cl.begin + il];
-            if (item.sole) {
+            if (item.sole & kItemSole) {
                 o[0] = ax;
                 o[1] = ay;
                 o[2] = az;
@@ -904,6 +904,449 @@ void k_pairs(PairArgs a) {
         atomicAdd(&a.counters->candidates, wc.cand);
         atomicAdd(&a.counters->steps, wc.steps);
         atomicAdd(&a.counters->screened, wc.screened);
+    }
+}
+
+// ---- pairs evaluated once for both partners -----------------------------------
+//
+// All-active FP32 forward calls: each unordered pair {i, j} is evaluated once
+// and its force is applied to both particles (Newton's third law; the
+// receiver/supplier tile pairing of section 2.1.3, "Tiles", visits each tile
+// pair once for the same reason).  A cluster visits only the upper half of
+// its 27-tile stencil (t = 13 .. 26, whose mirror images are the lower half)
+// and, in its own tile, only the particles after it; its own pairs are
+// evaluated separately (below).
+//
+// Lanes form four rows of 16.  A cluster of 16 R receivers (R = 1, 2, 4) sits
+// in the rows with receiver 16 (row % R) + lane; the screened suppliers come
+// in blocks of 16 (4 / R) list entries, row r holding entries 16 (r / R) ..
+// + 15, so the R rows that share a block hold the cluster's R parts.  In 16
+// steps each lane meets every entry of its row: at step S it takes the entry
+// S places along its row (a DPP row rotation, folded into the subtraction
+// that forms the separation), and the reaction goes back to the entry's own
+// lane by the opposite rotation (folded into the addition).  After the block
+// the R rows' reactions on an entry are summed and added to the supplier's
+// total with one FP64 atomic per component.
+//
+// Precision (FP32 on cluster-relative coordinates; positions, the periodic
+// image and the sums stay FP64): every particle enters the block as its
+// offset from the centre of the cluster's box, rounded to FP32 (suppliers
+// with their periodic image applied in FP64 first).  The separation, r^2
+// and the cut-off test are FP32.  Two rare cases take the FP64 positions
+// instead, so that the accepted pairs are exactly those of the plain FP64
+// evaluation and close pairs keep FP32 relative accuracy:
+//   - r^2 within a relative 2^-17 of r_cut^2 (the FP32 r^2 is within 2^-20
+//     of the exact one for offsets up to 2.2 r_cut, the largest a cluster
+//     inside one tile can have): the test is repeated in FP64;
+//   - r below a tenth of the receiver's offset, where the rounding of the
+//     offsets (2^-24 of their size) would exceed 2^-21 of r: the separation
+//     is recomputed in FP64 and rounded.
+// The pair factor is the FP32 shape of FwdF32 (hardware rsqrt and the H
+// polynomial); a block's sums are FP32 over its 16 steps and then FP64.
+//
+// The sums go to an FP64 array in sorted order, one component after the
+// other (three arrays of n), which a final pass writes to acc_out.
+
+constexpr int kRing = 128;                    // list entries per wave (a ring)
+constexpr unsigned kIdxBits = 27;             // sorted index bits of a list entry
+constexpr unsigned kIdxMask = (1u << kIdxBits) - 1u;
+
+// The value of the lane S places along this lane's row of 16 (DPP row
+// rotation; every source lane is valid, so the move can fold into the VALU
+// instruction that uses it).
+template <int S>
+__device__ __forceinline__ float rot16(float v) {
+    if constexpr (S == 0) {
+        return v;
+    } else {
+        return __builtin_bit_cast(
+            float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x120 + S, 0xf, 0xf, true));
+    }
+}
+template <int S>
+__device__ __forceinline__ int rot16i(int v) {
+    if constexpr (S == 0) return v;
+    else return __builtin_amdgcn_mov_dpp(v, 0x120 + S, 0xf, 0xf, true);
+}
+
+// v where this lane's bit of the wave mask is set, else 0: one v_cndmask
+// with the mask as its selector.
+__device__ __forceinline__ float keep_lanes(unsigned long long mask, float v) {
+    float r;
+    asm("v_cndmask_b32 %0, 0, %1, %2" : "=v"(r) : "v"(v), "s"(mask));
+    return r;
+}
+
+// This lane's receiver and its sums.
+struct MutualLane {
+    float hx, hy, hz;     // offset from the cluster centre (far away for idle lanes)
+    float ki;             // r^2 below which the separation is recomputed in FP64
+    float mu;             // mu_i (FP32)
+    int i_sorted;
+    float axf = 0.f, ayf = 0.f, azf = 0.f;   // block sums (FP32)
+    float jx = 0.f, jy = 0.f, jz = 0.f;      // reaction on this lane's entry (FP32)
+};
+
+// The separation of receiver i_sorted and list entry jr (sorted index |
+// image << kIdxBits) from the FP64 positions, as the plain evaluation forms
+// it: (x_i - x_j) - n' box, rounded to FP32 with its r^2 (w < 0: the pair
+// fails 0 < r^2 < r_cut^2).  Out of line: it runs for about one step in a
+// thousand.
+__device__ __attribute__((noinline)) float4 mutual_fp64_sep(const double4 *__restrict__ sp,
+                                                            int i_sorted, int jr, double box,
+                                                            double rc2) {
+    const int j = (int)((unsigned)jr & kIdxMask);
+    const int img = (int)((unsigned)jr >> kIdxBits);
+    const double4 pi = sp[i_sorted];
+    const double4 pj = sp[j];
+    double ddx = pi.x - pj.x, ddy = pi.y - pj.y, ddz = pi.z - pj.z;
+    if (img != 13) {
+        ddx -= (double)(img / 9 - 1) * box;
+        ddy -= (double)((img / 3) % 3 - 1) * box;
+        ddz -= (double)(img % 3 - 1) * box;
+    }
+    const double r2d = dist2(ddx, ddy, ddz);
+    const bool ok = (r2d < rc2) & (r2d > 0.0);
+    return make_float4((float)ddx, (float)ddy, (float)ddz, ok ? (float)r2d : -1.0f);
+}
+
+// One step of a block: this lane's receiver against the entry S places along
+// its row.  SELF: the cluster's own particles, each ordered pair evaluated
+// from both ends, no reaction.
+template <int S, bool UNIT, bool SELF>
+__device__ __forceinline__ void mutual_step(MutualLane &m, const float4 &e, int jid,
+                                            const PairArgs &a, unsigned &cnt, unsigned &rare_n) {
+    // each step's values die within it: keep the scheduler from interleaving
+    // the unrolled steps (which multiplies the live registers)
+    __builtin_amdgcn_sched_barrier(0);
+    float dx = m.hx - rot16<S>(e.x);
+    float dy = m.hy - rot16<S>(e.y);
+    float dz = m.hz - rot16<S>(e.z);
+    float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    // pairs decided in FP32: ki <= r^2 < rc2_lo; in FP64: r^2 < ki, and
+    // rc2_lo <= r^2 < rc2_hi (the masks are wave-wide, the logic scalar)
+    const unsigned long long m_lo = ballot64(r2 < a.rc2_lo);
+    const unsigned long long m_far = ballot64(r2 >= m.ki);
+    const unsigned long long m_hi = ballot64(r2 < a.rc2_hi);
+    unsigned long long acc_m = m_lo & m_far;
+    const unsigned long long rare = (m_hi & ~m_lo) | ~m_far;
+    if (rare) {
+        const int jr = rot16i<S>(jid);   // all lanes active here
+        ++rare_n;
+        bool ok = false;
+        if ((rare >> (threadIdx.x & (kWave - 1))) & 1ull) {
+            const float4 q = mutual_fp64_sep(a.sp, m.i_sorted, jr, a.g.box, a.g.rc2);
+            ok = q.w > 0.0f;
+            dx = q.x;
+            dy = q.y;
+            dz = q.z;
+            r2 = ok ? q.w : 1.0f;
+        }
+        acc_m = (acc_m & ~rare) | (ballot64(ok) & rare);
+    }
+    cnt += (unsigned)__builtin_popcountll(acc_m);
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float h = h_poly(fmaf(r2, a.g.c2f, -P3M_HPOLY_T0));
+    const float ri3 = ri * ri * ri;
+    // lanes without a pair send no reaction
+    const float sh = keep_lanes(acc_m, fmaf(a.g.c3f, h, ri3));
+    float shj = sh, shi = sh;
+    if constexpr (!UNIT) {
+        shj = sh * rot16<S>(e.w);          // the force on i carries mu_j
+        shi = sh * m.mu;                   // the reaction on j carries mu_i
+    }
+    // the reaction's products first: a DPP read of a value written by the
+    // previous instruction would need wait states
+    const float fx = shi * dx, fy = shi * dy, fz = shi * dz;
+    m.axf = fmaf(-shj, dx, m.axf);
+    m.ayf = fmaf(-shj, dy, m.ayf);
+    m.azf = fmaf(-shj, dz, m.azf);
+    if constexpr (!SELF) {
+        m.jx += rot16<(16 - S) & 15>(fx);
+        m.jy += rot16<(16 - S) & 15>(fy);
+        m.jz += rot16<(16 - S) & 15>(fz);
+    }
+    // the sums are formed within the step: left to itself the compiler sinks
+    // the chains past the later steps' branches and keeps every step's
+    // separation and pair factor alive until the end of the block
+    asm volatile("" ::"v"(m.axf), "v"(m.ayf), "v"(m.azf), "v"(m.jx), "v"(m.jy), "v"(m.jz));
+}
+
+template <bool UNIT, bool SELF, int NS>
+__device__ __forceinline__ void mutual_steps(MutualLane &m, const float4 &e, int jid,
+                                             const PairArgs &a, unsigned &cnt, unsigned &rare_n) {
+    mutual_step<0, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+    mutual_step<1, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+    mutual_step<2, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+    mutual_step<3, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+    if constexpr (NS > 4) {
+        mutual_step<4, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step<5, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step<6, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step<7, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step<8, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step<9, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step<10, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step<11, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step<12, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step<13, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step<14, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step<15, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+    }
+}
+
+// Sums over the lanes of the R rows that hold the same block entries
+// (rows r and r ^ 1, r ^ 2 for R = 2, 4).
+template <int R>
+__device__ __forceinline__ float rows_sum(float v) {
+    if constexpr (R >= 2) v += __shfl_xor(v, 16, kWave);
+    if constexpr (R >= 4) v += __shfl_xor(v, 32, kWave);
+    return v;
+}
+
+template <int R, bool UNIT>
+struct MutualVisit {
+    static constexpr int EB = 64 / R;   // list entries per block of 16 steps
+    const PairArgs &a;
+    MutualLane &m;
+    float4 *lpos;        // ring: offset from the cluster centre, mu
+    int *lidx;           // ring: sorted index | image << kIdxBits
+    const double *lo, *hi;
+    double cx, cy, cz;   // the cluster centre
+    int lane;
+    int own_from;        // own tile: suppliers from this sorted index on
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    unsigned long long pairs = 0, steps = 0, screened = 0, rare = 0;
+    bool own = false;
+    int code = 13;
+    double shx = 0.0, shy = 0.0, shz = 0.0;
+    int fill = 0, jj = 0, head = 0, n_list = 0;
+
+    __device__ __forceinline__ void flush_i() {
+        ax += (double)m.axf;
+        ay += (double)m.ayf;
+        az += (double)m.azf;
+        m.axf = m.ayf = m.azf = 0.f;
+    }
+
+    // One block of nv (<= EB) list entries from the ring head.
+    __device__ __forceinline__ void block(int nv) {
+        wave_lds_sync();
+        const int row = lane >> 4;
+        const int k = (row / R) * 16 + (lane & 15);
+        float4 e = make_float4(-1.0e30f, -1.0e30f, -1.0e30f, 0.f);
+        int jid = -1;
+        if (k < nv) {
+            const int q = (head + k) & (kRing - 1);
+            e = lpos[q];
+            jid = lidx[q];
+        }
+        wave_lds_sync();   // the reads are done before later screens overwrite the ring
+        m.jx = m.jy = m.jz = 0.f;
+        unsigned cnt = 0, rn = 0;
+        mutual_steps<UNIT, false, 16>(m, e, jid, a, cnt, rn);
+        flush_i();
+        const float jx = rows_sum<R>(m.jx), jy = rows_sum<R>(m.jy), jz = rows_sum<R>(m.jz);
+        if (row % R == 0 && k < nv) {
+            const int j = (int)((unsigned)jid & kIdxMask);
+            atomicAdd(a.out + j, (double)jx);
+            atomicAdd(a.out + a.out_stride + j, (double)jy);
+            atomicAdd(a.out + 2 * a.out_stride + j, (double)jz);
+        }
+        pairs += 2ull * cnt;
+        steps += 16;
+        rare += rn;
+    }
+
+    // The cluster's own pairs (cnt <= 16 R particles), from both ends.
+    __device__ __forceinline__ void self_pass(int cnt, int begin) {
+        const int row = lane >> 4, l = lane & 15;
+        constexpr int passes = R == 4 ? 4 : 1;
+#pragma unroll 1
+        for (int p = 0; p < passes; ++p) {
+            // R = 1: row r holds the particles rotated by 4 r, so four steps
+            // cover every offset; R = 2: rows 0, 1 meet particles 0..15, rows
+            // 2, 3 particles 16..31; R = 4: row r meets part (r + p) % 4.
+            int idx;
+            if constexpr (R == 1) idx = (l + 4 * row) & 15;
+            else if constexpr (R == 2) idx = 16 * (row >> 1) + l;
+            else idx = 16 * ((row + p) & 3) + l;
+            float4 e = make_float4(-1.0e30f, -1.0e30f, -1.0e30f, 0.f);
+            int jid = -1;
+            if (idx < cnt) {
+                const double4 q = a.sp[begin + idx];
+                e = make_float4((float)(q.x - cx), (float)(q.y - cy), (float)(q.z - cz),
+                                UNIT ? 0.f : mu_f32(q.w));
+                jid = (begin + idx) | (13 << kIdxBits);
+            }
+            unsigned c = 0, rn = 0;
+            mutual_steps<UNIT, true, R == 1 ? 4 : 16>(m, e, jid, a, c, rn);
+            flush_i();
+            pairs += c;
+            steps += R == 1 ? 4 : 16;
+            rare += rn;
+        }
+    }
+
+    __device__ __forceinline__ void screen_chunk() {
+        if (fill == 0) return;
+        // lanes past `fill` read a record at most 63 past the end of the last
+        // run, inside the padded sorted array, and keep nothing
+        const double4 p = load_rec(a.sp + (jj + lane));
+        const double px = p.x + shx, py = p.y + shy, pz = p.z + shz;
+        const double gx = fmax(0.0, fmax(lo[0] - px, px - hi[0]));
+        const double gy = fmax(0.0, fmax(lo[1] - py, py - hi[1]));
+        const double gz = fmax(0.0, fmax(lo[2] - pz, pz - hi[2]));
+        const bool keep = (gx * gx + gy * gy + gz * gz < a.g.cull2) & (lane < fill);
+        const unsigned long long mk = ballot64(keep);
+        const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
+        if (keep) {
+            const int q = (head + n_list + off) & (kRing - 1);
+            lpos[q] = make_float4((float)(px - cx), (float)(py - cy), (float)(pz - cz),
+                                  UNIT ? 0.f : mu_f32(p.w));
+            lidx[q] = (jj + lane) | (code << kIdxBits);
+        }
+        n_list += __builtin_popcountll(mk);
+        fill = 0;
+        // n_list < EB before the chunk, so the ring never holds more than
+        // EB + 63 <= kRing - 1 entries
+        while (n_list >= EB) {
+            block(EB);
+            head = (head + EB) & (kRing - 1);
+            n_list -= EB;
+        }
+    }
+    __device__ __forceinline__ static double4 load_rec(const double4 *r) {
+        if constexpr (UNIT) {
+            const double2 xy = *reinterpret_cast<const double2 *>(r);
+            return make_double4(xy.x, xy.y, r->z, 0.0);
+        } else {
+            return *r;
+        }
+    }
+    __device__ __forceinline__ void tile(int t, int img, bool, double x, double y, double z) {
+        own = t == 13;
+        if (img != code) {
+            screen_chunk();   // the open chunk was loaded with the previous image
+            code = img;
+            shx = x;
+            shy = y;
+            shz = z;
+        }
+    }
+    __device__ __forceinline__ void run(int j0, int j1) {
+        j0 = __builtin_amdgcn_readfirstlane(j0);
+        j1 = __builtin_amdgcn_readfirstlane(j1);
+        if (own) j0 = max(j0, own_from);
+        if (j0 >= j1) return;
+        screened += (unsigned long long)(j1 - j0);
+        while (j0 < j1) {
+            if (lane >= fill) jj = j0 - fill;
+            const int take = min(j1 - j0, kWave - fill);
+            j0 += take;
+            fill += take;
+            if (fill == kWave) screen_chunk();
+        }
+    }
+    __device__ __forceinline__ void finish() {
+        screen_chunk();
+        if (n_list > 0) {
+            block(n_list);
+            head = (head + n_list) & (kRing - 1);
+            n_list = 0;
+        }
+    }
+};
+
+// The persistent kernel of the mutual evaluation: clusters of 16 R receivers,
+// one work item per wave, every particle a receiver.  a.out: three FP64
+// arrays of a.out_stride (= n) values in sorted order, zeroed before the
+// launch.
+template <int R, bool UNIT>
+__global__ __launch_bounds__(kForceBlock) void k_pairs_mutual(PairArgs a) {
+    constexpr int NW = kForceBlock / kWave;
+    __shared__ float4 ring_pos[NW][kRing];
+    __shared__ int ring_idx[NW][kRing];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    const int row = lane >> 4, l = lane & 15;
+    ItemCursor cursor;
+    unsigned long long pairs = 0, steps = 0, screened = 0, rare = 0;
+    for (int it = next_item(a, lane, cursor); it >= 0; it = next_item(a, lane, cursor)) {
+        const Item item = a.items[it];
+        const Cluster cl = a.clusters[item.cluster];
+        const int cnt = __builtin_amdgcn_readfirstlane(cl.count);
+        const int begin = __builtin_amdgcn_readfirstlane(cl.begin);
+        const double cx = 0.5 * (cl.lo[0] + cl.hi[0]);
+        const double cy = 0.5 * (cl.lo[1] + cl.hi[1]);
+        const double cz = 0.5 * (cl.lo[2] + cl.hi[2]);
+        MutualLane m;
+        const int idx = 16 * (row % R) + l;
+        const bool live = idx < cnt;
+        m.i_sorted = begin + (live ? idx : 0);
+        const double4 xp = a.sp[m.i_sorted];
+        m.hx = live ? (float)(xp.x - cx) : 1.0e30f;
+        m.hy = live ? (float)(xp.y - cy) : 1.0e30f;
+        m.hz = live ? (float)(xp.z - cz) : 1.0e30f;
+        m.mu = mu_f32(xp.w);
+        // separations below a tenth of the receiver's offset are recomputed
+        // in FP64 (and r^2 == 0, since ki is at least the smallest normal)
+        m.ki = fmaxf(0.01f * fmaf(m.hz, m.hz, fmaf(m.hy, m.hy, m.hx * m.hx)), 1.1754944e-38f);
+        if (!live) m.ki = 0.f;
+        MutualVisit<R, UNIT> v{a, m, ring_pos[w], ring_idx[w], cl.lo, cl.hi, cx, cy, cz, lane,
+                               begin + cnt};
+        if (item.sole & kItemFirst) v.self_pass(cnt, begin);
+        walk_item(v, item, cl, a, lane);
+        // the copies of a receiver in the rows r, r + R, ...
+        double ax = v.ax, ay = v.ay, az = v.az;
+        if constexpr (R <= 2) {
+            ax += __shfl_xor(ax, 32, kWave);
+            ay += __shfl_xor(ay, 32, kWave);
+            az += __shfl_xor(az, 32, kWave);
+        }
+        if constexpr (R == 1) {
+            ax += __shfl_xor(ax, 16, kWave);
+            ay += __shfl_xor(ay, 16, kWave);
+            az += __shfl_xor(az, 16, kWave);
+        }
+        if (row < R && live) {
+            atomicAdd(a.out + m.i_sorted, ax);
+            atomicAdd(a.out + a.out_stride + m.i_sorted, ay);
+            atomicAdd(a.out + 2 * a.out_stride + m.i_sorted, az);
+        }
+        pairs += v.pairs;
+        steps += v.steps;
+        screened += v.screened;
+        rare += v.rare;
+    }
+    if (lane == 0 && a.counters) {
+        atomicAdd(&a.counters->interactions, pairs);
+        atomicAdd(&a.counters->steps, steps);
+        atomicAdd(&a.counters->screened, screened);
+        atomicAdd(&a.counters->rare, rare);
+    }
+}
+
+// acc_out[3 perm[p] + c] = sums[c n + p]
+__global__ void k_mutual_out(const double *__restrict__ sums, const int *__restrict__ perm, int n,
+                             double *__restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const size_t o = 3 * (size_t)perm[p];
+    out[o] = sums[p];
+    out[o + 1] = sums[(size_t)n + p];
+    out[o + 2] = sums[2 * (size_t)n + p];
+}
+
+using MutualFn = void (*)(PairArgs);
+
+MutualFn mutual_kernel(int csize, bool unit) {
+    switch (csize) {
+    case 16: return unit ? k_pairs_mutual<1, true> : k_pairs_mutual<1, false>;
+    case 32: return unit ? k_pairs_mutual<2, true> : k_pairs_mutual<2, false>;
+    case 64: return unit ? k_pairs_mutual<4, true> : k_pairs_mutual<4, false>;
+    default: return nullptr;
     }
 }
 
@@ -985,6 +1428,30 @@ hipError_t launch_pairs(int mode, int screen, int tab, const PairArgs &a, int gr
     const PairsFn fn = pairs_kernel(mode, screen, tab, a.csize, unit, soft);
     if (!fn) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kForceBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs_mutual(const PairArgs &a, int grid, hipStream_t s) {
+    if (a.n_items <= 0) return hipSuccess;
+    const MutualFn fn = mutual_kernel(a.csize, a.unit_mass != 0);
+    if (!fn) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kForceBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+int mutual_blocks_per_cu(int csize, int unit_mass) {
+    const MutualFn fn = mutual_kernel(csize, unit_mass != 0);
+    int nb = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kForceBlock, 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_mutual_out(const double *sums, const int *perm, int n, double *out,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mutual_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, sums,
+                       perm, n, out);
     return hipGetLastError();
 }
 

@@ -80,15 +80,19 @@ struct Item {
     int cluster;
     int tiles;    // t0 | t1 << 8
     int subs;     // s0 | s1 << 16
-    int sole;     // 1: the only item of its cluster (its sums are stored, not added)
+    int sole;     // kItemSole: the only item of its cluster (its sums are stored, not
+                  // added); kItemFirst: the cluster's first item
 };
+constexpr int kItemSole = 1;
+constexpr int kItemFirst = 2;
 
 struct Counters {
     unsigned long long interactions;
     unsigned long long candidates;
     unsigned long long steps;        // wave steps over suppliers
     unsigned long long screened;     // supplier records tested against cluster boxes
-    unsigned long long pad[4];
+    unsigned long long rare;         // mutual kernel: wave steps that took the FP64 path
+    unsigned long long pad[3];
 };
 
 enum SelKind { SEL_ALL = 0, SEL_MASK = 1, SEL_RUNG = 2 };
@@ -163,12 +167,14 @@ hipError_t launch_cluster_count(const int *cell_start, const int *scan, int n, i
 hipError_t launch_cluster_write(const int *cell_start, const int *scan, const int *cl_off,
                                 int n, int n_sub, const Geom &g, int csize, Cluster *clusters,
                                 hipStream_t s);
+// half != 0: items over the upper half of the neighbour stencil only, for
+// the pair kernel that evaluates each pair once for both partners
 hipError_t launch_item_count(const Cluster *clusters, const int *n_clusters_dev,
                              int cluster_bound, const int *cell_start, const Geom &g,
-                             int target, int *item_cnt, hipStream_t s);
+                             int target, int half, int *item_cnt, hipStream_t s);
 hipError_t launch_item_write(const Cluster *clusters, int n_clusters, const int *cell_start,
-                             const Geom &g, int target, const int *item_off, Item *items,
-                             hipStream_t s);
+                             const Geom &g, int target, int half, const int *item_off,
+                             Item *items, hipStream_t s);
 hipError_t launch_gather_weights(const double *grad_acc, const uint8_t *sel_s, const int *perm,
                                  int n, int fp32, double4 *wa, hipStream_t s);
 // per cluster: receivers copied to rp / rperm / rwa (indexed like act_pos;
@@ -219,6 +225,8 @@ struct PairArgs {
     const float *htab;       // NGP: tab_n values; linear: tab_n (value, slope) pairs
     float tab_scale;         // table entries per unit of r^2: tab_n / r_cut^2
     int tab_n;
+    // mutual kernel: FP32 r^2 in [rc2_lo, rc2_hi) is tested again in FP64
+    float rc2_lo, rc2_hi;
     Geom g;
 };
 
@@ -267,6 +275,14 @@ hipError_t launch_pm_readout(const double4 *rec, const int *nkey, const int *per
                              double *acc, hipStream_t s);
 // pair-kernel workgroups resident per CU for the variant launch_pairs would run
 int pairs_blocks_per_cu(int mode, int screen, int tab, int csize, int unit_mass, int soft);
+// All-active FP32 forward with each pair evaluated once for both partners
+// (clusters of csize = 16, 32 or 64 receivers, items over the upper half of
+// the stencil).  a.out: three FP64 arrays of a.out_stride = n sums in sorted
+// order, zeroed before the launch; launch_mutual_out then writes acc_out.
+hipError_t launch_pairs_mutual(const PairArgs &a, int grid, hipStream_t s);
+int mutual_blocks_per_cu(int csize, int unit_mass);
+hipError_t launch_mutual_out(const double *sums, const int *perm, int n, double *out,
+                             hipStream_t s);
 
 // KDK step (kdk.hip).  Times in units of tau / 2, tau = dt / 2^L.
 struct KdkArgs {

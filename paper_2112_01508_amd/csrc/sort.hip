@@ -426,23 +426,32 @@ __device__ inline int neighbour_tile(int tile, int t, const Geom &g) {
 // supplier candidates (before subtile culling); a tile holding more than
 // `target` particles is split by subtile ranges.  Returns the item count and
 // writes the items when `out` is non-null.
+//
+// half != 0 (pairs evaluated once, for both partners): only the upper half
+// of the stencil, t = 13 .. 26, whose periodic mirror images are the lower
+// half; in the own tile (t = 13) only the particles after the cluster count,
+// and every cluster gets at least one item, so that its own pairs are
+// evaluated.  The first item of a cluster carries kItemFirst.
 __device__ int plan_items(int cidx, const Cluster &cl, const int *__restrict__ cs, const Geom &g,
-                          int target, Item *out, int sole = 0) {
-    int n = 0, acc = 0, t0 = 0;
+                          int target, Item *out, int sole, int half) {
+    int n = 0, acc = 0;
+    const int t_begin = half ? 13 : 0;
+    int t0 = t_begin;
     auto emit = [&](int a, int b, int s0, int s1) {
         if (out) {
             Item it;
             it.cluster = cidx;
             it.tiles = a | (b << 8);
             it.subs = s0 | (s1 << 16);
-            it.sole = sole;
+            it.sole = sole | (n == 0 ? kItemFirst : 0);
             out[n] = it;
         }
         ++n;
     };
-    for (int t = 0; t < 27; ++t) {
+    for (int t = t_begin; t < 27; ++t) {
         int nb = neighbour_tile(cl.tile, t, g);
         int w = cs[(size_t)(nb + 1) * g.ns3] - cs[(size_t)nb * g.ns3];
+        if (half && t == 13) w = cs[(size_t)(nb + 1) * g.ns3] - (cl.begin + cl.count);
         if (w > target) {
             if (acc > 0) emit(t0, t, 0, g.ns3);
             int parts = min((w + target - 1) / target, g.ns3);
@@ -460,24 +469,25 @@ __device__ int plan_items(int cidx, const Cluster &cl, const int *__restrict__ c
         }
     }
     if (acc > 0) emit(t0, 27, 0, g.ns3);
+    if (half && n == 0) emit(13, 14, 0, g.ns3);
     return n;
 }
 
 __global__ void k_item_count(const Cluster *__restrict__ clusters, const int *__restrict__ n_cl,
-                             int bound, const int *__restrict__ cs, Geom g, int target,
+                             int bound, const int *__restrict__ cs, Geom g, int target, int half,
                              int *__restrict__ item_cnt) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= bound) return;
-    item_cnt[c] = c < *n_cl ? plan_items(c, clusters[c], cs, g, target, nullptr) : 0;
+    item_cnt[c] = c < *n_cl ? plan_items(c, clusters[c], cs, g, target, nullptr, 0, half) : 0;
 }
 
 __global__ void k_item_write(const Cluster *__restrict__ clusters, int n_clusters,
-                             const int *__restrict__ cs, Geom g, int target,
+                             const int *__restrict__ cs, Geom g, int target, int half,
                              const int *__restrict__ item_off, Item *__restrict__ items) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_clusters) return;
     plan_items(c, clusters[c], cs, g, target, items + item_off[c],
-               item_off[c + 1] - item_off[c] == 1 ? 1 : 0);
+               item_off[c + 1] - item_off[c] == 1 ? kItemSole : 0, half);
 }
 
 __global__ void k_gather_weights(const double *__restrict__ w, const uint8_t *__restrict__ sel_s,
@@ -717,20 +727,20 @@ hipError_t launch_cluster_write(const int *cs, const int *scan, const int *cl_of
 }
 
 hipError_t launch_item_count(const Cluster *clusters, const int *n_clusters_dev, int bound,
-                             const int *cs, const Geom &g, int target, int *item_cnt,
+                             const int *cs, const Geom &g, int target, int half, int *item_cnt,
                              hipStream_t s) {
     if (bound == 0) return hipSuccess;
     hipLaunchKernelGGL(k_item_count, dim3(grid_for(bound, 128)), dim3(128), 0, s, clusters,
-                       n_clusters_dev, bound, cs, g, target, item_cnt);
+                       n_clusters_dev, bound, cs, g, target, half, item_cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_item_write(const Cluster *clusters, int n_clusters, const int *cs,
-                             const Geom &g, int target, const int *item_off, Item *items,
-                             hipStream_t s) {
+                             const Geom &g, int target, int half, const int *item_off,
+                             Item *items, hipStream_t s) {
     if (n_clusters == 0) return hipSuccess;
     hipLaunchKernelGGL(k_item_write, dim3(grid_for(n_clusters, 128)), dim3(128), 0, s, clusters,
-                       n_clusters, cs, g, target, item_off, items);
+                       n_clusters, cs, g, target, half, item_off, items);
     return hipGetLastError();
 }
 
