@@ -66,6 +66,16 @@ struct TuneKey {
         return std::tie(n, nt, precision, mode) < std::tie(o.n, o.nt, o.precision, o.mode);
     }
 };
+// Device buffers of one short-range call.  base != nullptr: every buffer is
+// a slice of [base, base + size), handed out anew at each call (nothing is
+// freed or allocated); else each buffer grows with hipMalloc.
+struct SrWork {
+    DevBuf key, rank, cells, sp, perm, sel, sp2, perm2, sel2, flags, actpos, ncl, clusters,
+        itemcnt, items, bsum, counters, wa, scal, rp, rperm, rwa, fbig, msum, htab;
+    unsigned char *base = nullptr;
+    size_t size = 0, used = 0;
+};
+
 struct TuneVal {
     int ns;
     int target;
@@ -82,11 +92,12 @@ struct p3m_sr_context {
     // shape, unit mass, softening
     int blocks_per_cu[4 * 2 * 4 * 3 * 4] = {};
     int mutual_blocks_per_cu[4 * 2] = {};   // by cluster size and unit mass
-    DevBuf key, rank, cells, sp, perm, sel, sp2, perm2, sel2, flags, actpos, ncl, clusters,
-        itemcnt, items, bsum, counters, wa, scal, rp, rperm, rwa, fbig, msum;
+    // short-range workspace: grown with hipMalloc as calls need it, or (the
+    // no-alloc entry point) carved from the library's fixed device array
+    SrWork work, fixed;
+    Counters *last_counters = nullptr;   // counters of the most recent call
     int cfg_ns = 0, cfg_target = 0, cfg_csize = 0, cfg_screen = -1;
     int cfg_shape = SHAPE_POLY, cfg_tab_n = 0;   // FP32 forward shape (p3m_sr_set_shape)
-    DevBuf htab;
     double eps = 0.0;   // Plummer-equivalent softening length (0: point particles)
     std::map<TuneKey, TuneVal> tuned;
     p3m_sr_stats stats{};
@@ -137,6 +148,22 @@ int ensure(p3m_sr_context *h, DevBuf &b, size_t bytes, hipStream_t s) {
         want = bytes;
     }
     b.cap = want;
+    return P3M_OK;
+}
+
+// A buffer of the call's workspace set: a fresh 256-byte aligned slice of
+// the fixed region, or a grown allocation.
+int take(p3m_sr_context *h, SrWork &w, DevBuf &b, size_t bytes, hipStream_t s) {
+    if (!w.base) return ensure(h, b, bytes, s);
+    if (bytes == 0) bytes = 16;
+    const size_t need = (bytes + 255) & ~(size_t)255;
+    if (w.used + need > w.size)
+        return set_error(P3M_EUNSUPPORTED,
+                         "the call needs more than the %zu bytes of the no-alloc workspace",
+                         w.size);
+    b.p = w.base + w.used;
+    b.cap = bytes;
+    w.used += need;
     return P3M_OK;
 }
 
@@ -254,7 +281,7 @@ bool valid_csize(int c) { return c == 8 || c == 16 || c == 32 || c == 64; }
 // eq. bspline_force: eps_B = 2.8 eps).
 constexpr double kBsplinePerPlummer = 2.8;
 
-int run(p3m_sr_context *h, const Request &r) {
+int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     hipStream_t s = r.stream;
     const int n = (int)r.n;
     const bool fp32 = r.precision == P3M_FP32;
@@ -311,11 +338,7 @@ int run(p3m_sr_context *h, const Request &r) {
     st.ms_build = st.ms_pairs = st.ms_total = -1.0f;
     h->last_stream = s;
     h->timed_last = false;
-    if (h->timing) {
-        for (int k = 0; k < 4; ++k)
-            if (!h->ev[k]) P3M_HIP(hipEventCreate(&h->ev[k]));
-        P3M_HIP(hipEventRecord(h->ev[0], s));
-    }
+    if (h->timing) P3M_HIP(hipEventRecord(h->ev[0], s));
 
     const size_t out_elems = (size_t)n_sub * (size_t)n * 3;
     if (n == 0) {
@@ -323,50 +346,55 @@ int run(p3m_sr_context *h, const Request &r) {
         return P3M_OK;
     }
 
-    // ---- workspace ----
+    // ---- workspace (every buffer is taken before the first launch, apart
+    // from the work items, whose count the device reports) ----
+    w.used = 0;
     const size_t nflags = (size_t)n * n_sub;
     const size_t ncl_len = (size_t)n_sub * g.nt3;
     const size_t cl_bound = ncl_len + (nflags + csize - 1) / csize;
     const size_t scan_max = std::max(std::max(ncells, nflags), std::max(ncl_len, cl_bound));
     int rc;
-    if ((rc = ensure(h, h->key, sizeof(int) * n, s))) return rc;
-    if ((rc = ensure(h, h->rank, sizeof(int) * n, s))) return rc;
-    if ((rc = ensure(h, h->cells, sizeof(int) * (ncells + 1), s))) return rc;
-    if ((rc = ensure(h, h->fbig, sizeof(int) * (2 + (size_t)n / kFineBig), s))) return rc;
-    if ((rc = ensure(h, h->sp, sizeof(double4) * ((size_t)n + kSupplierPad), s))) return rc;
-    if ((rc = ensure(h, h->perm, sizeof(int) * n, s))) return rc;
-    if ((rc = ensure(h, h->sel, (size_t)n, s))) return rc;
-    if ((rc = ensure(h, h->sp2, sizeof(double4) * ((size_t)n + kSupplierPad), s))) return rc;
-    if ((rc = ensure(h, h->perm2, sizeof(int) * n, s))) return rc;
-    if ((rc = ensure(h, h->sel2, (size_t)n, s))) return rc;
-    if ((rc = ensure(h, h->flags, sizeof(int) * (nflags + 1), s))) return rc;
-    if ((rc = ensure(h, h->actpos, sizeof(int) * (nflags + 1), s))) return rc;
-    if ((rc = ensure(h, h->ncl, sizeof(int) * (ncl_len + 1), s))) return rc;
-    if ((rc = ensure(h, h->clusters, sizeof(Cluster) * cl_bound, s))) return rc;
-    if ((rc = ensure(h, h->itemcnt, sizeof(int) * (cl_bound + 1), s))) return rc;
-    if ((rc = ensure(h, h->bsum, sizeof(int) * scan_block_sums_needed(scan_max), s))) return rc;
-    if ((rc = ensure(h, h->counters, sizeof(Counters), s))) return rc;
-    if ((rc = ensure(h, h->scal, sizeof(int) * (16 + kXcds), s))) return rc;
-    if ((rc = ensure(h, h->rp, sizeof(double4) * (nflags + 1), s))) return rc;
-    if ((rc = ensure(h, h->rperm, sizeof(int) * (nflags + 1), s))) return rc;
-    if (r.backward && (rc = ensure(h, h->rwa, sizeof(double4) * (nflags + 1), s))) return rc;
-    if (r.backward && (rc = ensure(h, h->wa, sizeof(double4) * ((size_t)n + kSupplierPad), s))) return rc;
-    if (mutual && (rc = ensure(h, h->msum, sizeof(double) * 3 * (size_t)n, s))) return rc;
+    if ((rc = take(h, w, w.key, sizeof(int) * n, s))) return rc;
+    if ((rc = take(h, w, w.rank, sizeof(int) * n, s))) return rc;
+    if ((rc = take(h, w, w.cells, sizeof(int) * (ncells + 1), s))) return rc;
+    if ((rc = take(h, w, w.fbig, sizeof(int) * (2 + (size_t)n / kFineBig), s))) return rc;
+    if ((rc = take(h, w, w.sp, sizeof(double4) * ((size_t)n + kSupplierPad), s))) return rc;
+    if ((rc = take(h, w, w.perm, sizeof(int) * n, s))) return rc;
+    if ((rc = take(h, w, w.sel, (size_t)n, s))) return rc;
+    if ((rc = take(h, w, w.sp2, sizeof(double4) * ((size_t)n + kSupplierPad), s))) return rc;
+    if ((rc = take(h, w, w.perm2, sizeof(int) * n, s))) return rc;
+    if ((rc = take(h, w, w.sel2, (size_t)n, s))) return rc;
+    if ((rc = take(h, w, w.flags, sizeof(int) * (nflags + 1), s))) return rc;
+    if ((rc = take(h, w, w.actpos, sizeof(int) * (nflags + 1), s))) return rc;
+    if ((rc = take(h, w, w.ncl, sizeof(int) * (ncl_len + 1), s))) return rc;
+    if ((rc = take(h, w, w.clusters, sizeof(Cluster) * cl_bound, s))) return rc;
+    if ((rc = take(h, w, w.itemcnt, sizeof(int) * (cl_bound + 1), s))) return rc;
+    if ((rc = take(h, w, w.bsum, sizeof(int) * scan_block_sums_needed(scan_max), s))) return rc;
+    if ((rc = take(h, w, w.counters, sizeof(Counters), s))) return rc;
+    if ((rc = take(h, w, w.scal, sizeof(int) * (16 + kXcds), s))) return rc;
+    if ((rc = take(h, w, w.rp, sizeof(double4) * (nflags + 1), s))) return rc;
+    if ((rc = take(h, w, w.rperm, sizeof(int) * (nflags + 1), s))) return rc;
+    if (r.backward && (rc = take(h, w, w.rwa, sizeof(double4) * (nflags + 1), s))) return rc;
+    if (r.backward && (rc = take(h, w, w.wa, sizeof(double4) * ((size_t)n + kSupplierPad), s))) return rc;
+    if (mutual && (rc = take(h, w, w.msum, sizeof(double) * 3 * (size_t)n, s))) return rc;
+    if (shape != SHAPE_POLY && (rc = take(h, w, w.htab, kTabFloats * sizeof(float), s)))
+        return rc;
 
-    int *key = (int *)h->key.p, *rank = (int *)h->rank.p, *cells = (int *)h->cells.p;
-    double4 *sp = (double4 *)h->sp.p;
-    int *perm = (int *)h->perm.p;
-    uint8_t *sel_s = (uint8_t *)h->sel.p;
-    int *flags = (int *)h->flags.p, *actpos = (int *)h->actpos.p, *ncl = (int *)h->ncl.p;
-    Cluster *clusters = (Cluster *)h->clusters.p;
-    int *itemcnt = (int *)h->itemcnt.p, *bsum = (int *)h->bsum.p;
-    Counters *counters = (Counters *)h->counters.p;
-    int *scal = (int *)h->scal.p;   // [16 ..] the XCD work queues
+    int *key = (int *)w.key.p, *rank = (int *)w.rank.p, *cells = (int *)w.cells.p;
+    double4 *sp = (double4 *)w.sp.p;
+    int *perm = (int *)w.perm.p;
+    uint8_t *sel_s = (uint8_t *)w.sel.p;
+    int *flags = (int *)w.flags.p, *actpos = (int *)w.actpos.p, *ncl = (int *)w.ncl.p;
+    Cluster *clusters = (Cluster *)w.clusters.p;
+    int *itemcnt = (int *)w.itemcnt.p, *bsum = (int *)w.bsum.p;
+    Counters *counters = (Counters *)w.counters.p;
+    h->last_counters = counters;
+    int *scal = (int *)w.scal.p;   // [16 ..] the XCD work queues
 
     // ---- sort ----
-    int *fbig = (int *)h->fbig.p;
+    int *fbig = (int *)w.fbig.p;
     int *queue = scal + 16;
-    double4 *sp_f = (double4 *)h->sp2.p;   // the sorted particles after the fine order
+    double4 *sp_f = (double4 *)w.sp2.p;   // the sorted particles after the fine order
     {
         // every small initialisation of the call in one launch
         FillSet f{};
@@ -382,8 +410,8 @@ int run(p3m_sr_context *h, const Request &r) {
     P3M_HIP(launch_scan(cells, cells, ncells, bsum, s));
     const uint8_t *sel_src = (r.sel_kind == SEL_ALL && !r.backward) ? nullptr : r.sel;
     {
-        int *perm_f = (int *)h->perm2.p;
-        uint8_t *sel_f = (uint8_t *)h->sel2.p;
+        int *perm_f = (int *)w.perm2.p;
+        uint8_t *sel_f = (uint8_t *)w.sel2.p;
         P3M_HIP(launch_scatter(r.pos, r.mass, sel_src, n, g, key, rank, cells, fp32 ? 1 : 0,
                                csize, sp, perm, sel_s, sp_f, perm_f, sel_f, s));
         // fine order inside dense subtiles (key/rank are free again as scratch)
@@ -414,47 +442,44 @@ int run(p3m_sr_context *h, const Request &r) {
                               mutual ? 1 : 0, itemcnt, s));
     P3M_HIP(launch_scan(itemcnt, itemcnt, cl_bound, bsum, s));
     P3M_HIP(launch_totals(flags + nflags, ncl + ncl_len, itemcnt + cl_bound, h->host_tot, s));
-    if (!h->tot_ev) P3M_HIP(hipEventCreateWithFlags(&h->tot_ev, hipEventDisableTiming));
     P3M_HIP(hipEventRecord(h->tot_ev, s));
 
     // work that needs no totals runs while the host waits for them
-    double4 *wa = r.backward ? (double4 *)h->wa.p : nullptr;
+    double4 *wa = r.backward ? (double4 *)w.wa.p : nullptr;
     if (r.backward) P3M_HIP(launch_gather_weights(r.grad_acc, sel_s, perm, n, fp32, wa, s));
     // with every particle a receiver the receivers are sp / perm / wa as they are
-    double4 *rp = all_recv ? nullptr : (double4 *)h->rp.p;
+    double4 *rp = all_recv ? nullptr : (double4 *)w.rp.p;
     P3M_HIP(launch_cluster_finish(clusters, ncl + ncl_len, cl_bound, csize, recv_pos, sp, perm, wa,
-                                  rp, (int *)h->rperm.p,
-                                  r.backward ? (double4 *)h->rwa.p : nullptr, s));
+                                  rp, (int *)w.rperm.p,
+                                  r.backward ? (double4 *)w.rwa.p : nullptr, s));
     // the mutual kernel adds into its sorted-order sums, then writes acc_out
-    if (mutual) P3M_HIP(launch_fill_f64((double *)h->msum.p, 0.0, 3 * (size_t)n, s));
+    if (mutual) P3M_HIP(launch_fill_f64((double *)w.msum.p, 0.0, 3 * (size_t)n, s));
     else P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, s));
-    if (shape != SHAPE_POLY) {
-        if ((rc = ensure(h, h->htab, kTabFloats * sizeof(float), s))) return rc;
-        P3M_HIP(launch_build_htab(shape, h->cfg_tab_n, g, (float *)h->htab.p, s));
-    }
+    if (shape != SHAPE_POLY)
+        P3M_HIP(launch_build_htab(shape, h->cfg_tab_n, g, (float *)w.htab.p, s));
     P3M_HIP(hipEventSynchronize(h->tot_ev));
     const int n_recv = h->host_tot[0], n_clusters = h->host_tot[1], n_items = h->host_tot[2];
     st.receivers = n_recv;
     st.clusters = n_clusters;
     st.items = n_items;
 
-    if ((rc = ensure(h, h->items, sizeof(Item) * (size_t)(n_items > 0 ? n_items : 1), s)))
+    if ((rc = take(h, w, w.items, sizeof(Item) * (size_t)(n_items > 0 ? n_items : 1), s)))
         return rc;
-    Item *items = (Item *)h->items.p;
+    Item *items = (Item *)w.items.p;
     P3M_HIP(launch_item_write(clusters, n_clusters, cells, g, target, mutual ? 1 : 0, itemcnt,
                               items, s));
 
     // ---- pairs ----
     PairArgs a{};
     a.sp = sp;
-    a.rp = all_recv ? sp : (const double4 *)h->rp.p;
-    a.rwa = all_recv ? wa : (const double4 *)h->rwa.p;
+    a.rp = all_recv ? sp : (const double4 *)w.rp.p;
+    a.rwa = all_recv ? wa : (const double4 *)w.rwa.p;
     a.cell_start = cells;
     a.clusters = clusters;
     a.items = items;
     a.wa = wa;
     a.queue = queue;
-    a.rperm = all_recv ? perm : (const int *)h->rperm.p;
+    a.rperm = all_recv ? perm : (const int *)w.rperm.p;
     a.out = r.out;
     a.out_stride = 3ll * n;
     a.counters = counters;
@@ -463,7 +488,7 @@ int run(p3m_sr_context *h, const Request &r) {
     a.csize = csize;
     a.g = g;
     if (shape != SHAPE_POLY) {
-        a.htab = (const float *)h->htab.p;
+        a.htab = (const float *)w.htab.p;
         a.tab_n = h->cfg_tab_n;
         a.tab_scale = (float)((double)h->cfg_tab_n / g.rc2);
     }
@@ -475,7 +500,7 @@ int run(p3m_sr_context *h, const Request &r) {
         int &slot_m = h->mutual_blocks_per_cu[cs_idx * 2 + unit];
         if (slot_m == 0) slot_m = mutual_blocks_per_cu(csize, unit);
         bpc = slot_m;
-        a.out = (double *)h->msum.p;
+        a.out = (double *)w.msum.p;
         a.out_stride = n;
         a.rc2_lo = (float)(g.rc2 * (1.0 - std::ldexp(1.0, -17)));
         a.rc2_hi = (float)(g.rc2 * (1.0 + std::ldexp(1.0, -17)));
@@ -494,7 +519,7 @@ int run(p3m_sr_context *h, const Request &r) {
     if (h->timing) P3M_HIP(hipEventRecord(h->ev[1], s));
     if (mutual) P3M_HIP(launch_pairs_mutual(a, (int)grid, s));
     else P3M_HIP(launch_pairs(mode, screen, shape, a, (int)grid, s));
-    if (mutual) P3M_HIP(launch_mutual_out((const double *)h->msum.p, perm, n, r.out, s));
+    if (mutual) P3M_HIP(launch_mutual_out((const double *)w.msum.p, perm, n, r.out, s));
     if (h->timing) {
         P3M_HIP(hipEventRecord(h->ev[2], s));
         h->timed_last = true;
@@ -611,6 +636,14 @@ int p3m_sr_create(p3m_sr_handle *out, int device) {
             hipSuccess ||
         h->n_cu <= 0)
         h->n_cu = 256;
+    // the events every call may record (timing, the totals' arrival)
+    bool ev_ok = hipEventCreateWithFlags(&h->tot_ev, hipEventDisableTiming) == hipSuccess;
+    for (hipEvent_t &e : h->ev) ev_ok = ev_ok && hipEventCreate(&e) == hipSuccess;
+    if (!ev_ok) {
+        (void)hipGetLastError();
+        p3m_sr_destroy(h);
+        return set_error(P3M_EHIP, "events could not be created");
+    }
     *out = h;
     return P3M_OK;
 }
@@ -619,16 +652,16 @@ int p3m_sr_destroy(p3m_sr_handle h) {
     if (!h) return P3M_OK;
     (void)hipSetDevice(h->device);
     (void)hipDeviceSynchronize();
-    DevBuf *bufs[] = {&h->key,     &h->rank,     &h->cells,  &h->sp,    &h->perm,
-                      &h->sel,     &h->sp2,      &h->perm2,  &h->sel2,  &h->flags,
-                      &h->actpos,  &h->ncl,      &h->clusters, &h->itemcnt, &h->items,
-                      &h->bsum,    &h->counters, &h->wa,     &h->scal,
-                      &h->rp,      &h->rperm,    &h->rwa,    &h->fbig,
-                      &h->pm_real, &h->pm_spec,  &h->pm_tab, &h->pm_key,  &h->pm_rank,
-                      &h->pm_cnt,  &h->pm_rec,   &h->pm_nkey, &h->pm_perm, &h->pm_recv,
-                      &h->kdk_acc, &h->kdk_lr,   &h->kdk_tq,  &h->kdk_tnext, &h->kdk_due,
-                      &h->kdk_scal, &h->htab,   &h->pm_bsum, &h->p3m_lr, &h->tune_w,
-                      &h->msum};
+    SrWork &w = h->work;
+    DevBuf *bufs[] = {&w.key,     &w.rank,     &w.cells,    &w.sp,      &w.perm,
+                      &w.sel,     &w.sp2,      &w.perm2,    &w.sel2,    &w.flags,
+                      &w.actpos,  &w.ncl,      &w.clusters, &w.itemcnt, &w.items,
+                      &w.bsum,    &w.counters, &w.wa,       &w.scal,    &w.rp,
+                      &w.rperm,   &w.rwa,      &w.fbig,     &w.msum,    &w.htab,
+                      &h->pm_real, &h->pm_spec, &h->pm_tab, &h->pm_key,  &h->pm_rank,
+                      &h->pm_cnt,  &h->pm_rec,  &h->pm_nkey, &h->pm_perm, &h->pm_recv,
+                      &h->kdk_acc, &h->kdk_lr,  &h->kdk_tq,  &h->kdk_tnext, &h->kdk_due,
+                      &h->kdk_scal, &h->pm_bsum, &h->p3m_lr, &h->tune_w};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : h->ev)
@@ -669,7 +702,7 @@ int p3m_sr_force(p3m_sr_handle h, const double *pos, const double *mass, const u
     r.precision = precision;
     r.out = acc_out;
     r.stream = (hipStream_t)stream;
-    return run(h, r);
+    return run(h, r, h->work);
 }
 
 int p3m_sr_force_backward(p3m_sr_handle h, const double *pos, const double *mass,
@@ -701,7 +734,7 @@ int p3m_sr_force_backward(p3m_sr_handle h, const double *pos, const double *mass
     r.grad_acc = grad_acc;
     r.out = grad_pos;
     r.stream = (hipStream_t)stream;
-    return run(h, r);
+    return run(h, r, h->work);
 }
 
 int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
@@ -736,7 +769,7 @@ int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
     r.precision = precision;
     r.out = acc_out;
     r.stream = (hipStream_t)stream;
-    return run(h, r);
+    return run(h, r, h->work);
 }
 
 int p3m_sr_set_config(p3m_sr_handle h, int subtiles_per_dim, int item_target, int cluster_size,
@@ -816,12 +849,12 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
         r.force_csize = v.csize;
         r.force_screen = v.screen + 1;
         int rc2;
-        if ((rc2 = run(h, r))) return rc2;   // warm-up (also grows the workspace)
+        if ((rc2 = run(h, r, h->work))) return rc2;   // warm-up (also grows the workspace)
         float tot = 0;
         const int reps = 3;
         for (int k = 0; k < reps; ++k) {
             P3M_HIP(hipEventRecord(e0, s));
-            if ((rc2 = run(h, r))) return rc2;
+            if ((rc2 = run(h, r, h->work))) return rc2;
             P3M_HIP(hipEventRecord(e1, s));
             P3M_HIP(hipEventSynchronize(e1));
             float ms = 0;
@@ -896,10 +929,10 @@ int p3m_sr_get_stats(p3m_sr_handle h, p3m_sr_stats *out) {
     if (!out) return set_error(P3M_EINVAL, "NULL stats pointer");
     if ((rc = set_device(h))) return rc;
     p3m_sr_stats st = h->stats;
-    if (h->counters.p && st.n > 0) {
+    if (h->last_counters && st.n > 0) {
         Counters c{};
         P3M_HIP(hipStreamSynchronize(h->last_stream));
-        P3M_HIP(hipMemcpy(&c, h->counters.p, sizeof(c), hipMemcpyDeviceToHost));
+        P3M_HIP(hipMemcpy(&c, h->last_counters, sizeof(c), hipMemcpyDeviceToHost));
         st.interactions = (int64_t)c.interactions;
         st.candidates = (int64_t)c.candidates;
         st.steps = (int64_t)c.steps;
@@ -1036,9 +1069,9 @@ int p3m_kdk_step(p3m_sr_handle h, double *pos, double *vel, const double *mass, 
     // short-range accelerations at the synchronised start: they set the rungs
     // (eq. rung, no momentum update) and drive the half kicks
     P3M_HIP(launch_fill_i32(scal, 0, 8, s));
-    if ((rc = run(h, r))) return rc;
+    if ((rc = run(h, r, h->work))) return rc;
     ++sr_calls;
-    if (np > 0) P3M_HIP(launch_kdk_accum((const Counters *)h->counters.p, pairs, s));
+    if (np > 0) P3M_HIP(launch_kdk_accum(h->last_counters, pairs, s));
     KdkArgs k{};
     k.dt = dt;
     k.two_eta_eps = 2.0 * eta * eps;
@@ -1074,9 +1107,9 @@ int p3m_kdk_step(p3m_sr_handle h, double *pos, double *vel, const double *mass, 
         if (n_due > 0) {
             r.sel = due;
             r.sel_kind = SEL_MASK;
-            if ((rc = run(h, r))) return rc;
+            if ((rc = run(h, r, h->work))) return rc;
             ++sr_calls;
-            P3M_HIP(launch_kdk_accum((const Counters *)h->counters.p, pairs, s));
+            P3M_HIP(launch_kdk_accum(h->last_counters, pairs, s));
             P3M_HIP(launch_kdk_kick(vel, acc, due, np, t, k, rung, t_q, t_next, s));
         }
         if (n_grid && t % span0 == 0) {
@@ -1157,7 +1190,7 @@ int p3m_force(p3m_sr_handle h, const double *pos, const double *mass, const uint
     r.precision = precision;
     r.out = acc_out;
     r.stream = s;
-    rc = run(h, r);
+    rc = run(h, r, h->work);
     // join before returning, also when the short range failed
     P3M_HIP(hipStreamWaitEvent(s, h->join_ev, 0));
     if (rc) return rc;
