@@ -157,6 +157,27 @@ int p3m_sr_force(p3m_sr_handle h, const double *pos, const double *mass,
                  int precision, double *acc_out, void *stream);
 
 /*
+ * p3m_sr_force for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation, arguments, layout choice and errors, with every
+ * workspace buffer carved from one fixed 64 MiB device array that the
+ * library holds on each GPU it runs on until the process ends; the call
+ * makes no hipMalloc, hipFree or other allocating call.
+ * Limits (EUNSUPPORTED, before any launch): n <= 2^18 particles, and the
+ * decomposition's buffers (about 150 bytes per particle plus 4 bytes per
+ * fine cell and 68 bytes per tile) must fit; if the work items the device
+ * plans for the call do not fit in the rest of the array, the call returns
+ * EUNSUPPORTED after its first kernels have run and acc_out is undefined.
+ * All calls on one GPU share the array: calls that overlap on one GPU (other
+ * streams, other threads, other handles) race and must be serialised by the
+ * caller.  Every part of the array a call reads is written or cleared by
+ * that call.
+ */
+int p3m_sr_force_noalloc(p3m_sr_handle h, const double *pos, const double *mass,
+                         const uint8_t *active, int64_t n, double box, double x_s,
+                         double r_cut, int precision, double *acc_out, void *stream);
+
+/*
  * Vector-Jacobian product of p3m_sr_force with respect to positions, for a
  * fixed pair set (the pairs with |r| < r_cut at these positions):
  *   grad_pos_k = sum_i (d acc_i / d x_k)^T grad_acc_i

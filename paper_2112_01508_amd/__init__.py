@@ -104,6 +104,7 @@ EXPORTS = {
     "p3m_lr_force": ([_P, _P, _P, _P, _I64, _D, _I, _D, _P, _P], _I),
     "p3m_lr_get_stats": ([_P, ctypes.POINTER(LrStats)], _I),
     "p3m_force": ([_P, _P, _P, _P, _I64, _D, _D, _D, _I, _I, _P, _P], _I),
+    "p3m_sr_force_noalloc": ([_P, _P, _P, _P, _I64, _D, _D, _D, _I, _P, _P], _I),
     "p3m_kdk_step": ([_P, _P, _P, _P, _P, _I64, _D, _D, _D, _I, _D, _I, _D, _D, _I, _I, _I, _P],
                      _I),
     "p3m_kdk_get_stats": ([_P, ctypes.POINTER(KdkStats)], _I),
@@ -218,6 +219,19 @@ class Context:
         _check(self._lib.p3m_sr_force(self._h, self._p(pos), self._p(mass), self._p(active), n,
                                       float(box), float(x_s), float(r_cut), _prec(precision),
                                       self._p(out), _stream_ptr(self.device)))
+        return out
+
+    def force_noalloc(self, pos, mass=None, active=None, *, box, x_s, r_cut, precision="fp32",
+                      out=None):
+        """p3m_sr_force_noalloc: the force with the library's fixed workspace
+        (no device allocation inside the call; n <= 2^18).  `out` (n x 3 FP64
+        on the device) is allocated here when not given."""
+        pos, mass, active, n = self._inputs(pos, mass, active, "active")
+        out = self._out(out, n)
+        _check(self._lib.p3m_sr_force_noalloc(self._h, self._p(pos), self._p(mass),
+                                              self._p(active), n, float(box), float(x_s),
+                                              float(r_cut), _prec(precision), self._p(out),
+                                              _stream_ptr(self.device)))
         return out
 
     def force_backward(self, pos, mass, active, grad_acc, *, box, x_s, r_cut, precision="fp32"):

@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -148,6 +149,46 @@ int ensure(p3m_sr_context *h, DevBuf &b, size_t bytes, hipStream_t s) {
         want = bytes;
     }
     b.cap = want;
+    return P3M_OK;
+}
+
+// ---- fixed workspace of p3m_sr_force_noalloc ---------------------------------
+//
+// One array per GPU the library runs on, held until the process ends.  Host
+// code never uses the array's name as an address: each device's address is
+// looked up once (with that device current) and kept in g_scratch_dev.
+// Every no-alloc call on a GPU uses the same array, so such calls must not
+// overlap on one GPU (they would race); every part of it a call reads is
+// written or cleared (by fill kernels) earlier in the same call.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+constexpr int64_t kNoAllocMaxN = (int64_t)1 << 18;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current.
+int scratch_address(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices)
+        return set_error(P3M_EUNSUPPORTED, "device %d is beyond the %d the library tracks", device,
+                         kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(P3M_EHIP, "hipGetSymbolAddress(scratch) failed: %s",
+                             hipGetErrorString(e));
+        g_scratch_dev[device] = p;
+    }
+    *out = g_scratch_dev[device];
     return P3M_OK;
 }
 
@@ -636,6 +677,17 @@ int p3m_sr_create(p3m_sr_handle *out, int device) {
             hipSuccess ||
         h->n_cu <= 0)
         h->n_cu = 256;
+    // the fixed workspace of the no-alloc entry point on this device
+    {
+        void *base = nullptr;
+        const int rc = scratch_address(device, &base);
+        if (rc) {
+            p3m_sr_destroy(h);
+            return rc;
+        }
+        h->fixed.base = (unsigned char *)base;
+        h->fixed.size = kNoAllocBytes;
+    }
     // the events every call may record (timing, the totals' arrival)
     bool ev_ok = hipEventCreateWithFlags(&h->tot_ev, hipEventDisableTiming) == hipSuccess;
     for (hipEvent_t &e : h->ev) ev_ok = ev_ok && hipEventCreate(&e) == hipSuccess;
@@ -703,6 +755,39 @@ int p3m_sr_force(p3m_sr_handle h, const double *pos, const double *mass, const u
     r.out = acc_out;
     r.stream = (hipStream_t)stream;
     return run(h, r, h->work);
+}
+
+int p3m_sr_force_noalloc(p3m_sr_handle h, const double *pos, const double *mass,
+                         const uint8_t *active, int64_t n, double box, double x_s, double r_cut,
+                         int precision, double *acc_out, void *stream) {
+    int rc;
+    if ((rc = check_geometry(n, box, x_s, r_cut))) return rc;
+    if (precision != P3M_FP32 && precision != P3M_FP64)
+        return set_error(P3M_EINVAL, "precision must be P3M_FP64 or P3M_FP32");
+    if (n > 0 && (!pos || !acc_out)) return set_error(P3M_EINVAL, "pos and acc_out are required");
+    if (!aligned8(pos) || !aligned8(acc_out) || !aligned8(mass))
+        return set_error(P3M_EINVAL, "pos, mass and acc_out must be 8-byte aligned");
+    if (n > kNoAllocMaxN)
+        return set_error(P3M_EUNSUPPORTED,
+                         "n = %lld exceeds the no-alloc limit of %lld particles", (long long)n,
+                         (long long)kNoAllocMaxN);
+    if ((rc = check_handle(h))) return rc;
+    if (!h->fixed.base) return set_error(P3M_EHIP, "the no-alloc workspace is not available");
+    if ((rc = set_device(h))) return rc;
+    Request r{};
+    r.pos = pos;
+    r.mass = mass;
+    r.sel = active;
+    r.sel_kind = active ? SEL_MASK : SEL_ALL;
+    r.n_sub = 1;
+    r.n = n;
+    r.box = box;
+    r.x_s = x_s;
+    r.r_cut = r_cut;
+    r.precision = precision;
+    r.out = acc_out;
+    r.stream = (hipStream_t)stream;
+    return run(h, r, h->fixed);
 }
 
 int p3m_sr_force_backward(p3m_sr_handle h, const double *pos, const double *mass,
