@@ -291,11 +291,11 @@ def kdk_leg(torch, ctx, pos, mass, wl, repeats=2):
     return res
 
 
-def batched_leg(torch, p3, name, steps, warmup, layouts=None):
-    """All 8 nested rung subsets (rung >= k, k = 0..7) in one persistent launch.
-    `layouts` maps precision to the (subtiles, item target, cluster size,
-    screen) the main workload's autotuner chose: tiles hold the same number
-    of particles at every configuration (the PM grid scales with N)."""
+def batched_leg(torch, p3, name, steps, warmup, layouts=None, tune=True):
+    """All 8 nested rung subsets (rung >= k, k = 0..7) in one persistent launch,
+    in the layout the autotuner picks for this batched call on its own
+    subsets (p3m_sr_autotune_batched), or in fixed `layouts` (precision ->
+    (subtiles, item target, cluster size, screen)) when tuning is off."""
     from workloads import make_workload
     log("generating", name, "with rungs")
     wl = make_workload(name)
@@ -311,7 +311,13 @@ def batched_leg(torch, p3, name, steps, warmup, layouts=None):
            "subset_sizes": [int((wl.rung >= k).sum()) for k in thr]}
     for prec in ("fp32", "fp64"):
         kw = dict(box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut, precision=prec)
-        if layouts and prec in layouts:
+        tune_s = 0.0
+        if tune:
+            t0 = time.perf_counter()
+            ctx.autotune_batched(pos, mass, rung, thr, out=out, **kw)
+            tune_s = time.perf_counter() - t0
+            log("batched", prec, "tuned in %.1f s" % tune_s, ctx.tune_status())
+        elif layouts and prec in layouts:
             ctx.set_config(*layouts[prec])
         wall = time_calls(torch, lambda: ctx.force_batched(pos, mass, rung, thr, out=out, **kw),
                           max(2, steps // 5), 1)
@@ -323,7 +329,9 @@ def batched_leg(torch, p3, name, steps, warmup, layouts=None):
                      "interactions": st["interactions"], "value": st["interactions"] / wall,
                      "achieved_tflops": 40 * st["interactions"] / (st["ms_pairs"] * 1e-3) / 1e12,
                      "subtiles_per_dim": st["subtiles_per_dim"], "items": st["items"],
-                     "cluster_size": st["cluster_size"], "screen": st["screen"]}
+                     "item_target": st["item_target"], "cluster_size": st["cluster_size"],
+                     "screen": st["screen"], "layout_from": "autotune_batched" if tune
+                     else "fixed", "tune_s": tune_s}
         log("batched", prec, "%.3f ms  interactions %d" % (wall * 1e3, st["interactions"]))
     ctx.close()
     return res
@@ -476,7 +484,7 @@ def main():
                             ("subtiles_per_dim", "item_target", "cluster_size", "screen"))
                    for p in results}
         line["batched"] = batched_leg(torch, p3, args.batched_workload, args.steps, args.warmup,
-                                      layouts=layouts)
+                                      layouts=layouts, tune=not (args.no_autotune or fixed))
 
     if not args.no_cpu_baseline:
         import oracle

@@ -219,15 +219,55 @@ int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
  * particle count and geometry use it.
  * acc_scratch is an n x 3 FP64 device buffer the trials write into.
  * level: 1 = subtiles only, 2 = subtiles and item size.  Synchronises.
+ * Results persist: each is filed (with its time) in a JSON cache under
+ * the device, n, the tile count, the precision, the call kind and the
+ * occupancy signature of the particle set (a 32-bin histogram of particles
+ * per tile), in the file named by the environment variable P3MSR_TUNE_CACHE
+ * (empty: no file) or else $HOME/.cache/p3msr/autotune.json, or the file set
+ * with p3m_sr_set_tune_cache.  A handle loads the file when it is created
+ * (its device's entries become the layouts later calls use), and an
+ * autotune call whose key and signature match a cached entry (normalised
+ * histograms within 0.05 in L1) installs it without timing anything, unless
+ * level has P3M_TUNE_FORCE.  p3m_sr_tune_status reports which happened.
  * Without P3M_TUNE_ADJOINT the forward is tuned, and the adjoint
  * (p3m_sr_force_backward) takes the same decomposition; with level |
  * P3M_TUNE_ADJOINT the adjoint is timed instead (unit weights on every
  * receiver, workspace of n x 3 doubles for them) and keeps its own winner.
  */
 #define P3M_TUNE_ADJOINT 4
+#define P3M_TUNE_FORCE 8
 int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass,
                     const uint8_t *active, int64_t n, double box, double x_s, double r_cut,
                     int precision, int level, double *acc_scratch, void *stream);
+
+/*
+ * The same measure-and-keep for the rung-batched call: times
+ * p3m_sr_force_batched on these rungs and thresholds (its own subsets, in
+ * one launch) for 1 and 2 subtiles per dimension crossed with the screened
+ * layouts of 16, 32 and 64 receivers (items of 4096; at level 2 also 1024
+ * and 16384 around the winner), each timed once after a warm-up call, and
+ * keeps the fastest for
+ * later batched calls with this n, geometry, precision and subset count
+ * (which otherwise take the forward's layout).  Cached like p3m_sr_autotune.
+ * acc_scratch: n_sub x n x 3 FP64 on the device.  level: 1 or 2, optionally
+ * | P3M_TUNE_FORCE.  Errors: those of p3m_sr_force_batched.  Synchronises.
+ */
+int p3m_sr_autotune_batched(p3m_sr_handle h, const double *pos, const double *mass,
+                            const uint8_t *rung, int64_t n, int n_sub, const uint8_t *min_rung,
+                            double box, double x_s, double r_cut, int precision, int level,
+                            double *acc_scratch, void *stream);
+
+/*
+ * Use `path` as the autotuner's cache file (NULL: the default of
+ * p3m_sr_autotune; "": none) and load it now (its entries for this device
+ * become the layouts later calls use).  A missing or unreadable file is an
+ * empty cache.
+ */
+int p3m_sr_set_tune_cache(p3m_sr_handle h, const char *path);
+
+/* What the last autotune call did: trials timed, and 1 if it installed a
+ * cached layout instead of timing. */
+int p3m_sr_tune_status(p3m_sr_handle h, int *trials_timed, int *from_cache);
 
 /*
  * Fix the decomposition instead of autotuning (0 / -1 = automatic):

@@ -79,6 +79,7 @@ class KdkStats(ctypes.Structure):
 
 P3M_KDK_FIXED_RUNGS = 1
 P3M_TUNE_ADJOINT = 4          # p3m_sr_autotune level flag: tune the adjoint
+P3M_TUNE_FORCE = 8            # autotune level flag: time even when a cached layout matches
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -105,6 +106,9 @@ EXPORTS = {
     "p3m_lr_get_stats": ([_P, ctypes.POINTER(LrStats)], _I),
     "p3m_force": ([_P, _P, _P, _P, _I64, _D, _D, _D, _I, _I, _P, _P], _I),
     "p3m_sr_force_noalloc": ([_P, _P, _P, _P, _I64, _D, _D, _D, _I, _P, _P], _I),
+    "p3m_sr_autotune_batched": ([_P, _P, _P, _P, _I64, _I, _P, _D, _D, _D, _I, _I, _P, _P], _I),
+    "p3m_sr_set_tune_cache": ([_P, ctypes.c_char_p], _I),
+    "p3m_sr_tune_status": ([_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], _I),
     "p3m_kdk_step": ([_P, _P, _P, _P, _P, _I64, _D, _D, _D, _I, _D, _I, _D, _D, _I, _I, _I, _P],
                      _I),
     "p3m_kdk_get_stats": ([_P, ctypes.POINTER(KdkStats)], _I),
@@ -263,6 +267,35 @@ class Context:
                                               self._p(out), _stream_ptr(self.device)))
         return out
 
+    def autotune_batched(self, pos, mass, rung, min_rung, *, box, x_s, r_cut, precision="fp32",
+                         level=1, force=False, out=None):
+        """Measure-and-keep tuning of the rung-batched call on these rungs and
+        thresholds (see p3m_sr_autotune_batched); `out` (n_sub x n x 3 FP64)
+        is optional scratch for the trials."""
+        pos, mass, rung, n = self._inputs(pos, mass, rung, "rung")
+        thr = bytes(int(v) for v in min_rung)
+        n_sub = len(thr)
+        if out is None:
+            out = torch.empty((n_sub, n, 3), dtype=torch.float64, device=self.device)
+        buf = ctypes.create_string_buffer(thr, max(n_sub, 1))
+        lvl = int(level) | (P3M_TUNE_FORCE if force else 0)
+        _check(self._lib.p3m_sr_autotune_batched(self._h, self._p(pos), self._p(mass),
+                                                 self._p(rung), n, n_sub,
+                                                 ctypes.cast(buf, ctypes.c_void_p), float(box),
+                                                 float(x_s), float(r_cut), _prec(precision), lvl,
+                                                 self._p(out), _stream_ptr(self.device)))
+
+    def set_tune_cache(self, path=None):
+        """Autotuner cache file (None: the default; "": none), loaded now."""
+        p = None if path is None else str(path).encode()
+        _check(self._lib.p3m_sr_set_tune_cache(self._h, p))
+
+    def tune_status(self) -> dict:
+        """What the last autotune call did: trials timed, cached layout used."""
+        t, c = ctypes.c_int(0), ctypes.c_int(0)
+        _check(self._lib.p3m_sr_tune_status(self._h, ctypes.byref(t), ctypes.byref(c)))
+        return {"trials": t.value, "from_cache": bool(c.value)}
+
     def force_long_range(self, pos, mass=None, active=None, *, box, n_grid, x_s, out=None):
         """Long-range (PM) acceleration (n, 3) FP64; see p3m_lr_force."""
         pos, mass, active, n = self._inputs(pos, mass, active, "active")
@@ -313,13 +346,13 @@ class Context:
         return s.as_dict()
 
     def autotune(self, pos, mass=None, active=None, *, box, x_s, r_cut, precision="fp32",
-                 level=1, out=None, adjoint=False):
+                 level=1, out=None, adjoint=False, force=False):
         """Measure-and-keep tuning of the decomposition for these inputs (of
         the adjoint instead of the forward with adjoint=True); `out` (n x 3
         FP64 on the device) is optional scratch for the trials."""
         pos, mass, active, n = self._inputs(pos, mass, active, "active")
         scratch = self._out(out, n)
-        lvl = int(level) | (P3M_TUNE_ADJOINT if adjoint else 0)
+        lvl = int(level) | (P3M_TUNE_ADJOINT if adjoint else 0) | (P3M_TUNE_FORCE if force else 0)
         _check(self._lib.p3m_sr_autotune(self._h, self._p(pos), self._p(mass), self._p(active),
                                          n, float(box), float(x_s), float(r_cut),
                                          _prec(precision), lvl, self._p(scratch),

@@ -22,6 +22,8 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <sys/stat.h>
+#include <unistd.h>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -58,14 +60,20 @@ struct DevBuf {
     size_t cap = 0;
 };
 
+// Tuned layouts are filed by particle count, tiles per dimension,
+// precision, call kind (forward, adjoint, rung-batched) and subset count.
+enum TuneKind { TUNE_FORWARD = 0, TUNE_ADJOINT = 1, TUNE_BATCHED = 2 };
 struct TuneKey {
     int64_t n;
     int nt;
     int precision;
-    int mode;
+    int kind;
+    int n_sub;
     bool operator<(const TuneKey &o) const {
-        return std::tie(n, nt, precision, mode) < std::tie(o.n, o.nt, o.precision, o.mode);
+        return std::tie(n, nt, precision, kind, n_sub) <
+               std::tie(o.n, o.nt, o.precision, o.kind, o.n_sub);
     }
+    bool operator==(const TuneKey &o) const { return !(*this < o) && !(o < *this); }
 };
 // Device buffers of one short-range call.  base != nullptr: every buffer is
 // a slice of [base, base + size), handed out anew at each call (nothing is
@@ -84,6 +92,34 @@ struct TuneVal {
     int screen;
 };
 
+// One result of the autotuner as kept in the persistent cache: the device,
+// the key, the occupancy signature of the particle set it was timed on (the
+// 32-bin histogram of particles per tile of launch_tile_hist), the layout
+// and its time.
+constexpr int kSigBins = 32;
+struct TuneEntry {
+    std::string device;
+    TuneKey key{};
+    int sig[kSigBins] = {};
+    TuneVal val{};
+    double ms = 0.0;
+};
+
+// Distance of two signatures: the L1 distance of the normalised histograms
+// (0 for the same occupancy, 2 for disjoint ones).
+double sig_distance(const int *a, const int *b) {
+    double ta = 0, tb = 0, d = 0;
+    for (int k = 0; k < kSigBins; ++k) {
+        ta += a[k];
+        tb += b[k];
+    }
+    if (ta <= 0 || tb <= 0) return ta == tb ? 0.0 : 2.0;
+    for (int k = 0; k < kSigBins; ++k) d += std::fabs(a[k] / ta - b[k] / tb);
+    return d;
+}
+// A cached layout is reused for a particle set whose signature is this close.
+constexpr double kSigMatch = 0.05;
+
 }  // namespace
 
 struct p3m_sr_context {
@@ -101,6 +137,11 @@ struct p3m_sr_context {
     int cfg_shape = SHAPE_POLY, cfg_tab_n = 0;   // FP32 forward shape (p3m_sr_set_shape)
     double eps = 0.0;   // Plummer-equivalent softening length (0: point particles)
     std::map<TuneKey, TuneVal> tuned;
+    // persistent autotuner cache: file (empty: none), its entries, this
+    // device's identity, and what the last autotune call did
+    std::string cache_path, device_id;
+    std::vector<TuneEntry> cache;
+    int tune_trials = 0, tune_from_cache = 0;
     p3m_sr_stats stats{};
     hipStream_t last_stream = nullptr;
     bool timing = false;
@@ -110,7 +151,7 @@ struct p3m_sr_context {
     int *host_tot = nullptr;   // pinned: receivers, clusters, items of the current call
     // long-range PM workspace and timing
     DevBuf pm_real, pm_spec, pm_tab, pm_key, pm_rank, pm_cnt, pm_rec, pm_nkey, pm_perm, pm_recv,
-        pm_bsum, p3m_lr, tune_w;
+        pm_bsum, p3m_lr, tune_w, tune_sig;
     // p3m_force: the long-range half runs on this stream beside the short range
     hipStream_t aux = nullptr;
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
@@ -209,6 +250,115 @@ int take(p3m_sr_context *h, SrWork &w, DevBuf &b, size_t bytes, hipStream_t s) {
 }
 
 bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+// ---- persistent autotuner cache ----------------------------------------------
+//
+// A JSON file holding one object per line:
+//   {"device": "...", "n": N, "nt": ..., "precision": p, "kind": k, "n_sub": s,
+//    "ns": ..., "target": ..., "csize": ..., "screen": ..., "ms": ..., "sig": [32 ints]}
+// in an array.  Lines that do not parse are ignored.
+
+std::string device_identity(int device) {
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        (void)hipGetLastError();
+        return "unknown";
+    }
+    std::string id = std::string(prop.gcnArchName) + "/" + prop.name + "/" +
+                     std::to_string(prop.multiProcessorCount);
+    for (char &c : id)
+        if (c == '"' || c == '\\' || c == ' ' || c < 32) c = '_';
+    return id;
+}
+
+bool valid_layout(int csize, int screen) {
+    const bool cs = csize == 8 || csize == 16 || csize == 32 || csize == 64;
+    return cs && screen >= 0 && screen <= 2 && (screen != 2 || csize >= 16);
+}
+
+bool parse_entry(const std::string &line, TuneEntry &e) {
+    char dev[160] = {};
+    long long n = 0;
+    const char *p = line.c_str();
+    const char *q = std::strstr(p, "{\"device\": \"");
+    if (!q) return false;
+    int used = 0;
+    if (std::sscanf(q,
+                    "{\"device\": \"%159[^\"]\", \"n\": %lld, \"nt\": %d, \"precision\": %d, "
+                    "\"kind\": %d, \"n_sub\": %d, \"ns\": %d, \"target\": %d, \"csize\": %d, "
+                    "\"screen\": %d, \"ms\": %lf, \"sig\": [%n",
+                    dev, &n, &e.key.nt, &e.key.precision, &e.key.kind, &e.key.n_sub, &e.val.ns,
+                    &e.val.target, &e.val.csize, &e.val.screen, &e.ms, &used) < 11 ||
+        used == 0)
+        return false;
+    q += used;
+    for (int k = 0; k < kSigBins; ++k) {
+        int consumed = 0;
+        if (std::sscanf(q, " %d%n", &e.sig[k], &consumed) < 1) return false;
+        q += consumed;
+        while (*q == ',' || *q == ' ') ++q;
+    }
+    e.device = dev;
+    e.key.n = n;
+    return e.key.n >= 0 && e.key.nt >= 3 && e.val.ns >= 1 && e.val.ns <= 16 &&
+           valid_layout(e.val.csize, e.val.screen);
+}
+
+void load_cache(p3m_sr_context *h) {
+    h->cache.clear();
+    if (h->cache_path.empty()) return;
+    FILE *f = std::fopen(h->cache_path.c_str(), "r");
+    if (!f) return;
+    std::string line;
+    char buf[1024];
+    while (std::fgets(buf, sizeof(buf), f)) {
+        line = buf;
+        TuneEntry e;
+        if (parse_entry(line, e)) h->cache.push_back(e);
+    }
+    std::fclose(f);
+    // this device's entries are the layouts calls use until they are re-tuned
+    for (const TuneEntry &e : h->cache)
+        if (e.device == h->device_id) h->tuned[e.key] = e.val;
+}
+
+void mkdir_parents(const std::string &path) {
+    for (size_t k = 1; k < path.size(); ++k)
+        if (path[k] == '/') (void)mkdir(path.substr(0, k).c_str(), 0755);
+}
+
+// Write the cache (a temporary file renamed over the old one); failures to
+// write are ignored: the cache is an optimisation.
+void save_cache(const p3m_sr_context *h) {
+    if (h->cache_path.empty()) return;
+    mkdir_parents(h->cache_path);
+    const std::string tmp = h->cache_path + ".tmp" + std::to_string((long long)getpid());
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "[\n");
+    for (size_t k = 0; k < h->cache.size(); ++k) {
+        const TuneEntry &e = h->cache[k];
+        std::fprintf(f,
+                     "{\"device\": \"%s\", \"n\": %lld, \"nt\": %d, \"precision\": %d, "
+                     "\"kind\": %d, \"n_sub\": %d, \"ns\": %d, \"target\": %d, \"csize\": %d, "
+                     "\"screen\": %d, \"ms\": %.6g, \"sig\": [",
+                     e.device.c_str(), (long long)e.key.n, e.key.nt, e.key.precision, e.key.kind,
+                     e.key.n_sub, e.val.ns, e.val.target, e.val.csize, e.val.screen, e.ms);
+        for (int b = 0; b < kSigBins; ++b) std::fprintf(f, b ? ", %d" : "%d", e.sig[b]);
+        std::fprintf(f, "]}%s\n", k + 1 < h->cache.size() ? "," : "");
+    }
+    std::fprintf(f, "]\n");
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), h->cache_path.c_str()) != 0) std::remove(tmp.c_str());
+}
+
+std::string default_cache_path() {
+    const char *env = std::getenv("P3MSR_TUNE_CACHE");
+    if (env) return env;   // empty: no persistent cache
+    const char *home = std::getenv("HOME");
+    if (!home || !*home) return "";
+    return std::string(home) + "/.cache/p3msr/autotune.json";
+}
 
 int check_geometry(int64_t n, double box, double x_s, double r_cut) {
     if (n < 0) return set_error(P3M_EINVAL, "n must be >= 0 (got %lld)", (long long)n);
@@ -332,7 +482,12 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     // decomposition: explicit override > user config > autotuned > default
     int ns = 0, target = 0, csize = 0, screen = -1;
     const int mode = (r.backward ? 2 : 0) + (fp32 ? 0 : 1);
-    auto it = h->tuned.find(TuneKey{r.n, nt, r.precision, r.backward ? 1 : 0});
+    const int tkind = r.backward ? TUNE_ADJOINT
+                                 : (r.sel_kind == SEL_RUNG ? TUNE_BATCHED : TUNE_FORWARD);
+    auto it = h->tuned.find(TuneKey{r.n, nt, r.precision, tkind, tkind == TUNE_BATCHED ? n_sub : 1});
+    // a rung-batched call not tuned on its own takes the forward's layout
+    if (it == h->tuned.end() && tkind == TUNE_BATCHED)
+        it = h->tuned.find(TuneKey{r.n, nt, r.precision, TUNE_FORWARD, 1});
     if (it != h->tuned.end()) {
         ns = it->second.ns;
         target = it->second.target;
@@ -688,6 +843,10 @@ int p3m_sr_create(p3m_sr_handle *out, int device) {
         h->fixed.base = (unsigned char *)base;
         h->fixed.size = kNoAllocBytes;
     }
+    // the autotuner's persistent cache
+    h->device_id = device_identity(device);
+    h->cache_path = default_cache_path();
+    load_cache(h);
     // the events every call may record (timing, the totals' arrival)
     bool ev_ok = hipEventCreateWithFlags(&h->tot_ev, hipEventDisableTiming) == hipSuccess;
     for (hipEvent_t &e : h->ev) ev_ok = ev_ok && hipEventCreate(&e) == hipSuccess;
@@ -713,7 +872,7 @@ int p3m_sr_destroy(p3m_sr_handle h) {
                       &h->pm_real, &h->pm_spec, &h->pm_tab, &h->pm_key,  &h->pm_rank,
                       &h->pm_cnt,  &h->pm_rec,  &h->pm_nkey, &h->pm_perm, &h->pm_recv,
                       &h->kdk_acc, &h->kdk_lr,  &h->kdk_tq,  &h->kdk_tnext, &h->kdk_due,
-                      &h->kdk_scal, &h->pm_bsum, &h->p3m_lr, &h->tune_w};
+                      &h->kdk_scal, &h->pm_bsum, &h->p3m_lr, &h->tune_w, &h->tune_sig};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : h->ev)
@@ -877,6 +1036,118 @@ int p3m_sr_set_config(p3m_sr_handle h, int subtiles_per_dim, int item_target, in
     return P3M_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Measure-and-keep over the candidate layouts for request r (section 2.1.3,
+// "Subtiles": try a subdivision, time it, keep it if faster), filed under
+// `key`.  The occupancy signature of the inputs is taken from a first call;
+// unless level has P3M_TUNE_FORCE, a cached result for this device, key and
+// a matching signature is installed without timing anything.
+int tune(p3m_sr_context *h, Request &r, const TuneKey &key, int level,
+         const std::vector<int> &ns_list, const std::vector<std::pair<int, int>> &layouts,
+         const std::vector<int> &targets, const std::vector<int> &targets2, int reps) {
+    hipStream_t s = r.stream;
+    int rc;
+    h->tune_trials = 0;
+    h->tune_from_cache = 0;
+    // signature of the particle set, from the sort of a first call
+    TuneEntry entry;
+    entry.device = h->device_id;
+    entry.key = key;
+    if ((rc = run(h, r, h->work))) return rc;
+    if (r.n > 0) {
+        const p3m_sr_stats &st = h->stats;
+        const Geom g = make_geom(r.box, r.x_s, r.r_cut, st.tiles_per_dim, st.subtiles_per_dim,
+                                 0.0);
+        if ((rc = ensure(h, h->tune_sig, kSigBins * sizeof(int), s))) return rc;
+        int *hist = (int *)h->tune_sig.p;
+        P3M_HIP(launch_tile_hist((const int *)h->work.cells.p, g, hist, s));
+        P3M_HIP(hipMemcpyAsync(entry.sig, hist, sizeof(entry.sig), hipMemcpyDeviceToHost, s));
+        P3M_HIP(hipStreamSynchronize(s));
+    }
+    if (!(level & P3M_TUNE_FORCE)) {
+        for (const TuneEntry &e : h->cache) {
+            if (e.device == h->device_id && e.key == key &&
+                sig_distance(e.sig, entry.sig) <= kSigMatch) {
+                h->tuned[key] = e.val;
+                h->tune_from_cache = 1;
+                return P3M_OK;
+            }
+        }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    P3M_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return set_error(P3M_EHIP, "hipEventCreate failed");
+    }
+    struct EventGuard {
+        hipEvent_t a, b;
+        ~EventGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+    float best = 1e30f;
+    TuneVal best_v{pick_subtiles(key.nt, r.n, 0), 1024, kDefaultCsize, kDefaultScreen};
+    auto trial = [&](const TuneVal &v) -> int {
+        r.force_ns = v.ns;
+        r.force_target = v.target;
+        r.force_csize = v.csize;
+        r.force_screen = v.screen + 1;
+        int rc2;
+        if ((rc2 = run(h, r, h->work))) return rc2;   // warm-up (also grows the workspace)
+        float tot = 0;
+        for (int k = 0; k < reps; ++k) {
+            P3M_HIP(hipEventRecord(e0, s));
+            if ((rc2 = run(h, r, h->work))) return rc2;
+            P3M_HIP(hipEventRecord(e1, s));
+            P3M_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            P3M_HIP(hipEventElapsedTime(&ms, e0, e1));
+            tot += ms;
+        }
+        ++h->tune_trials;
+        // a later candidate must be faster by more than the run-to-run noise
+        // (about 2 %), so that near-ties do not flip the layout between runs
+        if (tot < best * 0.97f) {
+            best = tot;
+            best_v = v;
+        }
+        return P3M_OK;
+    };
+    for (int ns : ns_list) {
+        if (pick_subtiles(key.nt, r.n, ns) != ns) continue;
+        for (const auto &l : layouts)
+            for (int tg : targets)
+                if ((rc = trial(TuneVal{ns, tg, l.first, l.second}))) return rc;
+    }
+    if ((level & 3) >= 2) {
+        const TuneVal base = best_v;
+        for (int tg : targets2)
+            if ((rc = trial(TuneVal{base.ns, tg, base.csize, base.screen}))) return rc;
+    }
+    r.force_ns = r.force_target = r.force_csize = r.force_screen = 0;
+    h->tuned[key] = best_v;
+    entry.val = best_v;
+    entry.ms = best / reps;
+    bool replaced = false;
+    for (TuneEntry &e : h->cache)
+        if (e.device == entry.device && e.key == key) {
+            e = entry;
+            replaced = true;
+        }
+    if (!replaced) h->cache.push_back(entry);
+    save_cache(h);
+    return P3M_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, const uint8_t *active,
                     int64_t n, double box, double x_s, double r_cut, int precision, int level,
                     double *acc_scratch, void *stream) {
@@ -885,11 +1156,14 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     if (precision != P3M_FP32 && precision != P3M_FP64)
         return set_error(P3M_EINVAL, "precision must be P3M_FP64 or P3M_FP32");
     const bool adjoint = (level & P3M_TUNE_ADJOINT) != 0;
-    level &= ~P3M_TUNE_ADJOINT;
-    if (level < 1 || level > 2)
-        return set_error(P3M_EINVAL, "level must be 1 or 2, optionally | P3M_TUNE_ADJOINT");
+    const int base_level = level & ~(P3M_TUNE_ADJOINT | P3M_TUNE_FORCE);
+    if (base_level < 1 || base_level > 2)
+        return set_error(P3M_EINVAL,
+                         "level must be 1 or 2, optionally | P3M_TUNE_ADJOINT | P3M_TUNE_FORCE");
     if (n > 0 && (!pos || !acc_scratch))
         return set_error(P3M_EINVAL, "pos and acc_scratch are required");
+    if (!aligned8(pos) || !aligned8(mass) || !aligned8(acc_scratch))
+        return set_error(P3M_EINVAL, "pos, mass and acc_scratch must be 8-byte aligned");
     if ((rc = check_handle(h))) return rc;
     if ((rc = set_device(h))) return rc;
     hipStream_t s = (hipStream_t)stream;
@@ -916,64 +1190,83 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     const int nt = tiles_per_dim(box, r_cut);
     // level 1: subtiles x layout (cluster size, screening) x two item sizes;
     // level 2 also sweeps the item size around the level-1 winner
-    std::vector<int> ns_list = {1, 2, 3, 4};
     std::vector<std::pair<int, int>> layouts = {{64, 0}, {64, 1}, {32, 1}, {16, 1}, {8, 1},
                                                 {16, 0}, {8, 0}};
     // all-active FP32 forward calls can evaluate each pair once for both partners
     if (!adjoint && !active && precision == P3M_FP32 && h->eps == 0.0 &&
         h->cfg_shape == SHAPE_POLY)
         for (int c : {32, 64, 16}) layouts.push_back({c, kScreenMutual});
-    hipEvent_t e0, e1;
-    P3M_HIP(hipEventCreate(&e0));
-    P3M_HIP(hipEventCreate(&e1));
-    float best = 1e30f;
-    TuneVal best_v{pick_subtiles(nt, n, 0), 1024, kDefaultCsize, kDefaultScreen};
-    auto trial = [&](const TuneVal &v) -> int {
-        r.force_ns = v.ns;
-        r.force_target = v.target;
-        r.force_csize = v.csize;
-        r.force_screen = v.screen + 1;
-        int rc2;
-        if ((rc2 = run(h, r, h->work))) return rc2;   // warm-up (also grows the workspace)
-        float tot = 0;
-        const int reps = 3;
-        for (int k = 0; k < reps; ++k) {
-            P3M_HIP(hipEventRecord(e0, s));
-            if ((rc2 = run(h, r, h->work))) return rc2;
-            P3M_HIP(hipEventRecord(e1, s));
-            P3M_HIP(hipEventSynchronize(e1));
-            float ms = 0;
-            P3M_HIP(hipEventElapsedTime(&ms, e0, e1));
-            tot += ms;
-        }
-        // a later candidate must be faster by more than the run-to-run noise
-        // (about 2 %), so that near-ties do not flip the layout between runs
-        if (tot < best * 0.97f) {
-            best = tot;
-            best_v = v;
-        }
-        return P3M_OK;
-    };
-    for (int ns : ns_list) {
-        if (pick_subtiles(nt, n, ns) != ns) continue;
-        for (const auto &l : layouts)
-            for (int tg : {1024, 4096})
-                if ((rc = trial(TuneVal{ns, tg, l.first, l.second}))) return rc;
+    const TuneKey key{n, nt, precision, adjoint ? TUNE_ADJOINT : TUNE_FORWARD, 1};
+    rc = tune(h, r, key, level, {1, 2, 3, 4}, layouts, {1024, 4096},
+              {256, 512, 2048, 8192, 16384}, 3);
+    if (rc) return rc;
+    // until it is tuned on its own, the adjoint takes the forward's winner
+    // (with the mutual layout replaced by the plain screen: the adjoint has none)
+    if (!adjoint) {
+        TuneVal v = h->tuned[key];
+        if (v.screen == kScreenMutual) v.screen = 1;
+        const TuneKey adj{n, nt, precision, TUNE_ADJOINT, 1};
+        if (!h->tuned.count(adj)) h->tuned[adj] = v;
     }
-    if (level >= 2) {
-        const TuneVal base = best_v;
-        for (int tg : {256, 512, 2048, 8192, 16384})
-            if ((rc = trial(TuneVal{base.ns, tg, base.csize, base.screen}))) return rc;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (adjoint) {
-        h->tuned[TuneKey{n, nt, precision, 1}] = best_v;
-    } else {
-        // until it is tuned on its own, the adjoint takes the forward's winner
-        h->tuned[TuneKey{n, nt, precision, 0}] = best_v;
-        h->tuned[TuneKey{n, nt, precision, 1}] = best_v;
-    }
+    return P3M_OK;
+}
+
+int p3m_sr_autotune_batched(p3m_sr_handle h, const double *pos, const double *mass,
+                            const uint8_t *rung, int64_t n, int n_sub, const uint8_t *min_rung,
+                            double box, double x_s, double r_cut, int precision, int level,
+                            double *acc_scratch, void *stream) {
+    int rc;
+    if ((rc = check_geometry(n, box, x_s, r_cut))) return rc;
+    if (precision != P3M_FP32 && precision != P3M_FP64)
+        return set_error(P3M_EINVAL, "precision must be P3M_FP64 or P3M_FP32");
+    const int base_level = level & ~P3M_TUNE_FORCE;
+    if (base_level < 1 || base_level > 2)
+        return set_error(P3M_EINVAL, "level must be 1 or 2, optionally | P3M_TUNE_FORCE");
+    if (n_sub < 1 || n_sub > 64) return set_error(P3M_EINVAL, "n_sub must be in 1..64");
+    if (!min_rung) return set_error(P3M_EINVAL, "min_rung (host array) is required");
+    if (n > 0 && (!pos || !rung || !acc_scratch))
+        return set_error(P3M_EINVAL, "pos, rung and acc_scratch are required");
+    if ((double)n * n_sub > 2.0e9)
+        return set_error(P3M_EUNSUPPORTED, "n * n_sub exceeds the 2^31 receiver-row limit");
+    if (!aligned8(pos) || !aligned8(mass) || !aligned8(acc_scratch))
+        return set_error(P3M_EINVAL, "pos, mass and acc_scratch must be 8-byte aligned");
+    if ((rc = check_handle(h))) return rc;
+    if ((rc = set_device(h))) return rc;
+    Request r{};
+    r.pos = pos;
+    r.mass = mass;
+    r.sel = rung;
+    r.sel_kind = SEL_RUNG;
+    r.n_sub = n_sub;
+    r.thr = min_rung;
+    r.n = n;
+    r.box = box;
+    r.x_s = x_s;
+    r.r_cut = r_cut;
+    r.precision = precision;
+    r.out = acc_scratch;
+    r.stream = (hipStream_t)stream;
+    const int nt = tiles_per_dim(box, r_cut);
+    // a batched call is long (every subset's pairs): fewer candidates (the
+    // screened layouts), each timed once after its warm-up call
+    const std::vector<std::pair<int, int>> layouts = {{32, 1}, {16, 1}, {64, 1}};
+    return tune(h, r, TuneKey{n, nt, precision, TUNE_BATCHED, n_sub}, level, {1, 2}, layouts,
+                {4096}, {1024, 16384}, 1);
+}
+
+int p3m_sr_set_tune_cache(p3m_sr_handle h, const char *path) {
+    int rc;
+    if ((rc = check_handle(h))) return rc;
+    h->cache_path = path ? std::string(path) : default_cache_path();
+    load_cache(h);
+    return P3M_OK;
+}
+
+int p3m_sr_tune_status(p3m_sr_handle h, int *trials_timed, int *from_cache) {
+    int rc;
+    if ((rc = check_handle(h))) return rc;
+    if (trials_timed) *trials_timed = h->tune_trials;
+    if (from_cache) *from_cache = h->tune_from_cache;
     return P3M_OK;
 }
 

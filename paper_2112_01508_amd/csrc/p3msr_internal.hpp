@@ -175,6 +175,9 @@ hipError_t launch_item_count(const Cluster *clusters, const int *n_clusters_dev,
 hipError_t launch_item_write(const Cluster *clusters, int n_clusters, const int *cell_start,
                              const Geom &g, int target, int half, const int *item_off,
                              Item *items, hipStream_t s);
+// 32-bin histogram of particles per tile (log2 bins; bin 0: empty tiles),
+// the occupancy signature the autotuner files its results under
+hipError_t launch_tile_hist(const int *cell_start, const Geom &g, int *hist32, hipStream_t s);
 hipError_t launch_gather_weights(const double *grad_acc, const uint8_t *sel_s, const int *perm,
                                  int n, int fp32, double4 *wa, hipStream_t s);
 // per cluster: receivers copied to rp / rperm / rwa (indexed like act_pos;

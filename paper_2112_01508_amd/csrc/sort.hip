@@ -744,6 +744,23 @@ hipError_t launch_item_write(const Cluster *clusters, int n_clusters, const int 
     return hipGetLastError();
 }
 
+// Histogram of particles per tile in 32 bins: bin 0 empty tiles, bin b > 0
+// tiles holding [2^(b-1), 2^b) particles (hist zeroed before the launch).
+__global__ void k_tile_hist(const int *__restrict__ cs, Geom g, int *__restrict__ hist) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.nt3) return;
+    const int cnt = cs[(size_t)(t + 1) * g.ns3] - cs[(size_t)t * g.ns3];
+    const int b = cnt <= 0 ? 0 : min(31, 32 - __clz(cnt));
+    atomicAdd(&hist[b], 1);
+}
+
+hipError_t launch_tile_hist(const int *cell_start, const Geom &g, int *hist32, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, hist32, 0, (size_t)32);
+    hipLaunchKernelGGL(k_tile_hist, dim3(grid_for((size_t)g.nt3, 256)), dim3(256), 0, s,
+                       cell_start, g, hist32);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather_weights(const double *grad_acc, const uint8_t *sel_s, const int *perm,
                                  int n, int fp32, double4 *wa, hipStream_t s) {
     if (n == 0) return hipSuccess;

@@ -7,6 +7,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# contexts made by the tests keep no autotuner cache file unless a test
+# names one (p3m_sr_set_tune_cache), so runs do not see each other's results
+os.environ.setdefault("P3MSR_TUNE_CACHE", "")
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")

@@ -182,3 +182,47 @@ def test_autotune_level_is_checked(lib, level):
                              level, ctypes.c_void_p(8), None)
     assert rc == -1
     assert "level" in lib.p3m_sr_last_error().decode()
+
+
+@pytest.mark.parametrize("level", [0, 3, 4 | 8, -1])
+def test_batched_autotune_arguments_are_checked(lib, level):
+    thr = ctypes.create_string_buffer(b"\x00\x01", 2)
+    rc = lib.p3m_sr_autotune_batched(None, ctypes.c_void_p(8), None, ctypes.c_void_p(8), 10, 2,
+                                     ctypes.cast(thr, ctypes.c_void_p), 1.0, 0.01, 0.045, 1,
+                                     level, ctypes.c_void_p(8), None)
+    assert rc == -1 and "level" in lib.p3m_sr_last_error().decode()
+    # subset count, thresholds and pointers are checked before the handle
+    rc = lib.p3m_sr_autotune_batched(None, ctypes.c_void_p(8), None, ctypes.c_void_p(8), 10, 0,
+                                     ctypes.cast(thr, ctypes.c_void_p), 1.0, 0.01, 0.045, 1, 1,
+                                     ctypes.c_void_p(8), None)
+    assert rc == -1 and "n_sub" in lib.p3m_sr_last_error().decode()
+    rc = lib.p3m_sr_autotune_batched(None, ctypes.c_void_p(8), None, ctypes.c_void_p(8), 10, 2,
+                                     None, 1.0, 0.01, 0.045, 1, 1, ctypes.c_void_p(8), None)
+    assert rc == -1 and "min_rung" in lib.p3m_sr_last_error().decode()
+    rc = lib.p3m_sr_autotune_batched(None, ctypes.c_void_p(9), None, ctypes.c_void_p(8), 10, 2,
+                                     ctypes.cast(thr, ctypes.c_void_p), 1.0, 0.01, 0.045, 1, 1,
+                                     ctypes.c_void_p(8), None)
+    assert rc == -1 and "aligned" in lib.p3m_sr_last_error().decode()
+
+
+def test_autotune_checks_alignment(lib):
+    rc = lib.p3m_sr_autotune(None, ctypes.c_void_p(8), None, None, 10, 1.0, 0.01, 0.045, 1, 1,
+                             ctypes.c_void_p(12), None)
+    assert rc == -1 and "aligned" in lib.p3m_sr_last_error().decode()
+
+
+def test_tune_cache_calls_need_a_handle(lib):
+    assert lib.p3m_sr_set_tune_cache(None, b"/tmp/x.json") == -1
+    t, c = ctypes.c_int(5), ctypes.c_int(5)
+    assert lib.p3m_sr_tune_status(None, ctypes.byref(t), ctypes.byref(c)) == -1
+
+
+def test_noalloc_checks_arguments_before_the_handle(lib):
+    out = ctypes.c_void_p(8)
+    # n beyond the fixed workspace's limit
+    rc = lib.p3m_sr_force_noalloc(None, ctypes.c_void_p(8), None, None, (1 << 18) + 1, 1.0,
+                                  0.01, 0.045, 1, out, None)
+    assert rc == -4 and "no-alloc" in lib.p3m_sr_last_error().decode()
+    rc = lib.p3m_sr_force_noalloc(None, ctypes.c_void_p(8), None, None, 100, 1.0, 0.01, 0.045, 7,
+                                  out, None)
+    assert rc == -1

@@ -35,8 +35,10 @@ def test_autotuned_forward_and_adjoint(prec):
     assert ctx.stats()["interactions"] == int(cnt.sum())
 
     # the adjoint takes the forward's layout until it is tuned on its own
+    # (the screened kernel where the forward pairs once for both partners)
     ctx.force_backward(pos, m, None, to_dev(torch, w), **kw)
-    assert {k: ctx.stats()[k] for k in LAYOUT} == fwd
+    fwd_adj = dict(fwd, screen=1 if fwd["screen"] == 2 else fwd["screen"])
+    assert {k: ctx.stats()[k] for k in LAYOUT} == fwd_adj
     ctx.autotune(pos, m, None, level=1, adjoint=True, **kw)
     g = ctx.force_backward(pos, m, None, to_dev(torch, w), **kw).cpu().numpy()
     adj = {k: ctx.stats()[k] for k in LAYOUT}
@@ -48,3 +50,75 @@ def test_autotuned_forward_and_adjoint(prec):
     ctx.force(pos, m, None, **kw)
     assert {k: ctx.stats()[k] for k in LAYOUT} == fwd
     ctx.close()
+
+
+def test_batched_autotune_uses_its_own_subsets(tmp_path):
+    """The rung-batched call tuned on its own subsets (8 nested rung
+    thresholds of a reduced clustered256 set) runs in the tuned layout and
+    still matches the oracle on receivers stratified by rung."""
+    torch, p3 = gpu_or_skip()
+    ctx = p3.Context(0)
+    ctx.set_tune_cache(str(tmp_path / "tune.json"))
+    wl = make_workload("clustered256", n_side=64, with_rungs=True)
+    thr = list(range(8))
+    pos, rung = to_dev(torch, wl.pos), to_dev(torch, wl.rung)
+    kw = dict(box=1.0, x_s=wl.x_s, r_cut=wl.r_cut, precision="fp32")
+    ctx.autotune_batched(pos, None, rung, thr, **kw)
+    st = ctx.tune_status()
+    assert st["trials"] > 0 and not st["from_cache"]
+    out = ctx.force_batched(pos, None, rung, thr, **kw).cpu().numpy()
+    lay = {k: ctx.stats()[k] for k in LAYOUT}
+    print("batched layout", lay, flush=True)
+    assert lay["screen"] in (0, 1) and lay["item_target"] in (1024, 4096, 16384)
+    from workloads import stratified_by_rung
+    idx = stratified_by_rung(wl.rung, 64, wl.config_id)
+    ref, cnt, absum, _ = oracle.force(wl.pos, None, 1.0, wl.x_s, wl.r_cut, recv=idx)
+    for k in thr:
+        sel = wl.rung[idx] >= k
+        got = out[k][idx[sel]]
+        e = oracle.errors(got, ref[sel], absum[sel])
+        assert e["e_l2"] <= TOL["fp32"] and e["e_max_cond"] <= TOL["fp32"], (k, e)
+        assert np.all(out[k][wl.rung < k] == 0)
+    ctx.close()
+
+
+def test_cache_persists_across_handles(tmp_path):
+    """A second handle reading the same cache file reuses the first one's
+    tuned layouts (forward and batched) without timing, and calls run in
+    them; P3M_TUNE_FORCE times again."""
+    torch, p3 = gpu_or_skip()
+    path = str(tmp_path / "tune.json")
+    wl = make_workload("diff64", n_side=32, with_rungs=False)
+    rung = (np.arange(wl.n) % 4).astype(np.uint8)
+    pos, rg = to_dev(torch, wl.pos), to_dev(torch, rung)
+    kw = dict(box=1.0, x_s=wl.x_s, r_cut=wl.r_cut, precision="fp32")
+    a = p3.Context(0)
+    a.set_tune_cache(path)
+    a.autotune(pos, None, None, level=1, **kw)
+    assert a.tune_status()["trials"] > 0
+    a.force(pos, None, None, **kw)
+    lay_a = {k: a.stats()[k] for k in LAYOUT}
+    a.autotune_batched(pos, None, rg, [0, 1, 2, 3], **kw)
+    a.force_batched(pos, None, rg, [0, 1, 2, 3], **kw)
+    lay_ab = {k: a.stats()[k] for k in LAYOUT}
+    a.close()
+    text = open(path).read()
+    assert text.count('"device"') == 2          # the forward and the batched results
+    b = p3.Context(0)
+    b.set_tune_cache(path)
+    # the loaded layouts apply to calls right away
+    b.force(pos, None, None, **kw)
+    assert {k: b.stats()[k] for k in LAYOUT} == lay_a
+    b.autotune(pos, None, None, level=1, **kw)
+    assert b.tune_status() == {"trials": 0, "from_cache": True}
+    b.autotune_batched(pos, None, rg, [0, 1, 2, 3], **kw)
+    assert b.tune_status() == {"trials": 0, "from_cache": True}
+    b.force_batched(pos, None, rg, [0, 1, 2, 3], **kw)
+    assert {k: b.stats()[k] for k in LAYOUT} == lay_ab
+    # a different particle set of the same size does not match the signature
+    other = np.random.default_rng(3).random((wl.n, 3))
+    b.autotune(to_dev(torch, other), None, None, level=1, **kw)
+    assert b.tune_status()["trials"] > 0
+    b.autotune(pos, None, None, level=1, force=True, **kw)
+    assert b.tune_status()["trials"] > 0
+    b.close()
