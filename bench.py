@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_INTERACTION = 40          # forward pair, algorithmic convention
 PEAK_FP32_TFLOPS = 157.3            # MI355X FP32 vector (packed) peak
 PEAK_FP64_TFLOPS = 78.6             # MI355X FP64 vector peak
+PEAK_HBM_TBPS = 8.0                 # MI355X HBM3E
 
 
 def parse():
@@ -49,6 +50,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-tiled", action="store_true",
+                    help="skip the oracle's cell-list walk on the full uniform32, diff64 and "
+                         "clustered128 sets (about 20 s on 16 host threads)")
     ap.add_argument("--legs", default="adjoint,batched,softened,long_range,kdk,shapes",
                     help="extra measured legs beside the forward force: adjoint, batched, "
                          "softened, long_range, kdk, shapes")
@@ -74,14 +78,16 @@ def time_steps(torch, ctx, pos, mass, wl, prec, steps, warmup):
     wall = (time.perf_counter() - t0) / steps
     # per-kernel durations from HIP events on the launch stream, same calls
     ctx.set_timing(True)
-    pairs_ms, build_ms = [], []
+    pairs_ms, build_ms, sort_ms = [], [], []
     for _ in range(steps):
         ctx.force(pos, mass, None, out=out, **kw)
         st = ctx.stats()
         pairs_ms.append(st["ms_pairs"])
         build_ms.append(st["ms_build"])
+        sort_ms.append(st["ms_sort"])
     ctx.set_timing(False)
     st = ctx.stats()
+    st["ms_sort_median"] = statistics.median(sort_ms)
     return out, wall, st, statistics.median(pairs_ms), statistics.median(build_ms)
 
 
@@ -325,6 +331,18 @@ def batched_leg(torch, p3, name, steps, warmup, layouts=None, tune=True):
         ctx.force_batched(pos, mass, rung, thr, out=out, **kw)
         st = ctx.stats()
         ctx.set_timing(False)
+        if prec == "fp32":
+            # interactions of each subset (untimed single calls): rung k
+            # particles are kicked 2^k times per step of the rung hierarchy,
+            # so a step needs sum_i 2^rung_i n_nb(i) = sum_k 2^k (I_k - I_k+1)
+            inter_k = []
+            for k in thr:
+                ctx.force_batched(pos, mass, rung, [k], out=out[:1], **kw)
+                inter_k.append(ctx.stats()["interactions"])
+            per_step = sum((2 ** k) * (inter_k[k] - (inter_k[k + 1] if k + 1 < 8 else 0))
+                           for k in thr)
+            res["subset_interactions"] = inter_k
+            res["interactions_per_global_step"] = per_step
         res[prec] = {"ms_per_call": wall * 1e3, "pair_kernel_ms": st["ms_pairs"],
                      "interactions": st["interactions"], "value": st["interactions"] / wall,
                      "achieved_tflops": 40 * st["interactions"] / (st["ms_pairs"] * 1e-3) / 1e12,
@@ -334,6 +352,40 @@ def batched_leg(torch, p3, name, steps, warmup, layouts=None, tune=True):
                      else "fixed", "tune_s": tune_s}
         log("batched", prec, "%.3f ms  interactions %d" % (wall * 1e3, st["interactions"]))
     ctx.close()
+    return res
+
+
+def sort_record(st, n):
+    """HBM rate of the counting sort (cell keys, scan, scatter, fine order)
+    against its algorithmic bytes: each particle's position read once (24 B)
+    and its sorted record (32 B) and original index (4 B) written once, plus
+    the cell table counted and scanned (4 B per fine cell written, read and
+    written again)."""
+    cells = st["tiles_per_dim"] ** 3 * st["subtiles_per_dim"] ** 3
+    nbytes = 60 * n + 12 * cells
+    ms = st["ms_sort_median"]
+    gbps = nbytes / (ms * 1e-3) / 1e9
+    return {"ms": ms, "algorithmic_bytes": nbytes, "bytes_per_particle": 60,
+            "bytes_per_cell": 12, "gb_per_s": gbps, "frac_hbm": gbps / (PEAK_HBM_TBPS * 1e3),
+            "bound": "hbm"}
+
+
+def cpu_tiled_leg():
+    """The oracle's cell-list walk (FP64, OpenMP over receivers) on the full
+    uniform32, diff64 and clustered128 sets: the fair CPU rate beside the GPU
+    numbers, with the host threads it used."""
+    import oracle
+    from workloads import make_workload
+    oracle.build(force=False)
+    res = {"cores": oracle.threads(), "kind": "oracle (cell list, all N receivers)"}
+    for name in ("uniform32", "diff64", "clustered128"):
+        wl = make_workload(name, with_rungs=False)
+        t0 = time.perf_counter()
+        _, cnt, _ = oracle.force_full(wl.pos, None, wl.box, wl.x_s, wl.r_cut, method="tiled")
+        dt = time.perf_counter() - t0
+        res[name] = {"n": wl.n, "interactions": int(cnt.sum()), "seconds": dt,
+                     "value": float(cnt.sum()) / dt, "unit": "interactions/s"}
+        log("cpu tiled", name, "%.1f s  %.3e interactions/s" % (dt, cnt.sum() / dt))
     return res
 
 
@@ -441,6 +493,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
         "pair_kernel_ms": r32["pairs_ms"],
         "build_ms": r32["build_ms"],
+        "sort": sort_record(r32["stats"], wl.n),
     }
     prof = profiled_record("k_pairs_fwd_fp32_%s" % args.workload, r32["stats"])
     if prof:
@@ -521,6 +574,8 @@ def main():
         for key, rec in line.get("shapes", {}).items():
             e = oracle.errors(rec["_acc"][idx], ref, absum)
             rec["force_error"] = {"e_l2": e["e_l2"], "e_max_cond": e["e_max_cond"]}
+        if not args.no_cpu_tiled:
+            line["cpu_tiled"] = cpu_tiled_leg()
     for rec in line.get("shapes", {}).values():
         rec.pop("_acc", None)
     print(json.dumps(line), flush=True)

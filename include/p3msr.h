@@ -98,6 +98,9 @@ typedef struct {
     int64_t screened;        /* supplier records tested by the screen (0 without it) */
     double eps_b;            /* B-spline softening length of the call (0: none) */
     int64_t fp64_steps;      /* screen 2: wavefront steps that redid a pair in FP64 */
+    float ms_sort;           /* the counting sort into tile -> subtile -> fine order (keys,
+                                scan, scatter, fine order), when timing is on, else -1 */
+    int32_t pad1;
 } p3m_sr_stats;
 
 /* Timings of the most recent p3m_lr_force call (when timing is on, else -1). */

@@ -50,7 +50,8 @@ class Stats(ctypes.Structure):
                 ("ms_total", ctypes.c_float), ("cluster_size", ctypes.c_int32),
                 ("screen", ctypes.c_int32), ("shape", ctypes.c_int32),
                 ("screened", ctypes.c_int64), ("eps_b", ctypes.c_double),
-                ("fp64_steps", ctypes.c_int64)]
+                ("fp64_steps", ctypes.c_int64), ("ms_sort", ctypes.c_float),
+                ("pad1", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -146,7 +146,8 @@ struct p3m_sr_context {
     hipStream_t last_stream = nullptr;
     bool timing = false;
     bool timed_last = false;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // start, pairs start/end, end
+    // start, pairs start, pairs end, end, sort end
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hipEvent_t tot_ev = nullptr;   // after the totals of a call reach host memory
     int *host_tot = nullptr;   // pinned: receivers, clusters, items of the current call
     // long-range PM workspace and timing
@@ -531,7 +532,7 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     st.cluster_size = csize;
     st.screen = mutual ? kScreenMutual : screen;
     st.eps_b = kBsplinePerPlummer * h->eps;
-    st.ms_build = st.ms_pairs = st.ms_total = -1.0f;
+    st.ms_build = st.ms_pairs = st.ms_total = st.ms_sort = -1.0f;
     h->last_stream = s;
     h->timed_last = false;
     if (h->timing) P3M_HIP(hipEventRecord(h->ev[0], s));
@@ -618,6 +619,7 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
         perm = perm_f;
         sel_s = sel_f;
     }
+    if (h->timing) P3M_HIP(hipEventRecord(h->ev[4], s));
 
     // ---- receivers -> clusters -> items ----
     // the adjoint needs every particle as a receiver (its output rows are
@@ -1323,6 +1325,7 @@ int p3m_sr_get_stats(p3m_sr_handle h, p3m_sr_stats *out) {
         P3M_HIP(hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
         P3M_HIP(hipEventElapsedTime(&b, h->ev[1], h->ev[2]));
         P3M_HIP(hipEventElapsedTime(&t, h->ev[0], h->ev[3]));
+        P3M_HIP(hipEventElapsedTime(&st.ms_sort, h->ev[0], h->ev[4]));
         st.ms_build = a;
         st.ms_pairs = b;
         st.ms_total = t;
