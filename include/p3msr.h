@@ -100,7 +100,7 @@ typedef struct {
     int64_t fp64_steps;      /* screen 2: wavefront steps that redid a pair in FP64 */
     float ms_sort;           /* the counting sort into tile -> subtile -> fine order (keys,
                                 scan, scatter, fine order), when timing is on, else -1 */
-    int32_t pad1;
+    int32_t deterministic;   /* 1: the call ran in the deterministic mode (p3m_sr_set_deterministic) */
 } p3m_sr_stats;
 
 /* Timings of the most recent p3m_lr_force call (when timing is on, else -1). */
@@ -332,6 +332,40 @@ int p3m_sr_set_shape(p3m_sr_handle h, int kind, int table_size);
  * point particles.  EINVAL for a negative or non-finite eps.
  */
 int p3m_sr_set_softening(p3m_sr_handle h, double eps);
+
+/*
+ * Deterministic mode (enable = 1; 0, the default, turns it off): every
+ * following force, backward and batched call on this handle returns the
+ * same bits for the same inputs, call after call.  The sums are then taken
+ * in a fixed order:
+ *   - particles of a cell are ordered by (fine sub-cell, input index) with a
+ *     stable radix sort, instead of the order that the atomic counting gives;
+ *   - a cluster whose stencil is split into several work items gets each
+ *     item's sums in a slot of its own, added in item order after the pair
+ *     launch, instead of FP64 atomics;
+ *   - layout screen 2 runs as screen 1 (the kernel that evaluates each pair
+ *     for both partners adds its reactions with atomics).
+ * The accepted pairs are the same in both modes and the forces differ only
+ * by the rounding of the summation order.  The sort and the partial slots
+ * cost time and workspace (24 B per particle, 24 B per item and receiver
+ * slot).  Long-range (PM) and KDK calls are not covered.  EINVAL unless
+ * enable is 0 or 1.
+ */
+int p3m_sr_set_deterministic(p3m_sr_handle h, int enable);
+
+/*
+ * Debug limits for testing out-of-memory handling.  max_workspace_bytes > 0
+ * caps the device workspace this handle may hold (the short-range, PM and
+ * KDK buffers grown with hipMalloc); a growth that would pass it fails with
+ * P3M_ENOMEM before anything of the call is launched past that point, as a
+ * failed hipMalloc does.  fail_after >= 0 lets that many more growths
+ * succeed and makes the next one fail (-1: no such limit).  0 / -1 turn
+ * the limits off.  After a P3M_ENOMEM the handle stays usable: lifting the
+ * limit and calling again gives the normal result.  The no-alloc entry
+ * point, whose workspace is fixed, ignores both.  EINVAL for
+ * max_workspace_bytes < 0 or fail_after < -1.
+ */
+int p3m_sr_set_debug_limits(p3m_sr_handle h, int64_t max_workspace_bytes, int fail_after);
 
 /*
  * Record HIP events on the call's stream around the build phase and the

@@ -51,7 +51,7 @@ class Stats(ctypes.Structure):
                 ("screen", ctypes.c_int32), ("shape", ctypes.c_int32),
                 ("screened", ctypes.c_int64), ("eps_b", ctypes.c_double),
                 ("fp64_steps", ctypes.c_int64), ("ms_sort", ctypes.c_float),
-                ("pad1", ctypes.c_int32)]
+                ("deterministic", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -100,6 +100,8 @@ EXPORTS = {
     "p3m_sr_autotune": ([_P, _P, _P, _P, _I64, _D, _D, _D, _I, _I, _P, _P], _I),
     "p3m_sr_set_config": ([_P, _I, _I, _I, _I], _I),
     "p3m_sr_set_timing": ([_P, _I], _I),
+    "p3m_sr_set_deterministic": ([_P, _I], _I),
+    "p3m_sr_set_debug_limits": ([_P, _I64, _I], _I),
     "p3m_sr_set_softening": ([_P, ctypes.c_double], _I),
     "p3m_sr_set_shape": ([_P, _I, _I], _I),
     "p3m_sr_get_stats": ([_P, ctypes.POINTER(Stats)], _I),
@@ -380,6 +382,17 @@ class Context:
 
     def set_timing(self, enable=True):
         _check(self._lib.p3m_sr_set_timing(self._h, 1 if enable else 0))
+
+    def set_deterministic(self, enable=True):
+        """Fixed summation order, the same bits call after call; see
+        p3m_sr_set_deterministic."""
+        _check(self._lib.p3m_sr_set_deterministic(self._h, 1 if enable else 0))
+
+    def set_debug_limits(self, max_workspace_bytes=0, fail_after=-1):
+        """Make workspace growth fail with P3M_ENOMEM past a byte cap or after
+        fail_after more growths (0 / -1: off); see p3m_sr_set_debug_limits."""
+        _check(self._lib.p3m_sr_set_debug_limits(self._h, int(max_workspace_bytes),
+                                                 int(fail_after)))
 
     def stats(self) -> dict:
         s = Stats()

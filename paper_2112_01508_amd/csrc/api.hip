@@ -81,6 +81,9 @@ struct TuneKey {
 struct SrWork {
     DevBuf key, rank, cells, sp, perm, sel, sp2, perm2, sel2, flags, actpos, ncl, clusters,
         itemcnt, items, bsum, counters, wa, scal, rp, rperm, rwa, fbig, msum, htab;
+    // deterministic mode: radix-sort keys and values (two of each), digit
+    // counts, and the items' partial sums
+    DevBuf det_k, det_v, det_hist, partials;
     unsigned char *base = nullptr;
     size_t size = 0, used = 0;
 };
@@ -145,6 +148,14 @@ struct p3m_sr_context {
     p3m_sr_stats stats{};
     hipStream_t last_stream = nullptr;
     bool timing = false;
+    // fixed summation order (p3m_sr_set_deterministic)
+    bool deterministic = false;
+    // debug limits (p3m_sr_set_debug_limits): cap on the workspace bytes held
+    // through ensure() (0: none) and the number of growths allowed before
+    // one is made to fail (-1: none); alloc_bytes is what ensure() holds now
+    size_t dbg_max_bytes = 0;
+    int dbg_fail_after = -1;
+    size_t alloc_bytes = 0;
     bool timed_last = false;
     // start, pairs start, pairs end, end, sort end
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -175,10 +186,18 @@ int ensure(p3m_sr_context *h, DevBuf &b, size_t bytes, hipStream_t s) {
     if (h->last_stream && h->last_stream != s) P3M_HIP(hipStreamSynchronize(h->last_stream));
     if (b.p) {
         P3M_HIP(hipFree(b.p));
+        h->alloc_bytes -= b.cap;
         b.p = nullptr;
         b.cap = 0;
     }
     size_t want = bytes + bytes / 4;
+    if (h->dbg_fail_after == 0)
+        return set_error(P3M_ENOMEM, "device workspace of %zu bytes refused (debug limit)", bytes);
+    if (h->dbg_max_bytes && h->alloc_bytes + bytes > h->dbg_max_bytes)
+        return set_error(P3M_ENOMEM,
+                         "device workspace of %zu bytes would pass the debug limit of %zu bytes",
+                         bytes, h->dbg_max_bytes);
+    if (h->dbg_max_bytes && h->alloc_bytes + want > h->dbg_max_bytes) want = bytes;
     if (hipMalloc(&b.p, want) != hipSuccess) {
         (void)hipGetLastError();
         b.p = nullptr;
@@ -191,6 +210,8 @@ int ensure(p3m_sr_context *h, DevBuf &b, size_t bytes, hipStream_t s) {
         want = bytes;
     }
     b.cap = want;
+    h->alloc_bytes += want;
+    if (h->dbg_fail_after > 0) --h->dbg_fail_after;
     return P3M_OK;
 }
 
@@ -518,9 +539,11 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     // the polynomial shape, no softening, clusters of 16, 32 or 64 and fewer
     // than 2^27 particles (the list entries hold the sorted index in 27 bits);
     // other calls with this layout take the screened kernel
+    // (not in the deterministic mode: its reactions are added with atomics)
+    const bool det = h->deterministic;
     const bool mutual = screen == kScreenMutual && fp32 && !r.backward && all_recv &&
                         shape == SHAPE_POLY && g.eps_b == 0.0 && csize >= 16 &&
-                        r.n <= (int64_t)(1u << 27);
+                        r.n <= (int64_t)(1u << 27) && !det;
     if (screen == kScreenMutual && !mutual) screen = 1;
 
     p3m_sr_stats st{};
@@ -531,6 +554,7 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     st.precision = r.precision;
     st.cluster_size = csize;
     st.screen = mutual ? kScreenMutual : screen;
+    st.deterministic = det ? 1 : 0;
     st.eps_b = kBsplinePerPlummer * h->eps;
     st.ms_build = st.ms_pairs = st.ms_total = st.ms_sort = -1.0f;
     h->last_stream = s;
@@ -549,7 +573,9 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     const size_t nflags = (size_t)n * n_sub;
     const size_t ncl_len = (size_t)n_sub * g.nt3;
     const size_t cl_bound = ncl_len + (nflags + csize - 1) / csize;
-    const size_t scan_max = std::max(std::max(ncells, nflags), std::max(ncl_len, cl_bound));
+    const size_t det_hist = det ? stable_rank_hist_ints(n) : 0;
+    const size_t scan_max = std::max(std::max(std::max(ncells, nflags), std::max(ncl_len, cl_bound)),
+                                     det_hist);
     int rc;
     if ((rc = take(h, w, w.key, sizeof(int) * n, s))) return rc;
     if ((rc = take(h, w, w.rank, sizeof(int) * n, s))) return rc;
@@ -574,6 +600,11 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     if (r.backward && (rc = take(h, w, w.rwa, sizeof(double4) * (nflags + 1), s))) return rc;
     if (r.backward && (rc = take(h, w, w.wa, sizeof(double4) * ((size_t)n + kSupplierPad), s))) return rc;
     if (mutual && (rc = take(h, w, w.msum, sizeof(double) * 3 * (size_t)n, s))) return rc;
+    if (det) {
+        if ((rc = take(h, w, w.det_k, sizeof(unsigned long long) * 2 * (size_t)n, s))) return rc;
+        if ((rc = take(h, w, w.det_v, sizeof(int) * 2 * (size_t)n, s))) return rc;
+        if ((rc = take(h, w, w.det_hist, sizeof(int) * (det_hist + 1), s))) return rc;
+    }
     if (shape != SHAPE_POLY && (rc = take(h, w, w.htab, kTabFloats * sizeof(float), s)))
         return rc;
 
@@ -605,16 +636,25 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     }
     P3M_HIP(launch_keys(r.pos, n, g, key, rank, cells, s));
     P3M_HIP(launch_scan(cells, cells, ncells, bsum, s));
+    if (det) {
+        // ranks in (fine sub-cell, index) order instead of the atomics' order
+        unsigned long long *k64 = (unsigned long long *)w.det_k.p;
+        int *v = (int *)w.det_v.p;
+        P3M_HIP(launch_stable_ranks(r.pos, n, g, key, cells, k64, k64 + n, v, v + n,
+                                    (int *)w.det_hist.p, bsum, rank, s));
+    }
     const uint8_t *sel_src = (r.sel_kind == SEL_ALL && !r.backward) ? nullptr : r.sel;
     {
         int *perm_f = (int *)w.perm2.p;
         uint8_t *sel_f = (uint8_t *)w.sel2.p;
         P3M_HIP(launch_scatter(r.pos, r.mass, sel_src, n, g, key, rank, cells, fp32 ? 1 : 0,
-                               csize, sp, perm, sel_s, sp_f, perm_f, sel_f, s));
+                               csize, det, sp, perm, sel_s, sp_f, perm_f, sel_f, s));
         // fine order inside dense subtiles (key/rank are free again as scratch)
-        // a subtile no larger than one cluster gains nothing from the reorder
-        P3M_HIP(launch_fine_order(sp, perm, sel_s, cells, g, key, rank, sp_f, perm_f, sel_f,
-                                  csize, n, fbig, s));
+        // a subtile no larger than one cluster gains nothing from the reorder;
+        // the stable ranks are in fine order already
+        if (!det)
+            P3M_HIP(launch_fine_order(sp, perm, sel_s, cells, g, key, rank, sp_f, perm_f, sel_f,
+                                      csize, n, fbig, s));
         sp = sp_f;
         perm = perm_f;
         sel_s = sel_f;
@@ -664,6 +704,10 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     if ((rc = take(h, w, w.items, sizeof(Item) * (size_t)(n_items > 0 ? n_items : 1), s)))
         return rc;
     Item *items = (Item *)w.items.p;
+    if (det && (rc = take(h, w, w.partials,
+                          sizeof(double) * 3 * (size_t)csize * (size_t)(n_items > 0 ? n_items : 1),
+                          s)))
+        return rc;
     P3M_HIP(launch_item_write(clusters, n_clusters, cells, g, target, mutual ? 1 : 0, itemcnt,
                               items, s));
 
@@ -682,6 +726,7 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     a.out_stride = 3ll * n;
     a.counters = counters;
     a.n_items = n_items;
+    a.partials = det ? (double *)w.partials.p : nullptr;
     a.unit_mass = r.mass ? 0 : 1;
     a.csize = csize;
     a.g = g;
@@ -718,6 +763,9 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     if (mutual) P3M_HIP(launch_pairs_mutual(a, (int)grid, s));
     else P3M_HIP(launch_pairs(mode, screen, shape, a, (int)grid, s));
     if (mutual) P3M_HIP(launch_mutual_out((const double *)w.msum.p, perm, n, r.out, s));
+    if (det)
+        P3M_HIP(launch_item_reduce(clusters, ncl + ncl_len, (int)cl_bound, itemcnt, a.partials,
+                                   csize, a.rperm, r.out, a.out_stride, s));
     if (h->timing) {
         P3M_HIP(hipEventRecord(h->ev[2], s));
         h->timed_last = true;
@@ -1293,6 +1341,24 @@ int p3m_sr_set_softening(p3m_sr_handle h, double eps) {
         return set_error(P3M_EINVAL, "eps must be finite and >= 0");
     if ((rc = check_handle(h))) return rc;
     h->eps = eps;
+    return P3M_OK;
+}
+
+int p3m_sr_set_deterministic(p3m_sr_handle h, int enable) {
+    int rc;
+    if (enable != 0 && enable != 1) return set_error(P3M_EINVAL, "enable must be 0 or 1");
+    if ((rc = check_handle(h))) return rc;
+    h->deterministic = enable != 0;
+    return P3M_OK;
+}
+
+int p3m_sr_set_debug_limits(p3m_sr_handle h, int64_t max_workspace_bytes, int fail_after) {
+    int rc;
+    if (max_workspace_bytes < 0) return set_error(P3M_EINVAL, "max_workspace_bytes must be >= 0");
+    if (fail_after < -1) return set_error(P3M_EINVAL, "fail_after must be >= -1");
+    if ((rc = check_handle(h))) return rc;
+    h->dbg_max_bytes = (size_t)max_workspace_bytes;
+    h->dbg_fail_after = fail_after;
     return P3M_OK;
 }
 

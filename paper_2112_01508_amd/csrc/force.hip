@@ -882,13 +882,20 @@ void k_pairs(PairArgs a) {
             az = group_sum(az, lane, c.grp, c.cnt, c.G);
         }
         // group 0 holds the item's sums: stored when the item is its
-        // cluster's only one, else added (FP64 atomics) into the zeroed output
+        // cluster's only one, else added (FP64 atomics) into the zeroed output,
+        // or, in the deterministic mode, stored in the item's partial slot
+        // for the ordered reduction after the launch
         if (c.grp == 0) {
             double *o = a.out + (long long)cl.subset * a.out_stride + 3ll * a.rperm[cl.begin + il];
             if (item.sole & kItemSole) {
                 o[0] = ax;
                 o[1] = ay;
                 o[2] = az;
+            } else if (a.partials) {
+                double *q = a.partials + ((size_t)it * a.csize + il) * 3;
+                q[0] = ax;
+                q[1] = ay;
+                q[2] = az;
             } else {
                 atomicAdd(o, ax);
                 atomicAdd(o + 1, ay);

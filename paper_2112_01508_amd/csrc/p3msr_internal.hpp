@@ -142,11 +142,30 @@ hipError_t launch_scan(const int *in, int *out, size_t n, int *block_sums, hipSt
 // scatter into tile -> subtile order: particles of subtiles that the fine
 // order leaves as they are (at most max(csize, kFineMin)) go to sp2/perm2/sel2,
 // the others to sp/perm/sel_s for launch_fine_order
+// stable: ranks from launch_stable_ranks (already in fine order), so every
+// subtile goes to sp2/perm2/sel2 and no fine-order pass follows
 hipError_t launch_scatter(const double *pos, const double *mass, const uint8_t *sel, int n,
                           const Geom &g, const int *key, const int *rank,
-                          const int *cell_start, int fp32, int csize, double4 *sp, int *perm,
-                          uint8_t *sel_s, double4 *sp2, int *perm2, uint8_t *sel2,
+                          const int *cell_start, int fp32, int csize, bool stable, double4 *sp,
+                          int *perm, uint8_t *sel_s, double4 *sp2, int *perm2, uint8_t *sel2,
                           hipStream_t s);
+// Deterministic mode: rank[i] = place of particle i in its cell when the
+// cell's particles are ordered by (fine sub-cell, index) (cell_start: the
+// scanned cell counts; key: launch_keys' cell keys).  Scratch: k64a/k64b n
+// each, va/vb n each, hist stable_rank_hist_ints(n) + 1, bsum for a scan of
+// that many values.
+size_t stable_rank_hist_ints(int n);
+hipError_t launch_stable_ranks(const double *pos, int n, const Geom &g, const int *key,
+                               const int *cell_start, unsigned long long *k64a,
+                               unsigned long long *k64b, int *va, int *vb, int *hist, int *bsum,
+                               int *rank, hipStream_t s);
+// Deterministic mode: the sums of clusters with several items from the
+// items' partial slots (partials[(item * csize + receiver) * 3 + c]), added
+// in item order into out (item_off: the scanned item counts per cluster)
+hipError_t launch_item_reduce(const Cluster *clusters, const int *n_clusters_dev, int bound,
+                              const int *item_off, const double *partials, int csize,
+                              const int *rperm, double *out, long long out_stride,
+                              hipStream_t s);
 // reorder the particles of every subtile by the Morton index of their fine
 // sub-cell (sp/perm/sel -> sp2/perm2/sel2; fkey/frank: n ints of scratch;
 // big_list: 1 + n / kFineBig ints, big_list[0] zeroed before the call)
@@ -230,6 +249,10 @@ struct PairArgs {
     int tab_n;
     // mutual kernel: FP32 r^2 in [rc2_lo, rc2_hi) is tested again in FP64
     float rc2_lo, rc2_hi;
+    // deterministic mode: items of clusters with several items store their
+    // sums in partial slots ((item * csize + receiver) * 3) instead of
+    // adding them with atomics (nullptr: atomics)
+    double *partials;
     Geom g;
 };
 

@@ -12,6 +12,7 @@
 #include "p3msr_internal.hpp"
 
 #include <algorithm>
+#include <climits>
 
 namespace p3m {
 
@@ -346,6 +347,99 @@ __global__ __launch_bounds__(kFineBins) void k_fine_order_big(
     }
 }
 
+// ---- stable order (deterministic mode) ----------------------------------------
+//
+// The counting sort above ranks the particles of a cell (and of a fine
+// sub-cell) by atomics, so their order inside a cell can change between
+// calls, and with it the order of every floating-point sum.  The stable path
+// sorts the composite key cell << kFineBits | fine sub-cell with an LSD radix
+// sort (8-bit digits, stable passes) carrying the particle index; a cell's
+// particles then come in (fine sub-cell, index) order, the same on every call,
+// and the scatter writes that order directly (no fine-order pass).
+
+constexpr int kFineBits = 9;
+static_assert(kFineBins == 1 << kFineBits, "fine sub-cells per subtile");
+constexpr int kRsTile = 2048;   // elements per block (one wave) of a radix pass
+
+__global__ void k_rs_keys(const double *__restrict__ pos, int n, Geom g,
+                          const int *__restrict__ key, unsigned long long *__restrict__ k64,
+                          int *__restrict__ val) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double4 p;
+    p.x = wrap_coord(pos[3 * (size_t)i], g);
+    p.y = wrap_coord(pos[3 * (size_t)i + 1], g);
+    p.z = wrap_coord(pos[3 * (size_t)i + 2], g);
+    p.w = 0.0;
+    k64[i] = ((unsigned long long)(unsigned)key[i] << kFineBits) | (unsigned)fine_key(p, g);
+    val[i] = i;
+}
+
+// Digit counts of one block's elements, digit-major (hist[d * nblk + b]), so
+// that the exclusive scan of hist gives every (digit, block) its first slot.
+__global__ __launch_bounds__(kWave) void k_rs_hist(const unsigned long long *__restrict__ k64,
+                                                   int n, int shift, int nblk,
+                                                   int *__restrict__ hist) {
+    __shared__ int cnt[256];
+    const int lane = threadIdx.x;
+    for (int d = lane; d < 256; d += kWave) cnt[d] = 0;
+    wave_lds_sync();
+    const size_t base = (size_t)blockIdx.x * kRsTile;
+    for (int k = lane; k < kRsTile; k += kWave) {
+        const size_t e = base + k;
+        if (e < (size_t)n) atomicAdd(&cnt[(int)((k64[e] >> shift) & 255u)], 1);
+    }
+    wave_lds_sync();
+    for (int d = lane; d < 256; d += kWave) hist[(size_t)d * nblk + blockIdx.x] = cnt[d];
+}
+
+// Stable scatter of one block's elements by digit: 64 elements at a time in
+// index order, each placed after the block's earlier elements of its digit
+// (the running slot in LDS) and after the lanes below it with the same digit
+// (the lanes whose eight digit-bit ballots all agree with its own).
+__global__ __launch_bounds__(kWave) void k_rs_scatter(
+    const unsigned long long *__restrict__ kin, const int *__restrict__ vin, int n, int shift,
+    int nblk, const int *__restrict__ off, unsigned long long *__restrict__ kout,
+    int *__restrict__ vout) {
+    __shared__ int run[256];
+    const int lane = threadIdx.x;
+    for (int d = lane; d < 256; d += kWave) run[d] = off[(size_t)d * nblk + blockIdx.x];
+    wave_lds_sync();
+    const size_t base = (size_t)blockIdx.x * kRsTile;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int k = 0; k < kRsTile; k += kWave) {
+        const size_t e = base + k + lane;
+        const bool live = e < (size_t)n;
+        const unsigned long long key = live ? kin[e] : 0ull;
+        const int v = live ? vin[e] : 0;
+        const int d = (int)((key >> shift) & 255u);
+        unsigned long long m = __builtin_amdgcn_ballot_w64(live);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1;
+            const unsigned long long bb = __builtin_amdgcn_ballot_w64(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const int dst = run[d] + __builtin_popcountll(m & below);
+        wave_lds_sync();   // every lane has read its digit's slot
+        if (live) {
+            kout[dst] = key;
+            vout[dst] = v;
+            if ((m >> lane) == 1ull) run[d] = dst + 1;   // the group's last lane
+        }
+        wave_lds_sync();
+    }
+}
+
+// rank[i] = place of particle i inside its cell in the stable order.
+__global__ void k_rs_rank(const unsigned long long *__restrict__ k64,
+                          const int *__restrict__ val, int n, const int *__restrict__ cell_start,
+                          int *__restrict__ rank) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    rank[val[p]] = p - cell_start[(int)(k64[p] >> kFineBits)];
+}
+
 // ---- receiver selection and compaction ---------------------------------------
 
 struct Thresholds { uint8_t t[64]; };
@@ -488,6 +582,34 @@ __global__ void k_item_write(const Cluster *__restrict__ clusters, int n_cluster
     if (c >= n_clusters) return;
     plan_items(c, clusters[c], cs, g, target, items + item_off[c],
                item_off[c + 1] - item_off[c] == 1 ? kItemSole : 0, half);
+}
+
+// Deterministic mode: the sums of every cluster with several items, added
+// in item order from the items' partial slots (3 doubles per item and
+// receiver slot); a cluster's only item stored its sums itself.
+__global__ __launch_bounds__(kWave) void k_item_reduce(
+    const Cluster *__restrict__ clusters, const int *__restrict__ n_cl,
+    const int *__restrict__ item_off, const double *__restrict__ partials, int csize,
+    const int *__restrict__ rperm, double *__restrict__ out, long long out_stride) {
+    const int nc = *n_cl;
+    const int r = threadIdx.x;
+    for (int c = blockIdx.x; c < nc; c += gridDim.x) {
+        const int i0 = item_off[c], i1 = item_off[c + 1];
+        if (i1 - i0 <= 1) continue;
+        const Cluster cl = clusters[c];
+        if (r >= cl.count) continue;
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        for (int it = i0; it < i1; ++it) {
+            const double *q = partials + ((size_t)it * csize + r) * 3;
+            sx += q[0];
+            sy += q[1];
+            sz += q[2];
+        }
+        double *o = out + (long long)cl.subset * out_stride + 3ll * rperm[cl.begin + r];
+        o[0] = sx;
+        o[1] = sy;
+        o[2] = sz;
+    }
 }
 
 __global__ void k_gather_weights(const double *__restrict__ w, const uint8_t *__restrict__ sel_s,
@@ -648,12 +770,14 @@ hipError_t launch_scan(const int *in, int *out, size_t n, int *bsum, hipStream_t
 
 hipError_t launch_scatter(const double *pos, const double *mass, const uint8_t *sel, int n,
                           const Geom &g, const int *key, const int *rank, const int *cell_start,
-                          int fp32, int csize, double4 *sp, int *perm, uint8_t *sel_s,
-                          double4 *sp2, int *perm2, uint8_t *sel2, hipStream_t s) {
+                          int fp32, int csize, bool stable, double4 *sp, int *perm,
+                          uint8_t *sel_s, double4 *sp2, int *perm2, uint8_t *sel2,
+                          hipStream_t s) {
     if (n == 0) return hipSuccess;
+    // stable ranks are already in fine order: every subtile goes straight out
+    const int keep_max = stable ? INT_MAX : (csize > kFineMin ? csize : kFineMin);
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, pos, mass, sel, n, g,
-                       key, rank, cell_start, fp32, csize > kFineMin ? csize : kFineMin, sp,
-                       perm, sel_s, sp2, perm2, sel2);
+                       key, rank, cell_start, fp32, keep_max, sp, perm, sel_s, sp2, perm2, sel2);
     return hipGetLastError();
 }
 
@@ -766,6 +890,44 @@ hipError_t launch_gather_weights(const double *grad_acc, const uint8_t *sel_s, c
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather_weights, dim3(grid_for(n, 256)), dim3(256), 0, s, grad_acc, sel_s,
                        perm, n, fp32, wa);
+    return hipGetLastError();
+}
+
+size_t stable_rank_hist_ints(int n) { return (size_t)256 * ((n + kRsTile - 1) / kRsTile); }
+
+hipError_t launch_stable_ranks(const double *pos, int n, const Geom &g, const int *key,
+                               const int *cell_start, unsigned long long *k64a,
+                               unsigned long long *k64b, int *va, int *vb, int *hist, int *bsum,
+                               int *rank, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int nblk = (n + kRsTile - 1) / kRsTile;
+    const long long ncells = (long long)g.nt3 * g.ns3;
+    int bits = kFineBits;
+    while (bits < 64 && (1ll << (bits - kFineBits)) < ncells) ++bits;
+    hipLaunchKernelGGL(k_rs_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, pos, n, g, key, k64a,
+                       va);
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kWave), 0, s, k64a, n, shift, nblk, hist);
+        hipError_t e = launch_scan(hist, hist, (size_t)256 * nblk, bsum, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kWave), 0, s, k64a, va, n, shift, nblk,
+                           hist, k64b, vb);
+        std::swap(k64a, k64b);
+        std::swap(va, vb);
+    }
+    hipLaunchKernelGGL(k_rs_rank, dim3(grid_for(n, 256)), dim3(256), 0, s, k64a, va, n,
+                       cell_start, rank);
+    return hipGetLastError();
+}
+
+hipError_t launch_item_reduce(const Cluster *clusters, const int *n_clusters_dev, int bound,
+                              const int *item_off, const double *partials, int csize,
+                              const int *rperm, double *out, long long out_stride,
+                              hipStream_t s) {
+    if (bound == 0) return hipSuccess;
+    const int grid = std::min(bound, 65536);
+    hipLaunchKernelGGL(k_item_reduce, dim3(grid), dim3(kWave), 0, s, clusters, n_clusters_dev,
+                       item_off, partials, csize, rperm, out, out_stride);
     return hipGetLastError();
 }
 

@@ -226,3 +226,16 @@ def test_noalloc_checks_arguments_before_the_handle(lib):
     rc = lib.p3m_sr_force_noalloc(None, ctypes.c_void_p(8), None, None, 100, 1.0, 0.01, 0.045, 7,
                                   out, None)
     assert rc == -1
+
+
+def test_deterministic_and_debug_limit_arguments(lib):
+    assert lib.p3m_sr_set_deterministic(None, 2) == -1
+    assert "0 or 1" in lib.p3m_sr_last_error().decode()
+    assert lib.p3m_sr_set_deterministic(None, 1) == -1
+    assert "NULL handle" in lib.p3m_sr_last_error().decode()
+    assert lib.p3m_sr_set_debug_limits(None, -5, -1) == -1
+    assert "max_workspace_bytes" in lib.p3m_sr_last_error().decode()
+    assert lib.p3m_sr_set_debug_limits(None, 0, -2) == -1
+    assert "fail_after" in lib.p3m_sr_last_error().decode()
+    assert lib.p3m_sr_set_debug_limits(None, 1 << 20, 3) == -1
+    assert "NULL handle" in lib.p3m_sr_last_error().decode()
