@@ -273,6 +273,15 @@ int p3m_sr_set_tune_cache(p3m_sr_handle h, const char *path);
 int p3m_sr_tune_status(p3m_sr_handle h, int *trials_timed, int *from_cache);
 
 /*
+ * Read an autotuner cache file with the parser the handles use, without a
+ * handle or a GPU: *entries = the entries a handle would load (lines that
+ * do not parse, or hold an invalid layout, are skipped), *lines = the lines
+ * read (either pointer may be NULL).  EINVAL for a NULL path or a file that
+ * cannot be opened.
+ */
+int p3m_sr_tune_cache_check(const char *path, int *entries, int *lines);
+
+/*
  * Fix the decomposition instead of autotuning (0 / -1 = automatic):
  *   subtiles_per_dim  subtiles per tile per dimension, 1..16 (section 2.1.3
  *                     "Subtiles");

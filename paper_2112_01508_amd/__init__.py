@@ -112,6 +112,8 @@ EXPORTS = {
     "p3m_sr_autotune_batched": ([_P, _P, _P, _P, _I64, _I, _P, _D, _D, _D, _I, _I, _P, _P], _I),
     "p3m_sr_set_tune_cache": ([_P, ctypes.c_char_p], _I),
     "p3m_sr_tune_status": ([_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], _I),
+    "p3m_sr_tune_cache_check": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_int)], _I),
     "p3m_kdk_step": ([_P, _P, _P, _P, _P, _I64, _D, _D, _D, _I, _D, _I, _D, _D, _I, _I, _I, _P],
                      _I),
     "p3m_kdk_get_stats": ([_P, ctypes.POINTER(KdkStats)], _I),
@@ -134,6 +136,15 @@ def load_library(path: str = LIB_PATH):
             fn.restype = res
         _lib = lib
         return lib
+
+
+def tune_cache_check(path):
+    """(entries, lines) of an autotuner cache file as a handle would read it
+    (p3m_sr_tune_cache_check; needs no GPU)."""
+    lib = load_library()
+    e, l = ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib.p3m_sr_tune_cache_check(os.fsencode(path), ctypes.byref(e), ctypes.byref(l)))
+    return e.value, l.value
 
 
 def _check(rc: int):

@@ -326,19 +326,36 @@ bool parse_entry(const std::string &line, TuneEntry &e) {
            valid_layout(e.val.csize, e.val.screen);
 }
 
+// Entries of a cache file (false if it cannot be opened); *lines counts
+// its lines.  Lines of any length are read whole.
+bool read_cache_file(const std::string &path, std::vector<TuneEntry> &out, int *lines) {
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    std::string line;
+    char buf[1024];
+    int nl = 0;
+    for (;;) {
+        line.clear();
+        bool got = false;
+        while (std::fgets(buf, sizeof(buf), f)) {
+            got = true;
+            line += buf;
+            if (line.back() == '\n') break;
+        }
+        if (!got) break;
+        ++nl;
+        TuneEntry e;
+        if (parse_entry(line, e)) out.push_back(e);
+    }
+    std::fclose(f);
+    if (lines) *lines = nl;
+    return true;
+}
+
 void load_cache(p3m_sr_context *h) {
     h->cache.clear();
     if (h->cache_path.empty()) return;
-    FILE *f = std::fopen(h->cache_path.c_str(), "r");
-    if (!f) return;
-    std::string line;
-    char buf[1024];
-    while (std::fgets(buf, sizeof(buf), f)) {
-        line = buf;
-        TuneEntry e;
-        if (parse_entry(line, e)) h->cache.push_back(e);
-    }
-    std::fclose(f);
+    if (!read_cache_file(h->cache_path, h->cache, nullptr)) return;
     // this device's entries are the layouts calls use until they are re-tuned
     for (const TuneEntry &e : h->cache)
         if (e.device == h->device_id) h->tuned[e.key] = e.val;
@@ -1309,6 +1326,17 @@ int p3m_sr_set_tune_cache(p3m_sr_handle h, const char *path) {
     if ((rc = check_handle(h))) return rc;
     h->cache_path = path ? std::string(path) : default_cache_path();
     load_cache(h);
+    return P3M_OK;
+}
+
+int p3m_sr_tune_cache_check(const char *path, int *entries, int *lines) {
+    if (!path) return set_error(P3M_EINVAL, "NULL path");
+    std::vector<TuneEntry> v;
+    int nl = 0;
+    if (!read_cache_file(path, v, &nl))
+        return set_error(P3M_EINVAL, "cannot open the cache file %.200s", path);
+    if (entries) *entries = (int)v.size();
+    if (lines) *lines = nl;
     return P3M_OK;
 }
 
