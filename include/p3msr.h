@@ -25,9 +25,14 @@
  *     [0, box) are wrapped into the box.  Positions must be finite.
  *   - mass is n FP64 values holding G*m_j; NULL means all ones.
  *   - Every call is asynchronous on `stream` (a hipStream_t passed as
- *     void*, NULL = the null stream) apart from one small device-to-host
- *     read of work counts inside each force call; pointers must stay valid
- *     until the stream's work has completed.
+ *     void*, NULL = the null stream); pointers must stay valid until the
+ *     stream's work has completed.  The force calls do not wait for the
+ *     GPU: the work-item array is sized by a bound on the item count, and
+ *     the pair kernels read the count on the device.  Two cases wait for
+ *     the count instead (one small device-to-host read): the deterministic
+ *     mode, and layouts whose item bound passes 1 GiB (large rung-batched
+ *     calls with several subtiles per tile).  A call that grows the
+ *     workspace waits for the stream before freeing the old buffer.
  *   - Outputs are fully overwritten (rows of non-receivers become 0).
  *   - Errors return a negative code, leave outputs untouched when detected
  *     before any launch, and set a per-thread message (p3m_sr_last_error).

@@ -273,6 +273,10 @@ int take(p3m_sr_context *h, SrWork &w, DevBuf &b, size_t bytes, hipStream_t s) {
 
 bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
 
+// Largest work-item array sized by the bound on the item count; beyond it
+// the call waits for the count and sizes the array exactly.
+constexpr size_t kItemBoundBytes = size_t(1) << 30;
+
 // ---- persistent autotuner cache ----------------------------------------------
 //
 // A JSON file holding one object per line:
@@ -624,6 +628,17 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     }
     if (shape != SHAPE_POLY && (rc = take(h, w, w.htab, kTabFloats * sizeof(float), s)))
         return rc;
+    // work items: the array is sized by the bound on their count (plan_items
+    // gives a cluster at most plan_items_bound), so the host never waits for
+    // the count, unless that bound passes kItemBoundBytes (or what is left of
+    // the fixed workspace), or in the deterministic mode, whose partial slots
+    // are per item: then the host waits for the count (below)
+    const size_t item_bound = cl_bound * (size_t)plan_items_bound(g.ns3, mutual ? 1 : 0);
+    bool wait_count = det || item_bound * sizeof(Item) > kItemBoundBytes ||
+                      item_bound > (size_t)INT_MAX;
+    if (!wait_count && w.base && w.used + item_bound * sizeof(Item) + 256 > w.size)
+        wait_count = true;
+    if (!wait_count && (rc = take(h, w, w.items, sizeof(Item) * item_bound, s))) return rc;
 
     int *key = (int *)w.key.p, *rank = (int *)w.rank.p, *cells = (int *)w.cells.p;
     double4 *sp = (double4 *)w.sp.p;
@@ -697,9 +712,9 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
                               mutual ? 1 : 0, itemcnt, s));
     P3M_HIP(launch_scan(itemcnt, itemcnt, cl_bound, bsum, s));
     P3M_HIP(launch_totals(flags + nflags, ncl + ncl_len, itemcnt + cl_bound, h->host_tot, s));
-    P3M_HIP(hipEventRecord(h->tot_ev, s));
+    if (wait_count) P3M_HIP(hipEventRecord(h->tot_ev, s));
 
-    // work that needs no totals runs while the host waits for them
+    // work that needs no totals (the host waits for them only with wait_count)
     double4 *wa = r.backward ? (double4 *)w.wa.p : nullptr;
     if (r.backward) P3M_HIP(launch_gather_weights(r.grad_acc, sel_s, perm, n, fp32, wa, s));
     // with every particle a receiver the receivers are sp / perm / wa as they are
@@ -712,21 +727,18 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     else P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, s));
     if (shape != SHAPE_POLY)
         P3M_HIP(launch_build_htab(shape, h->cfg_tab_n, g, (float *)w.htab.p, s));
-    P3M_HIP(hipEventSynchronize(h->tot_ev));
-    const int n_recv = h->host_tot[0], n_clusters = h->host_tot[1], n_items = h->host_tot[2];
-    st.receivers = n_recv;
-    st.clusters = n_clusters;
-    st.items = n_items;
-
-    if ((rc = take(h, w, w.items, sizeof(Item) * (size_t)(n_items > 0 ? n_items : 1), s)))
-        return rc;
+    // receivers, clusters and items reach the stats when they are asked for
+    st.receivers = st.clusters = st.items = -1;
+    if (wait_count) {
+        P3M_HIP(hipEventSynchronize(h->tot_ev));
+        const size_t n_items = (size_t)std::max(h->host_tot[2], 1);
+        if ((rc = take(h, w, w.items, sizeof(Item) * n_items, s))) return rc;
+        if (det && (rc = take(h, w, w.partials, sizeof(double) * 3 * (size_t)csize * n_items, s)))
+            return rc;
+    }
     Item *items = (Item *)w.items.p;
-    if (det && (rc = take(h, w, w.partials,
-                          sizeof(double) * 3 * (size_t)csize * (size_t)(n_items > 0 ? n_items : 1),
-                          s)))
-        return rc;
-    P3M_HIP(launch_item_write(clusters, n_clusters, cells, g, target, mutual ? 1 : 0, itemcnt,
-                              items, s));
+    P3M_HIP(launch_item_write(clusters, ncl + ncl_len, (int)cl_bound, cells, g, target,
+                              mutual ? 1 : 0, itemcnt, items, s));
 
     // ---- pairs ----
     PairArgs a{};
@@ -742,7 +754,7 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     a.out = r.out;
     a.out_stride = 3ll * n;
     a.counters = counters;
-    a.n_items = n_items;
+    a.n_items_dev = itemcnt + cl_bound;
     a.partials = det ? (double *)w.partials.p : nullptr;
     a.unit_mass = r.mass ? 0 : 1;
     a.csize = csize;
@@ -771,11 +783,10 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
         if (slot_b == 0) slot_b = pairs_blocks_per_cu(mode, screen, shape, csize, unit, soft);
         bpc = slot_b;
     }
-    long long waves_wanted = (n_items + 0ll);
-    long long grid = std::min<long long>((waves_wanted + 3) / 4, (long long)h->n_cu * bpc);
+    // every resident block (the kernels read the item count and size their
+    // queue claims on the device; blocks without work leave at once)
+    long long grid = (long long)h->n_cu * bpc;
     if (grid < 1) grid = 1;
-    // items per queue atomic: about 32 claims per wave, at most 8 items each
-    a.batch = (int)std::max<long long>(1, std::min<long long>(8, n_items / (grid * 4 * 32)));
     if (h->timing) P3M_HIP(hipEventRecord(h->ev[1], s));
     if (mutual) P3M_HIP(launch_pairs_mutual(a, (int)grid, s));
     else P3M_HIP(launch_pairs(mode, screen, shape, a, (int)grid, s));
@@ -1403,6 +1414,14 @@ int p3m_sr_get_stats(p3m_sr_handle h, p3m_sr_stats *out) {
     if (!out) return set_error(P3M_EINVAL, "NULL stats pointer");
     if ((rc = set_device(h))) return rc;
     p3m_sr_stats st = h->stats;
+    if (st.n > 0 && st.items < 0) {
+        // the totals of the latest run of the call (k_totals writes them to
+        // pinned memory; a graph replay of the call writes them again)
+        P3M_HIP(hipStreamSynchronize(h->last_stream));
+        st.receivers = h->host_tot[0];
+        st.clusters = h->host_tot[1];
+        st.items = h->host_tot[2];
+    }
     if (h->last_counters && st.n > 0) {
         Counters c{};
         P3M_HIP(hipStreamSynchronize(h->last_stream));

@@ -749,19 +749,32 @@ struct ItemCursor {
     int victim = 0;         // chunks tried so far, from the home chunk on
 };
 
-__device__ inline int next_item(const PairArgs &a, int lane, ItemCursor &q) {
+// The launch's item count (read on the device) and the items a wave claims
+// per queue atomic: about 32 claims per wave, at most 8 items each.
+struct ItemQueue {
+    int n;
+    int batch;
+};
+__device__ inline ItemQueue item_queue(const PairArgs &a) {
+    const int n = __builtin_amdgcn_readfirstlane(*a.n_items_dev);
+    const long long waves = (long long)gridDim.x * (blockDim.x / kWave);
+    const long long b = (long long)n / (waves * 32);
+    return ItemQueue{n, (int)(b < 1 ? 1 : (b > 8 ? 8 : b))};
+}
+
+__device__ inline int next_item(const PairArgs &a, const ItemQueue &iq, int lane, ItemCursor &q) {
     if (q.cur < q.end) return q.cur++;
     const int home = (int)(blockIdx.x % kXcds);
     while (q.victim < kXcds) {
         const int x = (home + q.victim) % kXcds;
-        const int c0 = (int)((long long)a.n_items * x / kXcds);
-        const int c1 = (int)((long long)a.n_items * (x + 1) / kXcds);
+        const int c0 = (int)((long long)iq.n * x / kXcds);
+        const int c1 = (int)((long long)iq.n * (x + 1) / kXcds);
         int got = 0;
-        if (lane == 0) got = atomicAdd(&a.queue[x], a.batch);
+        if (lane == 0) got = atomicAdd(&a.queue[x], iq.batch);
         got = __builtin_amdgcn_readfirstlane(got);
         if (c0 + got < c1) {
             q.cur = c0 + got;
-            q.end = min(c0 + got + a.batch, c1);
+            q.end = min(c0 + got + iq.batch, c1);
             return q.cur++;
         }
         ++q.victim;
@@ -832,7 +845,8 @@ void k_pairs(PairArgs a) {
     void *wlist = wlists[SCREEN && BWD ? threadIdx.x / kWave : 0];
     ItemCursor cursor;
     WaveCounts wc;
-    for (int it = next_item(a, lane, cursor); it >= 0; it = next_item(a, lane, cursor)) {
+    const ItemQueue iq = item_queue(a);
+    for (int it = next_item(a, iq, lane, cursor); it >= 0; it = next_item(a, iq, lane, cursor)) {
         const Item item = a.items[it];
         const Cluster cl = a.clusters[item.cluster];
         // receivers replicated over G lane groups; lanes past G*cnt are idle
@@ -1280,7 +1294,8 @@ __global__ __launch_bounds__(kForceBlock) void k_pairs_mutual(PairArgs a) {
     const int row = lane >> 4, l = lane & 15;
     ItemCursor cursor;
     unsigned long long pairs = 0, steps = 0, screened = 0, rare = 0;
-    for (int it = next_item(a, lane, cursor); it >= 0; it = next_item(a, lane, cursor)) {
+    const ItemQueue iq = item_queue(a);
+    for (int it = next_item(a, iq, lane, cursor); it >= 0; it = next_item(a, iq, lane, cursor)) {
         const Item item = a.items[it];
         const Cluster cl = a.clusters[item.cluster];
         const int cnt = __builtin_amdgcn_readfirstlane(cl.count);
@@ -1425,7 +1440,6 @@ static PairsFn pairs_kernel(int mode, int screen, int tab, int csize, bool unit,
 
 hipError_t launch_pairs(int mode, int screen, int tab, const PairArgs &a, int grid,
                         hipStream_t s) {
-    if (a.n_items <= 0) return hipSuccess;
     const bool soft = a.g.eps_b > 0.0;
     if (mode == FWD_F32 && tab != SHAPE_POLY && !soft) {
         const int nf = tab == SHAPE_TAB_LINEAR ? 2 * a.tab_n : a.tab_n;
@@ -1439,7 +1453,6 @@ hipError_t launch_pairs(int mode, int screen, int tab, const PairArgs &a, int gr
 }
 
 hipError_t launch_pairs_mutual(const PairArgs &a, int grid, hipStream_t s) {
-    if (a.n_items <= 0) return hipSuccess;
     const MutualFn fn = mutual_kernel(a.csize, a.unit_mass != 0);
     if (!fn) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kForceBlock), 0, s, a);

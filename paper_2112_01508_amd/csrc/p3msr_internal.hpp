@@ -16,6 +16,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include <cstddef>
 #include <cstdint>
 
@@ -127,6 +129,76 @@ __device__ inline int wave_grouped_rank(int *counter, int key, bool live) {
     return live ? base + my_off : 0;
 }
 
+// ---- work items ---------------------------------------------------------------
+
+__device__ inline int neighbour_tile(int tile, int t, const Geom &g) {
+    int tx = tile / (g.nt * g.nt), ty = (tile / g.nt) % g.nt, tz = tile % g.nt;
+    int nx = tx + t / 9 - 1, ny = ty + (t / 3) % 3 - 1, nz = tz + t % 3 - 1;
+    nx += nx < 0 ? g.nt : (nx >= g.nt ? -g.nt : 0);
+    ny += ny < 0 ? g.nt : (ny >= g.nt ? -g.nt : 0);
+    nz += nz < 0 ? g.nt : (nz >= g.nt ? -g.nt : 0);
+    return (nx * g.nt + ny) * g.nt + nz;
+}
+
+// Greedy grouping of the 27 neighbour tiles into items of about `target`
+// supplier candidates (before subtile culling); a tile holding more than
+// `target` particles is split by subtile ranges.  Returns the item count and
+// writes the items when `out` is non-null.  At most 2 per stencil tile plus
+// one with one subtile per tile (a flush and the tile itself), at most
+// 1 + ns^3 per tile plus one otherwise (plan_items_bound).
+//
+// half != 0 (pairs evaluated once, for both partners): only the upper half
+// of the stencil, t = 13 .. 26, whose periodic mirror images are the lower
+// half; in the own tile (t = 13) only the particles after the cluster count,
+// and every cluster gets at least one item, so that its own pairs are
+// evaluated.  The first item of a cluster carries kItemFirst.
+// Upper bound on the items plan_items gives one cluster.
+inline long long plan_items_bound(int ns3, int half) {
+    const long long tiles = half ? 14 : 27;
+    return tiles * (ns3 == 1 ? 2 : 1 + ns3) + 2;
+}
+
+__device__ inline int plan_items(int cidx, const Cluster &cl, const int *__restrict__ cs,
+                                 const Geom &g, int target, Item *out, int sole, int half) {
+    int n = 0, acc = 0;
+    const int t_begin = half ? 13 : 0;
+    int t0 = t_begin;
+    auto emit = [&](int a, int b, int s0, int s1) {
+        if (out) {
+            Item it;
+            it.cluster = cidx;
+            it.tiles = a | (b << 8);
+            it.subs = s0 | (s1 << 16);
+            it.sole = sole | (n == 0 ? kItemFirst : 0);
+            out[n] = it;
+        }
+        ++n;
+    };
+    for (int t = t_begin; t < 27; ++t) {
+        int nb = neighbour_tile(cl.tile, t, g);
+        int w = cs[(size_t)(nb + 1) * g.ns3] - cs[(size_t)nb * g.ns3];
+        if (half && t == 13) w = cs[(size_t)(nb + 1) * g.ns3] - (cl.begin + cl.count);
+        if (w > target) {
+            if (acc > 0) emit(t0, t, 0, g.ns3);
+            int parts = min((w + target - 1) / target, g.ns3);
+            for (int q = 0; q < parts; ++q)
+                emit(t, t + 1, q * g.ns3 / parts, (q + 1) * g.ns3 / parts);
+            t0 = t + 1;
+            acc = 0;
+        } else if (acc + w > target) {
+            emit(t0, t, 0, g.ns3);
+            t0 = t;
+            acc = w;
+        } else {
+            if (acc == 0 && w == 0) t0 = t + 1;   // skip leading empty tiles
+            acc += w;
+        }
+    }
+    if (acc > 0) emit(t0, 27, 0, g.ns3);
+    if (half && n == 0) emit(13, 14, 0, g.ns3);
+    return n;
+}
+
 // ---- launchers (host functions defined in the .hip files) -----------------
 
 // sort.hip
@@ -191,9 +263,11 @@ hipError_t launch_cluster_write(const int *cell_start, const int *scan, const in
 hipError_t launch_item_count(const Cluster *clusters, const int *n_clusters_dev,
                              int cluster_bound, const int *cell_start, const Geom &g,
                              int target, int half, int *item_cnt, hipStream_t s);
-hipError_t launch_item_write(const Cluster *clusters, int n_clusters, const int *cell_start,
-                             const Geom &g, int target, int half, const int *item_off,
-                             Item *items, hipStream_t s);
+// every cluster's items at their offsets item_off (the scanned counts; the
+// array holds them all); the cluster count is read on the device
+hipError_t launch_item_write(const Cluster *clusters, const int *n_clusters_dev, int bound,
+                             const int *cell_start, const Geom &g, int target, int half,
+                             const int *item_off, Item *items, hipStream_t s);
 // 32-bin histogram of particles per tile (log2 bins; bin 0: empty tiles),
 // the occupancy signature the autotuner files its results under
 hipError_t launch_tile_hist(const int *cell_start, const Geom &g, int *hist32, hipStream_t s);
@@ -239,8 +313,8 @@ struct PairArgs {
     double *out;             // n_sub x n x 3, zeroed before the launch
     long long out_stride;    // elements per subset in out (3 n)
     Counters *counters;
-    int n_items;
-    int batch;               // items a wave claims per queue atomic (>= 1)
+    // the item count, read on the device (the host need not wait for it)
+    const int *n_items_dev;
     int unit_mass;           // no mass array: every mu_j is 1 (forward kernels specialise)
     int csize;               // cluster size (receivers per cluster, 8..64)
     // tabulated FP32 forward shape (kernel kind 1 or 2, see force.hip)

@@ -59,22 +59,51 @@ __device__ inline int key_of(int cx, int cy, int cz, const Geom &g) {
     return tile * g.ns3 + (sx * g.ns + sy) * g.ns + sz;
 }
 
-// Cell key and rank inside the cell, one atomic per distinct cell of a wave
-// (a dense cell's particles often share a wave; see wave_grouped_rank).
-__global__ void k_keys(const double *__restrict__ pos, int n, Geom g, int *__restrict__ key,
-                       int *__restrict__ rank, int *__restrict__ cell_count) {
+// Cell key and rank inside the cell, with one global atomic per distinct
+// cell of a block of kKeysBlock particles: the block's keys are counted in
+// an LDS hash table first (a dense halo cell's particles, which share blocks,
+// would otherwise hit one counter from every wave that holds any of them,
+// and those atomics serialise on its address).
+constexpr int kKeysBlock = 1024;
+constexpr int kKeysSlots = 2 * kKeysBlock;   // open addressing, at most half full
+
+__global__ __launch_bounds__(kKeysBlock) void k_keys(const double *__restrict__ pos, int n, Geom g,
+                                                     int *__restrict__ key,
+                                                     int *__restrict__ rank,
+                                                     int *__restrict__ cell_count) {
+    __shared__ int skey[kKeysSlots];
+    __shared__ int scnt[kKeysSlots];
+    for (int t = threadIdx.x; t < kKeysSlots; t += blockDim.x) {
+        skey[t] = -1;
+        scnt[t] = 0;
+    }
+    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = i < n;
-    int k = -1;
+    int slot = 0, local = 0, k = -1;
     if (live) {
         const double wx = wrap_coord(pos[3 * (size_t)i], g);
         const double wy = wrap_coord(pos[3 * (size_t)i + 1], g);
         const double wz = wrap_coord(pos[3 * (size_t)i + 2], g);
         k = key_of(cell_of(wx, g), cell_of(wy, g), cell_of(wz, g), g);
         key[i] = k;
+        // k >= 0 and the table never fills, so the probe ends
+        slot = (int)(((unsigned)k * 2654435761u) >> 21) & (kKeysSlots - 1);
+        for (;;) {
+            const int old = atomicCAS(&skey[slot], -1, k);
+            if (old == -1 || old == k) break;
+            slot = (slot + 1) & (kKeysSlots - 1);
+        }
+        local = atomicAdd(&scnt[slot], 1);
     }
-    const int rk = wave_grouped_rank(cell_count, k, live);
-    if (live) rank[i] = rk;
+    __syncthreads();
+    // one global atomic per occupied slot; its base replaces the count
+    for (int t = threadIdx.x; t < kKeysSlots; t += blockDim.x) {
+        const int kk = skey[t];
+        if (kk >= 0) scnt[t] = atomicAdd(&cell_count[kk], scnt[t]);
+    }
+    __syncthreads();
+    if (live) rank[i] = scnt[slot] + local;
 }
 
 // ---- exclusive scan (reduce / top / down-sweep) -----------------------------
@@ -507,66 +536,6 @@ __global__ void k_cluster_write(const int *__restrict__ cs, const int *__restric
 
 // ---- work items ------------------------------------------------------------
 
-__device__ inline int neighbour_tile(int tile, int t, const Geom &g) {
-    int tx = tile / (g.nt * g.nt), ty = (tile / g.nt) % g.nt, tz = tile % g.nt;
-    int nx = tx + t / 9 - 1, ny = ty + (t / 3) % 3 - 1, nz = tz + t % 3 - 1;
-    nx += nx < 0 ? g.nt : (nx >= g.nt ? -g.nt : 0);
-    ny += ny < 0 ? g.nt : (ny >= g.nt ? -g.nt : 0);
-    nz += nz < 0 ? g.nt : (nz >= g.nt ? -g.nt : 0);
-    return (nx * g.nt + ny) * g.nt + nz;
-}
-
-// Greedy grouping of the 27 neighbour tiles into items of about `target`
-// supplier candidates (before subtile culling); a tile holding more than
-// `target` particles is split by subtile ranges.  Returns the item count and
-// writes the items when `out` is non-null.
-//
-// half != 0 (pairs evaluated once, for both partners): only the upper half
-// of the stencil, t = 13 .. 26, whose periodic mirror images are the lower
-// half; in the own tile (t = 13) only the particles after the cluster count,
-// and every cluster gets at least one item, so that its own pairs are
-// evaluated.  The first item of a cluster carries kItemFirst.
-__device__ int plan_items(int cidx, const Cluster &cl, const int *__restrict__ cs, const Geom &g,
-                          int target, Item *out, int sole, int half) {
-    int n = 0, acc = 0;
-    const int t_begin = half ? 13 : 0;
-    int t0 = t_begin;
-    auto emit = [&](int a, int b, int s0, int s1) {
-        if (out) {
-            Item it;
-            it.cluster = cidx;
-            it.tiles = a | (b << 8);
-            it.subs = s0 | (s1 << 16);
-            it.sole = sole | (n == 0 ? kItemFirst : 0);
-            out[n] = it;
-        }
-        ++n;
-    };
-    for (int t = t_begin; t < 27; ++t) {
-        int nb = neighbour_tile(cl.tile, t, g);
-        int w = cs[(size_t)(nb + 1) * g.ns3] - cs[(size_t)nb * g.ns3];
-        if (half && t == 13) w = cs[(size_t)(nb + 1) * g.ns3] - (cl.begin + cl.count);
-        if (w > target) {
-            if (acc > 0) emit(t0, t, 0, g.ns3);
-            int parts = min((w + target - 1) / target, g.ns3);
-            for (int q = 0; q < parts; ++q)
-                emit(t, t + 1, q * g.ns3 / parts, (q + 1) * g.ns3 / parts);
-            t0 = t + 1;
-            acc = 0;
-        } else if (acc + w > target) {
-            emit(t0, t, 0, g.ns3);
-            t0 = t;
-            acc = w;
-        } else {
-            if (acc == 0 && w == 0) t0 = t + 1;   // skip leading empty tiles
-            acc += w;
-        }
-    }
-    if (acc > 0) emit(t0, 27, 0, g.ns3);
-    if (half && n == 0) emit(13, 14, 0, g.ns3);
-    return n;
-}
-
 __global__ void k_item_count(const Cluster *__restrict__ clusters, const int *__restrict__ n_cl,
                              int bound, const int *__restrict__ cs, Geom g, int target, int half,
                              int *__restrict__ item_cnt) {
@@ -575,13 +544,16 @@ __global__ void k_item_count(const Cluster *__restrict__ clusters, const int *__
     item_cnt[c] = c < *n_cl ? plan_items(c, clusters[c], cs, g, target, nullptr, 0, half) : 0;
 }
 
-__global__ void k_item_write(const Cluster *__restrict__ clusters, int n_clusters,
-                             const int *__restrict__ cs, Geom g, int target, int half,
+// Items of every cluster at their scanned offsets; the cluster count is
+// read on the device.
+__global__ void k_item_write(const Cluster *__restrict__ clusters, const int *__restrict__ n_cl,
+                             int bound, const int *__restrict__ cs, Geom g, int target, int half,
                              const int *__restrict__ item_off, Item *__restrict__ items) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_clusters) return;
-    plan_items(c, clusters[c], cs, g, target, items + item_off[c],
-               item_off[c + 1] - item_off[c] == 1 ? kItemSole : 0, half);
+    if (c >= bound || c >= *n_cl) return;
+    const int off = item_off[c];
+    plan_items(c, clusters[c], cs, g, target, items + off,
+               item_off[c + 1] - off == 1 ? kItemSole : 0, half);
 }
 
 // Deterministic mode: the sums of every cluster with several items, added
@@ -749,8 +721,8 @@ hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s) {
 hipError_t launch_keys(const double *pos, int n, const Geom &g, int *key, int *rank,
                        int *cell_count, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, pos, n, g, key, rank,
-                       cell_count);
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, kKeysBlock)), dim3(kKeysBlock), 0, s, pos, n, g,
+                       key, rank, cell_count);
     return hipGetLastError();
 }
 
@@ -859,12 +831,12 @@ hipError_t launch_item_count(const Cluster *clusters, const int *n_clusters_dev,
     return hipGetLastError();
 }
 
-hipError_t launch_item_write(const Cluster *clusters, int n_clusters, const int *cs,
-                             const Geom &g, int target, int half, const int *item_off,
-                             Item *items, hipStream_t s) {
-    if (n_clusters == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_item_write, dim3(grid_for(n_clusters, 128)), dim3(128), 0, s, clusters,
-                       n_clusters, cs, g, target, half, item_off, items);
+hipError_t launch_item_write(const Cluster *clusters, const int *n_clusters_dev, int bound,
+                             const int *cs, const Geom &g, int target, int half,
+                             const int *item_off, Item *items, hipStream_t s) {
+    if (bound == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_item_write, dim3(grid_for(bound, 128)), dim3(128), 0, s, clusters,
+                       n_clusters_dev, bound, cs, g, target, half, item_off, items);
     return hipGetLastError();
 }
 
