@@ -53,9 +53,10 @@ def parse():
     ap.add_argument("--no-cpu-tiled", action="store_true",
                     help="skip the oracle's cell-list walk on the full uniform32, diff64 and "
                          "clustered128 sets (about 20 s on 16 host threads)")
-    ap.add_argument("--legs", default="adjoint,batched,softened,long_range,kdk,shapes",
+    ap.add_argument("--legs", default="adjoint,batched,softened,long_range,kdk,shapes,deterministic",
                     help="extra measured legs beside the forward force: adjoint, batched, "
-                         "softened, long_range, kdk, shapes")
+                         "softened, long_range, kdk, shapes, deterministic; and, not run by "
+                         "default, subtiles (fixed subtile counts against the autotuner)")
     ap.add_argument("--batched-workload", default="clustered256")
     return ap.parse_args()
 
@@ -297,6 +298,107 @@ def kdk_leg(torch, ctx, pos, mass, wl, repeats=2):
     return res
 
 
+def deterministic_leg(torch, ctx, pos, mass, wl, steps, warmup, layout):
+    """The deterministic mode (p3m_sr_set_deterministic) against the default
+    atomic mode in the same layout (screen 2 runs as screen 1 there, so the
+    layout given is the screened one): time per call, pair-kernel time, and
+    whether two deterministic calls agree bit for bit."""
+    out = {"layout": dict(zip(("subtiles_per_dim", "item_target", "cluster_size", "screen"),
+                              layout))}
+    ctx.set_config(*layout)
+    try:
+        for prec in ("fp32", "fp64"):
+            res = {}
+            for det in (False, True):
+                ctx.set_deterministic(det)
+                _, wall, st, pairs_ms, build_ms = time_steps(torch, ctx, pos, mass, wl, prec,
+                                                             max(2, steps // 2), warmup)
+                res["det" if det else "atomic"] = {"ms_per_step": wall * 1e3,
+                                                   "pair_kernel_ms": pairs_ms,
+                                                   "build_ms": build_ms}
+            kw = dict(box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut, precision=prec)
+            a = ctx.force(pos, mass, None, **kw).cpu().numpy()
+            b = ctx.force(pos, mass, None, **kw).cpu().numpy()
+            res["bitwise_repeat"] = a.tobytes() == b.tobytes()
+            ctx.set_deterministic(False)
+            out[prec] = res
+            log("deterministic", prec, res)
+    finally:
+        ctx.set_deterministic(False)
+        ctx.set_config()
+    return out
+
+
+def subtiles_leg(torch, p3):
+    """Fixed subtiles per tile dimension (1..4; items of 4096, 32-receiver
+    clusters, screen 1, and screen 2 for the FP32 forward) against the
+    autotuner's choice (section 2.1.3, "Subtiles"; the paper's subtile
+    experiment), on the diff64 set (forward and adjoint) and the rung-batched
+    clustered256 launch, FP32 and FP64.  Pair-kernel ms (HIP events, median)."""
+    from workloads import make_workload
+    dev = torch.device("cuda", 0)
+    rows = []
+    for name in ("diff64", "clustered256"):
+        log("subtiles: generating", name)
+        wl = make_workload(name, with_rungs=(name == "clustered256"))
+        pos = torch.from_numpy(wl.pos).to(dev)
+        ctx = p3.Context(0)
+        if name == "clustered256":
+            rung = torch.from_numpy(wl.rung).to(dev)
+            thr = list(range(8))
+            out = torch.empty((8, wl.n, 3), dtype=torch.float64, device=dev)
+            calls = [("batched", prec) for prec in ("fp32", "fp64")]
+        else:
+            gen = torch.Generator(device=dev).manual_seed(4003)
+            w = torch.randn((wl.n, 3), dtype=torch.float64, device=dev, generator=gen)
+            out = torch.empty((wl.n, 3), dtype=torch.float64, device=dev)
+            calls = [(k, prec) for k in ("forward", "adjoint") for prec in ("fp32", "fp64")]
+        for kind, prec in calls:
+            kw = dict(box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut, precision=prec)
+            if kind == "batched":
+                fn, reps = (lambda: ctx.force_batched(pos, None, rung, thr, out=out, **kw)), 3
+            elif kind == "forward":
+                fn, reps = (lambda: ctx.force(pos, None, None, out=out, **kw)), 7
+            else:
+                fn, reps = (lambda: ctx.force_backward(pos, None, None, w, **kw)), 7
+
+            def timed():
+                fn()
+                ctx.set_timing(True)
+                ms = []
+                for _ in range(reps):
+                    fn()
+                    ms.append(ctx.stats()["ms_pairs"])
+                ctx.set_timing(False)
+                st = ctx.stats()
+                return statistics.median(ms), st
+
+            for screen in ([1, 2] if (kind == "forward" and prec == "fp32") else [1]):
+                for ns in (1, 2, 3, 4):
+                    ctx.set_config(ns, 4096, 32, screen)
+                    ms, st = timed()
+                    rows.append({"workload": name, "call": kind, "precision": prec, "ns": ns,
+                                 "screen": screen, "pair_kernel_ms": ms})
+                    log("subtiles", rows[-1])
+            ctx.set_config()
+            t0 = time.perf_counter()
+            if kind == "batched":
+                ctx.autotune_batched(pos, None, rung, thr, out=out, **kw)
+            else:
+                ctx.autotune(pos, None, None, level=2, adjoint=(kind == "adjoint"), **kw)
+            tune_s = time.perf_counter() - t0
+            ms, st = timed()
+            rows.append({"workload": name, "call": kind, "precision": prec, "tuned": True,
+                         "ns": st["subtiles_per_dim"], "item_target": st["item_target"],
+                         "cluster_size": st["cluster_size"], "screen": st["screen"],
+                         "pair_kernel_ms": ms, "tune_s": tune_s})
+            log("subtiles", rows[-1])
+        ctx.close()
+        del pos, out
+        torch.cuda.empty_cache()
+    return rows
+
+
 def batched_leg(torch, p3, name, steps, warmup, layouts=None, tune=True):
     """All 8 nested rung subsets (rung >= k, k = 0..7) in one persistent launch,
     in the layout the autotuner picks for this batched call on its own
@@ -532,6 +634,14 @@ def main():
         line["shapes"] = shapes_leg(torch, ctx, pos, mass, wl, args.steps, args.warmup)
     if "kdk" in legs:
         line["kdk"] = kdk_leg(torch, ctx, pos, mass, wl)
+    if "deterministic" in legs:
+        st32 = results["fp32"]["stats"]
+        layout = (st32["subtiles_per_dim"], st32["item_target"], st32["cluster_size"],
+                  min(st32["screen"], 1))
+        line["deterministic"] = deterministic_leg(torch, ctx, pos, mass, wl, args.steps,
+                                                  args.warmup, layout)
+    if "subtiles" in legs:
+        line["subtiles"] = subtiles_leg(torch, p3)
     if "batched" in legs:
         layouts = {p: tuple(results[p]["stats"][k] for k in
                             ("subtiles_per_dim", "item_target", "cluster_size", "screen"))
