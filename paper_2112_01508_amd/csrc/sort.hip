@@ -208,6 +208,89 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const int *in, int *ou
     }
 }
 
+// Single-pass exclusive scan (decoupled look-back).  Each block takes the
+// next tile number from a counter, so every tile before it belongs to a
+// block that is already running; it scans its tile, publishes the tile's
+// sum at once (nothing delays that), then walks back over the tiles before
+// it, adding their sums until it meets a published inclusive prefix, and
+// publishes its own.  status[t] (zeroed before the launch): 0 nothing yet,
+// 1 << 32 | sum, or 2 << 32 | inclusive prefix.  A wait longer than
+// kScan1Spins polls (which a running predecessor cannot cause) ends the wait
+// anyway and raises *stall.  out[n] = the total; in may equal out.
+constexpr unsigned long long kScanSum = 1ull << 32, kScanPrefix = 2ull << 32;
+constexpr int kScan1Spins = 1 << 20;
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_1pass(const int *in, int *out, size_t n,
+                                                           unsigned long long *status, int *ctr,
+                                                           unsigned long long *stall) {
+    __shared__ int lds[kScanBlock / kWave];
+    __shared__ int tile[kScanTile + kScanTile / 16];
+    __shared__ int s_tile, s_excl;
+    if (threadIdx.x == 0) s_tile = atomicAdd(ctr, 1);
+    __syncthreads();
+    const int t = s_tile;
+    const size_t base = (size_t)t * kScanTile;
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        const int e = k * kScanBlock + threadIdx.x;
+        const size_t i = base + e;
+        tile[scan_pad(e)] = i < n ? in[i] : 0;
+    }
+    __syncthreads();
+    const int first = threadIdx.x * kScanPerThread;
+    int v[kScanPerThread];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        v[k] = tile[scan_pad(first + k)];
+        sum += v[k];
+    }
+    int total;
+    int run = block_exclusive_scan(sum, lds, &total);
+    if (threadIdx.x == 0) {
+        int excl = 0;
+        if (t == 0) {
+            __hip_atomic_store(&status[0], kScanPrefix | (unsigned)total, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(&status[t], kScanSum | (unsigned)total, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            for (int p = t - 1; p >= 0; --p) {
+                unsigned long long st = 0;
+                int spins = 0;
+                do {
+                    st = __hip_atomic_load(&status[p], __ATOMIC_ACQUIRE,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                } while ((st >> 32) == 0 && ++spins < kScan1Spins);
+                if ((st >> 32) == 0) {
+                    atomicAdd(stall, 1ull);
+                    break;
+                }
+                excl += (int)(unsigned)(st & 0xffffffffull);
+                if ((st >> 32) == 2) break;
+            }
+            __hip_atomic_store(&status[t], kScanPrefix | (unsigned)(excl + total),
+                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_excl = excl;
+        if (base + kScanTile >= n) out[n] = excl + total;   // the last tile
+    }
+    __syncthreads();
+    run += s_excl;
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        tile[scan_pad(first + k)] = run;
+        run += v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        const int e = k * kScanBlock + threadIdx.x;
+        const size_t i = base + e;
+        if (i < n) out[i] = tile[scan_pad(e)];
+    }
+}
+
 // ---- scatter into tile -> subtile order --------------------------------------
 
 // Particles of subtiles with at most keep_max particles keep their scattered
@@ -657,9 +740,10 @@ __global__ __launch_bounds__(kFinishWaves * kWave) void k_cluster_finish(
         hz = fmax(hz, __shfl_xor(hz, off, kWave));
     }
     if (have && li == 0) {
-        cl.lo[0] = lx; cl.lo[1] = ly; cl.lo[2] = lz;
-        cl.hi[0] = hx; cl.hi[1] = hy; cl.hi[2] = hz;
-        clusters[c] = cl;
+        // only the box: the item kernels may read the other fields meanwhile
+        Cluster *o = clusters + c;
+        o->lo[0] = lx; o->lo[1] = ly; o->lo[2] = lz;
+        o->hi[0] = hx; o->hi[1] = hy; o->hi[2] = hz;
     }
 }
 
@@ -727,6 +811,20 @@ hipError_t launch_keys(const double *pos, int n, const Geom &g, int *key, int *r
 }
 
 size_t scan_block_sums_needed(size_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+size_t scan1_status_needed(size_t n) { return n == 0 ? 1 : (n + kScanTile - 1) / kScanTile; }
+
+hipError_t launch_scan1(const int *in, int *out, size_t n, unsigned long long *status, int *ctr,
+                        unsigned long long *stall, hipStream_t s) {
+    const size_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, out, 0, (size_t)1);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_1pass, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out, n,
+                       status, ctr, stall);
+    return hipGetLastError();
+}
 
 hipError_t launch_scan(const int *in, int *out, size_t n, int *bsum, hipStream_t s) {
     size_t nb = (n + kScanTile - 1) / kScanTile;
