@@ -685,7 +685,7 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     int *s1c = (int *)(s1 + s1_total);
     unsigned long long *stall = &counters->scan_stall;
     P3M_HIP(launch_keys(r.pos, n, g, key, rank, cells, s));
-    P3M_HIP(launch_scan1(cells, cells, ncells, s1, s1c, stall, s));
+    P3M_HIP(launch_scan1(cells, cells, ncells, s1, s1c, stall, bsum, s));
     if (det) {
         // ranks in (fine sub-cell, index) order instead of the atomics' order
         unsigned long long *k64 = (unsigned long long *)w.det_k.p;
@@ -720,11 +720,11 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
         recv_scan = recv_pos = nullptr;
     } else {
         P3M_HIP(launch_flags(sel_s, n, n_sub, kind, r.thr, flags, s));
-        P3M_HIP(launch_scan1(flags, flags, nflags, s1 + s1_cells, s1c + 1, stall, s));
+        P3M_HIP(launch_scan1(flags, flags, nflags, s1 + s1_cells, s1c + 1, stall, bsum, s));
         P3M_HIP(launch_compact(flags, n, n_sub, actpos, s));
     }
     P3M_HIP(launch_cluster_count(cells, recv_scan, n, n_sub, g, csize, ncl, s));
-    P3M_HIP(launch_scan1(ncl, ncl, ncl_len, s1 + s1_cells + s1_flags, s1c + 2, stall, s));
+    P3M_HIP(launch_scan1(ncl, ncl, ncl_len, s1 + s1_cells + s1_flags, s1c + 2, stall, bsum, s));
     P3M_HIP(launch_cluster_write(cells, recv_scan, ncl, n, n_sub, g, csize, clusters, s));
 
     // The cluster boxes, the receiver gather, the output clear and the table
@@ -752,9 +752,13 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     P3M_HIP(launch_item_count(clusters, ncl + ncl_len, (int)cl_bound, cells, g, target,
                               mutual ? 1 : 0, itemcnt, s));
     P3M_HIP(launch_scan1(itemcnt, itemcnt, cl_bound, s1 + s1_cells + s1_flags + s1_ncl, s1c + 3,
-                         stall, s));
-    P3M_HIP(launch_totals(flags + nflags, ncl + ncl_len, itemcnt + cl_bound, h->host_tot, s));
-    if (wait_count) P3M_HIP(hipEventRecord(h->tot_ev, s));
+                         stall, bsum, s));
+    // the three totals go to pinned memory for the stats; only a call that
+    // waits for the item count needs them before the pair kernel
+    if (wait_count) {
+        P3M_HIP(launch_totals(flags + nflags, ncl + ncl_len, itemcnt + cl_bound, h->host_tot, s));
+        P3M_HIP(hipEventRecord(h->tot_ev, s));
+    }
     // receivers, clusters and items reach the stats when they are asked for
     st.receivers = st.clusters = st.items = -1;
     if (wait_count) {
@@ -823,6 +827,8 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     if (det)
         P3M_HIP(launch_item_reduce(clusters, ncl + ncl_len, (int)cl_bound, itemcnt, a.partials,
                                    csize, a.rperm, r.out, a.out_stride, s));
+    if (!wait_count)
+        P3M_HIP(launch_totals(flags + nflags, ncl + ncl_len, itemcnt + cl_bound, h->host_tot, s));
     if (h->timing) {
         P3M_HIP(hipEventRecord(h->ev[2], s));
         h->timed_last = true;

@@ -212,12 +212,13 @@ size_t scan_block_sums_needed(size_t n);
 // exclusive scan of n int32 values; out has n+1 entries (out[n] = total).
 // in may equal out.
 hipError_t launch_scan(const int *in, int *out, size_t n, int *block_sums, hipStream_t s);
-// the same in one launch (decoupled look-back): status holds
+// the same in one launch (decoupled look-back) for up to 64 tiles of
+// kScanTile values, else as launch_scan (with bsum): status holds
 // scan1_status_needed(n) entries and *ctr one int, both zeroed before the
 // launch; a look-back that waited past its poll limit raises *stall
 size_t scan1_status_needed(size_t n);
 hipError_t launch_scan1(const int *in, int *out, size_t n, unsigned long long *status, int *ctr,
-                        unsigned long long *stall, hipStream_t s);
+                        unsigned long long *stall, int *bsum, hipStream_t s);
 // scatter into tile -> subtile order: particles of subtiles that the fine
 // order leaves as they are (at most max(csize, kFineMin)) go to sp2/perm2/sel2,
 // the others to sp/perm/sel_s for launch_fine_order

@@ -219,6 +219,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const int *in, int *ou
 // anyway and raises *stall.  out[n] = the total; in may equal out.
 constexpr unsigned long long kScanSum = 1ull << 32, kScanPrefix = 2ull << 32;
 constexpr int kScan1Spins = 1 << 20;
+constexpr int kScan1MaxTiles = 64;   // larger scans take the three-kernel path
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_1pass(const int *in, int *out, size_t n,
                                                            unsigned long long *status, int *ctr,
@@ -815,12 +816,16 @@ size_t scan_block_sums_needed(size_t n) { return (n + kScanTile - 1) / kScanTile
 size_t scan1_status_needed(size_t n) { return n == 0 ? 1 : (n + kScanTile - 1) / kScanTile; }
 
 hipError_t launch_scan1(const int *in, int *out, size_t n, unsigned long long *status, int *ctr,
-                        unsigned long long *stall, hipStream_t s) {
+                        unsigned long long *stall, int *bsum, hipStream_t s) {
     const size_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb == 0) {
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, out, 0, (size_t)1);
         return hipGetLastError();
     }
+    // one lane walks the look-back tile by tile: past a few dozen tiles the
+    // blocks running together wait on each other in a chain (a rung-batched
+    // flag scan of 134M values took 3.9 ms), where three launches take less
+    if (nb > (size_t)kScan1MaxTiles) return launch_scan(in, out, n, bsum, s);
     hipLaunchKernelGGL(k_scan_1pass, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out, n,
                        status, ctr, stall);
     return hipGetLastError();
