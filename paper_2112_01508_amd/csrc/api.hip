@@ -159,8 +159,10 @@ struct p3m_sr_context {
     int dbg_fail_after = -1;
     size_t alloc_bytes = 0;
     bool timed_last = false;
-    // start, pairs start, pairs end, end, sort end
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // start, pairs start, pairs end, end, sort end, sort end on the build
+    // stream (the dense subtiles' fine order)
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool sort_b = false;   // ev[5] was recorded by the timed call
     hipEvent_t tot_ev = nullptr;   // after the totals of a call reach host memory
     int *host_tot = nullptr;   // pinned: receivers, clusters, items of the current call
     // long-range PM workspace and timing
@@ -172,7 +174,7 @@ struct p3m_sr_context {
     // build phase: the cluster boxes and the output clear run on this stream
     // beside the item planning (forked from and joined to the call's stream)
     hipStream_t bstream = nullptr;
-    hipEvent_t bfork = nullptr, bjoin = nullptr;
+    hipEvent_t bfork = nullptr, bjoin = nullptr, bsort = nullptr, bsorted = nullptr;
     p3m_lr_stats lr_stats{};
     bool lr_timed = false;
     hipStream_t lr_stream = nullptr;
@@ -586,6 +588,7 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     st.ms_build = st.ms_pairs = st.ms_total = st.ms_sort = -1.0f;
     h->last_stream = s;
     h->timed_last = false;
+    h->sort_b = false;
     if (h->timing) P3M_HIP(hipEventRecord(h->ev[0], s));
 
     const size_t out_elems = (size_t)n_sub * (size_t)n * 3;
@@ -697,14 +700,30 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     {
         int *perm_f = (int *)w.perm2.p;
         uint8_t *sel_f = (uint8_t *)w.sel2.p;
+        // without a selector the selector arrays stay unwritten (nullptr):
+        // the later kernels then take every particle as active
+        if (!sel_src) sel_s = sel_f = nullptr;
         P3M_HIP(launch_scatter(r.pos, r.mass, sel_src, n, g, key, rank, cells, fp32 ? 1 : 0,
                                csize, det, sp, perm, sel_s, sp_f, perm_f, sel_f, s));
         // fine order inside dense subtiles (key/rank are free again as scratch)
         // a subtile no larger than one cluster gains nothing from the reorder;
-        // the stable ranks are in fine order already
-        if (!det)
-            P3M_HIP(launch_fine_order(sp, perm, sel_s, cells, g, key, rank, sp_f, perm_f, sel_f,
-                                      csize, n, fbig, s));
+        // the stable ranks are in fine order already.  The subtiles above
+        // kFineBig particles are ordered on the build stream meanwhile (the
+        // box kernel, later on that stream, needs both orders).
+        if (!det) {
+            P3M_HIP(launch_big_list(cells, g, fbig, s));
+            P3M_HIP(hipEventRecord(h->bsort, s));
+            P3M_HIP(hipStreamWaitEvent(h->bstream, h->bsort, 0));
+            P3M_HIP(launch_fine_order_big(sp, perm, sel_s, cells, g, key, rank, sp_f, perm_f,
+                                          sel_f, n, fbig, h->bstream));
+            if (h->timing) P3M_HIP(hipEventRecord(h->ev[5], h->bstream));
+            h->sort_b = h->timing;
+            // the receiver flags read the final selectors, the dense
+            // subtiles' among them: with flags the call's stream waits here
+            if (!all_recv) P3M_HIP(hipEventRecord(h->bsorted, h->bstream));
+            P3M_HIP(launch_fine_order_medium(sp, perm, sel_s, cells, g, key, rank, sp_f, perm_f,
+                                             sel_f, csize, s));
+        }
         sp = sp_f;
         perm = perm_f;
         sel_s = sel_f;
@@ -719,6 +738,7 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     if (all_recv) {
         recv_scan = recv_pos = nullptr;
     } else {
+        if (!det) P3M_HIP(hipStreamWaitEvent(s, h->bsorted, 0));
         P3M_HIP(launch_flags(sel_s, n, n_sub, kind, r.thr, flags, s));
         P3M_HIP(launch_scan1(flags, flags, nflags, s1 + s1_cells, s1c + 1, stall, bsum, s));
         P3M_HIP(launch_compact(flags, n, n_sub, actpos, s));
@@ -964,6 +984,8 @@ int p3m_sr_create(p3m_sr_handle *out, int device) {
     bool ev_ok = hipEventCreateWithFlags(&h->tot_ev, hipEventDisableTiming) == hipSuccess;
     for (hipEvent_t &e : h->ev) ev_ok = ev_ok && hipEventCreate(&e) == hipSuccess;
     ev_ok = ev_ok && hipEventCreateWithFlags(&h->bfork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&h->bsort, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&h->bsorted, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&h->bjoin, hipEventDisableTiming) == hipSuccess &&
             hipStreamCreateWithFlags(&h->bstream, hipStreamNonBlocking) == hipSuccess;
     if (!ev_ok) {
@@ -1002,6 +1024,8 @@ int p3m_sr_destroy(p3m_sr_handle h) {
     if (h->join_ev) (void)hipEventDestroy(h->join_ev);
     if (h->aux) (void)hipStreamDestroy(h->aux);
     if (h->bfork) (void)hipEventDestroy(h->bfork);
+    if (h->bsort) (void)hipEventDestroy(h->bsort);
+    if (h->bsorted) (void)hipEventDestroy(h->bsorted);
     if (h->bjoin) (void)hipEventDestroy(h->bjoin);
     if (h->bstream) (void)hipStreamDestroy(h->bstream);
     delete h;
@@ -1514,6 +1538,12 @@ int p3m_sr_get_stats(p3m_sr_handle h, p3m_sr_stats *out) {
         P3M_HIP(hipEventElapsedTime(&b, h->ev[1], h->ev[2]));
         P3M_HIP(hipEventElapsedTime(&t, h->ev[0], h->ev[3]));
         P3M_HIP(hipEventElapsedTime(&st.ms_sort, h->ev[0], h->ev[4]));
+        if (h->sort_b) {
+            float sb = 0;
+            P3M_HIP(hipEventSynchronize(h->ev[5]));
+            P3M_HIP(hipEventElapsedTime(&sb, h->ev[0], h->ev[5]));
+            st.ms_sort = std::max(st.ms_sort, sb);
+        }
         st.ms_build = a;
         st.ms_pairs = b;
         st.ms_total = t;

@@ -247,12 +247,21 @@ hipError_t launch_item_reduce(const Cluster *clusters, const int *n_clusters_dev
                               const int *rperm, double *out, long long out_stride,
                               hipStream_t s);
 // reorder the particles of every subtile by the Morton index of their fine
-// sub-cell (sp/perm/sel -> sp2/perm2/sel2; fkey/frank: n ints of scratch;
-// big_list: 1 + n / kFineBig ints, big_list[0] zeroed before the call)
-hipError_t launch_fine_order(const double4 *sp, const int *perm, const uint8_t *sel,
-                             const int *cell_start, const Geom &g, int *fkey, int *frank,
-                             double4 *sp2, int *perm2, uint8_t *sel2, int csize, int n,
-                             int *big_list, hipStream_t s);
+// sub-cell (sp/perm/sel -> sp2/perm2/sel2; sel == nullptr: no selector;
+// fkey/frank: n ints of scratch).  launch_big_list lists the subtiles above
+// kFineBig particles in big_list (1 + n / kFineBig ints, big_list[0] zeroed
+// before it); launch_fine_order_medium orders the others, and
+// launch_fine_order_big the listed ones (after launch_big_list; the two
+// orderings touch different subtiles and may run at the same time)
+hipError_t launch_big_list(const int *cell_start, const Geom &g, int *big_list, hipStream_t s);
+hipError_t launch_fine_order_medium(const double4 *sp, const int *perm, const uint8_t *sel,
+                                    const int *cell_start, const Geom &g, int *fkey, int *frank,
+                                    double4 *sp2, int *perm2, uint8_t *sel2, int csize,
+                                    hipStream_t s);
+hipError_t launch_fine_order_big(const double4 *sp, const int *perm, const uint8_t *sel,
+                                 const int *cell_start, const Geom &g, int *fkey, int *frank,
+                                 double4 *sp2, int *perm2, uint8_t *sel2, int n,
+                                 const int *big_list, hipStream_t s);
 hipError_t launch_flags(const uint8_t *sel_s, int n, int n_sub, int kind,
                         const uint8_t *thr_host, int *flags, hipStream_t s);
 hipError_t launch_compact(const int *scan, int n, int n_sub, int *act_pos, hipStream_t s);

@@ -326,7 +326,7 @@ __global__ void k_scatter(const double *__restrict__ pos, const double *__restri
     }
     sp[dst] = v;
     perm[dst] = i;
-    sel_s[dst] = sel ? sel[i] : (uint8_t)1;
+    if (sel) sel_s[dst] = sel[i];   // no selector: every particle takes part
 }
 
 // ---- fine order inside subtiles -------------------------------------------------
@@ -360,15 +360,16 @@ __device__ inline void wave_lds_sync() {
 // block.  Inside every subtile holding more than keep_max and at most
 // kFineBig particles the particles are reordered by fine_key (a counting sort
 // over kFineBins bins in LDS); smaller subtiles are already in place (the
-// scatter wrote them to sp2/perm2/sel2); larger ones are appended to big_list
-// (big_list[0] counts them) for k_fine_order_big.  Reads sp/perm/sel and writes sp2/perm2/sel2;
-// fkey/frank are scratch indexed by sorted position.  Consecutive receivers
-// then lie close together, so small clusters have small bounding boxes.
+// scatter wrote them to sp2/perm2/sel2); larger ones are k_fine_order_big's,
+// which can run at the same time.  Reads sp/perm/sel and writes sp2/perm2/sel2
+// (sel == nullptr: no selector); fkey/frank are scratch indexed by sorted
+// position.  Consecutive receivers then lie close together, so small
+// clusters have small bounding boxes.
 __global__ __launch_bounds__(kFineWaves * kWave) void k_fine_order(
     const double4 *__restrict__ sp, const int *__restrict__ perm, const uint8_t *__restrict__ sel,
     const int *__restrict__ cs, Geom g, int *__restrict__ fkey, int *__restrict__ frank,
     double4 *__restrict__ sp2, int *__restrict__ perm2, uint8_t *__restrict__ sel2, int keep_max,
-    int *__restrict__ big_list) {
+    int *__restrict__) {
     __shared__ int hists[kFineWaves][kFineBins];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
@@ -379,10 +380,7 @@ __global__ __launch_bounds__(kFineWaves * kWave) void k_fine_order(
         for (int s = 0; s < g.ns3; ++s) {
             const int a0 = c[s], a1 = c[s + 1];
             if (a1 - a0 <= keep_max) continue;   // written in place by k_scatter
-            if (a1 - a0 > kFineBig) {
-                if (lane == 0) big_list[1 + atomicAdd(big_list, 1)] = (int)(tile * g.ns3 + s);
-                continue;
-            }
+            if (a1 - a0 > kFineBig) continue;   // listed by k_big_list
             for (int b = lane; b < kFineBins; b += kWave) hist[b] = 0;
             wave_lds_sync();
             for (int i = a0 + lane; i < a1; i += kWave) {
@@ -415,15 +413,23 @@ __global__ __launch_bounds__(kFineWaves * kWave) void k_fine_order(
                 const int dst = a0 + hist[fkey[i]] + frank[i];
                 sp2[dst] = sp[i];
                 perm2[dst] = perm[i];
-                sel2[dst] = sel[i];
+                if (sel) sel2[dst] = sel[i];
             }
             wave_lds_sync();
         }
     }
 }
 
+// The subtiles holding more than kFineBig particles (big_list[0] counts
+// them, zeroed before the launch; the ids follow in any order).
+__global__ void k_big_list(const int *__restrict__ cs, long long cells, int *__restrict__ big_list) {
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    if (cs[c + 1] - cs[c] > kFineBig) big_list[1 + atomicAdd(big_list, 1)] = (int)c;
+}
+
 // Fine order of the subtiles holding more than kFineBig particles (listed
-// by k_fine_order): one block of kFineBins threads per subtile, the same
+// by k_big_list): one block of kFineBins threads per subtile, the same
 // counting sort with one bin per thread in the scan.  A single wave would
 // take the densest halo cores alone, long after the rest of the grid.
 __global__ __launch_bounds__(kFineBins) void k_fine_order_big(
@@ -454,7 +460,7 @@ __global__ __launch_bounds__(kFineBins) void k_fine_order_big(
             const int dst = a0 + hist[fkey[i]] + frank[i];
             sp2[dst] = sp[i];
             perm2[dst] = perm[i];
-            sel2[dst] = sel[i];
+            if (sel) sel2[dst] = sel[i];
         }
         __syncthreads();
     }
@@ -675,7 +681,7 @@ __global__ void k_gather_weights(const double *__restrict__ w, const uint8_t *__
     if (p >= n) return;
     size_t i = (size_t)perm[p];
     double x = 0, y = 0, z = 0;
-    if (sel_s[p]) {
+    if (!sel_s || sel_s[p]) {   // no selector: all active
         x = w[3 * i];
         y = w[3 * i + 1];
         z = w[3 * i + 2];
@@ -856,15 +862,29 @@ hipError_t launch_scatter(const double *pos, const double *mass, const uint8_t *
     return hipGetLastError();
 }
 
-hipError_t launch_fine_order(const double4 *sp, const int *perm, const uint8_t *sel,
-                             const int *cell_start, const Geom &g, int *fkey, int *frank,
-                             double4 *sp2, int *perm2, uint8_t *sel2, int csize, int n,
-                             int *big_list, hipStream_t s) {
+hipError_t launch_big_list(const int *cell_start, const Geom &g, int *big_list, hipStream_t s) {
     // big_list[0] was zeroed on the stream; it holds at most n / kFineBig ids
+    const long long cells = (long long)g.nt3 * g.ns3;
+    hipLaunchKernelGGL(k_big_list, dim3(grid_for((size_t)cells, 256)), dim3(256), 0, s,
+                       cell_start, cells, big_list);
+    return hipGetLastError();
+}
+
+hipError_t launch_fine_order_medium(const double4 *sp, const int *perm, const uint8_t *sel,
+                                    const int *cell_start, const Geom &g, int *fkey, int *frank,
+                                    double4 *sp2, int *perm2, uint8_t *sel2, int csize,
+                                    hipStream_t s) {
     long long grid = std::min<long long>((g.nt3 + kFineWaves - 1) / kFineWaves, 1ll << 20);
     hipLaunchKernelGGL(k_fine_order, dim3((unsigned)grid), dim3(kFineWaves * kWave), 0, s, sp,
                        perm, sel, cell_start, g, fkey, frank, sp2, perm2, sel2,
-                       csize > kFineMin ? csize : kFineMin, big_list);
+                       csize > kFineMin ? csize : kFineMin, (int *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_fine_order_big(const double4 *sp, const int *perm, const uint8_t *sel,
+                                 const int *cell_start, const Geom &g, int *fkey, int *frank,
+                                 double4 *sp2, int *perm2, uint8_t *sel2, int n,
+                                 const int *big_list, hipStream_t s) {
     const int big_grid = std::min(n / kFineBig, 256);
     if (big_grid > 0)
         hipLaunchKernelGGL(k_fine_order_big, dim3((unsigned)big_grid), dim3(kFineBins), 0, s, sp,
