@@ -211,8 +211,9 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const int *in, int *ou
 // Single-pass exclusive scan (decoupled look-back).  Each block takes the
 // next tile number from a counter, so every tile before it belongs to a
 // block that is already running; it scans its tile, publishes the tile's
-// sum at once (nothing delays that), then walks back over the tiles before
-// it, adding their sums until it meets a published inclusive prefix, and
+// sum at once (nothing delays that), then its first wave reads the status of
+// the 64 tiles before it together, adding their sums back to the nearest
+// published inclusive prefix (another window of 64 if there is none), and
 // publishes its own.  status[t] (zeroed before the launch): 0 nothing yet,
 // 1 << 32 | sum, or 2 << 32 | inclusive prefix.  A wait longer than
 // kScan1Spins polls (which a running predecessor cannot cause) ends the wait
@@ -248,33 +249,49 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_1pass(const int *in, int *o
     }
     int total;
     int run = block_exclusive_scan(sum, lds, &total);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < kWave) {
+        // the first wave: publish the tile's sum, then look back over the
+        // 64 tiles before the window's top at once; tiles before 0 count as
+        // a prefix of 0, so every window that reaches them ends the walk
+        const int lane = threadIdx.x;
+        if (lane == 0)
+            __hip_atomic_store(&status[t], (t == 0 ? kScanPrefix : kScanSum) | (unsigned)total,
+                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         int excl = 0;
-        if (t == 0) {
-            __hip_atomic_store(&status[0], kScanPrefix | (unsigned)total, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(&status[t], kScanSum | (unsigned)total, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            for (int p = t - 1; p >= 0; --p) {
-                unsigned long long st = 0;
-                int spins = 0;
-                do {
-                    st = __hip_atomic_load(&status[p], __ATOMIC_ACQUIRE,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                } while ((st >> 32) == 0 && ++spins < kScan1Spins);
-                if ((st >> 32) == 0) {
-                    atomicAdd(stall, 1ull);
+        for (int top = t - 1; top >= 0; top -= kWave) {
+            const int p = top - lane;
+            int spins = 0;
+            int near = kWave;   // lowest lane (nearest tile) holding a prefix
+            unsigned long long st = 0;
+            for (;;) {
+                st = p >= 0 ? __hip_atomic_load(&status[p], __ATOMIC_ACQUIRE,
+                                                 __HIP_MEMORY_SCOPE_AGENT)
+                            : kScanPrefix;
+                const unsigned long long pm = __builtin_amdgcn_ballot_w64((st >> 32) == 2);
+                const unsigned long long em = __builtin_amdgcn_ballot_w64((st >> 32) == 0);
+                near = pm ? __builtin_ctzll(pm) : kWave;
+                const unsigned long long need =
+                    near >= kWave - 1 ? ~0ull : ((2ull << near) - 1ull);
+                if ((em & need) == 0) break;
+                if (++spins >= kScan1Spins) {
+                    if (lane == 0) atomicAdd(stall, 1ull);
+                    near = -1;   // give up: the result is flagged as invalid
                     break;
                 }
-                excl += (int)(unsigned)(st & 0xffffffffull);
-                if ((st >> 32) == 2) break;
             }
-            __hip_atomic_store(&status[t], kScanPrefix | (unsigned)(excl + total),
-                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (near < 0) break;
+            int add = lane <= near ? (int)(unsigned)(st & 0xffffffffull) : 0;
+            for (int off = kWave / 2; off > 0; off >>= 1) add += __shfl_xor(add, off, kWave);
+            excl += add;
+            if (near < kWave) break;
         }
-        s_excl = excl;
-        if (base + kScanTile >= n) out[n] = excl + total;   // the last tile
+        if (lane == 0) {
+            if (t > 0)
+                __hip_atomic_store(&status[t], kScanPrefix | (unsigned)(excl + total),
+                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            s_excl = excl;
+            if (base + kScanTile >= n) out[n] = excl + total;   // the last tile
+        }
     }
     __syncthreads();
     run += s_excl;
@@ -828,9 +845,9 @@ hipError_t launch_scan1(const int *in, int *out, size_t n, unsigned long long *s
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, out, 0, (size_t)1);
         return hipGetLastError();
     }
-    // one lane walks the look-back tile by tile: past a few dozen tiles the
-    // blocks running together wait on each other in a chain (a rung-batched
-    // flag scan of 134M values took 3.9 ms), where three launches take less
+    // past a few dozen tiles the blocks running together wait on each
+    // other's prefixes in a chain (a rung-batched flag scan of 134M values
+    // took 3.9 ms with a one-lane look-back), where three launches take less
     if (nb > (size_t)kScan1MaxTiles) return launch_scan(in, out, n, bsum, s);
     hipLaunchKernelGGL(k_scan_1pass, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out, n,
                        status, ctr, stall);
