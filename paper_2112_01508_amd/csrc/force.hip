@@ -1280,73 +1280,104 @@ struct MutualVisit {
     }
 };
 
-// The persistent kernel of the mutual evaluation: clusters of 16 R receivers,
-// one work item per wave, every particle a receiver.  a.out: three FP64
-// arrays of a.out_stride (= n) values in sorted order, zeroed before the
-// launch.
+// Tallies of a wave's items.
+struct MutualTally {
+    unsigned long long pairs = 0, steps = 0, screened = 0, rare = 0;
+};
+
+// One work item in the layout of R rows per receiver copy (cnt <= 16 R).
 template <int R, bool UNIT>
-__global__ __launch_bounds__(kForceBlock) void k_pairs_mutual(PairArgs a) {
+__device__ __forceinline__ void mutual_item(const PairArgs &a, const Item &item,
+                                            const Cluster &cl, int cnt, int begin, int lane,
+                                            float4 *ring_pos, int *ring_idx, MutualTally &tally) {
+    const int row = lane >> 4, l = lane & 15;
+    const double cx = 0.5 * (cl.lo[0] + cl.hi[0]);
+    const double cy = 0.5 * (cl.lo[1] + cl.hi[1]);
+    const double cz = 0.5 * (cl.lo[2] + cl.hi[2]);
+    MutualLane m;
+    const int idx = 16 * (row % R) + l;
+    const bool live = idx < cnt;
+    m.i_sorted = begin + (live ? idx : 0);
+    const double4 xp = a.sp[m.i_sorted];
+    m.hx = live ? (float)(xp.x - cx) : 1.0e30f;
+    m.hy = live ? (float)(xp.y - cy) : 1.0e30f;
+    m.hz = live ? (float)(xp.z - cz) : 1.0e30f;
+    m.mu = mu_f32(xp.w);
+    // separations below a tenth of the receiver's offset are recomputed
+    // in FP64 (and r^2 == 0, since ki is at least the smallest normal)
+    m.ki = fmaxf(0.01f * fmaf(m.hz, m.hz, fmaf(m.hy, m.hy, m.hx * m.hx)), 1.1754944e-38f);
+    if (!live) m.ki = 0.f;
+    MutualVisit<R, UNIT> v{a, m, ring_pos, ring_idx, cl.lo, cl.hi, cx, cy, cz, lane,
+                           begin + cnt};
+    if (item.sole & kItemFirst) v.self_pass(cnt, begin);
+    walk_item(v, item, cl, a, lane);
+    // the copies of a receiver in the rows r, r + R, ...
+    double ax = v.ax, ay = v.ay, az = v.az;
+    if constexpr (R <= 2) {
+        ax += __shfl_xor(ax, 32, kWave);
+        ay += __shfl_xor(ay, 32, kWave);
+        az += __shfl_xor(az, 32, kWave);
+    }
+    if constexpr (R == 1) {
+        ax += __shfl_xor(ax, 16, kWave);
+        ay += __shfl_xor(ay, 16, kWave);
+        az += __shfl_xor(az, 16, kWave);
+    }
+    if (row < R && live) {
+        atomicAdd(a.out + m.i_sorted, ax);
+        atomicAdd(a.out + a.out_stride + m.i_sorted, ay);
+        atomicAdd(a.out + 2 * a.out_stride + m.i_sorted, az);
+    }
+    tally.pairs += v.pairs;
+    tally.steps += v.steps;
+    tally.screened += v.screened;
+    tally.rare += v.rare;
+}
+
+// The persistent kernel of the mutual evaluation: clusters of up to 16 RMAX
+// receivers, one work item per wave, every particle a receiver.  A cluster
+// that fills fewer rows (the last one of a tile is often short) runs in the
+// narrower layout, so its receivers meet 16 (4 / R) entries per block with
+// fewer idle lanes: 16 receivers or fewer in R = 1, 32 or fewer in R = 2.
+// a.out: three FP64 arrays of a.out_stride (= n) values in sorted order,
+// zeroed before the launch.
+template <int RMAX, bool UNIT>
+__global__ __launch_bounds__(kForceBlock) __attribute__((amdgpu_waves_per_eu(5)))
+void k_pairs_mutual(PairArgs a) {
     constexpr int NW = kForceBlock / kWave;
     __shared__ float4 ring_pos[NW][kRing];
     __shared__ int ring_idx[NW][kRing];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
-    const int row = lane >> 4, l = lane & 15;
     ItemCursor cursor;
-    unsigned long long pairs = 0, steps = 0, screened = 0, rare = 0;
+    MutualTally tally;
     const ItemQueue iq = item_queue(a);
     for (int it = next_item(a, iq, lane, cursor); it >= 0; it = next_item(a, iq, lane, cursor)) {
         const Item item = a.items[it];
         const Cluster cl = a.clusters[item.cluster];
         const int cnt = __builtin_amdgcn_readfirstlane(cl.count);
         const int begin = __builtin_amdgcn_readfirstlane(cl.begin);
-        const double cx = 0.5 * (cl.lo[0] + cl.hi[0]);
-        const double cy = 0.5 * (cl.lo[1] + cl.hi[1]);
-        const double cz = 0.5 * (cl.lo[2] + cl.hi[2]);
-        MutualLane m;
-        const int idx = 16 * (row % R) + l;
-        const bool live = idx < cnt;
-        m.i_sorted = begin + (live ? idx : 0);
-        const double4 xp = a.sp[m.i_sorted];
-        m.hx = live ? (float)(xp.x - cx) : 1.0e30f;
-        m.hy = live ? (float)(xp.y - cy) : 1.0e30f;
-        m.hz = live ? (float)(xp.z - cz) : 1.0e30f;
-        m.mu = mu_f32(xp.w);
-        // separations below a tenth of the receiver's offset are recomputed
-        // in FP64 (and r^2 == 0, since ki is at least the smallest normal)
-        m.ki = fmaxf(0.01f * fmaf(m.hz, m.hz, fmaf(m.hy, m.hy, m.hx * m.hx)), 1.1754944e-38f);
-        if (!live) m.ki = 0.f;
-        MutualVisit<R, UNIT> v{a, m, ring_pos[w], ring_idx[w], cl.lo, cl.hi, cx, cy, cz, lane,
-                               begin + cnt};
-        if (item.sole & kItemFirst) v.self_pass(cnt, begin);
-        walk_item(v, item, cl, a, lane);
-        // the copies of a receiver in the rows r, r + R, ...
-        double ax = v.ax, ay = v.ay, az = v.az;
-        if constexpr (R <= 2) {
-            ax += __shfl_xor(ax, 32, kWave);
-            ay += __shfl_xor(ay, 32, kWave);
-            az += __shfl_xor(az, 32, kWave);
+        if constexpr (RMAX >= 2) {
+            if (cnt <= 16) {
+                mutual_item<1, UNIT>(a, item, cl, cnt, begin, lane, ring_pos[w], ring_idx[w],
+                                     tally);
+                continue;
+            }
         }
-        if constexpr (R == 1) {
-            ax += __shfl_xor(ax, 16, kWave);
-            ay += __shfl_xor(ay, 16, kWave);
-            az += __shfl_xor(az, 16, kWave);
+        if constexpr (RMAX == 4) {
+            if (cnt <= 32) {
+                mutual_item<2, UNIT>(a, item, cl, cnt, begin, lane, ring_pos[w], ring_idx[w],
+                                     tally);
+                continue;
+            }
         }
-        if (row < R && live) {
-            atomicAdd(a.out + m.i_sorted, ax);
-            atomicAdd(a.out + a.out_stride + m.i_sorted, ay);
-            atomicAdd(a.out + 2 * a.out_stride + m.i_sorted, az);
-        }
-        pairs += v.pairs;
-        steps += v.steps;
-        screened += v.screened;
-        rare += v.rare;
+        mutual_item<RMAX, UNIT>(a, item, cl, cnt, begin, lane, ring_pos[w], ring_idx[w], tally);
     }
     if (lane == 0 && a.counters) {
-        atomicAdd(&a.counters->interactions, pairs);
-        atomicAdd(&a.counters->steps, steps);
-        atomicAdd(&a.counters->screened, screened);
-        atomicAdd(&a.counters->rare, rare);
+        atomicAdd(&a.counters->interactions, tally.pairs);
+        atomicAdd(&a.counters->steps, tally.steps);
+        atomicAdd(&a.counters->screened, tally.screened);
+        atomicAdd(&a.counters->rare, tally.rare);
     }
 }
 
