@@ -60,7 +60,8 @@ typedef enum {
     P3M_FP64 = 0, /* all pair arithmetic in FP64 */
     P3M_FP32 = 1  /* FP32 kernel shape, FP64 accumulation.  The separation, r^2 and the
                      cut-off test are FP64, except with layout screen = 2 on all-active
-                     forward calls (p3m_sr_set_config): FP32 on cluster-relative
+                     forward calls and on backward calls (p3m_sr_set_config): FP32
+                     on cluster-relative
                      coordinates, redone in FP64 where FP32 could decide a pair
                      differently or lose accuracy, so the accepted pairs are the FP64
                      ones */
@@ -302,15 +303,17 @@ int p3m_sr_tune_cache_check(const char *path, int *entries, int *lines);
  *                     loop (the subtile-pair culling of section 2.1.3
  *                     carried down to single suppliers); 0: no screening;
  *                     2: screened, and for all-active P3M_FP32 forward calls
- *                     (no softening, polynomial shape, n <= 2^27) each pair
- *                     is evaluated once for both partners (Newton's third
- *                     law, as the paper's tile pairing in section 2.1.3,
- *                     "Tiles"): clusters visit the upper half of their tile
- *                     stencil, the pair arithmetic is FP32 on coordinates
- *                     relative to the cluster's centre and the reactions are
- *                     added to the partners' FP64 sums; cluster_size must be
- *                     16, 32 or 64 (0 keeps the automatic choice); other calls
- *                     take layout 1; -1: automatic.
+ *                     (polynomial shape) and P3M_FP32 backward calls (no
+ *                     softening, n <= 2^27) each pair is evaluated once for
+ *                     both partners (Newton's third law, as the paper's tile
+ *                     pairing in section 2.1.3, "Tiles"; the adjoint's pair
+ *                     term is antisymmetric too): clusters visit the upper
+ *                     half of their tile stencil, the pair arithmetic is FP32
+ *                     on coordinates relative to the cluster's centre and the
+ *                     reactions are added to the partners' FP64 sums;
+ *                     cluster_size must be 16, 32 or 64 (0 keeps the
+ *                     automatic choice); other calls take layout 1;
+ *                     -1: automatic.
  * EINVAL outside those ranges.  Results do not depend on these settings
  * beyond FP64 summation order and, with screen 2, the FP32 rounding of the
  * separation (within the FP32 path's accuracy).

@@ -133,7 +133,7 @@ struct p3m_sr_context {
     // resident pair-kernel blocks per CU, per variant: mode, screen, cluster size,
     // shape, unit mass, softening
     int blocks_per_cu[4 * 2 * 4 * 3 * 4] = {};
-    int mutual_blocks_per_cu[4 * 2] = {};   // by cluster size and unit mass
+    int mutual_blocks_per_cu[4 * 2 * 2] = {};   // by cluster size, unit mass and adjoint
     // short-range workspace: grown with hipMalloc as calls need it, or (the
     // no-alloc entry point) carved from the library's fixed device array
     SrWork work, fixed;
@@ -564,13 +564,14 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     const bool all_recv = n_sub == 1 && (r.backward || r.sel_kind == SEL_ALL);
     // tabulated FP32 shape (point particles, forward only)
     const int shape = (fp32 && !r.backward && g.eps_b == 0.0) ? h->cfg_shape : SHAPE_POLY;
-    // each pair once for both partners: all-active FP32 forward calls with
-    // the polynomial shape, no softening, clusters of 16, 32 or 64 and fewer
-    // than 2^27 particles (the list entries hold the sorted index in 27 bits);
-    // other calls with this layout take the screened kernel
-    // (not in the deterministic mode: its reactions are added with atomics)
+    // each pair once for both partners: FP32 calls with every particle a
+    // receiver (all-active forward calls with the polynomial shape, and the
+    // adjoint), no softening, clusters of 16, 32 or 64 and fewer than 2^27
+    // particles (the list entries hold the sorted index in 27 bits); other
+    // calls with this layout take the screened kernel (not in the
+    // deterministic mode: its reactions are added with atomics)
     const bool det = h->deterministic;
-    const bool mutual = screen == kScreenMutual && fp32 && !r.backward && all_recv &&
+    const bool mutual = screen == kScreenMutual && fp32 && all_recv &&
                         shape == SHAPE_POLY && g.eps_b == 0.0 && csize >= 16 &&
                         r.n <= (int64_t)(1u << 27) && !det;
     if (screen == kScreenMutual && !mutual) screen = 1;
@@ -822,8 +823,8 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     const int cs_idx = csize == 8 ? 0 : csize == 16 ? 1 : csize == 32 ? 2 : 3;
     int bpc;
     if (mutual) {
-        int &slot_m = h->mutual_blocks_per_cu[cs_idx * 2 + unit];
-        if (slot_m == 0) slot_m = mutual_blocks_per_cu(csize, unit);
+        int &slot_m = h->mutual_blocks_per_cu[(cs_idx * 2 + (r.backward ? 1 : 0)) * 2 + unit];
+        if (slot_m == 0) slot_m = mutual_blocks_per_cu(csize, unit, r.backward);
         bpc = slot_m;
         a.out = (double *)w.msum.p;
         a.out_stride = n;
@@ -841,7 +842,7 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     long long grid = (long long)h->n_cu * bpc;
     if (grid < 1) grid = 1;
     if (h->timing) P3M_HIP(hipEventRecord(h->ev[1], s));
-    if (mutual) P3M_HIP(launch_pairs_mutual(a, (int)grid, s));
+    if (mutual) P3M_HIP(launch_pairs_mutual(a, r.backward, (int)grid, s));
     else P3M_HIP(launch_pairs(mode, screen, shape, a, (int)grid, s));
     if (mutual) P3M_HIP(launch_mutual_out((const double *)w.msum.p, perm, n, r.out, s));
     if (det)
@@ -1366,21 +1367,19 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     // level 2 also sweeps the item size around the level-1 winner
     std::vector<std::pair<int, int>> layouts = {{64, 0}, {64, 1}, {32, 1}, {16, 1}, {8, 1},
                                                 {16, 0}, {8, 0}};
-    // all-active FP32 forward calls can evaluate each pair once for both partners
-    if (!adjoint && !active && precision == P3M_FP32 && h->eps == 0.0 &&
-        h->cfg_shape == SHAPE_POLY)
+    // all-active FP32 forward calls and FP32 adjoints can evaluate each pair
+    // once for both partners
+    if ((adjoint || (!active && h->cfg_shape == SHAPE_POLY)) && precision == P3M_FP32 &&
+        h->eps == 0.0)
         for (int c : {32, 64, 16}) layouts.push_back({c, kScreenMutual});
     const TuneKey key{n, nt, precision, adjoint ? TUNE_ADJOINT : TUNE_FORWARD, 1};
     rc = tune(h, r, key, level, {1, 2, 3, 4}, layouts, {1024, 4096},
               {256, 512, 2048, 8192, 16384}, 3);
     if (rc) return rc;
     // until it is tuned on its own, the adjoint takes the forward's winner
-    // (with the mutual layout replaced by the plain screen: the adjoint has none)
     if (!adjoint) {
-        TuneVal v = h->tuned[key];
-        if (v.screen == kScreenMutual) v.screen = 1;
         const TuneKey adj{n, nt, precision, TUNE_ADJOINT, 1};
-        if (!h->tuned.count(adj)) h->tuned[adj] = v;
+        if (!h->tuned.count(adj)) h->tuned[adj] = h->tuned[key];
     }
     return P3M_OK;
 }

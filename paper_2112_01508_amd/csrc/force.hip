@@ -1006,6 +1006,7 @@ struct MutualLane {
     int i_sorted;
     float axf = 0.f, ayf = 0.f, azf = 0.f;   // block sums (FP32)
     float jx = 0.f, jy = 0.f, jz = 0.f;      // reaction on this lane's entry (FP32)
+    float wkx = 0.f, wky = 0.f, wkz = 0.f;   // adjoint: this receiver's w_k [k active]
 };
 
 // The separation of receiver i_sorted and list entry jr (sorted index |
@@ -1033,10 +1034,12 @@ __device__ __attribute__((noinline)) float4 mutual_fp64_sep(const double4 *__res
 
 // One step of a block: this lane's receiver against the entry S places along
 // its row.  SELF: the cluster's own particles, each ordered pair evaluated
-// from both ends, no reaction.
-template <int S, bool UNIT, bool SELF>
-__device__ __forceinline__ void mutual_step(MutualLane &m, const float4 &e, int jid,
-                                            const PairArgs &a, unsigned &cnt, unsigned &rare_n) {
+// from both ends, no reaction.  BWD: the adjoint's pair term instead of the
+// force; ew holds the entry's weight w_j [j active].
+template <int S, bool UNIT, bool SELF, bool BWD>
+__device__ __forceinline__ void mutual_step(MutualLane &m, const float4 &e, const float4 &ew,
+                                            int jid, const PairArgs &a, unsigned &cnt,
+                                            unsigned &rare_n) {
     // each step's values die within it: keep the scheduler from interleaving
     // the unrolled steps (which multiplies the live registers)
     __builtin_amdgcn_sched_barrier(0);
@@ -1066,6 +1069,45 @@ __device__ __forceinline__ void mutual_step(MutualLane &m, const float4 &e, int 
         acc_m = (acc_m & ~rare) | (ballot64(ok) & rare);
     }
     cnt += (unsigned)__builtin_popcountll(acc_m);
+    if constexpr (BWD) {
+        // the adjoint's term of the pair: receiver k gets -J(r) v and the
+        // entry j gets +J(r) v, v = mu_j w_k - mu_k w_j and J(r) v =
+        // phi v - c (r . v) r (J is even in r, so the pair term is
+        // antisymmetric and each pair is evaluated once for both)
+        float vx, vy, vz;
+        if constexpr (UNIT) {
+            vx = m.wkx - rot16<S>(ew.x);
+            vy = m.wky - rot16<S>(ew.y);
+            vz = m.wkz - rot16<S>(ew.z);
+        } else {
+            const float muj = rot16<S>(e.w);
+            vx = fmaf(muj, m.wkx, -(m.mu * rot16<S>(ew.x)));
+            vy = fmaf(muj, m.wky, -(m.mu * rot16<S>(ew.y)));
+            vz = fmaf(muj, m.wkz, -(m.mu * rot16<S>(ew.z)));
+        }
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float ri2 = ri * ri;
+        const float ex = __builtin_amdgcn_exp2f(r2 * (float)a.g.k2);
+        const float gu = ex * q_poly(fmaf(r2 * ri, a.g.k1f, -P3M_GPOLY_C0));
+        const float phi0 = gu * ri2 * ri;   // g / r^3
+        // lanes without a pair give no term
+        const float phi = keep_lanes(acc_m, phi0);
+        const float c = keep_lanes(acc_m, ri2 * fmaf(3.0f, phi0, a.g.kbf * ex));
+        const float crv = c * fmaf(dz, vz, fmaf(dy, vy, dx * vx));
+        const float ox = fmaf(-crv, dx, phi * vx);
+        const float oy = fmaf(-crv, dy, phi * vy);
+        const float oz = fmaf(-crv, dz, phi * vz);
+        m.axf -= ox;
+        m.ayf -= oy;
+        m.azf -= oz;
+        if constexpr (!SELF) {
+            m.jx += rot16<(16 - S) & 15>(ox);
+            m.jy += rot16<(16 - S) & 15>(oy);
+            m.jz += rot16<(16 - S) & 15>(oz);
+        }
+        asm volatile("" ::"v"(m.axf), "v"(m.ayf), "v"(m.azf), "v"(m.jx), "v"(m.jy), "v"(m.jz));
+        return;
+    }
     const float ri = __builtin_amdgcn_rsqf(r2);
     const float h = h_poly(fmaf(r2, a.g.c2f, -P3M_HPOLY_T0));
     const float ri3 = ri * ri * ri;
@@ -1093,26 +1135,27 @@ __device__ __forceinline__ void mutual_step(MutualLane &m, const float4 &e, int 
     asm volatile("" ::"v"(m.axf), "v"(m.ayf), "v"(m.azf), "v"(m.jx), "v"(m.jy), "v"(m.jz));
 }
 
-template <bool UNIT, bool SELF, int NS>
-__device__ __forceinline__ void mutual_steps(MutualLane &m, const float4 &e, int jid,
-                                             const PairArgs &a, unsigned &cnt, unsigned &rare_n) {
-    mutual_step<0, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-    mutual_step<1, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-    mutual_step<2, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-    mutual_step<3, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+template <bool UNIT, bool SELF, int NS, bool BWD>
+__device__ __forceinline__ void mutual_steps(MutualLane &m, const float4 &e, const float4 &ew,
+                                             int jid, const PairArgs &a, unsigned &cnt,
+                                             unsigned &rare_n) {
+    mutual_step<0, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+    mutual_step<1, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+    mutual_step<2, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+    mutual_step<3, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
     if constexpr (NS > 4) {
-        mutual_step<4, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step<5, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step<6, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step<7, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step<8, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step<9, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step<10, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step<11, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step<12, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step<13, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step<14, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step<15, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step<4, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<5, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<6, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<7, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<8, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<9, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<10, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<11, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<12, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<13, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<14, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<15, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
     }
 }
 
@@ -1125,13 +1168,14 @@ __device__ __forceinline__ float rows_sum(float v) {
     return v;
 }
 
-template <int R, bool UNIT>
+template <int R, bool UNIT, bool BWD>
 struct MutualVisit {
     static constexpr int EB = 64 / R;   // list entries per block of 16 steps
     const PairArgs &a;
     MutualLane &m;
     float4 *lpos;        // ring: offset from the cluster centre, mu
     int *lidx;           // ring: sorted index | image << kIdxBits
+    float4 *lw;          // ring (adjoint): the entry's weight w_j [j active]
     const double *lo, *hi;
     double cx, cy, cz;   // the cluster centre
     int lane;
@@ -1156,16 +1200,18 @@ struct MutualVisit {
         const int row = lane >> 4;
         const int k = (row / R) * 16 + (lane & 15);
         float4 e = make_float4(-1.0e30f, -1.0e30f, -1.0e30f, 0.f);
+        float4 ew = make_float4(0.f, 0.f, 0.f, 0.f);
         int jid = -1;
         if (k < nv) {
             const int q = (head + k) & (kRing - 1);
             e = lpos[q];
             jid = lidx[q];
+            if constexpr (BWD) ew = lw[q];
         }
         wave_lds_sync();   // the reads are done before later screens overwrite the ring
         m.jx = m.jy = m.jz = 0.f;
         unsigned cnt = 0, rn = 0;
-        mutual_steps<UNIT, false, 16>(m, e, jid, a, cnt, rn);
+        mutual_steps<UNIT, false, 16, BWD>(m, e, ew, jid, a, cnt, rn);
         flush_i();
         const float jx = rows_sum<R>(m.jx), jy = rows_sum<R>(m.jy), jz = rows_sum<R>(m.jz);
         if (row % R == 0 && k < nv) {
@@ -1193,15 +1239,17 @@ struct MutualVisit {
             else if constexpr (R == 2) idx = 16 * (row >> 1) + l;
             else idx = 16 * ((row + p) & 3) + l;
             float4 e = make_float4(-1.0e30f, -1.0e30f, -1.0e30f, 0.f);
+            float4 ew = make_float4(0.f, 0.f, 0.f, 0.f);
             int jid = -1;
             if (idx < cnt) {
                 const double4 q = a.sp[begin + idx];
                 e = make_float4((float)(q.x - cx), (float)(q.y - cy), (float)(q.z - cz),
                                 UNIT ? 0.f : mu_f32(q.w));
                 jid = (begin + idx) | (13 << kIdxBits);
+                if constexpr (BWD) ew = reinterpret_cast<const float4 *>(a.wa)[begin + idx];
             }
             unsigned c = 0, rn = 0;
-            mutual_steps<UNIT, true, R == 1 ? 4 : 16>(m, e, jid, a, c, rn);
+            mutual_steps<UNIT, true, R == 1 ? 4 : 16, BWD>(m, e, ew, jid, a, c, rn);
             flush_i();
             pairs += c;
             steps += R == 1 ? 4 : 16;
@@ -1227,6 +1275,7 @@ struct MutualVisit {
             lpos[q] = make_float4((float)(px - cx), (float)(py - cy), (float)(pz - cz),
                                   UNIT ? 0.f : mu_f32(p.w));
             lidx[q] = (jj + lane) | (code << kIdxBits);
+            if constexpr (BWD) lw[q] = reinterpret_cast<const float4 *>(a.wa)[jj + lane];
         }
         n_list += __builtin_popcountll(mk);
         fill = 0;
@@ -1286,10 +1335,11 @@ struct MutualTally {
 };
 
 // One work item in the layout of R rows per receiver copy (cnt <= 16 R).
-template <int R, bool UNIT>
+template <int R, bool UNIT, bool BWD>
 __device__ __forceinline__ void mutual_item(const PairArgs &a, const Item &item,
                                             const Cluster &cl, int cnt, int begin, int lane,
-                                            float4 *ring_pos, int *ring_idx, MutualTally &tally) {
+                                            float4 *ring_pos, int *ring_idx, float4 *ring_w,
+                                            MutualTally &tally) {
     const int row = lane >> 4, l = lane & 15;
     const double cx = 0.5 * (cl.lo[0] + cl.hi[0]);
     const double cy = 0.5 * (cl.lo[1] + cl.hi[1]);
@@ -1307,8 +1357,16 @@ __device__ __forceinline__ void mutual_item(const PairArgs &a, const Item &item,
     // in FP64 (and r^2 == 0, since ki is at least the smallest normal)
     m.ki = fmaxf(0.01f * fmaf(m.hz, m.hz, fmaf(m.hy, m.hy, m.hx * m.hx)), 1.1754944e-38f);
     if (!live) m.ki = 0.f;
-    MutualVisit<R, UNIT> v{a, m, ring_pos, ring_idx, cl.lo, cl.hi, cx, cy, cz, lane,
-                           begin + cnt};
+    if constexpr (BWD) {
+        if (live) {
+            const float4 wk = reinterpret_cast<const float4 *>(a.wa)[m.i_sorted];
+            m.wkx = wk.x;
+            m.wky = wk.y;
+            m.wkz = wk.z;
+        }
+    }
+    MutualVisit<R, UNIT, BWD> v{a, m, ring_pos, ring_idx, ring_w, cl.lo, cl.hi, cx, cy, cz,
+                                lane, begin + cnt};
     if (item.sole & kItemFirst) v.self_pass(cnt, begin);
     walk_item(v, item, cl, a, lane);
     // the copies of a receiver in the rows r, r + R, ...
@@ -1341,12 +1399,13 @@ __device__ __forceinline__ void mutual_item(const PairArgs &a, const Item &item,
 // fewer idle lanes: 16 receivers or fewer in R = 1, 32 or fewer in R = 2.
 // a.out: three FP64 arrays of a.out_stride (= n) values in sorted order,
 // zeroed before the launch.
-template <int RMAX, bool UNIT>
+template <int RMAX, bool UNIT, bool BWD>
 __global__ __launch_bounds__(kForceBlock) __attribute__((amdgpu_waves_per_eu(5)))
 void k_pairs_mutual(PairArgs a) {
     constexpr int NW = kForceBlock / kWave;
     __shared__ float4 ring_pos[NW][kRing];
     __shared__ int ring_idx[NW][kRing];
+    __shared__ float4 ring_wt[BWD ? NW : 1][BWD ? kRing : 1];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
     ItemCursor cursor;
@@ -1359,19 +1418,20 @@ void k_pairs_mutual(PairArgs a) {
         const int begin = __builtin_amdgcn_readfirstlane(cl.begin);
         if constexpr (RMAX >= 2) {
             if (cnt <= 16) {
-                mutual_item<1, UNIT>(a, item, cl, cnt, begin, lane, ring_pos[w], ring_idx[w],
-                                     tally);
+                mutual_item<1, UNIT, BWD>(a, item, cl, cnt, begin, lane, ring_pos[w],
+                                          ring_idx[w], ring_wt[BWD ? w : 0], tally);
                 continue;
             }
         }
         if constexpr (RMAX == 4) {
             if (cnt <= 32) {
-                mutual_item<2, UNIT>(a, item, cl, cnt, begin, lane, ring_pos[w], ring_idx[w],
-                                     tally);
+                mutual_item<2, UNIT, BWD>(a, item, cl, cnt, begin, lane, ring_pos[w],
+                                          ring_idx[w], ring_wt[BWD ? w : 0], tally);
                 continue;
             }
         }
-        mutual_item<RMAX, UNIT>(a, item, cl, cnt, begin, lane, ring_pos[w], ring_idx[w], tally);
+        mutual_item<RMAX, UNIT, BWD>(a, item, cl, cnt, begin, lane, ring_pos[w], ring_idx[w],
+                                     ring_wt[BWD ? w : 0], tally);
     }
     if (lane == 0 && a.counters) {
         atomicAdd(&a.counters->interactions, tally.pairs);
@@ -1394,13 +1454,18 @@ __global__ void k_mutual_out(const double *__restrict__ sums, const int *__restr
 
 using MutualFn = void (*)(PairArgs);
 
-MutualFn mutual_kernel(int csize, bool unit) {
+template <bool BWD>
+MutualFn mutual_kernel_mode(int csize, bool unit) {
     switch (csize) {
-    case 16: return unit ? k_pairs_mutual<1, true> : k_pairs_mutual<1, false>;
-    case 32: return unit ? k_pairs_mutual<2, true> : k_pairs_mutual<2, false>;
-    case 64: return unit ? k_pairs_mutual<4, true> : k_pairs_mutual<4, false>;
+    case 16: return unit ? k_pairs_mutual<1, true, BWD> : k_pairs_mutual<1, false, BWD>;
+    case 32: return unit ? k_pairs_mutual<2, true, BWD> : k_pairs_mutual<2, false, BWD>;
+    case 64: return unit ? k_pairs_mutual<4, true, BWD> : k_pairs_mutual<4, false, BWD>;
     default: return nullptr;
     }
+}
+
+MutualFn mutual_kernel(int csize, bool unit, bool bwd) {
+    return bwd ? mutual_kernel_mode<true>(csize, unit) : mutual_kernel_mode<false>(csize, unit);
 }
 
 // The pair-kernel variant for a layout: all share the signature void(PairArgs).
@@ -1483,15 +1548,15 @@ hipError_t launch_pairs(int mode, int screen, int tab, const PairArgs &a, int gr
     return hipGetLastError();
 }
 
-hipError_t launch_pairs_mutual(const PairArgs &a, int grid, hipStream_t s) {
-    const MutualFn fn = mutual_kernel(a.csize, a.unit_mass != 0);
+hipError_t launch_pairs_mutual(const PairArgs &a, bool bwd, int grid, hipStream_t s) {
+    const MutualFn fn = mutual_kernel(a.csize, a.unit_mass != 0, bwd);
     if (!fn) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kForceBlock), 0, s, a);
     return hipGetLastError();
 }
 
-int mutual_blocks_per_cu(int csize, int unit_mass) {
-    const MutualFn fn = mutual_kernel(csize, unit_mass != 0);
+int mutual_blocks_per_cu(int csize, int unit_mass, bool bwd) {
+    const MutualFn fn = mutual_kernel(csize, unit_mass != 0, bwd);
     int nb = 0;
     if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kForceBlock, 0) != hipSuccess)
         return 1;

@@ -25,20 +25,28 @@ def gpu_vjp(env, pos, mass, active, w, box, x_s, r_cut, prec):
     return g.cpu().numpy()
 
 
-@pytest.mark.parametrize("prec, tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("prec, tol, screen", [("fp64", 1e-12, 1), ("fp32", 1e-5, 1),
+                                               ("fp32", 1e-5, 2)])
 @pytest.mark.parametrize("frac", [None, 0.3])
-def test_vjp_matches_oracle(env, prec, tol, frac):
+def test_vjp_matches_oracle(env, prec, tol, screen, frac):
     """Config with N = 64^3 clustered particles (PM grid 128^3), every row of
     the adjoint against the oracle's analytic VJP, with per-particle masses
-    and, once, 30 % of the particles active."""
-    print("vjp diff64 full", prec, frac, flush=True)
+    and, once, 30 % of the particles active; in FP32 also with each pair
+    evaluated once for both partners (screen 2)."""
+    torch, p3, ctx = env
+    print("vjp diff64 full", prec, "screen", screen, frac, flush=True)
     wl = make_workload("diff64")
     rng = np.random.default_rng(11)
     mass = rng.uniform(0.5, 2.0, wl.n)
     active = None if frac is None else (rng.random(wl.n) < frac).astype(np.uint8)
     w = rng.standard_normal((wl.n, 3))
     ref = oracle.vjp(wl.pos, mass, active, w, 1.0, wl.x_s, wl.r_cut, method="tiled")
-    g = gpu_vjp(env, wl.pos, mass, active, w, 1.0, wl.x_s, wl.r_cut, prec)
+    ctx.set_config(subtiles_per_dim=1, item_target=4096, cluster_size=32, screen=screen)
+    try:
+        g = gpu_vjp(env, wl.pos, mass, active, w, 1.0, wl.x_s, wl.r_cut, prec)
+        assert ctx.stats()["screen"] == screen
+    finally:
+        ctx.set_config()
     rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
     row = np.max(np.linalg.norm(g - ref, axis=1)) / np.max(np.linalg.norm(ref, axis=1))
     print("rel L2 %.3e  max row %.3e" % (rel, row), flush=True)
@@ -54,12 +62,15 @@ def test_vjp_matches_oracle(env, prec, tol, frac):
         assert np.all(np.abs(g.sum(axis=0)) <= bound * np.abs(g).sum(axis=0))
 
 
-@pytest.mark.parametrize("csize,screen", [(8, 1), (16, 1), (32, 1), (64, 1), (16, 0), (32, 0)])
+@pytest.mark.parametrize("csize,screen", [(8, 1), (16, 1), (32, 1), (64, 1), (16, 0), (32, 0),
+                                          (16, 2), (32, 2), (64, 2)])
 @pytest.mark.parametrize("prec, tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 def test_vjp_small_clusters(env, prec, tol, csize, screen):
     """The adjoint on small clusters (several copies of a cluster per wave),
     with and without the per-supplier screen (the listed suppliers carry
-    their weights), matches the oracle's VJP like the default layout does."""
+    their weights), and, in FP32, with each pair evaluated once for both
+    partners (screen 2; FP64 calls run it as screen 1), matches the oracle's
+    VJP like the default layout does."""
     torch, p3, ctx = env
     print("vjp clustered n_side=24 csize", csize, "screen", screen, prec, flush=True)
     wl = make_workload("diff64", n_side=24)
@@ -74,19 +85,25 @@ def test_vjp_small_clusters(env, prec, tol, csize, screen):
         st = ctx.stats()
     finally:
         ctx.set_config()
-    assert st["cluster_size"] == csize and st["screen"] == screen
+    assert st["cluster_size"] == csize
+    assert st["screen"] == (1 if (screen == 2 and prec == "fp64") else screen)
     rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
     row = np.max(np.linalg.norm(g - ref, axis=1)) / np.max(np.linalg.norm(ref, axis=1))
     assert rel <= tol and row <= tol, (rel, row)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_vjp_finite_differences_diff64(env, prec):
+@pytest.mark.parametrize("prec, screen", [("fp64", 1), ("fp32", 1), ("fp32", 2)])
+def test_vjp_finite_differences_diff64(env, prec, screen):
     """Config with N = 64^3 clustered particles, Gaussian weights: adjoint vs
     central differences (step 1e-6 L, pair set frozen) on 64 samples."""
-    print("diff64 FD", prec, flush=True)
+    torch, p3, ctx = env
+    print("diff64 FD", prec, "screen", screen, flush=True)
     wl = make_workload("diff64")
-    g = gpu_vjp(env, wl.pos, wl.mass, None, wl.weights, 1.0, wl.x_s, wl.r_cut, prec)
+    ctx.set_config(subtiles_per_dim=1, item_target=4096, cluster_size=32, screen=screen)
+    try:
+        g = gpu_vjp(env, wl.pos, wl.mass, None, wl.weights, 1.0, wl.x_s, wl.r_cut, prec)
+    finally:
+        ctx.set_config()
     idx = sample_indices(wl.n, 64, wl.config_id)
     fd, _ = oracle.fd_grad(wl.pos, wl.mass, None, wl.weights, 1.0, wl.x_s, wl.r_cut, idx,
                            h=1e-6, mode="fixed")

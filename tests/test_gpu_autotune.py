@@ -35,10 +35,9 @@ def test_autotuned_forward_and_adjoint(prec):
     assert ctx.stats()["interactions"] == int(cnt.sum())
 
     # the adjoint takes the forward's layout until it is tuned on its own
-    # (the screened kernel where the forward pairs once for both partners)
+    # (screen 2 included: the FP32 adjoint also pairs once for both partners)
     ctx.force_backward(pos, m, None, to_dev(torch, w), **kw)
-    fwd_adj = dict(fwd, screen=1 if fwd["screen"] == 2 else fwd["screen"])
-    assert {k: ctx.stats()[k] for k in LAYOUT} == fwd_adj
+    assert {k: ctx.stats()[k] for k in LAYOUT} == fwd
     ctx.autotune(pos, m, None, level=1, adjoint=True, **kw)
     g = ctx.force_backward(pos, m, None, to_dev(torch, w), **kw).cpu().numpy()
     adj = {k: ctx.stats()[k] for k in LAYOUT}
