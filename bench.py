@@ -492,22 +492,27 @@ def cpu_tiled_leg():
 
 
 def profiled_record(name, st):
-    """The committed rocprofv3 counter record of the pair kernel
-    (profiles/traffic.json), or None when the kernel sources or the
-    decomposition differ from the ones the counters were taken with."""
+    """The committed rocprofv3 counter record of the pair kernel in this
+    call's decomposition (profiles/traffic.json holds one per profiled
+    layout), or None when the kernel sources or the decomposition differ
+    from the ones the counters were taken with."""
     import hashlib
     try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[name]
+        recs = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[name]
     except (OSError, KeyError, ValueError):
         return None
+    if isinstance(recs, dict):
+        recs = [recs]
     h = hashlib.sha256()
     for f in ("force.hip", "p3msr_internal.hpp", "gpoly.inc"):
         with open(os.path.join(ROOT, "paper_2112_01508_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     keys = ("subtiles_per_dim", "item_target", "cluster_size", "screen")
-    if h.hexdigest() != rec.get("kernel_sources_sha256") or any(rec.get(k) != st[k] for k in keys):
-        return None
-    return rec
+    for rec in recs:
+        if h.hexdigest() == rec.get("kernel_sources_sha256") and all(
+                rec.get(k) == st[k] for k in keys):
+            return rec
+    return None
 
 
 def copy_probe():
