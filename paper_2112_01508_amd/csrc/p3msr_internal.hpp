@@ -100,36 +100,6 @@ struct Counters {
 
 enum SelKind { SEL_ALL = 0, SEL_MASK = 1, SEL_RUNG = 2 };
 
-// Rank of this lane's key in counter[key], one atomic per distinct key of the
-// wave: lanes sharing a key form a group whose first lane adds the group's
-// size; each member gets the returned base plus its place in the group.
-// On clustered sets the counting sorts' time follows the number of atomics
-// rather than their contention (spreading each counter over 8 copies made the
-// cell count slower, grouping made it faster).  Every lane of the wave must
-// call this; lanes with live == false take no part and get 0.
-__device__ inline int wave_grouped_rank(int *counter, int key, bool live) {
-    const int lane = (int)(threadIdx.x & (kWave - 1));
-    if (!live) key = -1;
-    unsigned long long todo = __ballot(live);
-    int my_lead = 0, my_off = 0, size = 0;
-    while (todo) {
-        const int lead = __ffsll((long long)todo) - 1;
-        const int kl = __builtin_amdgcn_readlane(key, lead);   // lead is wave-uniform
-        const unsigned long long grp = __ballot(key == kl) & todo;
-        if ((grp >> lane) & 1ull) {
-            my_lead = lead;
-            my_off = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(grp >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo((unsigned)grp, 0u));
-        }
-        if (lane == lead) size = __popcll(grp);
-        todo &= ~grp;
-    }
-    int base = 0;
-    if (live && lane == my_lead) base = atomicAdd(&counter[key], size);
-    base = __shfl(base, my_lead, kWave);
-    return live ? base + my_off : 0;
-}
-
 // ---- work items ---------------------------------------------------------------
 
 __device__ inline int neighbour_tile(int tile, int t, const Geom &g) {
