@@ -298,13 +298,19 @@ def kdk_leg(torch, ctx, pos, mass, wl, repeats=2):
     return res
 
 
-def deterministic_leg(torch, ctx, pos, mass, wl, steps, warmup, layout):
+def deterministic_leg(torch, ctx, pos, mass, wl, steps, warmup):
     """The deterministic mode (p3m_sr_set_deterministic) against the default
-    atomic mode in the same layout (screen 2 runs as screen 1 there, so the
-    layout given is the screened one): time per call, pair-kernel time, and
-    whether two deterministic calls agree bit for bit."""
-    out = {"layout": dict(zip(("subtiles_per_dim", "item_target", "cluster_size", "screen"),
-                              layout))}
+    atomic mode in the same layout, the one a deterministic FP32 call takes
+    (screen 2 cannot run there: after tuning, the fastest other layout):
+    time per call, pair-kernel time, and whether two deterministic calls
+    agree bit for bit."""
+    keys = ("subtiles_per_dim", "item_target", "cluster_size", "screen")
+    ctx.set_deterministic(True)
+    ctx.force(pos, mass, None, box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut, precision="fp32")
+    torch.cuda.synchronize()
+    layout = tuple(ctx.stats()[k] for k in keys)
+    ctx.set_deterministic(False)
+    out = {"layout": dict(zip(keys, layout))}
     ctx.set_config(*layout)
     try:
         for prec in ("fp32", "fp64"):
@@ -640,11 +646,8 @@ def main():
     if "kdk" in legs:
         line["kdk"] = kdk_leg(torch, ctx, pos, mass, wl)
     if "deterministic" in legs:
-        st32 = results["fp32"]["stats"]
-        layout = (st32["subtiles_per_dim"], st32["item_target"], st32["cluster_size"],
-                  min(st32["screen"], 1))
         line["deterministic"] = deterministic_leg(torch, ctx, pos, mass, wl, args.steps,
-                                                  args.warmup, layout)
+                                                  args.warmup)
     if "subtiles" in legs:
         line["subtiles"] = subtiles_leg(torch, p3)
     if "batched" in legs:

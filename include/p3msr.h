@@ -242,6 +242,12 @@ int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
  * (p3m_sr_force_backward) takes the same decomposition; with level |
  * P3M_TUNE_ADJOINT the adjoint is timed instead (unit weights on every
  * receiver, workspace of n x 3 doubles for them) and keeps its own winner.
+ * When the winner evaluates each pair once for both partners (screen 2),
+ * the three fastest of the other candidates are timed again and the
+ * fastest of them is kept (and cached, as kind 3 for the forward, 4 for
+ * the adjoint) beside it: calls with this key that cannot take screen 2
+ * (softened, with an active mask, with a tabulated shape, or in the
+ * deterministic mode) run in that layout.
  */
 #define P3M_TUNE_ADJOINT 4
 #define P3M_TUNE_FORCE 8

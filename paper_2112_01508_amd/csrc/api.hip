@@ -62,7 +62,22 @@ struct DevBuf {
 
 // Tuned layouts are filed by particle count, tiles per dimension,
 // precision, call kind (forward, adjoint, rung-batched) and subset count.
-enum TuneKind { TUNE_FORWARD = 0, TUNE_ADJOINT = 1, TUNE_BATCHED = 2 };
+// When the forward's or the adjoint's winner evaluates each pair once for
+// both partners, the fastest of the other layouts is filed too (the PLAIN
+// kinds), for the calls that layout cannot serve: softened, masked,
+// tabulated-shape and deterministic ones.
+enum TuneKind {
+    TUNE_FORWARD = 0,
+    TUNE_ADJOINT = 1,
+    TUNE_BATCHED = 2,
+    TUNE_FORWARD_PLAIN = 3,
+    TUNE_ADJOINT_PLAIN = 4
+};
+constexpr int kTuneKinds = 5;
+int plain_kind(int kind) {
+    return kind == TUNE_FORWARD ? TUNE_FORWARD_PLAIN
+                                : (kind == TUNE_ADJOINT ? TUNE_ADJOINT_PLAIN : -1);
+}
 struct TuneKey {
     int64_t n;
     int nt;
@@ -334,8 +349,8 @@ bool parse_entry(const std::string &line, TuneEntry &e) {
     }
     e.device = dev;
     e.key.n = n;
-    return e.key.n >= 0 && e.key.nt >= 3 && e.val.ns >= 1 && e.val.ns <= 16 &&
-           valid_layout(e.val.csize, e.val.screen);
+    return e.key.n >= 0 && e.key.nt >= 3 && e.key.kind >= 0 && e.key.kind < kTuneKinds &&
+           e.val.ns >= 1 && e.val.ns <= 16 && valid_layout(e.val.csize, e.val.screen);
 }
 
 // Entries of a cache file (false if it cannot be opened); *lines counts
@@ -530,6 +545,21 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     const int n_sub = r.n_sub;
     const int nt = tiles_per_dim(r.box, r.r_cut);
 
+    const double eps_b = kBsplinePerPlummer * h->eps;
+    // one subset with every particle a receiver: receivers are the sorted
+    // particles themselves, no flags, scan or compaction
+    const bool all_recv = n_sub == 1 && (r.backward || r.sel_kind == SEL_ALL);
+    // tabulated FP32 shape (point particles, forward only)
+    const int shape = (fp32 && !r.backward && eps_b == 0.0) ? h->cfg_shape : SHAPE_POLY;
+    // each pair once for both partners: FP32 calls with every particle a
+    // receiver (all-active forward calls with the polynomial shape, and the
+    // adjoint), no softening and fewer than 2^27 particles (the list entries
+    // hold the sorted index in 27 bits), not in the deterministic mode (its
+    // reactions are added with atomics), and clusters of 16, 32 or 64
+    const bool det = h->deterministic;
+    const bool mutual_ok = fp32 && all_recv && shape == SHAPE_POLY && eps_b == 0.0 &&
+                           r.n <= (int64_t)(1u << 27) && !det;
+
     // decomposition: explicit override > user config > autotuned > default
     int ns = 0, target = 0, csize = 0, screen = -1;
     const int mode = (r.backward ? 2 : 0) + (fp32 ? 0 : 1);
@@ -539,6 +569,13 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     // a rung-batched call not tuned on its own takes the forward's layout
     if (it == h->tuned.end() && tkind == TUNE_BATCHED)
         it = h->tuned.find(TuneKey{r.n, nt, r.precision, TUNE_FORWARD, 1});
+    // a tuned layout that pairs once for both partners, on a call that
+    // cannot: the fastest of the other layouts, where one was kept
+    if (it != h->tuned.end() && it->second.screen == kScreenMutual && !mutual_ok) {
+        const int pk = plain_kind(it->first.kind);
+        auto p = pk < 0 ? h->tuned.end() : h->tuned.find(TuneKey{r.n, nt, r.precision, pk, 1});
+        if (p != h->tuned.end()) it = p;
+    }
     if (it != h->tuned.end()) {
         ns = it->second.ns;
         target = it->second.target;
@@ -557,23 +594,10 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     if (target <= 0) target = 1024;
     if (!valid_csize(csize)) csize = kDefaultCsize;
     if (screen < 0) screen = kDefaultScreen;
-    const Geom g = make_geom(r.box, r.x_s, r.r_cut, nt, ns, kBsplinePerPlummer * h->eps);
+    const Geom g = make_geom(r.box, r.x_s, r.r_cut, nt, ns, eps_b);
     const size_t ncells = (size_t)g.nt3 * g.ns3;
-    // one subset with every particle a receiver: receivers are the sorted
-    // particles themselves, no flags, scan or compaction
-    const bool all_recv = n_sub == 1 && (r.backward || r.sel_kind == SEL_ALL);
-    // tabulated FP32 shape (point particles, forward only)
-    const int shape = (fp32 && !r.backward && g.eps_b == 0.0) ? h->cfg_shape : SHAPE_POLY;
-    // each pair once for both partners: FP32 calls with every particle a
-    // receiver (all-active forward calls with the polynomial shape, and the
-    // adjoint), no softening, clusters of 16, 32 or 64 and fewer than 2^27
-    // particles (the list entries hold the sorted index in 27 bits); other
-    // calls with this layout take the screened kernel (not in the
-    // deterministic mode: its reactions are added with atomics)
-    const bool det = h->deterministic;
-    const bool mutual = screen == kScreenMutual && fp32 && all_recv &&
-                        shape == SHAPE_POLY && g.eps_b == 0.0 && csize >= 16 &&
-                        r.n <= (int64_t)(1u << 27) && !det;
+    // other calls with this layout take the screened kernel
+    const bool mutual = screen == kScreenMutual && mutual_ok && csize >= 16;
     if (screen == kScreenMutual && !mutual) screen = 1;
 
     p3m_sr_stats st{};
@@ -1212,11 +1236,20 @@ int tune(p3m_sr_context *h, Request &r, const TuneKey &key, int level,
         P3M_HIP(hipMemcpyAsync(entry.sig, hist, sizeof(entry.sig), hipMemcpyDeviceToHost, s));
         P3M_HIP(hipStreamSynchronize(s));
     }
+    // the key under which the fastest layout other than the mutual one is
+    // kept, when the mutual one wins
+    TuneKey plain_key = key;
+    plain_key.kind = plain_kind(key.kind);
     if (!(level & P3M_TUNE_FORCE)) {
         for (const TuneEntry &e : h->cache) {
             if (e.device == h->device_id && e.key == key &&
                 sig_distance(e.sig, entry.sig) <= kSigMatch) {
                 h->tuned[key] = e.val;
+                h->tuned.erase(plain_key);
+                for (const TuneEntry &p : h->cache)
+                    if (plain_key.kind >= 0 && p.device == h->device_id && p.key == plain_key &&
+                        sig_distance(p.sig, entry.sig) <= kSigMatch)
+                        h->tuned[plain_key] = p.val;
                 h->tune_from_cache = 1;
                 return P3M_OK;
             }
@@ -1291,30 +1324,68 @@ int tune(p3m_sr_context *h, Request &r, const TuneKey &key, int level,
               [](const std::pair<float, TuneVal> &a, const std::pair<float, TuneVal> &b) {
                   return a.first < b.first;
               });
-    if (seen.size() > 1) {
-        float final_best = 1e30f;
-        for (size_t k = 0; k < seen.size() && k < 3; ++k) {
+    // re-time the three fastest of the candidates that `keep` accepts; the
+    // fastest of them wins outright
+    auto retime = [&](bool (*keep)(const TuneVal &), TuneVal *win, float *win_ms) -> int {
+        *win_ms = 1e30f;
+        int timed = 0;
+        for (size_t k = 0; k < seen.size() && timed < 3; ++k) {
+            if (!keep(seen[k].second)) continue;
             float ms = 0;
-            if ((rc = time_layout(seen[k].second, 2 * reps, &ms))) return rc;
+            int rc2;
+            if ((rc2 = time_layout(seen[k].second, 2 * reps, &ms))) return rc2;
             ++h->tune_trials;
-            if (ms < final_best) {
-                final_best = ms;
-                best_v = seen[k].second;
+            ++timed;
+            if (ms < *win_ms) {
+                *win_ms = ms;
+                *win = seen[k].second;
             }
         }
+        return P3M_OK;
+    };
+    if (seen.size() > 1) {
+        float final_best = 1e30f;
+        if ((rc = retime([](const TuneVal &) { return true; }, &best_v, &final_best))) return rc;
         best = final_best;
     }
+    // A mutual winner serves only the calls that can pair once for both
+    // partners; the others take the fastest of the remaining layouts.
+    bool have_plain = false;
+    TuneVal plain_v{};
+    float plain_ms = 1e30f;
+    if (plain_key.kind >= 0 && best_v.screen == kScreenMutual) {
+        if ((rc = retime([](const TuneVal &v) { return v.screen != kScreenMutual; }, &plain_v,
+                         &plain_ms)))
+            return rc;
+        have_plain = plain_ms < 1e30f;
+    }
     r.force_ns = r.force_target = r.force_csize = r.force_screen = 0;
-    h->tuned[key] = best_v;
-    entry.val = best_v;
-    entry.ms = best;
-    bool replaced = false;
-    for (TuneEntry &e : h->cache)
-        if (e.device == entry.device && e.key == key) {
-            e = entry;
-            replaced = true;
-        }
-    if (!replaced) h->cache.push_back(entry);
+    auto file = [&](const TuneKey &k, const TuneVal &v, float ms) {
+        h->tuned[k] = v;
+        TuneEntry e2 = entry;
+        e2.key = k;
+        e2.val = v;
+        e2.ms = ms;
+        bool replaced = false;
+        for (TuneEntry &e : h->cache)
+            if (e.device == e2.device && e.key == k) {
+                e = e2;
+                replaced = true;
+            }
+        if (!replaced) h->cache.push_back(e2);
+    };
+    file(key, best_v, best);
+    if (have_plain) {
+        file(plain_key, plain_v, plain_ms);
+    } else if (plain_key.kind >= 0) {
+        // no longer needed: the winner serves every call
+        h->tuned.erase(plain_key);
+        h->cache.erase(std::remove_if(h->cache.begin(), h->cache.end(),
+                                      [&](const TuneEntry &e) {
+                                          return e.device == h->device_id && e.key == plain_key;
+                                      }),
+                       h->cache.end());
+    }
     save_cache(h);
     return P3M_OK;
 }
@@ -1377,9 +1448,16 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
               {256, 512, 2048, 8192, 16384}, 3);
     if (rc) return rc;
     // until it is tuned on its own, the adjoint takes the forward's winner
+    // (and the forward's layout for the calls the winner cannot serve)
     if (!adjoint) {
         const TuneKey adj{n, nt, precision, TUNE_ADJOINT, 1};
-        if (!h->tuned.count(adj)) h->tuned[adj] = h->tuned[key];
+        const TuneKey fwd_plain{n, nt, precision, TUNE_FORWARD_PLAIN, 1};
+        const TuneKey adj_plain{n, nt, precision, TUNE_ADJOINT_PLAIN, 1};
+        if (!h->tuned.count(adj)) {
+            h->tuned[adj] = h->tuned[key];
+            auto p = h->tuned.find(fwd_plain);
+            if (p != h->tuned.end()) h->tuned[adj_plain] = p->second;
+        }
     }
     return P3M_OK;
 }

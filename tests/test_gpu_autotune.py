@@ -2,6 +2,8 @@
 subdivision, time it, keep it if faster) through the C ABI: after tuning the
 forward, and then the adjoint on its own, both calls run in the stored
 layouts and still match the oracle."""
+import json
+
 import numpy as np
 import pytest
 
@@ -101,8 +103,10 @@ def test_cache_persists_across_handles(tmp_path):
     a.force_batched(pos, None, rg, [0, 1, 2, 3], **kw)
     lay_ab = {k: a.stats()[k] for k in LAYOUT}
     a.close()
-    text = open(path).read()
-    assert text.count('"device"') == 2          # the forward and the batched results
+    kinds = sorted(e["kind"] for e in json.load(open(path)))
+    # the forward and the batched results (and, when the forward's winner
+    # pairs once for both partners, the layout kept for the other calls)
+    assert kinds in ([0, 2], [0, 2, 3]), kinds
     b = p3.Context(0)
     b.set_tune_cache(path)
     # the loaded layouts apply to calls right away
@@ -121,3 +125,68 @@ def test_cache_persists_across_handles(tmp_path):
     b.autotune(pos, None, None, level=1, force=True, **kw)
     assert b.tune_status()["trials"] > 0
     b.close()
+
+
+def test_calls_the_mutual_layout_cannot_serve_take_the_kept_one(tmp_path):
+    """On the clustered128 recipe (reduced) the FP32 forward's winner is
+    normally the mutual layout (screen 2); the tuner then also keeps the
+    fastest of the other layouts (kind 3 in the cache), and calls that cannot
+    pair once for both partners (masked, softened, deterministic) run in it,
+    while all-active calls keep the winner.  Every such call still matches the
+    oracle."""
+    torch, p3 = gpu_or_skip()
+    path = str(tmp_path / "tune.json")
+    wl = make_workload("clustered128", n_side=64)
+    print("autotune plain layout clustered128 n_side=64", flush=True)
+    kw = dict(box=1.0, x_s=wl.x_s, r_cut=wl.r_cut, precision="fp32")
+    ctx = p3.Context(0)
+    try:
+        ctx.set_tune_cache(path)
+        pos = to_dev(torch, wl.pos)
+        ctx.autotune(pos, None, None, level=1, **kw)
+        ents = {e["kind"]: e for e in json.load(open(path))}
+        win = tuple(ents[0][k] for k in ("ns", "target", "csize", "screen"))
+        ctx.force(pos, None, None, **kw)
+        lay = lambda: tuple(ctx.stats()[k] for k in LAYOUT)
+        assert lay() == win
+        print("winner", win, "kinds", sorted(ents), flush=True)
+        if win[3] != 2:
+            assert 3 not in ents
+            pytest.skip("the winner is not the mutual layout on this device")
+        plain = tuple(ents[3][k] for k in ("ns", "target", "csize", "screen"))
+        assert plain[3] in (0, 1)
+        idx = np.arange(0, wl.n, 997)
+        ref, _, absum, _ = oracle.force(wl.pos, None, 1.0, wl.x_s, wl.r_cut, recv=idx)
+        # an active mask
+        act = np.zeros(wl.n, dtype=np.uint8)
+        act[idx] = 1
+        out = ctx.force(pos, None, to_dev(torch, act), **kw).cpu().numpy()
+        assert lay() == plain
+        e = oracle.errors(out[idx], ref, absum)
+        assert e["e_l2"] <= TOL["fp32"] and e["e_max_cond"] <= TOL["fp32"], e
+        # the deterministic mode
+        ctx.set_deterministic(True)
+        out = ctx.force(pos, None, None, **kw).cpu().numpy()
+        assert lay() == plain
+        e = oracle.errors(out[idx], ref, absum)
+        assert e["e_l2"] <= TOL["fp32"] and e["e_max_cond"] <= TOL["fp32"], e
+        ctx.set_deterministic(False)
+        # softening
+        ctx.set_softening(1e-4)
+        ctx.force(pos, None, None, **kw)
+        assert lay() == plain
+        ctx.set_softening(0.0)
+        ctx.force(pos, None, None, **kw)
+        assert lay() == win
+        # a second handle installs both from the cache without timing
+        b = p3.Context(0)
+        try:
+            b.set_tune_cache(path)
+            b.autotune(pos, None, None, level=1, **kw)
+            assert b.tune_status() == {"trials": 0, "from_cache": True}
+            b.force(pos, None, to_dev(torch, act), **kw)
+            assert tuple(b.stats()[k] for k in LAYOUT) == plain
+        finally:
+            b.close()
+    finally:
+        ctx.close()
