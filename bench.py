@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOPS_PER_INTERACTION = 40          # forward pair, algorithmic convention
+ADJOINT_FLOPS = 60                  # adjoint pair (the VJP of one interaction)
 PEAK_FP32_TFLOPS = 157.3            # MI355X FP32 vector (packed) peak
 PEAK_FP64_TFLOPS = 78.6             # MI355X FP64 vector peak
 PEAK_HBM_TBPS = 8.0                 # MI355X HBM3E
@@ -53,7 +54,8 @@ def parse():
     ap.add_argument("--no-cpu-tiled", action="store_true",
                     help="skip the oracle's cell-list walk on the full uniform32, diff64 and "
                          "clustered128 sets (about 20 s on 16 host threads)")
-    ap.add_argument("--legs", default="adjoint,batched,softened,long_range,kdk,shapes,deterministic",
+    ap.add_argument("--legs", default="adjoint,batched,softened,long_range,kdk,shapes,deterministic,"
+                                      "configs",
                     help="extra measured legs beside the forward force: adjoint, batched, "
                          "softened, long_range, kdk, shapes, deterministic; and, not run by "
                          "default, subtiles (fixed subtile counts against the autotuner)")
@@ -122,7 +124,7 @@ def adjoint_leg(torch, ctx, pos, mass, wl, steps, warmup, tune=True):
         out[prec] = {"ms_per_call": wall * 1e3, "pair_kernel_ms": st["ms_pairs"],
                      "interactions": st["interactions"],
                      "value": st["interactions"] / wall,
-                     "achieved_tflops": 60 * st["interactions"] / (st["ms_pairs"] * 1e-3) / 1e12,
+                     "achieved_tflops": ADJOINT_FLOPS * st["interactions"] / (st["ms_pairs"] * 1e-3) / 1e12,
                      "layout": {k: st[k] for k in ("subtiles_per_dim", "item_target",
                                                    "cluster_size", "screen")}}
         log("adjoint", prec, "%.3f ms" % (wall * 1e3))
@@ -463,6 +465,182 @@ def batched_leg(torch, p3, name, steps, warmup, layouts=None, tune=True):
     return res
 
 
+LAYOUT_KEYS = ("subtiles_per_dim", "item_target", "cluster_size", "screen")
+
+
+def configs_leg(torch, p3, steps, warmup, scale=True):
+    """The other configurations: uniform32 (plain method, FP64 and FP32
+    forward, autotuned), diff64 (forward and adjoint in both precisions, the
+    adjoint autotuned on its own) and scale512 (N = 512^3, 1000 halos: the
+    all-active FP32 forward, the 8 rung subsets in one persistent launch and
+    the FP32 adjoint, in fixed layouts, since one trial is seconds there).
+    GPU rows of uniform32 (all of them) and of 64 sampled diff64 particles
+    are kept for the oracle comparison made with the CPU baseline; scale512's
+    parity is the 4096-receiver check of its GPU tests."""
+    from workloads import make_workload
+    from workloads.generators import gaussian_weights
+    dev = torch.device("cuda", 0)
+    res = {}
+    ctx = p3.Context(0)
+    try:
+        # uniform32: every row is kept (32768 x 32768 brute force is cheap)
+        wl = make_workload("uniform32")
+        pos = torch.from_numpy(wl.pos).to(dev)
+        r = {"n": wl.n}
+        for prec in ("fp64", "fp32"):
+            kw = dict(box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut, precision=prec)
+            ctx.autotune(pos, None, None, level=1, **kw)
+            acc, wall, st, pairs_ms, _ = time_steps(torch, ctx, pos, None, wl, prec, steps,
+                                                    warmup)
+            r[prec] = {"value": st["interactions"] / wall, "ms_per_step": wall * 1e3,
+                       "pair_kernel_ms": pairs_ms, "interactions": st["interactions"],
+                       "layout": {k: st[k] for k in LAYOUT_KEYS}, "_acc": acc.cpu().numpy()}
+            log("uniform32", prec, "%.4f ms/step  pairs %.4f ms" % (wall * 1e3, pairs_ms))
+        res["uniform32"] = r
+        # diff64: forward and adjoint (loss sum_i w_i . a_i, seeded Gaussian w)
+        wl = make_workload("diff64")
+        pos = torch.from_numpy(wl.pos).to(dev)
+        mass = None if bool((wl.mass == 1.0).all()) else torch.from_numpy(wl.mass).to(dev)
+        w = gaussian_weights(wl.n, wl.config_id)
+        wd = torch.from_numpy(w).to(dev)
+        from workloads import sample_indices
+        idx = sample_indices(wl.n, 64, wl.config_id, salt=7)
+        r = {"n": wl.n, "_idx": idx, "_w": w}
+        for prec in ("fp64", "fp32"):
+            kw = dict(box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut, precision=prec)
+            ctx.autotune(pos, mass, None, level=1, **kw)
+            _, wall, st, pairs_ms, _ = time_steps(torch, ctx, pos, mass, wl, prec, steps, warmup)
+            fwd = {"value": st["interactions"] / wall, "ms_per_step": wall * 1e3,
+                   "pair_kernel_ms": pairs_ms, "interactions": st["interactions"],
+                   "layout": {k: st[k] for k in LAYOUT_KEYS}}
+            ctx.autotune(pos, mass, None, level=1, adjoint=True, **kw)
+            call = lambda: ctx.force_backward(pos, mass, None, wd, **kw)
+            wall_b = time_calls(torch, call, steps, warmup)
+            ctx.set_timing(True)
+            g = call()
+            stb = ctx.stats()
+            ctx.set_timing(False)
+            r[prec] = {"forward": fwd,
+                       "adjoint": {"ms_per_call": wall_b * 1e3, "pair_kernel_ms": stb["ms_pairs"],
+                                   "value": stb["interactions"] / wall_b,
+                                   "layout": {k: stb[k] for k in LAYOUT_KEYS}},
+                       "_grad": g[torch.from_numpy(idx).to(dev)].cpu().numpy()}
+            log("diff64", prec, "forward %.3f ms  adjoint %.3f ms" % (wall * 1e3, wall_b * 1e3))
+        res["diff64"] = r
+        del pos, mass, wd, g
+    finally:
+        ctx.close()
+    torch.cuda.empty_cache()
+    if scale:
+        res["scale512"] = scale512_leg(torch, p3)
+    return res
+
+
+def scale512_leg(torch, p3):
+    """scale512 (N = 512^3, 1000 halos hold 50 %, rungs 0-7 from grid counts)
+    on one GPU: each call once after a warm-up call (the batched one once,
+    after the forward has grown most of the workspace), HIP-event pair-kernel
+    times beside the wall clock."""
+    from workloads import make_workload
+    from workloads.generators import gaussian_weights
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    wl = make_workload("scale512")
+    log("scale512 generated in %.1f s" % (time.perf_counter() - t0))
+    pos = torch.from_numpy(wl.pos).to(dev)
+    rung = torch.from_numpy(wl.rung).to(dev)
+    kw = dict(box=wl.box, x_s=wl.x_s, r_cut=wl.r_cut, precision="fp32")
+    thr = list(range(8))
+    res = {"workload": "scale512: N=%d clustered (1000 halos hold 50%%), PM grid %d^3, "
+                       "rungs 0-7 from grid counts" % (wl.n, wl.n_pm),
+           "subset_sizes": [int((wl.rung >= k).sum()) for k in thr],
+           "parity": "4096 receivers against the FP64 oracle in the GPU tests"}
+    ctx = p3.Context(0)
+
+    def once(name, fn, layout, warm=True, flops=FLOPS_PER_INTERACTION):
+        ctx.set_config(*layout)
+        if warm:
+            fn()
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        t1 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        st = ctx.stats()
+        ctx.set_timing(False)
+        rec = {"ms_per_call": wall * 1e3, "pair_kernel_ms": st["ms_pairs"],
+               "build_ms": st["ms_build"], "interactions": st["interactions"],
+               "value": st["interactions"] / wall,
+               "achieved_tflops": flops * st["interactions"] / (st["ms_pairs"] * 1e-3) / 1e12,
+               "layout": {k: st[k] for k in LAYOUT_KEYS}}
+        log("scale512", name, "%.1f ms  pairs %.1f ms  %.3g interactions"
+            % (wall * 1e3, st["ms_pairs"], st["interactions"]))
+        return rec
+
+    try:
+        out = torch.empty((wl.n, 3), dtype=torch.float64, device=dev)
+        res["forward_fp32"] = once(
+            "forward", lambda: ctx.force(pos, None, None, out=out, **kw), (1, 4096, 32, 2))
+        del out
+        out8 = torch.empty((8, wl.n, 3), dtype=torch.float64, device=dev)
+        res["batched_fp32"] = once(
+            "batched", lambda: ctx.force_batched(pos, None, rung, thr, out=out8, **kw),
+            (2, 4096, 32, 1), warm=False)
+        del out8
+        wd = torch.from_numpy(gaussian_weights(wl.n, wl.config_id)).to(dev)
+        res["adjoint_fp32"] = once(
+            "adjoint", lambda: ctx.force_backward(pos, None, None, wd, **kw),
+            (1, 4096, 32, 2), flops=ADJOINT_FLOPS)
+        del wd
+    finally:
+        ctx.set_config()
+        ctx.close()
+    del pos, rung
+    torch.cuda.empty_cache()
+    return res
+
+
+def configs_errors(cfg):
+    """Force errors of the uniform32 rows (every row, against the oracle's
+    brute force, with the exact pair count) and the VJP errors of the diff64
+    sampled rows (against the oracle's cell-list VJP), filled into the
+    configs leg's records; part of the CPU-baseline work."""
+    import numpy as np
+
+    import oracle
+    from workloads import make_workload
+    if "uniform32" in cfg:
+        u = make_workload("uniform32")
+        ref_u, cnt_u, absum_u = oracle.force_full(u.pos, None, u.box, u.x_s, u.r_cut)
+        for prec in ("fp64", "fp32"):
+            rec = cfg["uniform32"][prec]
+            e = oracle.errors(rec["_acc"], ref_u, absum_u)
+            rec["force_error"] = {"e_l2": e["e_l2"], "e_max_cond": e["e_max_cond"], "rows": u.n}
+            rec["interactions_match_oracle"] = rec["interactions"] == int(cnt_u.sum())
+    if "diff64" in cfg:
+        d = make_workload("diff64")
+        rd = cfg["diff64"]
+        g_ref = oracle.vjp(d.pos, d.mass, None, rd["_w"], d.box, d.x_s, d.r_cut,
+                           kidx=rd["_idx"], method="tiled")
+        for prec in ("fp64", "fp32"):
+            got = rd[prec]["_grad"]
+            rd[prec]["adjoint"]["vjp_error"] = {
+                "rel_l2": float(np.linalg.norm(got - g_ref) / np.linalg.norm(g_ref)),
+                "max_row": float(np.max(np.linalg.norm(got - g_ref, axis=1))
+                                 / np.max(np.linalg.norm(g_ref, axis=1))),
+                "rows": int(rd["_idx"].size)}
+
+
+def configs_strip(cfg):
+    """Drop the configs leg's kept GPU rows before the line is printed."""
+    for prec in ("fp64", "fp32"):
+        cfg.get("uniform32", {}).get(prec, {}).pop("_acc", None)
+        cfg.get("diff64", {}).get(prec, {}).pop("_grad", None)
+    for k in ("_idx", "_w"):
+        cfg.get("diff64", {}).pop(k, None)
+
+
 def sort_record(st, n):
     """HBM rate of the counting sort (cell keys, scan, scatter, fine order)
     against its algorithmic bytes: each particle's position read once (24 B)
@@ -650,6 +828,9 @@ def main():
                                                   args.warmup)
     if "subtiles" in legs:
         line["subtiles"] = subtiles_leg(torch, p3)
+    if "configs" in legs:
+        line["configs"] = configs_leg(torch, p3, args.steps, args.warmup,
+                                      scale="noscale" not in legs)
     if "batched" in legs:
         layouts = {p: tuple(results[p]["stats"][k] for k in
                             ("subtiles_per_dim", "item_target", "cluster_size", "screen"))
@@ -692,10 +873,12 @@ def main():
         for key, rec in line.get("shapes", {}).items():
             e = oracle.errors(rec["_acc"][idx], ref, absum)
             rec["force_error"] = {"e_l2": e["e_l2"], "e_max_cond": e["e_max_cond"]}
+        configs_errors(line.get("configs", {}))
         if not args.no_cpu_tiled:
             line["cpu_tiled"] = cpu_tiled_leg()
     for rec in line.get("shapes", {}).values():
         rec.pop("_acc", None)
+    configs_strip(line.get("configs", {}))
     print(json.dumps(line), flush=True)
 
 

@@ -648,8 +648,9 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     if ((rc = take(h, w, w.clusters, sizeof(Cluster) * cl_bound, s))) return rc;
     if ((rc = take(h, w, w.itemcnt, sizeof(int) * (cl_bound + 1), s))) return rc;
     if ((rc = take(h, w, w.bsum, sizeof(int) * scan_block_sums_needed(scan_max), s))) return rc;
-    if ((rc = take(h, w, w.counters, sizeof(Counters), s))) return rc;
-    if ((rc = take(h, w, w.scal, sizeof(int) * (16 + kXcds), s))) return rc;
+    if ((rc = take(h, w, w.counters, sizeof(Counters) * kCounterCopies * kCounterStride, s)))
+        return rc;
+    if ((rc = take(h, w, w.scal, sizeof(int) * kXcds * kQueueStride, s))) return rc;
     if ((rc = take(h, w, w.rp, sizeof(double4) * (nflags + 1), s))) return rc;
     if ((rc = take(h, w, w.rperm, sizeof(int) * (nflags + 1), s))) return rc;
     if (r.backward && (rc = take(h, w, w.rwa, sizeof(double4) * (nflags + 1), s))) return rc;
@@ -691,19 +692,19 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     int *itemcnt = (int *)w.itemcnt.p, *bsum = (int *)w.bsum.p;
     Counters *counters = (Counters *)w.counters.p;
     h->last_counters = counters;
-    int *scal = (int *)w.scal.p;   // [16 ..] the XCD work queues
+    int *scal = (int *)w.scal.p;   // the XCD work queues, kQueueStride ints apart
 
     // ---- sort ----
     int *fbig = (int *)w.fbig.p;
-    int *queue = scal + 16;
+    int *queue = scal;
     double4 *sp_f = (double4 *)w.sp2.p;   // the sorted particles after the fine order
     {
         // every small initialisation of the call in one launch
         FillSet f{};
         f.add(cells, ncells + 1, 0);
-        f.add((int *)counters, sizeof(Counters) / sizeof(int), 0);
+        f.add((int *)counters, sizeof(Counters) * kCounterCopies * kCounterStride / sizeof(int), 0);
         f.add(fbig, 1, 0);
-        f.add(queue, kXcds, 0);
+        f.add(queue, kXcds * kQueueStride, 0);
         f.add((int *)(sp_f + n), kSupplierPad * sizeof(double4) / sizeof(int), 0);
         if (all_recv) f.add(flags + nflags, 1, n);   // the receiver total
         f.add((int *)w.scan1.p, 2 * s1_total + 4, 0);
@@ -1596,9 +1597,19 @@ int p3m_sr_get_stats(p3m_sr_handle h, p3m_sr_stats *out) {
         st.items = h->host_tot[2];
     }
     if (h->last_counters && st.n > 0) {
-        Counters c{};
+        Counters cp[kCounterCopies * kCounterStride];
         P3M_HIP(hipStreamSynchronize(h->last_stream));
-        P3M_HIP(hipMemcpy(&c, h->last_counters, sizeof(c), hipMemcpyDeviceToHost));
+        P3M_HIP(hipMemcpy(cp, h->last_counters, sizeof(cp), hipMemcpyDeviceToHost));
+        Counters c{};
+        for (int k = 0; k < kCounterCopies; ++k) {
+            const Counters &e = cp[k * kCounterStride];
+            c.interactions += e.interactions;
+            c.candidates += e.candidates;
+            c.steps += e.steps;
+            c.screened += e.screened;
+            c.rare += e.rare;
+            c.scan_stall += e.scan_stall;
+        }
         st.interactions = (int64_t)c.interactions;
         st.candidates = (int64_t)c.candidates;
         st.steps = (int64_t)c.steps;

@@ -770,7 +770,7 @@ __device__ inline int next_item(const PairArgs &a, const ItemQueue &iq, int lane
         const int c0 = (int)((long long)iq.n * x / kXcds);
         const int c1 = (int)((long long)iq.n * (x + 1) / kXcds);
         int got = 0;
-        if (lane == 0) got = atomicAdd(&a.queue[x], iq.batch);
+        if (lane == 0) got = atomicAdd(a.queue + x * kQueueStride, iq.batch);
         got = __builtin_amdgcn_readfirstlane(got);
         if (c0 + got < c1) {
             q.cur = c0 + got;
@@ -920,11 +920,12 @@ void k_pairs(PairArgs a) {
     unsigned long long tot = (unsigned long long)wc.n_lane;
     for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, kWave);
     tot += wc.n_ok;
-    if (lane == 0 && a.counters) {
-        atomicAdd(&a.counters->interactions, tot);
-        atomicAdd(&a.counters->candidates, wc.cand);
-        atomicAdd(&a.counters->steps, wc.steps);
-        atomicAdd(&a.counters->screened, wc.screened);
+    if (lane == 0 && a.counters && wc.steps + wc.screened + wc.cand + tot > 0) {
+        Counters *k = a.counters + (blockIdx.x % kCounterCopies) * kCounterStride;
+        atomicAdd(&k->interactions, tot);
+        atomicAdd(&k->candidates, wc.cand);
+        atomicAdd(&k->steps, wc.steps);
+        atomicAdd(&k->screened, wc.screened);
     }
 }
 
@@ -1433,11 +1434,12 @@ void k_pairs_mutual(PairArgs a) {
         mutual_item<RMAX, UNIT, BWD>(a, item, cl, cnt, begin, lane, ring_pos[w], ring_idx[w],
                                      ring_wt[BWD ? w : 0], tally);
     }
-    if (lane == 0 && a.counters) {
-        atomicAdd(&a.counters->interactions, tally.pairs);
-        atomicAdd(&a.counters->steps, tally.steps);
-        atomicAdd(&a.counters->screened, tally.screened);
-        atomicAdd(&a.counters->rare, tally.rare);
+    if (lane == 0 && a.counters && tally.pairs + tally.steps + tally.screened + tally.rare > 0) {
+        Counters *k = a.counters + (blockIdx.x % kCounterCopies) * kCounterStride;
+        atomicAdd(&k->interactions, tally.pairs);
+        atomicAdd(&k->steps, tally.steps);
+        atomicAdd(&k->screened, tally.screened);
+        atomicAdd(&k->rare, tally.rare);
     }
 }
 

@@ -127,9 +127,14 @@ __global__ void k_axpy3(double *__restrict__ vel, const double *__restrict__ acc
     vel[j] = vel[j] + acc[j] * dk;
 }
 
-// Adds one force call's accepted-pair count to the period's total.
+// Adds one force call's accepted-pair count (the sum of its counter copies)
+// to the period's total.
 __global__ void k_kdk_accum(const Counters *__restrict__ c, unsigned long long *__restrict__ total) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *total += c->interactions;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        unsigned long long s = 0;
+        for (int k = 0; k < kCounterCopies; ++k) s += c[k * kCounterStride].interactions;
+        *total += s;
+    }
 }
 
 unsigned blocks(size_t n) { return (unsigned)((n + 255) / 256); }

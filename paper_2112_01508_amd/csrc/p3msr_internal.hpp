@@ -97,6 +97,14 @@ struct Counters {
     unsigned long long scan_stall;   // single-pass scans whose look-back hit its poll limit
     unsigned long long pad[2];
 };
+static_assert(256 % sizeof(Counters) == 0, "Counters copies are 256 B apart");
+
+// The pair kernels add their waves' counts into one Counters copy per XCD,
+// each in a 256 B line of its own (the readers sum the copies): one copy for
+// every wave would queue their atomics on one cache line at the end of the
+// launch.
+constexpr int kCounterCopies = 8;
+constexpr int kCounterStride = 256 / sizeof(Counters);
 
 enum SelKind { SEL_ALL = 0, SEL_MASK = 1, SEL_RUNG = 2 };
 
@@ -286,6 +294,10 @@ hipError_t launch_fill_multi(const FillSet &f, hipStream_t s);
 // force.hip
 enum PairMode { FWD_F32 = 0, FWD_F64 = 1, BWD_F32 = 2, BWD_F64 = 3 };
 constexpr int kXcds = 8;   // MI355X: workgroups are dealt round-robin to 8 XCDs
+static_assert(kCounterCopies == kXcds, "one Counters copy per XCD");
+// ints between the XCD work counters: each in a 256 B line of its own, so
+// claims from different XCDs do not queue on one cache line
+constexpr int kQueueStride = 64;
 
 struct PairArgs {
     const double4 *sp;       // suppliers in sorted order
@@ -295,11 +307,11 @@ struct PairArgs {
     const Cluster *clusters;
     const Item *items;
     const double4 *wa;       // backward: suppliers' w * [active], sorted (FP32: float4 bits)
-    int *queue;              // kXcds work counters, zero at launch
+    int *queue;              // kXcds work counters kQueueStride ints apart, zero at launch
     const int *rperm;        // original index of each receiver row (indexed like act_pos)
     double *out;             // n_sub x n x 3, zeroed before the launch
     long long out_stride;    // elements per subset in out (3 n)
-    Counters *counters;
+    Counters *counters;      // kCounterCopies copies, kCounterStride apart
     // the item count, read on the device (the host need not wait for it)
     const int *n_items_dev;
     int unit_mass;           // no mass array: every mu_j is 1 (forward kernels specialise)
