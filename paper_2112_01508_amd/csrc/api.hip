@@ -747,6 +747,11 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
             // the receiver flags read the final selectors, the dense
             // subtiles' among them: with flags the call's stream waits here
             if (!all_recv) P3M_HIP(hipEventRecord(h->bsorted, h->bstream));
+            // the output (the mutual kernel: its sorted-order sums) is cleared
+            // on the build stream meanwhile; nothing before the pair kernel
+            // reads it
+            if (mutual) P3M_HIP(launch_fill_f64((double *)w.msum.p, 0.0, 3 * (size_t)n, h->bstream));
+            else P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, h->bstream));
             P3M_HIP(launch_fine_order_medium(sp, perm, sel_s, cells, g, key, rank, sp_f, perm_f,
                                              sel_f, csize, s));
         }
@@ -773,7 +778,8 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     P3M_HIP(launch_scan1(ncl, ncl, ncl_len, s1 + s1_cells + s1_flags, s1c + 2, stall, bsum, s));
     P3M_HIP(launch_cluster_write(cells, recv_scan, ncl, n, n_sub, g, csize, clusters, s));
 
-    // The cluster boxes, the receiver gather, the output clear and the table
+    // The cluster boxes, the receiver gather, the table (and in the
+    // deterministic mode the output clear)
     // need neither each other's results nor the item planning: they run on
     // the build stream beside it, joined before the pair kernel.  (The box
     // kernel writes only the boxes of the cluster records, the item kernels
@@ -788,9 +794,9 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     P3M_HIP(launch_cluster_finish(clusters, ncl + ncl_len, cl_bound, csize, recv_pos, sp, perm, wa,
                                   rp, (int *)w.rperm.p,
                                   r.backward ? (double4 *)w.rwa.p : nullptr, bs));
-    // the mutual kernel adds into its sorted-order sums, then writes acc_out
-    if (mutual) P3M_HIP(launch_fill_f64((double *)w.msum.p, 0.0, 3 * (size_t)n, bs));
-    else P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, bs));
+    // the output is cleared here in the deterministic mode (which has no
+    // mutual kernel), else on the build stream beside the fine order
+    if (det) P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, bs));
     if (shape != SHAPE_POLY)
         P3M_HIP(launch_build_htab(shape, h->cfg_tab_n, g, (float *)w.htab.p, bs));
     P3M_HIP(hipEventRecord(h->bjoin, bs));

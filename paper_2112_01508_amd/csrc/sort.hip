@@ -60,52 +60,64 @@ __device__ inline int key_of(int cx, int cy, int cz, const Geom &g) {
 }
 
 // Cell key and rank inside the cell, with one global atomic per distinct
-// cell of a block of kKeysBlock particles: the block's keys are counted in
-// an LDS hash table first (a dense halo cell's particles, which share blocks,
-// would otherwise hit one counter from every wave that holds any of them,
-// and those atomics serialise on its address).
-constexpr int kKeysBlock = 1024;
-constexpr int kKeysSlots = 2 * kKeysBlock;   // open addressing, at most half full
+// cell of a block of kKeysThreads x PPT particles: the block's keys are
+// counted in an LDS hash table first (a dense halo cell's particles, which
+// share blocks, would otherwise hit one counter from every wave that holds
+// any of them, and those atomics serialise on its address).  The global
+// atomics bound the kernel, so larger blocks (more particles sharing a cell)
+// pay off.
+constexpr int kKeysThreads = 1024;
 
-__global__ __launch_bounds__(kKeysBlock) void k_keys(const double *__restrict__ pos, int n, Geom g,
-                                                     int *__restrict__ key,
-                                                     int *__restrict__ rank,
-                                                     int *__restrict__ cell_count) {
-    __shared__ int skey[kKeysSlots];
-    __shared__ int scnt[kKeysSlots];
-    for (int t = threadIdx.x; t < kKeysSlots; t += blockDim.x) {
+template <int PPT>
+__global__ __launch_bounds__(kKeysThreads) void k_keys(const double *__restrict__ pos, int n,
+                                                       Geom g, int *__restrict__ key,
+                                                       int *__restrict__ rank,
+                                                       int *__restrict__ cell_count) {
+    constexpr int kSlots = 2 * kKeysThreads * PPT;   // open addressing, at most half full
+    constexpr int kShift = 32 - __builtin_ctz(kSlots);
+    __shared__ int skey[kSlots];
+    __shared__ int scnt[kSlots];
+    for (int t = threadIdx.x; t < kSlots; t += blockDim.x) {
         skey[t] = -1;
         scnt[t] = 0;
     }
     __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = i < n;
-    int slot = 0, local = 0, k = -1;
-    if (live) {
-        const double wx = wrap_coord(pos[3 * (size_t)i], g);
-        const double wy = wrap_coord(pos[3 * (size_t)i + 1], g);
-        const double wz = wrap_coord(pos[3 * (size_t)i + 2], g);
-        k = key_of(cell_of(wx, g), cell_of(wy, g), cell_of(wz, g), g);
-        key[i] = k;
-        // k >= 0 and the table never fills, so the probe ends
-        slot = (int)(((unsigned)k * 2654435761u) >> 21) & (kKeysSlots - 1);
-        for (;;) {
-            const int old = atomicCAS(&skey[slot], -1, k);
-            if (old == -1 || old == k) break;
-            slot = (slot + 1) & (kKeysSlots - 1);
+    int slot[PPT], local[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const long long i = ((long long)blockIdx.x * PPT + p) * kKeysThreads + threadIdx.x;
+        slot[p] = -1;
+        local[p] = 0;
+        if (i < n) {
+            const double wx = wrap_coord(pos[3 * (size_t)i], g);
+            const double wy = wrap_coord(pos[3 * (size_t)i + 1], g);
+            const double wz = wrap_coord(pos[3 * (size_t)i + 2], g);
+            const int k = key_of(cell_of(wx, g), cell_of(wy, g), cell_of(wz, g), g);
+            key[i] = k;
+            // k >= 0 and the table never fills, so the probe ends
+            int sl = (int)(((unsigned)k * 2654435761u) >> kShift);
+            for (;;) {
+                const int old = atomicCAS(&skey[sl], -1, k);
+                if (old == -1 || old == k) break;
+                sl = (sl + 1) & (kSlots - 1);
+            }
+            slot[p] = sl;
+            local[p] = atomicAdd(&scnt[sl], 1);
         }
-        local = atomicAdd(&scnt[slot], 1);
     }
     __syncthreads();
     // one global atomic per occupied slot; its base replaces the count
-    for (int t = threadIdx.x; t < kKeysSlots; t += blockDim.x) {
+    for (int t = threadIdx.x; t < kSlots; t += blockDim.x) {
         const int kk = skey[t];
         if (kk >= 0) scnt[t] = atomicAdd(&cell_count[kk], scnt[t]);
     }
     __syncthreads();
-    if (live) rank[i] = scnt[slot] + local;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const long long i = ((long long)blockIdx.x * PPT + p) * kKeysThreads + threadIdx.x;
+        if (slot[p] >= 0) rank[i] = scnt[slot[p]] + local[p];
+    }
 }
-
 // ---- exclusive scan (reduce / top / down-sweep) -----------------------------
 
 __device__ inline int block_exclusive_scan(int v, int *lds, int *total) {
@@ -829,8 +841,21 @@ hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s) {
 hipError_t launch_keys(const double *pos, int n, const Geom &g, int *key, int *rank,
                        int *cell_count, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, kKeysBlock)), dim3(kKeysBlock), 0, s, pos, n, g,
-                       key, rank, cell_count);
+    // the largest block (more particles per global atomic) that still gives
+    // every CU a block: 8 particles per thread from N = 2^21, 1 below 2^19
+    const size_t per_cu = (size_t)n / (256 * kKeysThreads);
+    if (per_cu >= 8)
+        hipLaunchKernelGGL(k_keys<8>, dim3(grid_for(n, kKeysThreads * 8)), dim3(kKeysThreads), 0,
+                           s, pos, n, g, key, rank, cell_count);
+    else if (per_cu >= 4)
+        hipLaunchKernelGGL(k_keys<4>, dim3(grid_for(n, kKeysThreads * 4)), dim3(kKeysThreads), 0,
+                           s, pos, n, g, key, rank, cell_count);
+    else if (per_cu >= 2)
+        hipLaunchKernelGGL(k_keys<2>, dim3(grid_for(n, kKeysThreads * 2)), dim3(kKeysThreads), 0,
+                           s, pos, n, g, key, rank, cell_count);
+    else
+        hipLaunchKernelGGL(k_keys<1>, dim3(grid_for(n, kKeysThreads)), dim3(kKeysThreads), 0, s,
+                           pos, n, g, key, rank, cell_count);
     return hipGetLastError();
 }
 
