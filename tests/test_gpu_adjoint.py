@@ -110,8 +110,10 @@ def test_vjp_finite_differences_diff64(env, prec, screen):
     rel = np.linalg.norm(g[idx] - fd, axis=1) / np.linalg.norm(fd, axis=1)
     print("max rel %.3e median %.3e" % (rel.max(), np.median(rel)), flush=True)
     assert rel.max() <= 1e-4
-    # translation invariance with every particle active: sum_k grad_k = 0
-    assert np.all(np.abs(g.sum(axis=0)) <= 1e-6 * np.abs(g).sum(axis=0))
+    # translation invariance with every particle active: sum_k grad_k = 0 (to
+    # the rounding of the sums: FP64 pair terms, FP32 ones)
+    bound = {"fp64": 1e-12, "fp32": 1e-6}[prec]
+    assert np.all(np.abs(g.sum(axis=0)) <= bound * np.abs(g).sum(axis=0))
 
 
 def test_autograd_function(env):
