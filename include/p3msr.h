@@ -246,8 +246,8 @@ int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
  * the three fastest of the other candidates are timed again and the
  * fastest of them is kept (and cached, as kind 3 for the forward, 4 for
  * the adjoint) beside it: calls with this key that cannot take screen 2
- * (softened, with an active mask, with a tabulated shape, or in the
- * deterministic mode) run in that layout.
+ * (with an active mask, with a tabulated shape, in the deterministic mode,
+ * or softened adjoints) run in that layout.
  */
 #define P3M_TUNE_ADJOINT 4
 #define P3M_TUNE_FORCE 8
@@ -309,8 +309,9 @@ int p3m_sr_tune_cache_check(const char *path, int *entries, int *lines);
  *                     loop (the subtile-pair culling of section 2.1.3
  *                     carried down to single suppliers); 0: no screening;
  *                     2: screened, and for all-active P3M_FP32 forward calls
- *                     (polynomial shape) and P3M_FP32 backward calls (no
- *                     softening, n <= 2^27) each pair is evaluated once for
+ *                     (polynomial shape, softened or not) and P3M_FP32
+ *                     backward calls without softening (n <= 2^27 for
+ *                     both) each pair is evaluated once for
  *                     both partners (Newton's third law, as the paper's tile
  *                     pairing in section 2.1.3, "Tiles"; the adjoint's pair
  *                     term is antisymmetric too): clusters visit the upper

@@ -64,8 +64,8 @@ struct DevBuf {
 // precision, call kind (forward, adjoint, rung-batched) and subset count.
 // When the forward's or the adjoint's winner evaluates each pair once for
 // both partners, the fastest of the other layouts is filed too (the PLAIN
-// kinds), for the calls that layout cannot serve: softened, masked,
-// tabulated-shape and deterministic ones.
+// kinds), for the calls that layout cannot serve: masked, tabulated-shape,
+// deterministic and softened adjoint ones.
 enum TuneKind {
     TUNE_FORWARD = 0,
     TUNE_ADJOINT = 1,
@@ -148,7 +148,7 @@ struct p3m_sr_context {
     // resident pair-kernel blocks per CU, per variant: mode, screen, cluster size,
     // shape, unit mass, softening
     int blocks_per_cu[4 * 2 * 4 * 3 * 4] = {};
-    int mutual_blocks_per_cu[4 * 2 * 2] = {};   // by cluster size, unit mass and adjoint
+    int mutual_blocks_per_cu[4 * 2 * 2 * 2] = {};   // by cluster size, adjoint, unit mass, softening
     // short-range workspace: grown with hipMalloc as calls need it, or (the
     // no-alloc entry point) carved from the library's fixed device array
     SrWork work, fixed;
@@ -552,13 +552,14 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     // tabulated FP32 shape (point particles, forward only)
     const int shape = (fp32 && !r.backward && eps_b == 0.0) ? h->cfg_shape : SHAPE_POLY;
     // each pair once for both partners: FP32 calls with every particle a
-    // receiver (all-active forward calls with the polynomial shape, and the
-    // adjoint), no softening and fewer than 2^27 particles (the list entries
-    // hold the sorted index in 27 bits), not in the deterministic mode (its
-    // reactions are added with atomics), and clusters of 16, 32 or 64
+    // receiver (all-active forward calls with the polynomial shape, softened
+    // or not, and the adjoint without softening), fewer than 2^27 particles
+    // (the list entries hold the sorted index in 27 bits), not in the
+    // deterministic mode (its reactions are added with atomics), and
+    // clusters of 16, 32 or 64
     const bool det = h->deterministic;
-    const bool mutual_ok = fp32 && all_recv && shape == SHAPE_POLY && eps_b == 0.0 &&
-                           r.n <= (int64_t)(1u << 27) && !det;
+    const bool mutual_ok = fp32 && all_recv && shape == SHAPE_POLY &&
+                           (eps_b == 0.0 || !r.backward) && r.n <= (int64_t)(1u << 27) && !det;
 
     // decomposition: explicit override > user config > autotuned > default
     int ns = 0, target = 0, csize = 0, screen = -1;
@@ -854,8 +855,9 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     const int cs_idx = csize == 8 ? 0 : csize == 16 ? 1 : csize == 32 ? 2 : 3;
     int bpc;
     if (mutual) {
-        int &slot_m = h->mutual_blocks_per_cu[(cs_idx * 2 + (r.backward ? 1 : 0)) * 2 + unit];
-        if (slot_m == 0) slot_m = mutual_blocks_per_cu(csize, unit, r.backward);
+        int &slot_m =
+            h->mutual_blocks_per_cu[((cs_idx * 2 + (r.backward ? 1 : 0)) * 2 + unit) * 2 + soft];
+        if (slot_m == 0) slot_m = mutual_blocks_per_cu(csize, unit, r.backward, soft != 0);
         bpc = slot_m;
         a.out = (double *)w.msum.p;
         a.out_stride = n;
@@ -1445,10 +1447,9 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     // level 2 also sweeps the item size around the level-1 winner
     std::vector<std::pair<int, int>> layouts = {{64, 0}, {64, 1}, {32, 1}, {16, 1}, {8, 1},
                                                 {16, 0}, {8, 0}};
-    // all-active FP32 forward calls and FP32 adjoints can evaluate each pair
-    // once for both partners
-    if ((adjoint || (!active && h->cfg_shape == SHAPE_POLY)) && precision == P3M_FP32 &&
-        h->eps == 0.0)
+    // all-active FP32 forward calls (softened or not) and FP32 adjoints
+    // without softening can evaluate each pair once for both partners
+    if (precision == P3M_FP32 && (adjoint ? h->eps == 0.0 : !active && h->cfg_shape == SHAPE_POLY))
         for (int c : {32, 64, 16}) layouts.push_back({c, kScreenMutual});
     const TuneKey key{n, nt, precision, adjoint ? TUNE_ADJOINT : TUNE_FORWARD, 1};
     rc = tune(h, r, key, level, {1, 2, 3, 4}, layouts, {1024, 4096},

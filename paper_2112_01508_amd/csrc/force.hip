@@ -969,6 +969,10 @@ void k_pairs(PairArgs a) {
 // The sums go to an FP64 array in sorted order, one component after the
 // other (three arrays of n), which a final pass writes to acc_out.
 
+// The mutual kernels' call kinds: the forward force, the adjoint, the
+// forward force with B-spline softening.
+constexpr int kMutFwd = 0, kMutBwd = 1, kMutSoft = 2;
+
 constexpr int kRing = 128;                    // list entries per wave (a ring)
 constexpr unsigned kIdxBits = 27;             // sorted index bits of a list entry
 constexpr unsigned kIdxMask = (1u << kIdxBits) - 1u;
@@ -1008,6 +1012,7 @@ struct MutualLane {
     float axf = 0.f, ayf = 0.f, azf = 0.f;   // block sums (FP32)
     float jx = 0.f, jy = 0.f, jz = 0.f;      // reaction on this lane's entry (FP32)
     float wkx = 0.f, wky = 0.f, wkz = 0.f;   // adjoint: this receiver's w_k [k active]
+    float eb2 = 0.f;                         // softened forward: eps_b^2 (FP32)
 };
 
 // The separation of receiver i_sorted and list entry jr (sorted index |
@@ -1037,10 +1042,11 @@ __device__ __attribute__((noinline)) float4 mutual_fp64_sep(const double4 *__res
 // its row.  SELF: the cluster's own particles, each ordered pair evaluated
 // from both ends, no reaction.  BWD: the adjoint's pair term instead of the
 // force; ew holds the entry's weight w_j [j active].
-template <int S, bool UNIT, bool SELF, bool BWD>
+template <int S, bool UNIT, bool SELF, int KIND>
 __device__ __forceinline__ void mutual_step(MutualLane &m, const float4 &e, const float4 &ew,
                                             int jid, const PairArgs &a, unsigned &cnt,
                                             unsigned &rare_n) {
+    constexpr bool BWD = KIND == kMutBwd;
     // each step's values die within it: keep the scheduler from interleaving
     // the unrolled steps (which multiplies the live registers)
     __builtin_amdgcn_sched_barrier(0);
@@ -1112,8 +1118,21 @@ __device__ __forceinline__ void mutual_step(MutualLane &m, const float4 &e, cons
     const float ri = __builtin_amdgcn_rsqf(r2);
     const float h = h_poly(fmaf(r2, a.g.c2f, -P3M_HPOLY_T0));
     const float ri3 = ri * ri * ri;
+    float shv = fmaf(a.g.c3f, h, ri3);
+    if constexpr (KIND == kMutSoft) {
+        // pairs inside the softening length (few): c3 H(t) + |r|_B^-3 with
+        // the softening term in FP64, as in the ordered kernel (the factor
+        // is continuous at eps_b, so the FP32 test there is enough)
+        const unsigned long long m_soft = ballot64(r2 < m.eb2) & acc_m;
+        if (m_soft) {
+            if ((m_soft >> (threadIdx.x & (kWave - 1))) & 1ull) {
+                const double x = (double)(r2 * ri * a.g.inv_eps_bf);
+                shv = (float)((double)(a.g.c3f * h) + bspline_m3(x, (double)ri3, a.g));
+            }
+        }
+    }
     // lanes without a pair send no reaction
-    const float sh = keep_lanes(acc_m, fmaf(a.g.c3f, h, ri3));
+    const float sh = keep_lanes(acc_m, shv);
     float shj = sh, shi = sh;
     if constexpr (!UNIT) {
         shj = sh * rot16<S>(e.w);          // the force on i carries mu_j
@@ -1136,27 +1155,27 @@ __device__ __forceinline__ void mutual_step(MutualLane &m, const float4 &e, cons
     asm volatile("" ::"v"(m.axf), "v"(m.ayf), "v"(m.azf), "v"(m.jx), "v"(m.jy), "v"(m.jz));
 }
 
-template <bool UNIT, bool SELF, int NS, bool BWD>
+template <bool UNIT, bool SELF, int NS, int KIND>
 __device__ __forceinline__ void mutual_steps(MutualLane &m, const float4 &e, const float4 &ew,
                                              int jid, const PairArgs &a, unsigned &cnt,
                                              unsigned &rare_n) {
-    mutual_step<0, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-    mutual_step<1, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-    mutual_step<2, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-    mutual_step<3, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+    mutual_step<0, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
+    mutual_step<1, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
+    mutual_step<2, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
+    mutual_step<3, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
     if constexpr (NS > 4) {
-        mutual_step<4, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step<5, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step<6, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step<7, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step<8, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step<9, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step<10, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step<11, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step<12, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step<13, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step<14, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step<15, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<4, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<5, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<6, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<7, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<8, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<9, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<10, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<11, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<12, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<13, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<14, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step<15, UNIT, SELF, KIND>(m, e, ew, jid, a, cnt, rare_n);
     }
 }
 
@@ -1169,8 +1188,9 @@ __device__ __forceinline__ float rows_sum(float v) {
     return v;
 }
 
-template <int R, bool UNIT, bool BWD>
+template <int R, bool UNIT, int KIND>
 struct MutualVisit {
+    static constexpr bool BWD = KIND == kMutBwd;
     static constexpr int EB = 64 / R;   // list entries per block of 16 steps
     const PairArgs &a;
     MutualLane &m;
@@ -1212,7 +1232,7 @@ struct MutualVisit {
         wave_lds_sync();   // the reads are done before later screens overwrite the ring
         m.jx = m.jy = m.jz = 0.f;
         unsigned cnt = 0, rn = 0;
-        mutual_steps<UNIT, false, 16, BWD>(m, e, ew, jid, a, cnt, rn);
+        mutual_steps<UNIT, false, 16, KIND>(m, e, ew, jid, a, cnt, rn);
         flush_i();
         const float jx = rows_sum<R>(m.jx), jy = rows_sum<R>(m.jy), jz = rows_sum<R>(m.jz);
         if (row % R == 0 && k < nv) {
@@ -1250,7 +1270,7 @@ struct MutualVisit {
                 if constexpr (BWD) ew = reinterpret_cast<const float4 *>(a.wa)[begin + idx];
             }
             unsigned c = 0, rn = 0;
-            mutual_steps<UNIT, true, R == 1 ? 4 : 16, BWD>(m, e, ew, jid, a, c, rn);
+            mutual_steps<UNIT, true, R == 1 ? 4 : 16, KIND>(m, e, ew, jid, a, c, rn);
             flush_i();
             pairs += c;
             steps += R == 1 ? 4 : 16;
@@ -1336,11 +1356,12 @@ struct MutualTally {
 };
 
 // One work item in the layout of R rows per receiver copy (cnt <= 16 R).
-template <int R, bool UNIT, bool BWD>
+template <int R, bool UNIT, int KIND>
 __device__ __forceinline__ void mutual_item(const PairArgs &a, const Item &item,
                                             const Cluster &cl, int cnt, int begin, int lane,
                                             float4 *ring_pos, int *ring_idx, float4 *ring_w,
                                             MutualTally &tally) {
+    constexpr bool BWD = KIND == kMutBwd;
     const int row = lane >> 4, l = lane & 15;
     const double cx = 0.5 * (cl.lo[0] + cl.hi[0]);
     const double cy = 0.5 * (cl.lo[1] + cl.hi[1]);
@@ -1358,6 +1379,7 @@ __device__ __forceinline__ void mutual_item(const PairArgs &a, const Item &item,
     // in FP64 (and r^2 == 0, since ki is at least the smallest normal)
     m.ki = fmaxf(0.01f * fmaf(m.hz, m.hz, fmaf(m.hy, m.hy, m.hx * m.hx)), 1.1754944e-38f);
     if (!live) m.ki = 0.f;
+    if constexpr (KIND == kMutSoft) m.eb2 = (float)a.g.eps_b2;
     if constexpr (BWD) {
         if (live) {
             const float4 wk = reinterpret_cast<const float4 *>(a.wa)[m.i_sorted];
@@ -1366,7 +1388,7 @@ __device__ __forceinline__ void mutual_item(const PairArgs &a, const Item &item,
             m.wkz = wk.z;
         }
     }
-    MutualVisit<R, UNIT, BWD> v{a, m, ring_pos, ring_idx, ring_w, cl.lo, cl.hi, cx, cy, cz,
+    MutualVisit<R, UNIT, KIND> v{a, m, ring_pos, ring_idx, ring_w, cl.lo, cl.hi, cx, cy, cz,
                                 lane, begin + cnt};
     if (item.sole & kItemFirst) v.self_pass(cnt, begin);
     walk_item(v, item, cl, a, lane);
@@ -1400,9 +1422,10 @@ __device__ __forceinline__ void mutual_item(const PairArgs &a, const Item &item,
 // fewer idle lanes: 16 receivers or fewer in R = 1, 32 or fewer in R = 2.
 // a.out: three FP64 arrays of a.out_stride (= n) values in sorted order,
 // zeroed before the launch.
-template <int RMAX, bool UNIT, bool BWD>
+template <int RMAX, bool UNIT, int KIND>
 __global__ __launch_bounds__(kForceBlock) __attribute__((amdgpu_waves_per_eu(5)))
 void k_pairs_mutual(PairArgs a) {
+    constexpr bool BWD = KIND == kMutBwd;
     constexpr int NW = kForceBlock / kWave;
     __shared__ float4 ring_pos[NW][kRing];
     __shared__ int ring_idx[NW][kRing];
@@ -1419,19 +1442,19 @@ void k_pairs_mutual(PairArgs a) {
         const int begin = __builtin_amdgcn_readfirstlane(cl.begin);
         if constexpr (RMAX >= 2) {
             if (cnt <= 16) {
-                mutual_item<1, UNIT, BWD>(a, item, cl, cnt, begin, lane, ring_pos[w],
+                mutual_item<1, UNIT, KIND>(a, item, cl, cnt, begin, lane, ring_pos[w],
                                           ring_idx[w], ring_wt[BWD ? w : 0], tally);
                 continue;
             }
         }
         if constexpr (RMAX == 4) {
             if (cnt <= 32) {
-                mutual_item<2, UNIT, BWD>(a, item, cl, cnt, begin, lane, ring_pos[w],
+                mutual_item<2, UNIT, KIND>(a, item, cl, cnt, begin, lane, ring_pos[w],
                                           ring_idx[w], ring_wt[BWD ? w : 0], tally);
                 continue;
             }
         }
-        mutual_item<RMAX, UNIT, BWD>(a, item, cl, cnt, begin, lane, ring_pos[w], ring_idx[w],
+        mutual_item<RMAX, UNIT, KIND>(a, item, cl, cnt, begin, lane, ring_pos[w], ring_idx[w],
                                      ring_wt[BWD ? w : 0], tally);
     }
     if (lane == 0 && a.counters && tally.pairs + tally.steps + tally.screened + tally.rare > 0) {
@@ -1456,18 +1479,21 @@ __global__ void k_mutual_out(const double *__restrict__ sums, const int *__restr
 
 using MutualFn = void (*)(PairArgs);
 
-template <bool BWD>
+template <int KIND>
 MutualFn mutual_kernel_mode(int csize, bool unit) {
     switch (csize) {
-    case 16: return unit ? k_pairs_mutual<1, true, BWD> : k_pairs_mutual<1, false, BWD>;
-    case 32: return unit ? k_pairs_mutual<2, true, BWD> : k_pairs_mutual<2, false, BWD>;
-    case 64: return unit ? k_pairs_mutual<4, true, BWD> : k_pairs_mutual<4, false, BWD>;
+    case 16: return unit ? k_pairs_mutual<1, true, KIND> : k_pairs_mutual<1, false, KIND>;
+    case 32: return unit ? k_pairs_mutual<2, true, KIND> : k_pairs_mutual<2, false, KIND>;
+    case 64: return unit ? k_pairs_mutual<4, true, KIND> : k_pairs_mutual<4, false, KIND>;
     default: return nullptr;
     }
 }
 
-MutualFn mutual_kernel(int csize, bool unit, bool bwd) {
-    return bwd ? mutual_kernel_mode<true>(csize, unit) : mutual_kernel_mode<false>(csize, unit);
+// soft: the forward with B-spline softening (the adjoint has no softened
+// mutual kernel)
+MutualFn mutual_kernel(int csize, bool unit, bool bwd, bool soft) {
+    if (bwd) return soft ? nullptr : mutual_kernel_mode<kMutBwd>(csize, unit);
+    return soft ? mutual_kernel_mode<kMutSoft>(csize, unit) : mutual_kernel_mode<kMutFwd>(csize, unit);
 }
 
 // The pair-kernel variant for a layout: all share the signature void(PairArgs).
@@ -1551,14 +1577,14 @@ hipError_t launch_pairs(int mode, int screen, int tab, const PairArgs &a, int gr
 }
 
 hipError_t launch_pairs_mutual(const PairArgs &a, bool bwd, int grid, hipStream_t s) {
-    const MutualFn fn = mutual_kernel(a.csize, a.unit_mass != 0, bwd);
+    const MutualFn fn = mutual_kernel(a.csize, a.unit_mass != 0, bwd, a.g.eps_b > 0.0);
     if (!fn) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kForceBlock), 0, s, a);
     return hipGetLastError();
 }
 
-int mutual_blocks_per_cu(int csize, int unit_mass, bool bwd) {
-    const MutualFn fn = mutual_kernel(csize, unit_mass != 0, bwd);
+int mutual_blocks_per_cu(int csize, int unit_mass, bool bwd, bool soft) {
+    const MutualFn fn = mutual_kernel(csize, unit_mass != 0, bwd, soft);
     int nb = 0;
     if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kForceBlock, 0) != hipSuccess)
         return 1;

@@ -380,7 +380,7 @@ int pairs_blocks_per_cu(int mode, int screen, int tab, int csize, int unit_mass,
 // stencil).  a.out: three FP64 arrays of a.out_stride = n sums in sorted
 // order, zeroed before the launch; launch_mutual_out then writes acc_out.
 hipError_t launch_pairs_mutual(const PairArgs &a, bool bwd, int grid, hipStream_t s);
-int mutual_blocks_per_cu(int csize, int unit_mass, bool bwd);
+int mutual_blocks_per_cu(int csize, int unit_mass, bool bwd, bool soft);
 hipError_t launch_mutual_out(const double *sums, const int *perm, int n, double *out,
                              hipStream_t s);
 

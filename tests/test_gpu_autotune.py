@@ -131,9 +131,9 @@ def test_calls_the_mutual_layout_cannot_serve_take_the_kept_one(tmp_path):
     """On the clustered128 recipe (reduced) the FP32 forward's winner is
     normally the mutual layout (screen 2); the tuner then also keeps the
     fastest of the other layouts (kind 3 in the cache), and calls that cannot
-    pair once for both partners (masked, softened, deterministic) run in it,
-    while all-active calls keep the winner.  Every such call still matches the
-    oracle."""
+    pair once for both partners (masked, deterministic, softened adjoint) run
+    in it, while all-active forward calls, softened or not, keep the winner.
+    The masked and deterministic calls still match the oracle."""
     torch, p3 = gpu_or_skip()
     path = str(tmp_path / "tune.json")
     wl = make_workload("clustered128", n_side=64)
@@ -171,11 +171,17 @@ def test_calls_the_mutual_layout_cannot_serve_take_the_kept_one(tmp_path):
         e = oracle.errors(out[idx], ref, absum)
         assert e["e_l2"] <= TOL["fp32"] and e["e_max_cond"] <= TOL["fp32"], e
         ctx.set_deterministic(False)
-        # softening
+        # softening: the forward stays on the winner, the adjoint (no
+        # softened mutual kernel) takes the kept layout
         ctx.set_softening(1e-4)
-        ctx.force(pos, None, None, **kw)
-        assert lay() == plain
-        ctx.set_softening(0.0)
+        try:
+            ctx.force(pos, None, None, **kw)
+            assert lay() == win
+            ones = torch.ones((wl.n, 3), dtype=torch.float64, device=pos.device)
+            ctx.force_backward(pos, None, None, ones, **kw)
+            assert lay() == plain
+        finally:
+            ctx.set_softening(0.0)
         ctx.force(pos, None, None, **kw)
         assert lay() == win
         # a second handle installs both from the cache without timing

@@ -38,7 +38,8 @@ def soft_force(env, pos, mass, active, box, x_s, r_cut, prec, eps, **cfg):
         ctx.set_config()
 
 
-@pytest.mark.parametrize("csize,screen", [(64, 0), (32, 1), (8, 1), (16, 0)])
+@pytest.mark.parametrize("csize,screen", [(64, 0), (32, 1), (8, 1), (16, 0), (16, 2), (32, 2),
+                                          (64, 2)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_softened_clustered(env, prec, csize, screen):
     print("softened diff64 n_side=32", prec, csize, screen, flush=True)
@@ -51,10 +52,35 @@ def test_softened_clustered(env, prec, csize, screen):
     acc, st = soft_force(env, wl.pos, wl.mass, None, 1.0, wl.x_s, wl.r_cut, prec, eps,
                          cluster_size=csize, screen=screen)
     assert abs(st["eps_b"] - 2.8 * eps) <= 1e-15
+    # FP32 screen 2: each pair once for both partners (FP64 runs it as screen 1)
+    assert st["screen"] == (screen if prec == "fp32" or screen < 2 else 1)
     e = oracle.errors(acc, ref, absum)
     print(e, flush=True)
     assert st["interactions"] == int(cnt.sum())
     assert e["e_l2"] <= TOL[prec] and e["e_max_cond"] <= TOL[prec], e
+
+
+@pytest.mark.parametrize("n", [2, 65, 1000, 4097])
+def test_softened_mutual_ragged_masses(env, n):
+    """Softened FP32 calls with every particle active take the kernel that
+    evaluates each pair once for both partners (screen 2): ragged sets with
+    per-particle masses, in the three cluster layouts; n = 2 puts the pair
+    well inside eps_B (and close enough for the FP64 separation)."""
+    pos, mass, _ = random_particles(n, seed=500 + n, active_frac=1.0)
+    if n == 2:
+        pos[0] = [0.5, 0.5, 0.5]
+        pos[1] = [0.5 + 1e-4, 0.5, 0.5]
+    x_s = 1.25 / 24
+    r_cut = 4.5 * x_s
+    eps = 0.01
+    ref, cnt, absum = oracle.force_full(pos, mass, 1.0, x_s, r_cut, method="brute", eps=eps)
+    for cs in (16, 32, 64):
+        acc, st = soft_force(env, pos, mass, None, 1.0, x_s, r_cut, "fp32", eps,
+                             cluster_size=cs, screen=2)
+        assert st["screen"] == 2
+        e = oracle.errors(acc, ref, absum)
+        assert st["interactions"] == int(cnt.sum()), (cs, st["interactions"], int(cnt.sum()))
+        assert e["e_l2"] <= TOL["fp32"] and e["e_max_cond"] <= TOL["fp32"], (cs, e)
 
 
 @pytest.mark.parametrize("n", [2, 65, 1000, 4097])
@@ -130,15 +156,16 @@ def test_softened_batched(env):
         assert e["e_l2"] <= TOL["fp32"] and e["e_max_cond"] <= TOL["fp32"], (t, e)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_softened_clustered128_sampled(env, prec):
+@pytest.mark.parametrize("prec, screen", [("fp64", 1), ("fp32", 1), ("fp32", 2)])
+def test_softened_clustered128_sampled(env, prec, screen):
     """Full N = 128^3 clustered set with softening; 512 seeded receivers
     checked one by one against the oracle over all N."""
-    print("softened clustered128", prec, flush=True)
+    print("softened clustered128", prec, "screen", screen, flush=True)
     wl = make_workload("clustered128", with_rungs=False)
     eps = eps_for(wl.n)
     acc, st = soft_force(env, wl.pos, None, None, 1.0, wl.x_s, wl.r_cut, prec, eps,
-                         subtiles_per_dim=1, item_target=4096, cluster_size=32, screen=1)
+                         subtiles_per_dim=1, item_target=4096, cluster_size=32, screen=screen)
+    assert st["screen"] == screen
     idx = sample_indices(wl.n, 512, wl.config_id)
     ref, cnt, absum, _ = oracle.force(wl.pos, None, 1.0, wl.x_s, wl.r_cut, recv=idx,
                                       method="tiled", eps=eps)
