@@ -806,8 +806,8 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
                               mutual ? 1 : 0, itemcnt, s));
     P3M_HIP(launch_scan1(itemcnt, itemcnt, cl_bound, s1 + s1_cells + s1_flags + s1_ncl, s1c + 3,
                          stall, bsum, s));
-    // the three totals go to pinned memory for the stats; only a call that
-    // waits for the item count needs them before the pair kernel
+    // the three totals go to pinned memory for the stats: here when the call
+    // waits for the item count, else from the item writer
     if (wait_count) {
         P3M_HIP(launch_totals(flags + nflags, ncl + ncl_len, itemcnt + cl_bound, h->host_tot, s));
         P3M_HIP(hipEventRecord(h->tot_ev, s));
@@ -822,8 +822,10 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
             return rc;
     }
     Item *items = (Item *)w.items.p;
+    // the totals for the stats (already there when the call waited for them)
     P3M_HIP(launch_item_write(clusters, ncl + ncl_len, (int)cl_bound, cells, g, target,
-                              mutual ? 1 : 0, itemcnt, items, s));
+                              mutual ? 1 : 0, itemcnt, items, flags + nflags, itemcnt + cl_bound,
+                              wait_count ? nullptr : h->host_tot, s));
     P3M_HIP(hipStreamWaitEvent(s, h->bjoin, 0));
 
     // ---- pairs ----
@@ -881,8 +883,6 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     if (det)
         P3M_HIP(launch_item_reduce(clusters, ncl + ncl_len, (int)cl_bound, itemcnt, a.partials,
                                    csize, a.rperm, r.out, a.out_stride, s));
-    if (!wait_count)
-        P3M_HIP(launch_totals(flags + nflags, ncl + ncl_len, itemcnt + cl_bound, h->host_tot, s));
     if (h->timing) {
         P3M_HIP(hipEventRecord(h->ev[2], s));
         h->timed_last = true;

@@ -259,10 +259,13 @@ hipError_t launch_item_count(const Cluster *clusters, const int *n_clusters_dev,
                              int cluster_bound, const int *cell_start, const Geom &g,
                              int target, int half, int *item_cnt, hipStream_t s);
 // every cluster's items at their offsets item_off (the scanned counts; the
-// array holds them all); the cluster count is read on the device
+// array holds them all); the cluster count is read on the device.  host_tot
+// (nullable, pinned): receives the receiver total *tot_recv, the cluster
+// count and the item total *tot_items.
 hipError_t launch_item_write(const Cluster *clusters, const int *n_clusters_dev, int bound,
                              const int *cell_start, const Geom &g, int target, int half,
-                             const int *item_off, Item *items, hipStream_t s);
+                             const int *item_off, Item *items, const int *tot_recv,
+                             const int *tot_items, int *host_tot, hipStream_t s);
 // 32-bin histogram of particles per tile (log2 bins; bin 0: empty tiles),
 // the occupancy signature the autotuner files its results under
 hipError_t launch_tile_hist(const int *cell_start, const Geom &g, int *hist32, hipStream_t s);

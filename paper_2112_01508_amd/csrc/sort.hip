@@ -665,10 +665,19 @@ __global__ void k_item_count(const Cluster *__restrict__ clusters, const int *__
 
 // Items of every cluster at their scanned offsets; the cluster count is
 // read on the device.
+// tot (nullable): the call's receiver, cluster and item totals (three device
+// counters) copied to the pinned host array host_tot by the first thread,
+// so no launch after the pair kernel is needed for them.
 __global__ void k_item_write(const Cluster *__restrict__ clusters, const int *__restrict__ n_cl,
                              int bound, const int *__restrict__ cs, Geom g, int target, int half,
-                             const int *__restrict__ item_off, Item *__restrict__ items) {
+                             const int *__restrict__ item_off, Item *__restrict__ items,
+                             const int *tot_recv, const int *tot_items, int *host_tot) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (host_tot && c == 0) {
+        host_tot[0] = *tot_recv;
+        host_tot[1] = *n_cl;
+        host_tot[2] = *tot_items;
+    }
     if (c >= bound || c >= *n_cl) return;
     const int off = item_off[c];
     plan_items(c, clusters[c], cs, g, target, items + off,
@@ -998,10 +1007,12 @@ hipError_t launch_item_count(const Cluster *clusters, const int *n_clusters_dev,
 
 hipError_t launch_item_write(const Cluster *clusters, const int *n_clusters_dev, int bound,
                              const int *cs, const Geom &g, int target, int half,
-                             const int *item_off, Item *items, hipStream_t s) {
-    if (bound == 0) return hipSuccess;
+                             const int *item_off, Item *items, const int *tot_recv,
+                             const int *tot_items, int *host_tot, hipStream_t s) {
+    if (bound == 0 && !host_tot) return hipSuccess;
     hipLaunchKernelGGL(k_item_write, dim3(grid_for(bound, 128)), dim3(128), 0, s, clusters,
-                       n_clusters_dev, bound, cs, g, target, half, item_off, items);
+                       n_clusters_dev, bound, cs, g, target, half, item_off, items, tot_recv,
+                       tot_items, host_tot);
     return hipGetLastError();
 }
 
