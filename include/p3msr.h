@@ -319,8 +319,9 @@ int p3m_sr_tune_cache_check(const char *path, int *entries, int *lines);
  *                     on coordinates relative to the cluster's centre and the
  *                     reactions are added to the partners' FP64 sums;
  *                     cluster_size must be 16, 32 or 64 (0 keeps the
- *                     automatic choice); other calls take layout 1;
- *                     -1: automatic.
+ *                     automatic choice); other calls take screen 1 (or,
+ *                     with an autotuned screen 2, the layout the autotuner
+ *                     kept beside it); -1: automatic.
  * EINVAL outside those ranges.  Results do not depend on these settings
  * beyond FP64 summation order and, with screen 2, the FP32 rounding of the
  * separation (within the FP32 path's accuracy).
@@ -367,8 +368,9 @@ int p3m_sr_set_softening(p3m_sr_handle h, double eps);
  *   - a cluster whose stencil is split into several work items gets each
  *     item's sums in a slot of its own, added in item order after the pair
  *     launch, instead of FP64 atomics;
- *   - layout screen 2 runs as screen 1 (the kernel that evaluates each pair
- *     for both partners adds its reactions with atomics).
+ *   - layout screen 2 runs as screen 1, or as the layout the autotuner kept
+ *     beside an autotuned screen 2 (the kernel that evaluates each pair for
+ *     both partners adds its reactions with atomics).
  * The accepted pairs are the same in both modes and the forces differ only
  * by the rounding of the summation order.  The sort and the partial slots
  * cost time and workspace (24 B per particle, 24 B per item and receiver
