@@ -190,6 +190,10 @@ struct p3m_sr_context {
     // beside the item planning (forked from and joined to the call's stream)
     hipStream_t bstream = nullptr;
     hipEvent_t bfork = nullptr, bjoin = nullptr, bsort = nullptr, bsorted = nullptr;
+    // with every particle a receiver: the cluster and item planning runs on
+    // this stream beside the scatter and the fine order
+    hipStream_t pstream = nullptr;
+    hipEvent_t pfork = nullptr, pjoin = nullptr;
     p3m_lr_stats lr_stats{};
     bool lr_timed = false;
     hipStream_t lr_stream = nullptr;
@@ -683,6 +687,12 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     if (!wait_count && w.base && w.used + item_bound * sizeof(Item) + 256 > w.size)
         wait_count = true;
     if (!wait_count && (rc = take(h, w, w.items, sizeof(Item) * item_bound, s))) return rc;
+    // With every particle a receiver the clusters and items follow from the
+    // cell counts alone (a cluster is a run of consecutive sorted particles
+    // of one subtile, whatever their order inside it): their planning runs
+    // on its own stream beside the scatter and the fine order, and only the
+    // cluster boxes, which read the final order, wait for both.
+    const bool early_plan = all_recv && !det && !wait_count;
 
     int *key = (int *)w.key.p, *rank = (int *)w.rank.p, *cells = (int *)w.cells.p;
     double4 *sp = (double4 *)w.sp.p;
@@ -716,6 +726,32 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     unsigned long long *stall = &counters->scan_stall;
     P3M_HIP(launch_keys(r.pos, n, g, key, rank, cells, s));
     P3M_HIP(launch_scan1(cells, cells, ncells, s1, s1c, stall, bsum, s));
+    if (early_plan) {
+        P3M_HIP(hipEventRecord(h->pfork, s));
+        P3M_HIP(hipStreamWaitEvent(h->pstream, h->pfork, 0));
+        hipStream_t ps = h->pstream;
+        P3M_HIP(launch_cluster_count(cells, nullptr, n, n_sub, g, csize, ncl, ps));
+        P3M_HIP(launch_scan1(ncl, ncl, ncl_len, s1 + s1_cells + s1_flags, s1c + 2, stall, bsum, ps));
+        P3M_HIP(launch_cluster_write(cells, nullptr, ncl, n, n_sub, g, csize, clusters, ps));
+        P3M_HIP(launch_item_count(clusters, ncl + ncl_len, (int)cl_bound, cells, g, target,
+                                  mutual ? 1 : 0, itemcnt, ps));
+        P3M_HIP(launch_scan1(itemcnt, itemcnt, cl_bound, s1 + s1_cells + s1_flags + s1_ncl,
+                             s1c + 3, stall, bsum, ps));
+        P3M_HIP(launch_item_write(clusters, ncl + ncl_len, (int)cl_bound, cells, g, target,
+                                  mutual ? 1 : 0, itemcnt, (Item *)w.items.p, flags + nflags,
+                                  itemcnt + cl_bound, h->host_tot, ps));
+        if (shape != SHAPE_POLY)
+            P3M_HIP(launch_build_htab(shape, h->cfg_tab_n, g, (float *)w.htab.p, ps));
+        P3M_HIP(hipEventRecord(h->pjoin, ps));
+        // the output (the mutual kernel: its sorted-order sums) is cleared
+        // on the build stream before the dense subtiles' fine order; nothing
+        // before the pair kernel reads it
+        P3M_HIP(hipStreamWaitEvent(h->bstream, h->pfork, 0));
+        if (mutual)
+            P3M_HIP(launch_fill_f64((double *)w.msum.p, 0.0, 3 * (size_t)n, h->bstream));
+        else
+            P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, h->bstream));
+    }
     if (det) {
         // ranks in (fine sub-cell, index) order instead of the atomics' order
         unsigned long long *k64 = (unsigned long long *)w.det_k.p;
@@ -736,7 +772,7 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
         // a subtile no larger than one cluster gains nothing from the reorder;
         // the stable ranks are in fine order already.  The subtiles above
         // kFineBig particles are ordered on the build stream meanwhile (the
-        // box kernel, later on that stream, needs both orders).
+        // box kernel needs both orders).
         if (!det) {
             P3M_HIP(launch_big_list(cells, g, fbig, s));
             P3M_HIP(hipEventRecord(h->bsort, s));
@@ -747,12 +783,17 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
             h->sort_b = h->timing;
             // the receiver flags read the final selectors, the dense
             // subtiles' among them: with flags the call's stream waits here
-            if (!all_recv) P3M_HIP(hipEventRecord(h->bsorted, h->bstream));
+            // (and the cluster boxes read the final order)
+            if (!all_recv || early_plan) P3M_HIP(hipEventRecord(h->bsorted, h->bstream));
             // the output (the mutual kernel: its sorted-order sums) is cleared
-            // on the build stream meanwhile; nothing before the pair kernel
-            // reads it
-            if (mutual) P3M_HIP(launch_fill_f64((double *)w.msum.p, 0.0, 3 * (size_t)n, h->bstream));
-            else P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, h->bstream));
+            // on the build stream meanwhile (with the early planning: before
+            // the fine order there); nothing before the pair kernel reads it
+            if (!early_plan) {
+                if (mutual)
+                    P3M_HIP(launch_fill_f64((double *)w.msum.p, 0.0, 3 * (size_t)n, h->bstream));
+                else
+                    P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, h->bstream));
+            }
             P3M_HIP(launch_fine_order_medium(sp, perm, sel_s, cells, g, key, rank, sp_f, perm_f,
                                              sel_f, csize, s));
         }
@@ -767,66 +808,77 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     // the particles near any active one); activity enters through wa
     const int kind = r.backward ? SEL_ALL : r.sel_kind;
     const int *recv_scan = flags, *recv_pos = actpos;
-    if (all_recv) {
-        recv_scan = recv_pos = nullptr;
-    } else {
-        if (!det) P3M_HIP(hipStreamWaitEvent(s, h->bsorted, 0));
-        P3M_HIP(launch_flags(sel_s, n, n_sub, kind, r.thr, flags, s));
-        P3M_HIP(launch_scan1(flags, flags, nflags, s1 + s1_cells, s1c + 1, stall, bsum, s));
-        P3M_HIP(launch_compact(flags, n, n_sub, actpos, s));
-    }
-    P3M_HIP(launch_cluster_count(cells, recv_scan, n, n_sub, g, csize, ncl, s));
-    P3M_HIP(launch_scan1(ncl, ncl, ncl_len, s1 + s1_cells + s1_flags, s1c + 2, stall, bsum, s));
-    P3M_HIP(launch_cluster_write(cells, recv_scan, ncl, n, n_sub, g, csize, clusters, s));
-
-    // The cluster boxes, the receiver gather, the table (and in the
-    // deterministic mode the output clear)
-    // need neither each other's results nor the item planning: they run on
-    // the build stream beside it, joined before the pair kernel.  (The box
-    // kernel writes only the boxes of the cluster records, the item kernels
-    // read only the other fields.)
-    P3M_HIP(hipEventRecord(h->bfork, s));
-    P3M_HIP(hipStreamWaitEvent(h->bstream, h->bfork, 0));
-    hipStream_t bs = h->bstream;
     double4 *wa = r.backward ? (double4 *)w.wa.p : nullptr;
-    if (r.backward) P3M_HIP(launch_gather_weights(r.grad_acc, sel_s, perm, n, fp32, wa, bs));
-    // with every particle a receiver the receivers are sp / perm / wa as they are
-    double4 *rp = all_recv ? nullptr : (double4 *)w.rp.p;
-    P3M_HIP(launch_cluster_finish(clusters, ncl + ncl_len, cl_bound, csize, recv_pos, sp, perm, wa,
-                                  rp, (int *)w.rperm.p,
-                                  r.backward ? (double4 *)w.rwa.p : nullptr, bs));
-    // the output is cleared here in the deterministic mode (which has no
-    // mutual kernel), else on the build stream beside the fine order
-    if (det) P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, bs));
-    if (shape != SHAPE_POLY)
-        P3M_HIP(launch_build_htab(shape, h->cfg_tab_n, g, (float *)w.htab.p, bs));
-    P3M_HIP(hipEventRecord(h->bjoin, bs));
-
-    P3M_HIP(launch_item_count(clusters, ncl + ncl_len, (int)cl_bound, cells, g, target,
-                              mutual ? 1 : 0, itemcnt, s));
-    P3M_HIP(launch_scan1(itemcnt, itemcnt, cl_bound, s1 + s1_cells + s1_flags + s1_ncl, s1c + 3,
-                         stall, bsum, s));
-    // the three totals go to pinned memory for the stats: here when the call
-    // waits for the item count, else from the item writer
-    if (wait_count) {
-        P3M_HIP(launch_totals(flags + nflags, ncl + ncl_len, itemcnt + cl_bound, h->host_tot, s));
-        P3M_HIP(hipEventRecord(h->tot_ev, s));
-    }
     // receivers, clusters and items reach the stats when they are asked for
     st.receivers = st.clusters = st.items = -1;
-    if (wait_count) {
-        P3M_HIP(hipEventSynchronize(h->tot_ev));
-        const size_t n_items = (size_t)std::max(h->host_tot[2], 1);
-        if ((rc = take(h, w, w.items, sizeof(Item) * n_items, s))) return rc;
-        if (det && (rc = take(h, w, w.partials, sizeof(double) * 3 * (size_t)csize * n_items, s)))
-            return rc;
+    if (early_plan) {
+        // the clusters and items are planned on their own stream already;
+        // the boxes wait for both halves of the fine order and for the
+        // planning, which is then also done before the pair kernel
+        P3M_HIP(hipStreamWaitEvent(s, h->bsorted, 0));
+        P3M_HIP(hipStreamWaitEvent(s, h->pjoin, 0));
+        if (r.backward) P3M_HIP(launch_gather_weights(r.grad_acc, sel_s, perm, n, fp32, wa, s));
+        P3M_HIP(launch_cluster_finish(clusters, ncl + ncl_len, cl_bound, csize, nullptr, sp, perm,
+                                      wa, nullptr, nullptr, nullptr, s));
+    } else {
+        if (all_recv) {
+            recv_scan = recv_pos = nullptr;
+        } else {
+            if (!det) P3M_HIP(hipStreamWaitEvent(s, h->bsorted, 0));
+            P3M_HIP(launch_flags(sel_s, n, n_sub, kind, r.thr, flags, s));
+            P3M_HIP(launch_scan1(flags, flags, nflags, s1 + s1_cells, s1c + 1, stall, bsum, s));
+            P3M_HIP(launch_compact(flags, n, n_sub, actpos, s));
+        }
+        P3M_HIP(launch_cluster_count(cells, recv_scan, n, n_sub, g, csize, ncl, s));
+        P3M_HIP(launch_scan1(ncl, ncl, ncl_len, s1 + s1_cells + s1_flags, s1c + 2, stall, bsum, s));
+        P3M_HIP(launch_cluster_write(cells, recv_scan, ncl, n, n_sub, g, csize, clusters, s));
+
+        // The cluster boxes, the receiver gather, the table (and in the
+        // deterministic mode the output clear) need neither each other's
+        // results nor the item planning: they run on the build stream beside
+        // it, joined before the pair kernel.  (The box kernel writes only the
+        // boxes of the cluster records, the item kernels read only the other
+        // fields.)
+        P3M_HIP(hipEventRecord(h->bfork, s));
+        P3M_HIP(hipStreamWaitEvent(h->bstream, h->bfork, 0));
+        hipStream_t bs = h->bstream;
+        if (r.backward) P3M_HIP(launch_gather_weights(r.grad_acc, sel_s, perm, n, fp32, wa, bs));
+        // with every particle a receiver the receivers are sp / perm / wa as they are
+        double4 *rp = all_recv ? nullptr : (double4 *)w.rp.p;
+        P3M_HIP(launch_cluster_finish(clusters, ncl + ncl_len, cl_bound, csize, recv_pos, sp, perm,
+                                      wa, rp, (int *)w.rperm.p,
+                                      r.backward ? (double4 *)w.rwa.p : nullptr, bs));
+        // the output is cleared here in the deterministic mode (which has no
+        // mutual kernel), else on the build stream beside the fine order
+        if (det) P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, bs));
+        if (shape != SHAPE_POLY)
+            P3M_HIP(launch_build_htab(shape, h->cfg_tab_n, g, (float *)w.htab.p, bs));
+        P3M_HIP(hipEventRecord(h->bjoin, bs));
+
+        P3M_HIP(launch_item_count(clusters, ncl + ncl_len, (int)cl_bound, cells, g, target,
+                                  mutual ? 1 : 0, itemcnt, s));
+        P3M_HIP(launch_scan1(itemcnt, itemcnt, cl_bound, s1 + s1_cells + s1_flags + s1_ncl,
+                             s1c + 3, stall, bsum, s));
+        // the three totals go to pinned memory for the stats: here when the
+        // call waits for the item count, else from the item writer
+        if (wait_count) {
+            P3M_HIP(launch_totals(flags + nflags, ncl + ncl_len, itemcnt + cl_bound, h->host_tot,
+                                  s));
+            P3M_HIP(hipEventRecord(h->tot_ev, s));
+            P3M_HIP(hipEventSynchronize(h->tot_ev));
+            const size_t n_items = (size_t)std::max(h->host_tot[2], 1);
+            if ((rc = take(h, w, w.items, sizeof(Item) * n_items, s))) return rc;
+            if (det &&
+                (rc = take(h, w, w.partials, sizeof(double) * 3 * (size_t)csize * n_items, s)))
+                return rc;
+        }
+        // the totals for the stats (already there when the call waited for them)
+        P3M_HIP(launch_item_write(clusters, ncl + ncl_len, (int)cl_bound, cells, g, target,
+                                  mutual ? 1 : 0, itemcnt, (Item *)w.items.p, flags + nflags,
+                                  itemcnt + cl_bound, wait_count ? nullptr : h->host_tot, s));
+        P3M_HIP(hipStreamWaitEvent(s, h->bjoin, 0));
     }
     Item *items = (Item *)w.items.p;
-    // the totals for the stats (already there when the call waited for them)
-    P3M_HIP(launch_item_write(clusters, ncl + ncl_len, (int)cl_bound, cells, g, target,
-                              mutual ? 1 : 0, itemcnt, items, flags + nflags, itemcnt + cl_bound,
-                              wait_count ? nullptr : h->host_tot, s));
-    P3M_HIP(hipStreamWaitEvent(s, h->bjoin, 0));
 
     // ---- pairs ----
     PairArgs a{};
@@ -1021,7 +1073,10 @@ int p3m_sr_create(p3m_sr_handle *out, int device) {
             hipEventCreateWithFlags(&h->bsort, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&h->bsorted, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&h->bjoin, hipEventDisableTiming) == hipSuccess &&
-            hipStreamCreateWithFlags(&h->bstream, hipStreamNonBlocking) == hipSuccess;
+            hipStreamCreateWithFlags(&h->bstream, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&h->pfork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&h->pjoin, hipEventDisableTiming) == hipSuccess &&
+            hipStreamCreateWithFlags(&h->pstream, hipStreamNonBlocking) == hipSuccess;
     if (!ev_ok) {
         (void)hipGetLastError();
         p3m_sr_destroy(h);
@@ -1062,6 +1117,9 @@ int p3m_sr_destroy(p3m_sr_handle h) {
     if (h->bsorted) (void)hipEventDestroy(h->bsorted);
     if (h->bjoin) (void)hipEventDestroy(h->bjoin);
     if (h->bstream) (void)hipStreamDestroy(h->bstream);
+    if (h->pfork) (void)hipEventDestroy(h->pfork);
+    if (h->pjoin) (void)hipEventDestroy(h->pjoin);
+    if (h->pstream) (void)hipStreamDestroy(h->pstream);
     delete h;
     return P3M_OK;
 }

@@ -34,7 +34,8 @@ constexpr int kFineBins = kFineSide * kFineSide * kFineSide;
 constexpr int kFineMin = 8;                 // subtiles with at most this many keep their order
 constexpr int kFineBig = 1024;              // larger subtiles are ordered by a whole block
 constexpr int kFineWaves = 4;               // tiles (one per wave) per fine-order block
-constexpr int kFinishWaves = 4;             // clusters (one per wave) per finishing block
+constexpr int kFinishWaves = 4;             // waves per block of the cluster box kernel
+constexpr int kFinishLanes = 8;             // lanes per cluster in the box kernel
 constexpr int kListCap = 224;               // screened supplier records per wave (LDS)
 constexpr int kListCapF32 = 176;            // the same for the six-wave FP32 forward kernel
 constexpr int kListCapAdjoint = 128;        // the same for the adjoint (entries carry weights)

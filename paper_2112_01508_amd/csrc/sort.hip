@@ -743,40 +743,60 @@ __device__ inline double wave_max(double v) {
 // Receivers of each cluster gathered into contiguous arrays (rp / rperm /
 // rwa, skipped when rp == nullptr: the receivers are then the sorted
 // particles themselves, act_pos == nullptr) and the cluster's bounding box.
-// One lane group of csize lanes per cluster, 64 / csize clusters per wave,
-// kFinishWaves waves per block; lanes past a cluster's count repeat its
-// first receiver.  The cluster count is read on the device, so the launch
-// can be sized by an upper bound before the count reaches the host.
+// A group of kFinishLanes lanes per cluster, kWave / kFinishLanes clusters
+// per wave, kFinishWaves waves per block; each lane takes PPL = csize /
+// kFinishLanes receivers, loaded together (the kernel is bound by the
+// latency of the two dependent loads, the record and then the receivers, so
+// fewer and fuller waves finish sooner), and entries past a cluster's count
+// repeat its first receiver.  The cluster count is read on the device, so
+// the launch can be sized by an upper bound before the count reaches the
+// host.
+template <int PPL>
 __global__ __launch_bounds__(kFinishWaves * kWave) void k_cluster_finish(
-    Cluster *__restrict__ clusters, const int *__restrict__ n_clusters_dev, int csize,
+    Cluster *__restrict__ clusters, const int *__restrict__ n_clusters_dev,
     const int *__restrict__ act_pos, const double4 *__restrict__ sp, const int *__restrict__ perm,
     const double4 *__restrict__ wa, double4 *__restrict__ rp, int *__restrict__ rperm,
     double4 *__restrict__ rwa) {
+    constexpr int per_wave = kWave / kFinishLanes;
     const int n_clusters = *n_clusters_dev;
-    const int per_wave = kWave / csize;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = blockIdx.x * kFinishWaves + (int)(threadIdx.x / kWave);
     if (wave * per_wave >= n_clusters) return;   // whole waves leave together
-    const int c = wave * per_wave + lane / csize;
-    const int li = lane & (csize - 1);
+    const int c = wave * per_wave + lane / kFinishLanes;
+    const int li = lane & (kFinishLanes - 1);
     const bool have = c < n_clusters;
-    Cluster cl{};
-    double4 x = make_double4(0.0, 0.0, 0.0, 0.0);
+    double lx = 0.0, ly = 0.0, lz = 0.0, hx = 0.0, hy = 0.0, hz = 0.0;
     if (have) {
-        cl = clusters[c];
-        const bool live = li < cl.count;
-        const int a = cl.begin + (live ? li : 0);
-        const int p = act_pos ? act_pos[a] : a;
-        x = sp[p];
-        if (live && rp) {
-            rp[a] = x;
-            rperm[a] = perm[p];
-            if (rwa) rwa[a] = wa[p];
+        const int begin = clusters[c].begin, count = clusters[c].count;
+        double4 x[PPL];
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            const int q = li + kFinishLanes * k;
+            const int a = begin + (q < count ? q : 0);
+            const int p = act_pos ? act_pos[a] : a;
+            x[k] = sp[p];
+            if (q < count && rp) {
+                rp[a] = x[k];
+                rperm[a] = perm[p];
+                if (rwa) rwa[a] = wa[p];
+            }
+        }
+        lx = hx = x[0].x;
+        ly = hy = x[0].y;
+        lz = hz = x[0].z;
+#pragma unroll
+        for (int k = 1; k < PPL; ++k) {
+            lx = fmin(lx, x[k].x);
+            ly = fmin(ly, x[k].y);
+            lz = fmin(lz, x[k].z);
+            hx = fmax(hx, x[k].x);
+            hy = fmax(hy, x[k].y);
+            hz = fmax(hz, x[k].z);
         }
     }
-    // min / max over each aligned group of csize lanes
-    double lx = x.x, ly = x.y, lz = x.z, hx = x.x, hy = x.y, hz = x.z;
-    for (int off = csize >> 1; off > 0; off >>= 1) {
+    // min / max over each aligned group of kFinishLanes lanes
+#pragma unroll
+    for (int off = kFinishLanes >> 1; off > 0; off >>= 1) {
         lx = fmin(lx, __shfl_xor(lx, off, kWave));
         ly = fmin(ly, __shfl_xor(ly, off, kWave));
         lz = fmin(lz, __shfl_xor(lz, off, kWave));
@@ -814,10 +834,14 @@ hipError_t launch_cluster_finish(Cluster *clusters, const int *n_clusters_dev, s
                                  const int *perm, const double4 *wa, double4 *rp, int *rperm,
                                  double4 *rwa, hipStream_t s) {
     if (bound == 0) return hipSuccess;
-    const size_t per_block = (size_t)kFinishWaves * (kWave / csize);
-    hipLaunchKernelGGL(k_cluster_finish, dim3(grid_for(bound, (int)per_block)),
-                       dim3(kFinishWaves * kWave), 0, s, clusters, n_clusters_dev, csize, act_pos,
-                       sp, perm, wa, rp, rperm, rwa);
+    const size_t per_block = (size_t)kFinishWaves * (kWave / kFinishLanes);
+    if (csize != 8 && csize != 16 && csize != 32 && csize != 64) return hipErrorInvalidValue;
+    auto fn = csize == 8    ? k_cluster_finish<1>
+              : csize == 16 ? k_cluster_finish<2>
+              : csize == 32 ? k_cluster_finish<4>
+                            : k_cluster_finish<8>;
+    hipLaunchKernelGGL(fn, dim3(grid_for(bound, (int)per_block)), dim3(kFinishWaves * kWave), 0,
+                       s, clusters, n_clusters_dev, act_pos, sp, perm, wa, rp, rperm, rwa);
     return hipGetLastError();
 }
 
