@@ -747,6 +747,8 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
         // on the build stream before the dense subtiles' fine order; nothing
         // before the pair kernel reads it
         P3M_HIP(hipStreamWaitEvent(h->bstream, h->pfork, 0));
+        // the dense subtiles' list needs only the cell counts as well
+        P3M_HIP(launch_big_list(cells, g, fbig, h->bstream));
         if (mutual)
             P3M_HIP(launch_fill_f64((double *)w.msum.p, 0.0, 3 * (size_t)n, h->bstream));
         else
@@ -774,7 +776,7 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
         // kFineBig particles are ordered on the build stream meanwhile (the
         // box kernel needs both orders).
         if (!det) {
-            P3M_HIP(launch_big_list(cells, g, fbig, s));
+            if (!early_plan) P3M_HIP(launch_big_list(cells, g, fbig, s));
             P3M_HIP(hipEventRecord(h->bsort, s));
             P3M_HIP(hipStreamWaitEvent(h->bstream, h->bsort, 0));
             P3M_HIP(launch_fine_order_big(sp, perm, sel_s, cells, g, key, rank, sp_f, perm_f,
