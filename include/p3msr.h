@@ -26,7 +26,10 @@
  *   - mass is n FP64 values holding G*m_j; NULL means all ones.
  *   - Every call is asynchronous on `stream` (a hipStream_t passed as
  *     void*, NULL = the null stream); pointers must stay valid until the
- *     stream's work has completed.  The force calls do not wait for the
+ *     stream's work has completed.  Parts of a call's build phase run on
+ *     streams of the handle (default priority) that wait for `stream` and
+ *     that `stream` waits for before the pair kernel, so a call's work is
+ *     done when `stream`'s is.  The force calls do not wait for the
  *     GPU: the work-item array is sized by a bound on the item count, and
  *     the pair kernels read the count on the device.  Two cases wait for
  *     the count instead (one small device-to-host read): the deterministic
