@@ -743,16 +743,9 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
         if (shape != SHAPE_POLY)
             P3M_HIP(launch_build_htab(shape, h->cfg_tab_n, g, (float *)w.htab.p, ps));
         P3M_HIP(hipEventRecord(h->pjoin, ps));
-        // the output (the mutual kernel: its sorted-order sums) is cleared
-        // on the build stream before the dense subtiles' fine order; nothing
-        // before the pair kernel reads it
-        P3M_HIP(hipStreamWaitEvent(h->bstream, h->pfork, 0));
         // the dense subtiles' list needs only the cell counts as well
+        P3M_HIP(hipStreamWaitEvent(h->bstream, h->pfork, 0));
         P3M_HIP(launch_big_list(cells, g, fbig, h->bstream));
-        if (mutual)
-            P3M_HIP(launch_fill_f64((double *)w.msum.p, 0.0, 3 * (size_t)n, h->bstream));
-        else
-            P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, h->bstream));
     }
     if (det) {
         // ranks in (fine sub-cell, index) order instead of the atomics' order
@@ -785,17 +778,15 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
             h->sort_b = h->timing;
             // the receiver flags read the final selectors, the dense
             // subtiles' among them: with flags the call's stream waits here
-            // (and the cluster boxes read the final order)
-            if (!all_recv || early_plan) P3M_HIP(hipEventRecord(h->bsorted, h->bstream));
+            if (!all_recv) P3M_HIP(hipEventRecord(h->bsorted, h->bstream));
             // the output (the mutual kernel: its sorted-order sums) is cleared
-            // on the build stream meanwhile (with the early planning: before
-            // the fine order there); nothing before the pair kernel reads it
-            if (!early_plan) {
-                if (mutual)
-                    P3M_HIP(launch_fill_f64((double *)w.msum.p, 0.0, 3 * (size_t)n, h->bstream));
-                else
-                    P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, h->bstream));
-            }
+            // on the build stream meanwhile; nothing before the pair kernel
+            // reads it
+            if (mutual) P3M_HIP(launch_fill_f64((double *)w.msum.p, 0.0, 3 * (size_t)n, h->bstream));
+            else P3M_HIP(launch_fill_f64(r.out, 0.0, out_elems, h->bstream));
+            // with the early planning the cluster boxes wait here: they read
+            // the final order (and the pair kernel the cleared output)
+            if (early_plan) P3M_HIP(hipEventRecord(h->bsorted, h->bstream));
             P3M_HIP(launch_fine_order_medium(sp, perm, sel_s, cells, g, key, rank, sp_f, perm_f,
                                              sel_f, csize, s));
         }
