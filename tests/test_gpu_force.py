@@ -217,6 +217,25 @@ def test_edge_cases(env):
     assert ei.value.code == -1
 
 
+@pytest.mark.parametrize("csize,screen", [(8, 1), (16, 0), (32, 2), (64, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tiny_all_active_sets(env, prec, csize, screen):
+    """All-active calls on 1 to 40 particles packed into a few cells (one
+    cluster, clusters shorter than a wave's lane group, a single occupied
+    subtile): exact pair counts, and rows without a partner exactly 0."""
+    x_s, r_cut = 0.01, 0.045
+    for n in (1, 2, 5, 40):
+        print("tiny all-active n=%d" % n, prec, csize, screen, flush=True)
+        rng = np.random.default_rng(100 + n)
+        pos = np.mod(0.3 + rng.random((n, 3)) * 0.05, 1.0)
+        mass = rng.uniform(0.5, 2.0, n)
+        ref, cnt, absum = oracle.force_full(pos, mass, 1.0, x_s, r_cut, method="brute")
+        acc, st = run_force(env, pos, mass, None, 1.0, x_s, r_cut, prec, cluster_size=csize,
+                            screen=screen)
+        check(acc, st, ref, cnt, absum, prec)
+        assert np.all(acc[absum == 0] == 0)
+
+
 @pytest.mark.parametrize("csize,screen", [(32, 1), (8, 1), (64, 0)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_lattice_pairs_on_the_cutoff(env, prec, csize, screen):
