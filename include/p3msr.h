@@ -106,7 +106,8 @@ typedef struct {
     int32_t shape;           /* p3m_shape of the FP32 forward kernel shape used */
     int64_t screened;        /* supplier records tested by the screen (0 without it) */
     double eps_b;            /* B-spline softening length of the call (0: none) */
-    int64_t fp64_steps;      /* screen 2: wavefront steps that redid a pair in FP64 */
+    int64_t fp64_steps;      /* screen 2: wavefront steps that redid a pair in the plain
+                                FP64 form (x_i - x_j) - n' box */
     float ms_sort;           /* the counting sort into tile -> subtile -> fine order (keys,
                                 scan, scatter, fine order), when timing is on, else -1 */
     int32_t deterministic;   /* 1: the call ran in the deterministic mode (p3m_sr_set_deterministic) */
@@ -224,7 +225,8 @@ int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
  * section 2.1.3 "Subtiles": try a finer subdivision, time it, keep it if
  * faster).  Times p3m_sr_force on these inputs for candidate subtile counts
  * per dimension crossed with cluster layouts (cluster size, screening, and
- * for all-active FP32 forward calls the mutual layout screen = 2) and,
+ * for all-active forward calls and unsoftened FP32 adjoints the mutual
+ * layout screen = 2) and,
  * at level >= 2, work-item sizes around the winner; stores the fastest in the
  * handle (a candidate replaces an earlier one only when more than 3 % faster,
  * so near-ties do not flip with timing noise); later calls on the same
@@ -250,7 +252,8 @@ int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
  * fastest of them is kept (and cached, as kind 3 for the forward, 4 for
  * the adjoint) beside it: calls with this key that cannot take screen 2
  * (with an active mask, with a tabulated shape, in the deterministic mode,
- * or softened adjoints) run in that layout.
+ * softened adjoints, FP64 adjoints and softened FP64 calls) run in that
+ * layout.
  */
 #define P3M_TUNE_ADJOINT 4
 #define P3M_TUNE_FORCE 8
@@ -312,22 +315,26 @@ int p3m_sr_tune_cache_check(const char *path, int *entries, int *lines);
  *                     loop (the subtile-pair culling of section 2.1.3
  *                     carried down to single suppliers); 0: no screening;
  *                     2: screened, and for all-active P3M_FP32 forward calls
- *                     (polynomial shape, softened or not) and P3M_FP32
- *                     backward calls without softening (n <= 2^27 for
- *                     both) each pair is evaluated once for
+ *                     (polynomial shape, softened or not), P3M_FP32
+ *                     backward calls without softening and all-active
+ *                     P3M_FP64 forward calls without softening (n <= 2^27
+ *                     for all) each pair is evaluated once for
  *                     both partners (Newton's third law, as the paper's tile
  *                     pairing in section 2.1.3, "Tiles"; the adjoint's pair
  *                     term is antisymmetric too): clusters visit the upper
- *                     half of their tile stencil, the pair arithmetic is FP32
- *                     on coordinates relative to the cluster's centre and the
+ *                     half of their tile stencil, the pair arithmetic is on
+ *                     coordinates relative to the cluster's centre (FP32, or
+ *                     FP64 for P3M_FP64 calls, where pairs within a relative
+ *                     2^-40 of r_cut^2 or much closer than the receiver's
+ *                     offset are redone in the plain form) and the
  *                     reactions are added to the partners' FP64 sums;
  *                     cluster_size must be 16, 32 or 64 (0 keeps the
  *                     automatic choice); other calls take screen 1 (or,
  *                     with an autotuned screen 2, the layout the autotuner
  *                     kept beside it); -1: automatic.
  * EINVAL outside those ranges.  Results do not depend on these settings
- * beyond FP64 summation order and, with screen 2, the FP32 rounding of the
- * separation (within the FP32 path's accuracy).
+ * beyond FP64 summation order and, with screen 2, the rounding of the
+ * separation (within the path's accuracy).
  */
 int p3m_sr_set_config(p3m_sr_handle h, int subtiles_per_dim, int item_target,
                       int cluster_size, int screen);

@@ -148,7 +148,7 @@ struct p3m_sr_context {
     // resident pair-kernel blocks per CU, per variant: mode, screen, cluster size,
     // shape, unit mass, softening
     int blocks_per_cu[4 * 2 * 4 * 3 * 4] = {};
-    int mutual_blocks_per_cu[4 * 2 * 2 * 2] = {};   // by cluster size, adjoint, unit mass, softening
+    int mutual_blocks_per_cu[4 * 2 * 2 * 2 * 2] = {};   // by cluster size, adjoint, unit mass, softening, FP64
     // short-range workspace: grown with hipMalloc as calls need it, or (the
     // no-alloc entry point) carved from the library's fixed device array
     SrWork work, fixed;
@@ -555,15 +555,17 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     const bool all_recv = n_sub == 1 && (r.backward || r.sel_kind == SEL_ALL);
     // tabulated FP32 shape (point particles, forward only)
     const int shape = (fp32 && !r.backward && eps_b == 0.0) ? h->cfg_shape : SHAPE_POLY;
-    // each pair once for both partners: FP32 calls with every particle a
-    // receiver (all-active forward calls with the polynomial shape, softened
-    // or not, and the adjoint without softening), fewer than 2^27 particles
+    // each pair once for both partners: calls with every particle a receiver
+    // (FP32: all-active forward calls with the polynomial shape, softened or
+    // not, and the adjoint without softening; FP64: all-active forward calls
+    // without softening), fewer than 2^27 particles
     // (the list entries hold the sorted index in 27 bits), not in the
     // deterministic mode (its reactions are added with atomics), and
     // clusters of 16, 32 or 64
     const bool det = h->deterministic;
-    const bool mutual_ok = fp32 && all_recv && shape == SHAPE_POLY &&
-                           (eps_b == 0.0 || !r.backward) && r.n <= (int64_t)(1u << 27) && !det;
+    const bool mutual_ok = all_recv && shape == SHAPE_POLY &&
+                           (fp32 ? (eps_b == 0.0 || !r.backward) : (eps_b == 0.0 && !r.backward)) &&
+                           r.n <= (int64_t)(1u << 27) && !det;
 
     // decomposition: explicit override > user config > autotuned > default
     int ns = 0, target = 0, csize = 0, screen = -1;
@@ -903,8 +905,9 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     int bpc;
     if (mutual) {
         int &slot_m =
-            h->mutual_blocks_per_cu[((cs_idx * 2 + (r.backward ? 1 : 0)) * 2 + unit) * 2 + soft];
-        if (slot_m == 0) slot_m = mutual_blocks_per_cu(csize, unit, r.backward, soft != 0);
+            h->mutual_blocks_per_cu[(((cs_idx * 2 + (r.backward ? 1 : 0)) * 2 + unit) * 2 + soft) * 2 +
+                                    (fp32 ? 0 : 1)];
+        if (slot_m == 0) slot_m = mutual_blocks_per_cu(csize, unit, r.backward, soft != 0, !fp32);
         bpc = slot_m;
         a.out = (double *)w.msum.p;
         a.out_stride = n;
@@ -922,7 +925,7 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     long long grid = (long long)h->n_cu * bpc;
     if (grid < 1) grid = 1;
     if (h->timing) P3M_HIP(hipEventRecord(h->ev[1], s));
-    if (mutual) P3M_HIP(launch_pairs_mutual(a, r.backward, (int)grid, s));
+    if (mutual) P3M_HIP(launch_pairs_mutual(a, r.backward, !fp32, (int)grid, s));
     else P3M_HIP(launch_pairs(mode, screen, shape, a, (int)grid, s));
     if (mutual) P3M_HIP(launch_mutual_out((const double *)w.msum.p, perm, n, r.out, s));
     if (det)
@@ -1498,9 +1501,12 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     // level 2 also sweeps the item size around the level-1 winner
     std::vector<std::pair<int, int>> layouts = {{64, 0}, {64, 1}, {32, 1}, {16, 1}, {8, 1},
                                                 {16, 0}, {8, 0}};
-    // all-active FP32 forward calls (softened or not) and FP32 adjoints
-    // without softening can evaluate each pair once for both partners
-    if (precision == P3M_FP32 && (adjoint ? h->eps == 0.0 : !active && h->cfg_shape == SHAPE_POLY))
+    // all-active FP32 forward calls (softened or not), FP32 adjoints without
+    // softening and all-active FP64 forward calls without softening can
+    // evaluate each pair once for both partners
+    const bool fp32_t = precision == P3M_FP32;
+    if (adjoint ? (fp32_t && h->eps == 0.0)
+                : (!active && (fp32_t ? h->cfg_shape == SHAPE_POLY : h->eps == 0.0)))
         for (int c : {32, 64, 16}) layouts.push_back({c, kScreenMutual});
     const TuneKey key{n, nt, precision, adjoint ? TUNE_ADJOINT : TUNE_FORWARD, 1};
     rc = tune(h, r, key, level, {1, 2, 3, 4}, layouts, {1024, 4096},

@@ -972,6 +972,14 @@ void k_pairs(PairArgs a) {
 // The mutual kernels' call kinds: the forward force, the adjoint, the
 // forward force with B-spline softening.
 constexpr int kMutFwd = 0, kMutBwd = 1, kMutSoft = 2;
+// The FP64 forward force: FP64 offsets, separations, shape and sums.
+constexpr int kMutF64 = 3;
+
+template <bool B, class T, class F> struct MutPick { using type = T; };
+template <class T, class F> struct MutPick<false, T, F> { using type = F; };
+// A list entry in the ring (offset from the cluster centre and mu): FP32,
+// or FP64 for kMutF64.
+template <int KIND> using MutEntry = typename MutPick<KIND == kMutF64, double4, float4>::type;
 
 constexpr int kRing = 128;                    // list entries per wave (a ring)
 constexpr unsigned kIdxBits = 27;             // sorted index bits of a list entry
@@ -994,6 +1002,19 @@ __device__ __forceinline__ int rot16i(int v) {
     if constexpr (S == 0) return v;
     else return __builtin_amdgcn_mov_dpp(v, 0x120 + S, 0xf, 0xf, true);
 }
+// An FP64 value: two DPP moves (a rotation does not fold into FP64
+// instructions).
+template <int S>
+__device__ __forceinline__ double rot16(double v) {
+    if constexpr (S == 0) {
+        return v;
+    } else {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = (unsigned)rot16i<S>((int)(unsigned)b);
+        const unsigned hi = (unsigned)rot16i<S>((int)(unsigned)(b >> 32));
+        return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+    }
+}
 
 // v where this lane's bit of the wave mask is set, else 0: one v_cndmask
 // with the mask as its selector.
@@ -1001,6 +1022,15 @@ __device__ __forceinline__ float keep_lanes(unsigned long long mask, float v) {
     float r;
     asm("v_cndmask_b32 %0, 0, %1, %2" : "=v"(r) : "v"(v), "s"(mask));
     return r;
+}
+
+// v where this lane's bit of the wave mask is set, else 0 (FP64: both halves).
+__device__ __forceinline__ double keep_lanes(unsigned long long mask, double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    unsigned lo, hi;
+    asm("v_cndmask_b32 %0, 0, %1, %2" : "=v"(lo) : "v"((unsigned)b), "s"(mask));
+    asm("v_cndmask_b32 %0, 0, %1, %2" : "=v"(hi) : "v"((unsigned)(b >> 32)), "s"(mask));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
 // This lane's receiver and its sums.
@@ -1179,10 +1209,122 @@ __device__ __forceinline__ void mutual_steps(MutualLane &m, const float4 &e, con
     }
 }
 
+// The FP64 kind: this lane's receiver, its sums (FP64 throughout) and the
+// cut-off band (wave-uniform).
+struct MutualLane64 {
+    double hx, hy, hz;    // offset from the cluster centre (far away for idle lanes)
+    double ki;            // r^2 below which the separation is recomputed as the plain form
+    double mu;            // mu_i
+    double rlo, rhi;      // r_cut^2 (1 -+ 2^-40)
+    int i_sorted;
+    double ax = 0.0, ay = 0.0, az = 0.0;   // the receiver's sums
+    double jx = 0.0, jy = 0.0, jz = 0.0;   // reaction on this lane's entry
+};
+
+// mutual_fp64_sep without the rounding to FP32.
+__device__ __attribute__((noinline)) double4 mutual_sep_plain(const double4 *__restrict__ sp,
+                                                              int i_sorted, int jr, double box,
+                                                              double rc2) {
+    const int j = (int)((unsigned)jr & kIdxMask);
+    const int img = (int)((unsigned)jr >> kIdxBits);
+    const double4 pi = sp[i_sorted];
+    const double4 pj = sp[j];
+    double ddx = pi.x - pj.x, ddy = pi.y - pj.y, ddz = pi.z - pj.z;
+    if (img != 13) {
+        ddx -= (double)(img / 9 - 1) * box;
+        ddy -= (double)((img / 3) % 3 - 1) * box;
+        ddz -= (double)(img % 3 - 1) * box;
+    }
+    const double r2d = dist2(ddx, ddy, ddz);
+    const bool ok = (r2d < rc2) & (r2d > 0.0);
+    return make_double4(ddx, ddy, ddz, ok ? r2d : -1.0);
+}
+
+// One FP64 step: this lane's receiver against the entry S places along its
+// row.  The separation of two offsets from the cluster centre can differ
+// from the plain form (x_i - x_j) - n' box in its last bits, so pairs within
+// a relative 2^-40 of r_cut^2 and pairs closer than a tenth of the
+// receiver's offset are redone in the plain form: the accepted pairs are the
+// plain form's.
+template <int S, bool UNIT, bool SELF>
+__device__ __forceinline__ void mutual_step64(MutualLane64 &m, const double4 &e, int jid,
+                                              const PairArgs &a, unsigned &cnt,
+                                              unsigned &rare_n) {
+    __builtin_amdgcn_sched_barrier(0);
+    double dx = m.hx - rot16<S>(e.x);
+    double dy = m.hy - rot16<S>(e.y);
+    double dz = m.hz - rot16<S>(e.z);
+    double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const unsigned long long m_lo = ballot64(r2 < m.rlo);
+    const unsigned long long m_far = ballot64(r2 >= m.ki);
+    const unsigned long long m_hi = ballot64(r2 < m.rhi);
+    unsigned long long acc_m = m_lo & m_far;
+    const unsigned long long rare = (m_hi & ~m_lo) | ~m_far;
+    if (rare) {
+        const int jr = rot16i<S>(jid);   // all lanes active here
+        ++rare_n;
+        bool ok = false;
+        if ((rare >> (threadIdx.x & (kWave - 1))) & 1ull) {
+            const double4 q = mutual_sep_plain(a.sp, m.i_sorted, jr, a.g.box, a.g.rc2);
+            ok = q.w > 0.0;
+            dx = q.x;
+            dy = q.y;
+            dz = q.z;
+            r2 = ok ? q.w : 1.0;
+        }
+        acc_m = (acc_m & ~rare) | (ballot64(ok) & rare);
+    }
+    cnt += (unsigned)__builtin_popcountll(acc_m);
+    const double ri = rsqrt_pos(r2);
+    const double h = h64(fma(r2, a.g.c2, -P3M_H64_T0), a.g.h64);
+    const double ri3 = ri * ri * ri;
+    // lanes without a pair send no reaction
+    const double sh = keep_lanes(acc_m, fma(a.g.c3, h, ri3));
+    double shj = sh, shi = sh;
+    if constexpr (!UNIT) {
+        shj = sh * rot16<S>(e.w);
+        shi = sh * m.mu;
+    }
+    const double fx = shi * dx, fy = shi * dy, fz = shi * dz;
+    m.ax = fma(-shj, dx, m.ax);
+    m.ay = fma(-shj, dy, m.ay);
+    m.az = fma(-shj, dz, m.az);
+    if constexpr (!SELF) {
+        m.jx += rot16<(16 - S) & 15>(fx);
+        m.jy += rot16<(16 - S) & 15>(fy);
+        m.jz += rot16<(16 - S) & 15>(fz);
+    }
+    asm volatile("" ::"v"(m.ax), "v"(m.ay), "v"(m.az), "v"(m.jx), "v"(m.jy), "v"(m.jz));
+}
+
+template <bool UNIT, bool SELF, int NS>
+__device__ __forceinline__ void mutual_steps64(MutualLane64 &m, const double4 &e, int jid,
+                                               const PairArgs &a, unsigned &cnt,
+                                               unsigned &rare_n) {
+    mutual_step64<0, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+    mutual_step64<1, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+    mutual_step64<2, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+    mutual_step64<3, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+    if constexpr (NS > 4) {
+        mutual_step64<4, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step64<5, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step64<6, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step64<7, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step64<8, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step64<9, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step64<10, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step64<11, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step64<12, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step64<13, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step64<14, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step64<15, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+    }
+}
+
 // Sums over the lanes of the R rows that hold the same block entries
 // (rows r and r ^ 1, r ^ 2 for R = 2, 4).
-template <int R>
-__device__ __forceinline__ float rows_sum(float v) {
+template <int R, class T>
+__device__ __forceinline__ T rows_sum(T v) {
     if constexpr (R >= 2) v += __shfl_xor(v, 16, kWave);
     if constexpr (R >= 4) v += __shfl_xor(v, 32, kWave);
     return v;
@@ -1191,10 +1333,12 @@ __device__ __forceinline__ float rows_sum(float v) {
 template <int R, bool UNIT, int KIND>
 struct MutualVisit {
     static constexpr bool BWD = KIND == kMutBwd;
+    static constexpr bool F64 = KIND == kMutF64;
+    using Lane = typename MutPick<F64, MutualLane64, MutualLane>::type;
     static constexpr int EB = 64 / R;   // list entries per block of 16 steps
     const PairArgs &a;
-    MutualLane &m;
-    float4 *lpos;        // ring: offset from the cluster centre, mu
+    Lane &m;
+    MutEntry<KIND> *lpos;   // ring: offset from the cluster centre, mu
     int *lidx;           // ring: sorted index | image << kIdxBits
     float4 *lw;          // ring (adjoint): the entry's weight w_j [j active]
     const double *lo, *hi;
@@ -1208,11 +1352,18 @@ struct MutualVisit {
     double shx = 0.0, shy = 0.0, shz = 0.0;
     int fill = 0, jj = 0, head = 0, n_list = 0;
 
+    // FP32 block sums into the FP64 ones (the FP64 kind sums in FP64 throughout)
     __device__ __forceinline__ void flush_i() {
-        ax += (double)m.axf;
-        ay += (double)m.ayf;
-        az += (double)m.azf;
-        m.axf = m.ayf = m.azf = 0.f;
+        if constexpr (!F64) {
+            ax += (double)m.axf;
+            ay += (double)m.ayf;
+            az += (double)m.azf;
+            m.axf = m.ayf = m.azf = 0.f;
+        }
+    }
+    __device__ __forceinline__ static MutEntry<KIND> far_entry() {
+        if constexpr (F64) return make_double4(-1.0e30, -1.0e30, -1.0e30, 0.0);
+        else return make_float4(-1.0e30f, -1.0e30f, -1.0e30f, 0.f);
     }
 
     // One block of nv (<= EB) list entries from the ring head.
@@ -1220,7 +1371,7 @@ struct MutualVisit {
         wave_lds_sync();
         const int row = lane >> 4;
         const int k = (row / R) * 16 + (lane & 15);
-        float4 e = make_float4(-1.0e30f, -1.0e30f, -1.0e30f, 0.f);
+        MutEntry<KIND> e = far_entry();
         float4 ew = make_float4(0.f, 0.f, 0.f, 0.f);
         int jid = -1;
         if (k < nv) {
@@ -1232,9 +1383,10 @@ struct MutualVisit {
         wave_lds_sync();   // the reads are done before later screens overwrite the ring
         m.jx = m.jy = m.jz = 0.f;
         unsigned cnt = 0, rn = 0;
-        mutual_steps<UNIT, false, 16, KIND>(m, e, ew, jid, a, cnt, rn);
+        if constexpr (F64) mutual_steps64<UNIT, false, 16>(m, e, jid, a, cnt, rn);
+        else mutual_steps<UNIT, false, 16, KIND>(m, e, ew, jid, a, cnt, rn);
         flush_i();
-        const float jx = rows_sum<R>(m.jx), jy = rows_sum<R>(m.jy), jz = rows_sum<R>(m.jz);
+        const auto jx = rows_sum<R>(m.jx), jy = rows_sum<R>(m.jy), jz = rows_sum<R>(m.jz);
         if (row % R == 0 && k < nv) {
             const int j = (int)((unsigned)jid & kIdxMask);
             atomicAdd(a.out + j, (double)jx);
@@ -1259,18 +1411,22 @@ struct MutualVisit {
             if constexpr (R == 1) idx = (l + 4 * row) & 15;
             else if constexpr (R == 2) idx = 16 * (row >> 1) + l;
             else idx = 16 * ((row + p) & 3) + l;
-            float4 e = make_float4(-1.0e30f, -1.0e30f, -1.0e30f, 0.f);
+            MutEntry<KIND> e = far_entry();
             float4 ew = make_float4(0.f, 0.f, 0.f, 0.f);
             int jid = -1;
             if (idx < cnt) {
                 const double4 q = a.sp[begin + idx];
-                e = make_float4((float)(q.x - cx), (float)(q.y - cy), (float)(q.z - cz),
-                                UNIT ? 0.f : mu_f32(q.w));
+                if constexpr (F64)
+                    e = make_double4(q.x - cx, q.y - cy, q.z - cz, UNIT ? 0.0 : q.w);
+                else
+                    e = make_float4((float)(q.x - cx), (float)(q.y - cy), (float)(q.z - cz),
+                                    UNIT ? 0.f : mu_f32(q.w));
                 jid = (begin + idx) | (13 << kIdxBits);
                 if constexpr (BWD) ew = reinterpret_cast<const float4 *>(a.wa)[begin + idx];
             }
             unsigned c = 0, rn = 0;
-            mutual_steps<UNIT, true, R == 1 ? 4 : 16, KIND>(m, e, ew, jid, a, c, rn);
+            if constexpr (F64) mutual_steps64<UNIT, true, R == 1 ? 4 : 16>(m, e, jid, a, c, rn);
+            else mutual_steps<UNIT, true, R == 1 ? 4 : 16, KIND>(m, e, ew, jid, a, c, rn);
             flush_i();
             pairs += c;
             steps += R == 1 ? 4 : 16;
@@ -1293,8 +1449,11 @@ struct MutualVisit {
                                                   __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
         if (keep) {
             const int q = (head + n_list + off) & (kRing - 1);
-            lpos[q] = make_float4((float)(px - cx), (float)(py - cy), (float)(pz - cz),
-                                  UNIT ? 0.f : mu_f32(p.w));
+            if constexpr (F64)
+                lpos[q] = make_double4(px - cx, py - cy, pz - cz, UNIT ? 0.0 : p.w);
+            else
+                lpos[q] = make_float4((float)(px - cx), (float)(py - cy), (float)(pz - cz),
+                                      UNIT ? 0.f : mu_f32(p.w));
             lidx[q] = (jj + lane) | (code << kIdxBits);
             if constexpr (BWD) lw[q] = reinterpret_cast<const float4 *>(a.wa)[jj + lane];
         }
@@ -1359,27 +1518,42 @@ struct MutualTally {
 template <int R, bool UNIT, int KIND>
 __device__ __forceinline__ void mutual_item(const PairArgs &a, const Item &item,
                                             const Cluster &cl, int cnt, int begin, int lane,
-                                            float4 *ring_pos, int *ring_idx, float4 *ring_w,
-                                            MutualTally &tally) {
+                                            MutEntry<KIND> *ring_pos, int *ring_idx,
+                                            float4 *ring_w, MutualTally &tally) {
     constexpr bool BWD = KIND == kMutBwd;
+    constexpr bool F64 = KIND == kMutF64;
     const int row = lane >> 4, l = lane & 15;
     const double cx = 0.5 * (cl.lo[0] + cl.hi[0]);
     const double cy = 0.5 * (cl.lo[1] + cl.hi[1]);
     const double cz = 0.5 * (cl.lo[2] + cl.hi[2]);
-    MutualLane m;
+    typename MutualVisit<R, UNIT, KIND>::Lane m;
     const int idx = 16 * (row % R) + l;
     const bool live = idx < cnt;
     m.i_sorted = begin + (live ? idx : 0);
     const double4 xp = a.sp[m.i_sorted];
-    m.hx = live ? (float)(xp.x - cx) : 1.0e30f;
-    m.hy = live ? (float)(xp.y - cy) : 1.0e30f;
-    m.hz = live ? (float)(xp.z - cz) : 1.0e30f;
-    m.mu = mu_f32(xp.w);
-    // separations below a tenth of the receiver's offset are recomputed
-    // in FP64 (and r^2 == 0, since ki is at least the smallest normal)
-    m.ki = fmaxf(0.01f * fmaf(m.hz, m.hz, fmaf(m.hy, m.hy, m.hx * m.hx)), 1.1754944e-38f);
-    if (!live) m.ki = 0.f;
-    if constexpr (KIND == kMutSoft) m.eb2 = (float)a.g.eps_b2;
+    if constexpr (F64) {
+        m.hx = live ? xp.x - cx : 1.0e30;
+        m.hy = live ? xp.y - cy : 1.0e30;
+        m.hz = live ? xp.z - cz : 1.0e30;
+        m.mu = xp.w;
+        // separations below a tenth of the receiver's offset take the plain
+        // form (and r^2 == 0, since ki is at least the smallest normal)
+        m.ki = live ? fmax(0.01 * fma(m.hz, m.hz, fma(m.hy, m.hy, m.hx * m.hx)),
+                           2.2250738585072014e-308)
+                    : 0.0;
+        m.rlo = a.g.rc2 * (1.0 - 0x1p-40);
+        m.rhi = a.g.rc2 * (1.0 + 0x1p-40);
+    } else {
+        m.hx = live ? (float)(xp.x - cx) : 1.0e30f;
+        m.hy = live ? (float)(xp.y - cy) : 1.0e30f;
+        m.hz = live ? (float)(xp.z - cz) : 1.0e30f;
+        m.mu = mu_f32(xp.w);
+        // separations below a tenth of the receiver's offset are recomputed
+        // in FP64 (and r^2 == 0, since ki is at least the smallest normal)
+        m.ki = fmaxf(0.01f * fmaf(m.hz, m.hz, fmaf(m.hy, m.hy, m.hx * m.hx)), 1.1754944e-38f);
+        if (!live) m.ki = 0.f;
+        if constexpr (KIND == kMutSoft) m.eb2 = (float)a.g.eps_b2;
+    }
     if constexpr (BWD) {
         if (live) {
             const float4 wk = reinterpret_cast<const float4 *>(a.wa)[m.i_sorted];
@@ -1394,6 +1568,11 @@ __device__ __forceinline__ void mutual_item(const PairArgs &a, const Item &item,
     walk_item(v, item, cl, a, lane);
     // the copies of a receiver in the rows r, r + R, ...
     double ax = v.ax, ay = v.ay, az = v.az;
+    if constexpr (F64) {
+        ax = m.ax;
+        ay = m.ay;
+        az = m.az;
+    }
     if constexpr (R <= 2) {
         ax += __shfl_xor(ax, 32, kWave);
         ay += __shfl_xor(ay, 32, kWave);
@@ -1423,11 +1602,12 @@ __device__ __forceinline__ void mutual_item(const PairArgs &a, const Item &item,
 // a.out: three FP64 arrays of a.out_stride (= n) values in sorted order,
 // zeroed before the launch.
 template <int RMAX, bool UNIT, int KIND>
-__global__ __launch_bounds__(kForceBlock) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ __launch_bounds__(kForceBlock)
+__attribute__((amdgpu_waves_per_eu(KIND == kMutF64 ? 4 : 5)))
 void k_pairs_mutual(PairArgs a) {
     constexpr bool BWD = KIND == kMutBwd;
     constexpr int NW = kForceBlock / kWave;
-    __shared__ float4 ring_pos[NW][kRing];
+    __shared__ MutEntry<KIND> ring_pos[NW][kRing];
     __shared__ int ring_idx[NW][kRing];
     __shared__ float4 ring_wt[BWD ? NW : 1][BWD ? kRing : 1];
     const int lane = threadIdx.x & (kWave - 1);
@@ -1490,8 +1670,9 @@ MutualFn mutual_kernel_mode(int csize, bool unit) {
 }
 
 // soft: the forward with B-spline softening (the adjoint has no softened
-// mutual kernel)
-MutualFn mutual_kernel(int csize, bool unit, bool bwd, bool soft) {
+// mutual kernel); f64: the FP64 forward (neither adjoint nor softening)
+MutualFn mutual_kernel(int csize, bool unit, bool bwd, bool soft, bool f64) {
+    if (f64) return (bwd || soft) ? nullptr : mutual_kernel_mode<kMutF64>(csize, unit);
     if (bwd) return soft ? nullptr : mutual_kernel_mode<kMutBwd>(csize, unit);
     return soft ? mutual_kernel_mode<kMutSoft>(csize, unit) : mutual_kernel_mode<kMutFwd>(csize, unit);
 }
@@ -1576,15 +1757,15 @@ hipError_t launch_pairs(int mode, int screen, int tab, const PairArgs &a, int gr
     return hipGetLastError();
 }
 
-hipError_t launch_pairs_mutual(const PairArgs &a, bool bwd, int grid, hipStream_t s) {
-    const MutualFn fn = mutual_kernel(a.csize, a.unit_mass != 0, bwd, a.g.eps_b > 0.0);
+hipError_t launch_pairs_mutual(const PairArgs &a, bool bwd, bool f64, int grid, hipStream_t s) {
+    const MutualFn fn = mutual_kernel(a.csize, a.unit_mass != 0, bwd, a.g.eps_b > 0.0, f64);
     if (!fn) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kForceBlock), 0, s, a);
     return hipGetLastError();
 }
 
-int mutual_blocks_per_cu(int csize, int unit_mass, bool bwd, bool soft) {
-    const MutualFn fn = mutual_kernel(csize, unit_mass != 0, bwd, soft);
+int mutual_blocks_per_cu(int csize, int unit_mass, bool bwd, bool soft, bool f64) {
+    const MutualFn fn = mutual_kernel(csize, unit_mass != 0, bwd, soft, f64);
     int nb = 0;
     if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kForceBlock, 0) != hipSuccess)
         return 1;

@@ -379,12 +379,13 @@ hipError_t launch_pm_readout(const double4 *rec, const int *nkey, const int *per
 // pair-kernel workgroups resident per CU for the variant launch_pairs would run
 int pairs_blocks_per_cu(int mode, int screen, int tab, int csize, int unit_mass, int soft);
 // All-active FP32 forward (bwd: the FP32 adjoint, every particle a receiver,
-// weights in a.wa) with each pair evaluated once for both partners (clusters
+// weights in a.wa; f64: the FP64 forward, without softening) with each pair
+// evaluated once for both partners (clusters
 // of csize = 16, 32 or 64 receivers, items over the upper half of the
 // stencil).  a.out: three FP64 arrays of a.out_stride = n sums in sorted
 // order, zeroed before the launch; launch_mutual_out then writes acc_out.
-hipError_t launch_pairs_mutual(const PairArgs &a, bool bwd, int grid, hipStream_t s);
-int mutual_blocks_per_cu(int csize, int unit_mass, bool bwd, bool soft);
+hipError_t launch_pairs_mutual(const PairArgs &a, bool bwd, bool f64, int grid, hipStream_t s);
+int mutual_blocks_per_cu(int csize, int unit_mass, bool bwd, bool soft, bool f64);
 hipError_t launch_mutual_out(const double *sums, const int *perm, int n, double *out,
                              hipStream_t s);
 

@@ -26,7 +26,8 @@ def env():
 
 LAYOUTS = [("fp32", dict(cluster_size=32, screen=2)),    # pairs for both partners
            ("fp32", dict(cluster_size=32, screen=1)),
-           ("fp64", dict(cluster_size=16, screen=1, item_target=512))]
+           ("fp64", dict(cluster_size=16, screen=1, item_target=512)),
+           ("fp64", dict(cluster_size=32, screen=2))]
 
 
 @pytest.mark.parametrize("prec, layout", LAYOUTS)

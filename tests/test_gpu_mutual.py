@@ -6,8 +6,9 @@ through the C ABI.
 Bars as for every FP32 path: e_L2 and e_max_cond <= 1e-5, and the exact
 accepted-pair count of the plain FP64 evaluation (pairs whose FP32 r^2 lies
 near r_cut^2 are decided in FP64).  Calls this layout does not cover (an
-active mask, FP64) fall back to the screened kernel; softened forward calls
-stay on it (pairs inside eps_B take the softened factor).
+active mask) fall back to the screened kernel; softened forward calls stay on
+it (pairs inside eps_B take the softened factor), and so do all-active FP64
+calls (the FP64 kind, tested on its own in test_gpu_mutual_fp64.py).
 """
 import numpy as np
 import pytest
@@ -215,9 +216,9 @@ def test_dense_subtiles_and_smallest_tiling(env, csize):
 
 
 def test_other_calls_fall_back(env):
-    """An active mask and FP64 take the screened kernel with the same cluster
-    size, a softened all-active FP32 call stays on the mutual kernel; results
-    match the oracle."""
+    """An active mask takes the screened kernel with the same cluster size;
+    an all-active FP64 call and a softened all-active FP32 call stay on the
+    mutual kernel; results match the oracle."""
     torch, p3, ctx = env
     pos, mass, active = random_particles(3000, seed=9, active_frac=0.5)
     x_s = 1.25 / 24
@@ -229,7 +230,7 @@ def test_other_calls_fall_back(env):
     check(acc, st, ref, cnt, absum)
     ref, cnt, absum = oracle.force_full(pos, mass, 1.0, x_s, r_cut, method="brute")
     acc, st = run(env, pos, mass, 1.0, x_s, r_cut, 32, prec="fp64")
-    assert st["screen"] == 1
+    assert st["screen"] == 2
     check(acc, st, ref, cnt, absum, "fp64")
     ctx.set_softening(0.002)
     try:
