@@ -972,14 +972,17 @@ void k_pairs(PairArgs a) {
 // The mutual kernels' call kinds: the forward force, the adjoint, the
 // forward force with B-spline softening.
 constexpr int kMutFwd = 0, kMutBwd = 1, kMutSoft = 2;
-// The FP64 forward force: FP64 offsets, separations, shape and sums.
-constexpr int kMutF64 = 3;
+// The FP64 forward force and the FP64 adjoint: FP64 offsets, separations,
+// pair terms and sums.
+constexpr int kMutF64 = 3, kMutF64Bwd = 4;
+template <int KIND> constexpr bool kMutIsF64 = KIND == kMutF64 || KIND == kMutF64Bwd;
+template <int KIND> constexpr bool kMutIsBwd = KIND == kMutBwd || KIND == kMutF64Bwd;
 
 template <bool B, class T, class F> struct MutPick { using type = T; };
 template <class T, class F> struct MutPick<false, T, F> { using type = F; };
-// A list entry in the ring (offset from the cluster centre and mu): FP32,
-// or FP64 for kMutF64.
-template <int KIND> using MutEntry = typename MutPick<KIND == kMutF64, double4, float4>::type;
+// A list entry in the ring (offset from the cluster centre and mu), and an
+// entry's adjoint weight: FP32, or FP64 for the FP64 kinds.
+template <int KIND> using MutEntry = typename MutPick<kMutIsF64<KIND>, double4, float4>::type;
 
 constexpr int kRing = 128;                    // list entries per wave (a ring)
 constexpr unsigned kIdxBits = 27;             // sorted index bits of a list entry
@@ -1219,6 +1222,7 @@ struct MutualLane64 {
     int i_sorted;
     double ax = 0.0, ay = 0.0, az = 0.0;   // the receiver's sums
     double jx = 0.0, jy = 0.0, jz = 0.0;   // reaction on this lane's entry
+    double wkx = 0.0, wky = 0.0, wkz = 0.0;   // adjoint: this receiver's w_k [k active]
 };
 
 // mutual_fp64_sep without the rounding to FP32.
@@ -1246,10 +1250,10 @@ __device__ __attribute__((noinline)) double4 mutual_sep_plain(const double4 *__r
 // a relative 2^-40 of r_cut^2 and pairs closer than a tenth of the
 // receiver's offset are redone in the plain form: the accepted pairs are the
 // plain form's.
-template <int S, bool UNIT, bool SELF>
-__device__ __forceinline__ void mutual_step64(MutualLane64 &m, const double4 &e, int jid,
-                                              const PairArgs &a, unsigned &cnt,
-                                              unsigned &rare_n) {
+template <int S, bool UNIT, bool SELF, bool BWD>
+__device__ __forceinline__ void mutual_step64(MutualLane64 &m, const double4 &e,
+                                              const double4 &ew, int jid, const PairArgs &a,
+                                              unsigned &cnt, unsigned &rare_n) {
     __builtin_amdgcn_sched_barrier(0);
     double dx = m.hx - rot16<S>(e.x);
     double dy = m.hy - rot16<S>(e.y);
@@ -1275,6 +1279,44 @@ __device__ __forceinline__ void mutual_step64(MutualLane64 &m, const double4 &e,
         acc_m = (acc_m & ~rare) | (ballot64(ok) & rare);
     }
     cnt += (unsigned)__builtin_popcountll(acc_m);
+    if constexpr (BWD) {
+        // the adjoint's term, as in the FP32 kind: receiver k gets -J(r) v
+        // and the entry j gets +J(r) v, v = mu_j w_k - mu_k w_j, J(r) v =
+        // phi v - c (r . v) r with phi and c of the FP64 screened kernel
+        double vx, vy, vz;
+        if constexpr (UNIT) {
+            vx = m.wkx - rot16<S>(ew.x);
+            vy = m.wky - rot16<S>(ew.y);
+            vz = m.wkz - rot16<S>(ew.z);
+        } else {
+            const double muj = rot16<S>(e.w);
+            vx = fma(muj, m.wkx, -(m.mu * rot16<S>(ew.x)));
+            vy = fma(muj, m.wky, -(m.mu * rot16<S>(ew.y)));
+            vz = fma(muj, m.wkz, -(m.mu * rot16<S>(ew.z)));
+        }
+        const double ri = rsqrt_pos(r2);
+        const double ri2 = ri * ri;
+        double dh;
+        const double h = h64_d(fma(r2, a.g.c2, -P3M_H64_T0), a.g.h64, dh);
+        // lanes without a pair give no term
+        const double phi = keep_lanes(acc_m, fma(a.g.c3, h, ri2 * ri));
+        const double c =
+            keep_lanes(acc_m, fma(3.0 * ri2 * ri2, ri, -2.0 * a.g.c2 * a.g.c3 * dh));
+        const double crv = c * fma(dz, vz, fma(dy, vy, dx * vx));
+        const double ox = fma(-crv, dx, phi * vx);
+        const double oy = fma(-crv, dy, phi * vy);
+        const double oz = fma(-crv, dz, phi * vz);
+        m.ax -= ox;
+        m.ay -= oy;
+        m.az -= oz;
+        if constexpr (!SELF) {
+            m.jx += rot16<(16 - S) & 15>(ox);
+            m.jy += rot16<(16 - S) & 15>(oy);
+            m.jz += rot16<(16 - S) & 15>(oz);
+        }
+        asm volatile("" ::"v"(m.ax), "v"(m.ay), "v"(m.az), "v"(m.jx), "v"(m.jy), "v"(m.jz));
+        return;
+    }
     const double ri = rsqrt_pos(r2);
     const double h = h64(fma(r2, a.g.c2, -P3M_H64_T0), a.g.h64);
     const double ri3 = ri * ri * ri;
@@ -1297,27 +1339,27 @@ __device__ __forceinline__ void mutual_step64(MutualLane64 &m, const double4 &e,
     asm volatile("" ::"v"(m.ax), "v"(m.ay), "v"(m.az), "v"(m.jx), "v"(m.jy), "v"(m.jz));
 }
 
-template <bool UNIT, bool SELF, int NS>
-__device__ __forceinline__ void mutual_steps64(MutualLane64 &m, const double4 &e, int jid,
-                                               const PairArgs &a, unsigned &cnt,
-                                               unsigned &rare_n) {
-    mutual_step64<0, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-    mutual_step64<1, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-    mutual_step64<2, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-    mutual_step64<3, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+template <bool UNIT, bool SELF, int NS, bool BWD>
+__device__ __forceinline__ void mutual_steps64(MutualLane64 &m, const double4 &e,
+                                               const double4 &ew, int jid, const PairArgs &a,
+                                               unsigned &cnt, unsigned &rare_n) {
+    mutual_step64<0, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+    mutual_step64<1, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+    mutual_step64<2, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+    mutual_step64<3, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
     if constexpr (NS > 4) {
-        mutual_step64<4, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step64<5, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step64<6, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step64<7, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step64<8, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step64<9, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step64<10, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step64<11, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step64<12, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step64<13, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step64<14, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
-        mutual_step64<15, UNIT, SELF>(m, e, jid, a, cnt, rare_n);
+        mutual_step64<4, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<5, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<6, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<7, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<8, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<9, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<10, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<11, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<12, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<13, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<14, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<15, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
     }
 }
 
@@ -1332,15 +1374,15 @@ __device__ __forceinline__ T rows_sum(T v) {
 
 template <int R, bool UNIT, int KIND>
 struct MutualVisit {
-    static constexpr bool BWD = KIND == kMutBwd;
-    static constexpr bool F64 = KIND == kMutF64;
+    static constexpr bool BWD = kMutIsBwd<KIND>;
+    static constexpr bool F64 = kMutIsF64<KIND>;
     using Lane = typename MutPick<F64, MutualLane64, MutualLane>::type;
     static constexpr int EB = 64 / R;   // list entries per block of 16 steps
     const PairArgs &a;
     Lane &m;
     MutEntry<KIND> *lpos;   // ring: offset from the cluster centre, mu
     int *lidx;           // ring: sorted index | image << kIdxBits
-    float4 *lw;          // ring (adjoint): the entry's weight w_j [j active]
+    MutEntry<KIND> *lw;   // ring (adjoint): the entry's weight w_j [j active]
     const double *lo, *hi;
     double cx, cy, cz;   // the cluster centre
     int lane;
@@ -1361,6 +1403,12 @@ struct MutualVisit {
             m.axf = m.ayf = m.azf = 0.f;
         }
     }
+    // an entry's adjoint weight (FP32 records for the FP32 adjoint)
+    __device__ __forceinline__ static MutEntry<KIND> wa_entry_of(const PairArgs &a, int j) {
+        if constexpr (F64) return a.wa[j];
+        else return reinterpret_cast<const float4 *>(a.wa)[j];
+    }
+    __device__ __forceinline__ MutEntry<KIND> wa_entry(int j) const { return wa_entry_of(a, j); }
     __device__ __forceinline__ static MutEntry<KIND> far_entry() {
         if constexpr (F64) return make_double4(-1.0e30, -1.0e30, -1.0e30, 0.0);
         else return make_float4(-1.0e30f, -1.0e30f, -1.0e30f, 0.f);
@@ -1372,7 +1420,7 @@ struct MutualVisit {
         const int row = lane >> 4;
         const int k = (row / R) * 16 + (lane & 15);
         MutEntry<KIND> e = far_entry();
-        float4 ew = make_float4(0.f, 0.f, 0.f, 0.f);
+        MutEntry<KIND> ew{};
         int jid = -1;
         if (k < nv) {
             const int q = (head + k) & (kRing - 1);
@@ -1383,7 +1431,7 @@ struct MutualVisit {
         wave_lds_sync();   // the reads are done before later screens overwrite the ring
         m.jx = m.jy = m.jz = 0.f;
         unsigned cnt = 0, rn = 0;
-        if constexpr (F64) mutual_steps64<UNIT, false, 16>(m, e, jid, a, cnt, rn);
+        if constexpr (F64) mutual_steps64<UNIT, false, 16, BWD>(m, e, ew, jid, a, cnt, rn);
         else mutual_steps<UNIT, false, 16, KIND>(m, e, ew, jid, a, cnt, rn);
         flush_i();
         const auto jx = rows_sum<R>(m.jx), jy = rows_sum<R>(m.jy), jz = rows_sum<R>(m.jz);
@@ -1412,7 +1460,7 @@ struct MutualVisit {
             else if constexpr (R == 2) idx = 16 * (row >> 1) + l;
             else idx = 16 * ((row + p) & 3) + l;
             MutEntry<KIND> e = far_entry();
-            float4 ew = make_float4(0.f, 0.f, 0.f, 0.f);
+            MutEntry<KIND> ew{};
             int jid = -1;
             if (idx < cnt) {
                 const double4 q = a.sp[begin + idx];
@@ -1422,10 +1470,11 @@ struct MutualVisit {
                     e = make_float4((float)(q.x - cx), (float)(q.y - cy), (float)(q.z - cz),
                                     UNIT ? 0.f : mu_f32(q.w));
                 jid = (begin + idx) | (13 << kIdxBits);
-                if constexpr (BWD) ew = reinterpret_cast<const float4 *>(a.wa)[begin + idx];
+                if constexpr (BWD) ew = wa_entry(begin + idx);
             }
             unsigned c = 0, rn = 0;
-            if constexpr (F64) mutual_steps64<UNIT, true, R == 1 ? 4 : 16>(m, e, jid, a, c, rn);
+            if constexpr (F64)
+                mutual_steps64<UNIT, true, R == 1 ? 4 : 16, BWD>(m, e, ew, jid, a, c, rn);
             else mutual_steps<UNIT, true, R == 1 ? 4 : 16, KIND>(m, e, ew, jid, a, c, rn);
             flush_i();
             pairs += c;
@@ -1455,7 +1504,7 @@ struct MutualVisit {
                 lpos[q] = make_float4((float)(px - cx), (float)(py - cy), (float)(pz - cz),
                                       UNIT ? 0.f : mu_f32(p.w));
             lidx[q] = (jj + lane) | (code << kIdxBits);
-            if constexpr (BWD) lw[q] = reinterpret_cast<const float4 *>(a.wa)[jj + lane];
+            if constexpr (BWD) lw[q] = wa_entry(jj + lane);
         }
         n_list += __builtin_popcountll(mk);
         fill = 0;
@@ -1519,9 +1568,9 @@ template <int R, bool UNIT, int KIND>
 __device__ __forceinline__ void mutual_item(const PairArgs &a, const Item &item,
                                             const Cluster &cl, int cnt, int begin, int lane,
                                             MutEntry<KIND> *ring_pos, int *ring_idx,
-                                            float4 *ring_w, MutualTally &tally) {
-    constexpr bool BWD = KIND == kMutBwd;
-    constexpr bool F64 = KIND == kMutF64;
+                                            MutEntry<KIND> *ring_w, MutualTally &tally) {
+    constexpr bool BWD = kMutIsBwd<KIND>;
+    constexpr bool F64 = kMutIsF64<KIND>;
     const int row = lane >> 4, l = lane & 15;
     const double cx = 0.5 * (cl.lo[0] + cl.hi[0]);
     const double cy = 0.5 * (cl.lo[1] + cl.hi[1]);
@@ -1556,7 +1605,7 @@ __device__ __forceinline__ void mutual_item(const PairArgs &a, const Item &item,
     }
     if constexpr (BWD) {
         if (live) {
-            const float4 wk = reinterpret_cast<const float4 *>(a.wa)[m.i_sorted];
+            const MutEntry<KIND> wk = MutualVisit<R, UNIT, KIND>::wa_entry_of(a, m.i_sorted);
             m.wkx = wk.x;
             m.wky = wk.y;
             m.wkz = wk.z;
@@ -1603,13 +1652,13 @@ __device__ __forceinline__ void mutual_item(const PairArgs &a, const Item &item,
 // zeroed before the launch.
 template <int RMAX, bool UNIT, int KIND>
 __global__ __launch_bounds__(kForceBlock)
-__attribute__((amdgpu_waves_per_eu(KIND == kMutF64 ? 4 : 5)))
+__attribute__((amdgpu_waves_per_eu(kMutIsF64<KIND> ? 4 : 5)))
 void k_pairs_mutual(PairArgs a) {
-    constexpr bool BWD = KIND == kMutBwd;
+    constexpr bool BWD = kMutIsBwd<KIND>;
     constexpr int NW = kForceBlock / kWave;
     __shared__ MutEntry<KIND> ring_pos[NW][kRing];
     __shared__ int ring_idx[NW][kRing];
-    __shared__ float4 ring_wt[BWD ? NW : 1][BWD ? kRing : 1];
+    __shared__ MutEntry<KIND> ring_wt[BWD ? NW : 1][BWD ? kRing : 1];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
     ItemCursor cursor;
@@ -1670,9 +1719,12 @@ MutualFn mutual_kernel_mode(int csize, bool unit) {
 }
 
 // soft: the forward with B-spline softening (the adjoint has no softened
-// mutual kernel); f64: the FP64 forward (neither adjoint nor softening)
+// mutual kernel); f64: the FP64 forward and adjoint (without softening)
 MutualFn mutual_kernel(int csize, bool unit, bool bwd, bool soft, bool f64) {
-    if (f64) return (bwd || soft) ? nullptr : mutual_kernel_mode<kMutF64>(csize, unit);
+    if (f64) {
+        if (soft) return nullptr;
+        return bwd ? mutual_kernel_mode<kMutF64Bwd>(csize, unit) : mutual_kernel_mode<kMutF64>(csize, unit);
+    }
     if (bwd) return soft ? nullptr : mutual_kernel_mode<kMutBwd>(csize, unit);
     return soft ? mutual_kernel_mode<kMutSoft>(csize, unit) : mutual_kernel_mode<kMutFwd>(csize, unit);
 }

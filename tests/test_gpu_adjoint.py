@@ -26,7 +26,7 @@ def gpu_vjp(env, pos, mass, active, w, box, x_s, r_cut, prec):
 
 
 @pytest.mark.parametrize("prec, tol, screen", [("fp64", 1e-12, 1), ("fp32", 1e-5, 1),
-                                               ("fp32", 1e-5, 2)])
+                                               ("fp32", 1e-5, 2), ("fp64", 1e-12, 2)])
 @pytest.mark.parametrize("frac", [None, 0.3])
 def test_vjp_matches_oracle(env, prec, tol, screen, frac):
     """Config with N = 64^3 clustered particles (PM grid 128^3), every row of
@@ -69,8 +69,8 @@ def test_vjp_small_clusters(env, prec, tol, csize, screen):
     """The adjoint on small clusters (several copies of a cluster per wave),
     with and without the per-supplier screen (the listed suppliers carry
     their weights), and, in FP32, with each pair evaluated once for both
-    partners (screen 2; FP64 calls run it as screen 1), matches the oracle's
-    VJP like the default layout does."""
+    partners (screen 2, in FP32 and in FP64), matches the oracle's VJP like
+    the default layout does."""
     torch, p3, ctx = env
     print("vjp clustered n_side=24 csize", csize, "screen", screen, prec, flush=True)
     wl = make_workload("diff64", n_side=24)
@@ -86,13 +86,13 @@ def test_vjp_small_clusters(env, prec, tol, csize, screen):
     finally:
         ctx.set_config()
     assert st["cluster_size"] == csize
-    assert st["screen"] == (1 if (screen == 2 and prec == "fp64") else screen)
+    assert st["screen"] == screen
     rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
     row = np.max(np.linalg.norm(g - ref, axis=1)) / np.max(np.linalg.norm(ref, axis=1))
     assert rel <= tol and row <= tol, (rel, row)
 
 
-@pytest.mark.parametrize("prec, screen", [("fp64", 1), ("fp32", 1), ("fp32", 2)])
+@pytest.mark.parametrize("prec, screen", [("fp64", 1), ("fp32", 1), ("fp32", 2), ("fp64", 2)])
 def test_vjp_finite_differences_diff64(env, prec, screen):
     """Config with N = 64^3 clustered particles, Gaussian weights: adjoint vs
     central differences (step 1e-6 L, pair set frozen) on 64 samples."""

@@ -37,13 +37,9 @@ def test_autotuned_forward_and_adjoint(prec):
     assert ctx.stats()["interactions"] == int(cnt.sum())
 
     # the adjoint takes the forward's layout until it is tuned on its own
-    # (screen 2 included: the FP32 adjoint also pairs once for both partners;
-    # the FP64 adjoint does not, and takes the layout kept beside that winner)
+    # (screen 2 included: the adjoint also pairs once for both partners)
     ctx.force_backward(pos, m, None, to_dev(torch, w), **kw)
-    if prec == "fp64" and fwd["screen"] == 2:
-        assert ctx.stats()["screen"] in (0, 1)
-    else:
-        assert {k: ctx.stats()[k] for k in LAYOUT} == fwd
+    assert {k: ctx.stats()[k] for k in LAYOUT} == fwd
     ctx.autotune(pos, m, None, level=1, adjoint=True, **kw)
     g = ctx.force_backward(pos, m, None, to_dev(torch, w), **kw).cpu().numpy()
     adj = {k: ctx.stats()[k] for k in LAYOUT}

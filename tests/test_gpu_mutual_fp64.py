@@ -6,8 +6,9 @@ wavefront's rows) vs the FP64 CPU oracle, through the C ABI.
 Bars as for every FP64 path: e_L2 and e_max_cond <= 1e-12 and the exact
 accepted-pair count of the oracle (pairs whose squared distance lies within a
 relative 2^-40 of r_cut^2, or closer than a tenth of the receiver's offset
-from the cluster centre, are evaluated in the plain form).  FP64 adjoints and
-softened FP64 calls keep the screened kernel.
+from the cluster centre, are evaluated in the plain form).  The FP64 adjoint
+takes the same layout (rows against the oracle's VJP to 1e-12); softened FP64
+calls keep the screened kernel.
 """
 import numpy as np
 import pytest
@@ -135,20 +136,43 @@ def test_clustered128_pair_count_exact(env):
     assert st["interactions"] == int(cnt.sum())
 
 
-def test_adjoint_and_softened_keep_the_screened_kernel(env):
+@pytest.mark.parametrize("csize", [16, 32, 64])
+@pytest.mark.parametrize("masses", [False, True])
+def test_adjoint_pairs_once(env, csize, masses):
+    """The FP64 adjoint in the same layout: every row against the oracle's
+    analytic VJP, with half the particles active (activity enters through
+    the weights)."""
+    torch, p3, ctx = env
+    print("fp64 mutual adjoint csize", csize, "masses", masses, flush=True)
+    wl = make_workload("diff64", n_side=24)
+    rng = np.random.default_rng(13)
+    mass = rng.uniform(0.5, 2.0, wl.n) if masses else None
+    active = (rng.random(wl.n) < 0.5).astype(np.uint8)
+    w = rng.standard_normal((wl.n, 3))
+    ref = oracle.vjp(wl.pos, mass, active, w, 1.0, wl.x_s, wl.r_cut, method="tiled")
+    ctx.set_config(cluster_size=csize, screen=2)
+    try:
+        g = ctx.force_backward(to_dev(torch, wl.pos), to_dev(torch, mass), to_dev(torch, active),
+                               to_dev(torch, w), box=1.0, x_s=wl.x_s, r_cut=wl.r_cut,
+                               precision="fp64").cpu().numpy()
+        st = ctx.stats()
+    finally:
+        ctx.set_config()
+    assert st["screen"] == 2 and st["cluster_size"] == csize
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    row = np.max(np.linalg.norm(g - ref, axis=1)) / np.max(np.linalg.norm(ref, axis=1))
+    assert rel <= 1e-12 and row <= 1e-12, (rel, row)
+
+
+def test_softened_keeps_the_screened_kernel(env):
     torch, p3, ctx = env
     pos, mass, _ = random_particles(3000, seed=9)
     x_s = 1.25 / 24
     r_cut = 4.5 * x_s
     w = np.random.default_rng(4).standard_normal((3000, 3))
     ctx.set_config(cluster_size=32, screen=2)
+    ctx.set_softening(0.002)
     try:
-        g = ctx.force_backward(to_dev(torch, pos), to_dev(torch, mass), None, to_dev(torch, w),
-                               box=1.0, x_s=x_s, r_cut=r_cut, precision="fp64").cpu().numpy()
-        assert ctx.stats()["screen"] == 1
-        ref = oracle.vjp(pos, mass, None, w, 1.0, x_s, r_cut, method="tiled")
-        assert np.linalg.norm(g - ref) <= 1e-12 * np.linalg.norm(ref)
-        ctx.set_softening(0.002)
         acc = ctx.force(to_dev(torch, pos), to_dev(torch, mass), None, box=1.0, x_s=x_s,
                         r_cut=r_cut, precision="fp64").cpu().numpy()
         assert ctx.stats()["screen"] == 1
@@ -156,6 +180,9 @@ def test_adjoint_and_softened_keep_the_screened_kernel(env):
                                             eps=0.002)
         e = oracle.errors(acc, ref, absum)
         assert e["e_l2"] <= TOL["fp64"] and e["e_max_cond"] <= TOL["fp64"], e
+        ctx.force_backward(to_dev(torch, pos), to_dev(torch, mass), None, to_dev(torch, w),
+                           box=1.0, x_s=x_s, r_cut=r_cut, precision="fp64")
+        assert ctx.stats()["screen"] == 1
     finally:
         ctx.set_softening(0.0)
         ctx.set_config()
