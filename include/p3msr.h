@@ -225,8 +225,8 @@ int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
  * section 2.1.3 "Subtiles": try a finer subdivision, time it, keep it if
  * faster).  Times p3m_sr_force on these inputs for candidate subtile counts
  * per dimension crossed with cluster layouts (cluster size, screening, and
- * for all-active forward calls and unsoftened FP32 adjoints the mutual
- * layout screen = 2) and,
+ * for all-active forward calls and unsoftened adjoints the mutual layout
+ * screen = 2) and,
  * at level >= 2, work-item sizes around the winner; stores the fastest in the
  * handle (a candidate replaces an earlier one only when more than 3 % faster,
  * so near-ties do not flip with timing noise); later calls on the same
@@ -252,8 +252,7 @@ int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
  * fastest of them is kept (and cached, as kind 3 for the forward, 4 for
  * the adjoint) beside it: calls with this key that cannot take screen 2
  * (with an active mask, with a tabulated shape, in the deterministic mode,
- * softened adjoints, FP64 adjoints and softened FP64 calls) run in that
- * layout.
+ * softened adjoints and softened FP64 calls) run in that layout.
  */
 #define P3M_TUNE_ADJOINT 4
 #define P3M_TUNE_FORCE 8
@@ -315,10 +314,10 @@ int p3m_sr_tune_cache_check(const char *path, int *entries, int *lines);
  *                     loop (the subtile-pair culling of section 2.1.3
  *                     carried down to single suppliers); 0: no screening;
  *                     2: screened, and for all-active P3M_FP32 forward calls
- *                     (polynomial shape, softened or not), P3M_FP32
- *                     backward calls without softening and all-active
- *                     P3M_FP64 forward calls without softening (n <= 2^27
- *                     for all) each pair is evaluated once for
+ *                     (polynomial shape, softened or not), all-active
+ *                     P3M_FP64 forward calls without softening and backward
+ *                     calls without softening (n <= 2^27 for all) each pair
+ *                     is evaluated once for
  *                     both partners (Newton's third law, as the paper's tile
  *                     pairing in section 2.1.3, "Tiles"; the adjoint's pair
  *                     term is antisymmetric too): clusters visit the upper
