@@ -966,6 +966,11 @@ void k_pairs(PairArgs a) {
 // The pair factor is the FP32 shape of FwdF32 (hardware rsqrt and the H
 // polynomial); a block's sums are FP32 over its 16 steps and then FP64.
 //
+// The FP64 kinds (forward and adjoint of FP64 calls) keep the offsets, the
+// pair term and every sum in FP64; a rotated FP64 operand takes two DPP
+// moves, and the two rare cases are a relative 2^-40 band around r_cut^2
+// and the same close-pair rule, redone in the plain form (x_i - x_j) - n' box.
+//
 // The sums go to an FP64 array in sorted order, one component after the
 // other (three arrays of n), which a final pass writes to acc_out.
 
