@@ -556,15 +556,15 @@ int run(p3m_sr_context *h, const Request &r, SrWork &w) {
     // tabulated FP32 shape (point particles, forward only)
     const int shape = (fp32 && !r.backward && eps_b == 0.0) ? h->cfg_shape : SHAPE_POLY;
     // each pair once for both partners: calls with every particle a receiver
-    // (FP32: all-active forward calls with the polynomial shape, softened or
-    // not, and the adjoint without softening; FP64: all-active forward calls
-    // and the adjoint, without softening), fewer than 2^27 particles
+    // (all-active forward calls with the polynomial shape, softened or not,
+    // and the adjoint without softening, in both precisions), fewer than 2^27
+    // particles
     // (the list entries hold the sorted index in 27 bits), not in the
     // deterministic mode (its reactions are added with atomics), and
     // clusters of 16, 32 or 64
     const bool det = h->deterministic;
     const bool mutual_ok = all_recv && shape == SHAPE_POLY &&
-                           (fp32 ? (eps_b == 0.0 || !r.backward) : eps_b == 0.0) &&
+                           (eps_b == 0.0 || !r.backward) &&
                            r.n <= (int64_t)(1u << 27) && !det;
 
     // decomposition: explicit override > user config > autotuned > default
@@ -1501,12 +1501,11 @@ int p3m_sr_autotune(p3m_sr_handle h, const double *pos, const double *mass, cons
     // level 2 also sweeps the item size around the level-1 winner
     std::vector<std::pair<int, int>> layouts = {{64, 0}, {64, 1}, {32, 1}, {16, 1}, {8, 1},
                                                 {16, 0}, {8, 0}};
-    // all-active FP32 forward calls (softened or not), all-active FP64
-    // forward calls without softening and adjoints without softening can
-    // evaluate each pair once for both partners
+    // all-active forward calls (softened or not; FP32 ones with the
+    // polynomial shape) and adjoints without softening can evaluate each pair
+    // once for both partners
     const bool fp32_t = precision == P3M_FP32;
-    if (adjoint ? h->eps == 0.0
-                : (!active && (fp32_t ? h->cfg_shape == SHAPE_POLY : h->eps == 0.0)))
+    if (adjoint ? h->eps == 0.0 : (!active && (!fp32_t || h->cfg_shape == SHAPE_POLY)))
         for (int c : {32, 64, 16}) layouts.push_back({c, kScreenMutual});
     const TuneKey key{n, nt, precision, adjoint ? TUNE_ADJOINT : TUNE_FORWARD, 1};
     rc = tune(h, r, key, level, {1, 2, 3, 4}, layouts, {1024, 4096},

@@ -966,10 +966,11 @@ void k_pairs(PairArgs a) {
 // The pair factor is the FP32 shape of FwdF32 (hardware rsqrt and the H
 // polynomial); a block's sums are FP32 over its 16 steps and then FP64.
 //
-// The FP64 kinds (forward and adjoint of FP64 calls) keep the offsets, the
-// pair term and every sum in FP64; a rotated FP64 operand takes two DPP
-// moves, and the two rare cases are a relative 2^-40 band around r_cut^2
-// and the same close-pair rule, redone in the plain form (x_i - x_j) - n' box.
+// The FP64 kinds (forward, softened forward and adjoint of FP64 calls) keep
+// the offsets, the pair term and every sum in FP64; a rotated FP64 operand
+// takes two DPP moves, and the two rare cases are a relative 2^-40 band
+// around r_cut^2 and the same close-pair rule, redone in the plain form
+// (x_i - x_j) - n' box.
 //
 // The sums go to an FP64 array in sorted order, one component after the
 // other (three arrays of n), which a final pass writes to acc_out.
@@ -977,10 +978,11 @@ void k_pairs(PairArgs a) {
 // The mutual kernels' call kinds: the forward force, the adjoint, the
 // forward force with B-spline softening.
 constexpr int kMutFwd = 0, kMutBwd = 1, kMutSoft = 2;
-// The FP64 forward force and the FP64 adjoint: FP64 offsets, separations,
-// pair terms and sums.
-constexpr int kMutF64 = 3, kMutF64Bwd = 4;
-template <int KIND> constexpr bool kMutIsF64 = KIND == kMutF64 || KIND == kMutF64Bwd;
+// The FP64 forward force, the FP64 adjoint and the softened FP64 forward
+// force: FP64 offsets, separations, pair terms and sums.
+constexpr int kMutF64 = 3, kMutF64Bwd = 4, kMutF64Soft = 5;
+template <int KIND>
+constexpr bool kMutIsF64 = KIND == kMutF64 || KIND == kMutF64Bwd || KIND == kMutF64Soft;
 template <int KIND> constexpr bool kMutIsBwd = KIND == kMutBwd || KIND == kMutF64Bwd;
 
 template <bool B, class T, class F> struct MutPick { using type = T; };
@@ -1255,7 +1257,7 @@ __device__ __attribute__((noinline)) double4 mutual_sep_plain(const double4 *__r
 // a relative 2^-40 of r_cut^2 and pairs closer than a tenth of the
 // receiver's offset are redone in the plain form: the accepted pairs are the
 // plain form's.
-template <int S, bool UNIT, bool SELF, bool BWD>
+template <int S, bool UNIT, bool SELF, bool BWD, bool SOFT>
 __device__ __forceinline__ void mutual_step64(MutualLane64 &m, const double4 &e,
                                               const double4 &ew, int jid, const PairArgs &a,
                                               unsigned &cnt, unsigned &rare_n) {
@@ -1325,8 +1327,18 @@ __device__ __forceinline__ void mutual_step64(MutualLane64 &m, const double4 &e,
     const double ri = rsqrt_pos(r2);
     const double h = h64(fma(r2, a.g.c2, -P3M_H64_T0), a.g.h64);
     const double ri3 = ri * ri * ri;
+    double shv = fma(a.g.c3, h, ri3);
+    if constexpr (SOFT) {
+        // pairs inside the softening length (few): c3 H(t) + |r|_B^-3, as
+        // in the screened FP64 kernel
+        const unsigned long long m_soft = ballot64(r2 < a.g.eps_b2) & acc_m;
+        if (m_soft) {
+            if ((m_soft >> (threadIdx.x & (kWave - 1))) & 1ull)
+                shv = fma(a.g.c3, h, bspline_m3(r2 * ri * a.g.inv_eps_b, ri3, a.g));
+        }
+    }
     // lanes without a pair send no reaction
-    const double sh = keep_lanes(acc_m, fma(a.g.c3, h, ri3));
+    const double sh = keep_lanes(acc_m, shv);
     double shj = sh, shi = sh;
     if constexpr (!UNIT) {
         shj = sh * rot16<S>(e.w);
@@ -1344,27 +1356,27 @@ __device__ __forceinline__ void mutual_step64(MutualLane64 &m, const double4 &e,
     asm volatile("" ::"v"(m.ax), "v"(m.ay), "v"(m.az), "v"(m.jx), "v"(m.jy), "v"(m.jz));
 }
 
-template <bool UNIT, bool SELF, int NS, bool BWD>
+template <bool UNIT, bool SELF, int NS, bool BWD, bool SOFT>
 __device__ __forceinline__ void mutual_steps64(MutualLane64 &m, const double4 &e,
                                                const double4 &ew, int jid, const PairArgs &a,
                                                unsigned &cnt, unsigned &rare_n) {
-    mutual_step64<0, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-    mutual_step64<1, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-    mutual_step64<2, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-    mutual_step64<3, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+    mutual_step64<0, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
+    mutual_step64<1, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
+    mutual_step64<2, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
+    mutual_step64<3, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
     if constexpr (NS > 4) {
-        mutual_step64<4, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step64<5, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step64<6, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step64<7, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step64<8, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step64<9, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step64<10, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step64<11, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step64<12, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step64<13, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step64<14, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
-        mutual_step64<15, UNIT, SELF, BWD>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<4, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<5, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<6, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<7, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<8, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<9, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<10, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<11, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<12, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<13, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<14, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
+        mutual_step64<15, UNIT, SELF, BWD, SOFT>(m, e, ew, jid, a, cnt, rare_n);
     }
 }
 
@@ -1436,7 +1448,8 @@ struct MutualVisit {
         wave_lds_sync();   // the reads are done before later screens overwrite the ring
         m.jx = m.jy = m.jz = 0.f;
         unsigned cnt = 0, rn = 0;
-        if constexpr (F64) mutual_steps64<UNIT, false, 16, BWD>(m, e, ew, jid, a, cnt, rn);
+        if constexpr (F64)
+            mutual_steps64<UNIT, false, 16, BWD, KIND == kMutF64Soft>(m, e, ew, jid, a, cnt, rn);
         else mutual_steps<UNIT, false, 16, KIND>(m, e, ew, jid, a, cnt, rn);
         flush_i();
         const auto jx = rows_sum<R>(m.jx), jy = rows_sum<R>(m.jy), jz = rows_sum<R>(m.jz);
@@ -1479,7 +1492,8 @@ struct MutualVisit {
             }
             unsigned c = 0, rn = 0;
             if constexpr (F64)
-                mutual_steps64<UNIT, true, R == 1 ? 4 : 16, BWD>(m, e, ew, jid, a, c, rn);
+                mutual_steps64<UNIT, true, R == 1 ? 4 : 16, BWD, KIND == kMutF64Soft>(m, e, ew,
+                                                                                    jid, a, c, rn);
             else mutual_steps<UNIT, true, R == 1 ? 4 : 16, KIND>(m, e, ew, jid, a, c, rn);
             flush_i();
             pairs += c;
@@ -1724,11 +1738,11 @@ MutualFn mutual_kernel_mode(int csize, bool unit) {
 }
 
 // soft: the forward with B-spline softening (the adjoint has no softened
-// mutual kernel); f64: the FP64 forward and adjoint (without softening)
+// mutual kernel); f64: the FP64 kinds (likewise)
 MutualFn mutual_kernel(int csize, bool unit, bool bwd, bool soft, bool f64) {
     if (f64) {
-        if (soft) return nullptr;
-        return bwd ? mutual_kernel_mode<kMutF64Bwd>(csize, unit) : mutual_kernel_mode<kMutF64>(csize, unit);
+        if (bwd) return soft ? nullptr : mutual_kernel_mode<kMutF64Bwd>(csize, unit);
+        return soft ? mutual_kernel_mode<kMutF64Soft>(csize, unit) : mutual_kernel_mode<kMutF64>(csize, unit);
     }
     if (bwd) return soft ? nullptr : mutual_kernel_mode<kMutBwd>(csize, unit);
     return soft ? mutual_kernel_mode<kMutSoft>(csize, unit) : mutual_kernel_mode<kMutFwd>(csize, unit);

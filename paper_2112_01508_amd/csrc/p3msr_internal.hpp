@@ -379,7 +379,7 @@ hipError_t launch_pm_readout(const double4 *rec, const int *nkey, const int *per
 // pair-kernel workgroups resident per CU for the variant launch_pairs would run
 int pairs_blocks_per_cu(int mode, int screen, int tab, int csize, int unit_mass, int soft);
 // All-active FP32 forward (bwd: the FP32 adjoint, every particle a receiver,
-// weights in a.wa; f64: the FP64 forward and adjoint, without softening) with each pair
+// weights in a.wa; f64: the FP64 kinds, the adjoint without softening) with each pair
 // evaluated once for both partners (clusters
 // of csize = 16, 32 or 64 receivers, items over the upper half of the
 // stencil).  a.out: three FP64 arrays of a.out_stride = n sums in sorted
