@@ -252,7 +252,7 @@ int p3m_sr_force_batched(p3m_sr_handle h, const double *pos, const double *mass,
  * fastest of them is kept (and cached, as kind 3 for the forward, 4 for
  * the adjoint) beside it: calls with this key that cannot take screen 2
  * (with an active mask, with a tabulated shape, in the deterministic mode,
- * softened adjoints and softened FP64 calls) run in that layout.
+ * or softened adjoints) run in that layout.
  */
 #define P3M_TUNE_ADJOINT 4
 #define P3M_TUNE_FORCE 8
@@ -315,7 +315,7 @@ int p3m_sr_tune_cache_check(const char *path, int *entries, int *lines);
  *                     carried down to single suppliers); 0: no screening;
  *                     2: screened, and for all-active P3M_FP32 forward calls
  *                     (polynomial shape, softened or not), all-active
- *                     P3M_FP64 forward calls without softening and backward
+ *                     P3M_FP64 forward calls (softened or not) and backward
  *                     calls without softening (n <= 2^27 for all) each pair
  *                     is evaluated once for
  *                     both partners (Newton's third law, as the paper's tile
