@@ -339,7 +339,7 @@ def deterministic_leg(torch, ctx, pos, mass, wl, steps, warmup):
 
 def subtiles_leg(torch, p3):
     """Fixed subtiles per tile dimension (1..4; items of 4096, 32-receiver
-    clusters, screen 1, and screen 2 for the FP32 forward and adjoint) against the
+    clusters, screen 1, and screen 2 for the forward and the adjoint) against the
     autotuner's choice (section 2.1.3, "Subtiles"; the paper's subtile
     experiment), on the diff64 set (forward and adjoint) and the rung-batched
     clustered256 launch, FP32 and FP64.  Pair-kernel ms (HIP events, median)."""
@@ -381,7 +381,7 @@ def subtiles_leg(torch, p3):
                 st = ctx.stats()
                 return statistics.median(ms), st
 
-            for screen in ([1, 2] if (kind in ("forward", "adjoint") and prec == "fp32") else [1]):
+            for screen in ([1, 2] if kind in ("forward", "adjoint") else [1]):
                 for ns in (1, 2, 3, 4):
                     ctx.set_config(ns, 4096, 32, screen)
                     ms, st = timed()
